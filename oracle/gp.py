@@ -1,0 +1,419 @@
+"""FP64 CPU oracle of the explicit grand-potential phase-field step.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark use this module.  It shares no code with the HIP path: it
+is plain numpy, slow and written to be checked against MICROSIM
+(arXiv 2404.01035) Sec. 2.1 by eye.  It also runs on complex arrays, which lets
+the tests take complex-step derivatives of it.
+
+What one step computes (forward Euler; the paper states only the continuous
+equations, so this discrete scheme is the reading both implementations follow):
+
+Phase fields, Eq. phi_eqn without the elastic term:
+    tau eps dphi_a/dt = eps (div da/dgrad(phi_a) - da/dphi_a) - w_{,a}/eps - psi_{,a} - lambda
+  * a = sum_{a<b} gamma_ab a_c(q_ab)^2 |q_ab|^2, q_ab = phi_a grad phi_b - phi_b grad phi_a
+    (Eq. Eqn_a), evaluated on cell faces: on a face normal to axis n between
+    cells L and R, phi_bar = (phi_L + phi_R)/2, g = (phi_R - phi_L)/dx and
+    q_n = phi_bar_a g_b - phi_bar_b g_a.  For anisotropic pairs the tangential
+    components use the mean of the two cells' central differences.
+  * G_n = d(a_c^2 |q|^2)/dq_n; the face carries the flux
+    F_a = sum_b gamma_ab G_n dq_n/dg_a and the source s_a = sum_b gamma_ab G_n dq_n/dphi_bar_a;
+    a cell gets eps[sum_axes (F_hi - F_lo)/dx - (s_hi + s_lo)/2].
+  * w: multi-well (Eq. Well) or double obstacle (Eq. Obstacle); psi = sum_b h_b psi^b
+    with h from Eq. hphi and psi^b(mu, T) of a parabolic free energy (Sec. 3).
+  * lambda = (1/N) sum_a R_a keeps sum_a phi_a fixed.  The obstacle variant
+    clips to [0, 1] and renormalises after the update.
+
+Diffusion potentials, Eq. Mu_explicit_temperature with j_at = 0:
+    mu^{n+1} = mu^n + (dt div(M grad mu) - sum_a c^a(mu^n) [h_a(phi^{n+1}) - h_a(phi^n)]) / chi
+  * M_k = sum_a D^a_k chi^a_k h_a(phi^n) per cell (Eq. Mass_conservation), face
+    value the mean of the two cells; chi_k = sum_a h_a(phi^{n+1}) chi^a_k.
+  * B^a is temperature independent, so the dT/dt term vanishes.
+
+Boundaries: periodic (wrap) or zero-flux (ghost = mirror of the edge cell),
+per axis; corners by composition.  Temperature T(y, t) = T0 + G (y - y0 - V t)
+with t = n dt and y = j dx.
+
+Parity: every function here is pinned by tests against closed forms,
+invariants or brute force (see the test modules named test_oracle_*).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PERIODIC = 0
+NOFLUX = 1
+
+
+# ----------------------------------------------------------------------------
+# Grid helpers
+# ----------------------------------------------------------------------------
+
+def spatial_axes(p):
+    """(array axis, boundary code) for x, y[, z]; arrays are laid out (field, [z,] y, x)."""
+    ax = [(-1, p.bc[0]), (-2, p.bc[1])]
+    if p.dim == 3:
+        ax.append((-3, p.bc[2]))
+    return ax
+
+
+def pad(f, p):
+    """One ghost layer on every spatial axis: wrap (periodic) or edge copy (zero flux)."""
+    for a, bc in spatial_axes(p):
+        n = f.shape[a]
+        if bc == PERIODIC:
+            lo, hi = np.take(f, [n - 1], axis=a), np.take(f, [0], axis=a)
+        else:
+            lo, hi = np.take(f, [0], axis=a), np.take(f, [n - 1], axis=a)
+        f = np.concatenate([lo, f, hi], axis=a)
+    return f
+
+
+def _sub(F, nd, spec):
+    """Slice of a padded array: interior (1:-1) on every spatial axis unless overridden."""
+    idx = [slice(None)] * (F.ndim - nd) + [slice(1, -1)] * nd
+    for a, s in spec.items():
+        idx[F.ndim + a] = s
+    return F[tuple(idx)]
+
+
+def _along(F, a, s):
+    """Slice s along (negative) axis a."""
+    idx = [slice(None)] * F.ndim
+    idx[F.ndim + a] = s
+    return F[tuple(idx)]
+
+
+# ----------------------------------------------------------------------------
+# Point-wise model functions
+# ----------------------------------------------------------------------------
+
+def h(phi):
+    """Interpolation functions h_a (Eq. hphi); phi has the phase index first."""
+    N = phi.shape[0]
+    out = []
+    for a in range(N):
+        others = [b for b in range(N) if b != a]
+        cross = 0.0
+        for i in range(len(others)):
+            for j in range(i + 1, len(others)):
+                cross = cross + phi[others[i]] * phi[others[j]]
+        out.append(3.0 * phi[a] ** 2 - 2.0 * phi[a] ** 3 + 2.0 * phi[a] * cross)
+    return np.stack(out)
+
+
+def dh(phi):
+    """dh[b][a] = dh_b / dphi_a, differentiated by hand from Eq. hphi."""
+    N = phi.shape[0]
+    rows = []
+    for b in range(N):
+        others = [g for g in range(N) if g != b]
+        row = []
+        for a in range(N):
+            if a == b:
+                cross = 0.0
+                for i in range(len(others)):
+                    for j in range(i + 1, len(others)):
+                        cross = cross + phi[others[i]] * phi[others[j]]
+                row.append(6.0 * phi[b] - 6.0 * phi[b] ** 2 + 2.0 * cross)
+            else:
+                rest = 0.0
+                for g in others:
+                    if g != a:
+                        rest = rest + phi[g]
+                row.append(2.0 * phi[b] * rest)
+        rows.append(np.stack(row))
+    return np.stack(rows)
+
+
+def w(phi, p):
+    """Potential w: multi-well (Eq. Well) or double obstacle inside [0,1] (Eq. Obstacle)."""
+    N = phi.shape[0]
+    out = 0.0
+    for a in range(N):
+        for b in range(a + 1, N):
+            g = p.gamma[a][b]
+            if p.potential == "well":
+                out = out + 9.0 * g * phi[a] ** 2 * phi[b] ** 2
+            else:
+                out = out + 16.0 / np.pi ** 2 * g * phi[a] * phi[b]
+    if N == 3:
+        out = out + p.gamma3 * phi[0] * phi[1] * phi[2]
+    return out
+
+
+def dw(phi, p):
+    """dw/dphi_a for both potentials, each unordered triple counted once."""
+    N = phi.shape[0]
+    out = []
+    for a in range(N):
+        acc = 0.0
+        for b in range(N):
+            if b == a:
+                continue
+            g = p.gamma[a][b]
+            if p.potential == "well":
+                acc = acc + 18.0 * g * phi[a] * phi[b] ** 2
+            else:
+                acc = acc + 16.0 / np.pi ** 2 * g * phi[b]
+        if N == 3:
+            prod = 1.0
+            for b in range(N):
+                if b != a:
+                    prod = prod * phi[b]
+            acc = acc + p.gamma3 * prod
+        out.append(acc)
+    return np.stack(out)
+
+
+def chi_phase(p):
+    """Susceptibility dc^a_k/dmu_k = 1/(2 A^a_k) of the diagonal parabolic free energy."""
+    return 1.0 / (2.0 * np.asarray(p.A)[: p.nphases, : p.nmu])
+
+
+def c_phase(mu, p):
+    """Phase compositions c^a_k(mu) = (mu_k - B^a_k) / (2 A^a_k); shape (N, K-1, ...)."""
+    A = np.asarray(p.A)
+    B = np.asarray(p.B)
+    return np.stack([np.stack([(mu[k] - B[a][k]) / (2.0 * A[a][k]) for k in range(p.nmu)])
+                     for a in range(p.nphases)])
+
+
+def free_energy(c, a, p):
+    """f^a(c) = sum_k A^a_k c_k^2 + B^a_k c_k + C^a (Eq. free_energy_density, V_m = 1)."""
+    out = p.C[a]
+    for k in range(p.nmu):
+        out = out + p.A[a][k] * c[k] ** 2 + p.B[a][k] * c[k]
+    return out
+
+
+def psi_phase(mu, T, p):
+    """Grand potentials psi^a(mu, T) = f^a(c^a) - mu . c^a plus s^a (T - Te); shape (N, ...)."""
+    ca = c_phase(mu, p)
+    out = []
+    for a in range(p.nphases):
+        val = free_energy(ca[a], a, p)
+        for k in range(p.nmu):
+            val = val - mu[k] * ca[a][k]
+        out.append(val + p.s[a] * (T - p.Te))
+    return np.stack(out)
+
+
+def temperature(p, n, shape, y_origin=0):
+    """T(y, t) = T0 + G (y - y0 - V t) with y = j dx and t = n dt, broadcast to ``shape``."""
+    ny = shape[-2]
+    y = (np.arange(ny) + y_origin) * p.dx
+    t = n * p.dt
+    T = p.T0 + p.G * (y - p.y0 - p.V * t)
+    T = T.reshape((ny, 1))
+    return np.broadcast_to(T, shape)
+
+
+def G_normal(qn, qt, delta):
+    """Normal component of d(a_c^2 |q|^2)/dq for the four-fold a_c of Sec. 2.1.
+
+    a_c = 1 - delta (3 - 4 sum_i q_i^4 / |q|^4).  With m = q/|q| and
+    S4 = sum_i m_i^4, the derivative is
+    2 a_c^2 q_n + 32 delta a_c |q| (m_n^3 - m_n S4).  For |q|^2 <= 1e-30 the
+    direction is undefined and the isotropic limit 2 (1 - 3 delta)^2 q_n is used.
+    """
+    Q2 = qn * qn
+    for t in qt:
+        Q2 = Q2 + t * t
+    small = np.real(Q2) <= 1e-30
+    Q2s = np.where(small, 1.0, Q2)
+    rq = np.sqrt(Q2s)
+    mn = qn / rq
+    S4 = mn ** 4
+    for t in qt:
+        S4 = S4 + (t / rq) ** 4
+    ac = 1.0 - delta * (3.0 - 4.0 * S4)
+    full = 2.0 * ac * ac * qn + 32.0 * delta * ac * rq * (mn ** 3 - mn * S4)
+    lim = 2.0 * (1.0 - 3.0 * delta) ** 2 * qn
+    return np.where(small, lim, full)
+
+
+# ----------------------------------------------------------------------------
+# The step
+# ----------------------------------------------------------------------------
+
+def _faces(Pphi, p):
+    """Per axis: (F, s) face arrays of the gradient term, shape (N, ..., n_a + 1, ...)."""
+    nd = p.dim
+    N = p.nphases
+    dx = p.dx
+    axes = [a for a, _ in spatial_axes(p)]
+    out = []
+    for a in axes:
+        L = _sub(Pphi, nd, {a: slice(0, -1)})
+        R = _sub(Pphi, nd, {a: slice(1, None)})
+        pb = 0.5 * (L + R)
+        g = (R - L) / dx
+        tang = []
+        aniso = any(p.delta[i][j] != 0.0 for i in range(N) for j in range(i + 1, N))
+        if aniso:
+            for b in axes:
+                if b == a:
+                    continue
+                tl = (_sub(Pphi, nd, {a: slice(0, -1), b: slice(2, None)})
+                      - _sub(Pphi, nd, {a: slice(0, -1), b: slice(0, -2)})) / (2.0 * dx)
+                tr = (_sub(Pphi, nd, {a: slice(1, None), b: slice(2, None)})
+                      - _sub(Pphi, nd, {a: slice(1, None), b: slice(0, -2)})) / (2.0 * dx)
+                tang.append(0.5 * (tl + tr))
+        F = [0.0 * pb[0] for _ in range(N)]
+        S = [0.0 * pb[0] for _ in range(N)]
+        for i in range(N):
+            for j in range(i + 1, N):
+                qn = pb[i] * g[j] - pb[j] * g[i]
+                if p.delta[i][j] != 0.0:
+                    qt = [pb[i] * t[j] - pb[j] * t[i] for t in tang]
+                    Gn = G_normal(qn, qt, p.delta[i][j])
+                else:
+                    Gn = 2.0 * qn
+                gG = p.gamma[i][j] * Gn
+                F[i] = F[i] - gG * pb[j]
+                F[j] = F[j] + gG * pb[i]
+                S[i] = S[i] + gG * g[j]
+                S[j] = S[j] - gG * g[i]
+        out.append((a, np.stack(F), np.stack(S)))
+    return out
+
+
+def _rhs_padded(Pphi, Pmu, n, p, y_origin=0):
+    """R_a (before the Lagrange multiplier) on the interior of padded fields."""
+    nd = p.dim
+    phi = _sub(Pphi, nd, {})
+    mu = _sub(Pmu, nd, {})
+    grad = 0.0 * phi
+    for a, F, S in _faces(Pphi, p):
+        grad = grad + (_along(F, a, slice(1, None)) - _along(F, a, slice(0, -1))) / p.dx \
+            - 0.5 * (_along(S, a, slice(1, None)) + _along(S, a, slice(0, -1)))
+    T = temperature(p, n, phi.shape[1:], y_origin)
+    psi = psi_phase(mu, T, p)
+    dhm = dh(phi)
+    dpsi = [sum(psi[b] * dhm[b][a] for b in range(p.nphases)) for a in range(p.nphases)]
+    return p.eps * grad - dw(phi, p) / p.eps - np.stack(dpsi)
+
+
+def _step_padded(Pphi, Pmu, n, p, y_origin=0):
+    """One forward-Euler step of (phi, mu) on the interior of padded fields."""
+    nd = p.dim
+    N = p.nphases
+    phi = _sub(Pphi, nd, {})
+    mu = _sub(Pmu, nd, {})
+    # phase fields
+    R = _rhs_padded(Pphi, Pmu, n, p, y_origin)
+    lam = sum(R[a] for a in range(N)) / N
+    phin = phi + p.dt * (R - lam) / (p.tau * p.eps)
+    if p.potential == "obstacle":
+        phin = np.clip(phin, 0.0, 1.0)
+        phin = phin / phin.sum(axis=0, keepdims=True)
+    # diffusion potentials
+    chi = chi_phase(p)
+    D = np.asarray(p.D)[:N, : p.nmu]
+    hP = h(Pphi)
+    div = [0.0 * mu[k] for k in range(p.nmu)]
+    for k in range(p.nmu):
+        M = sum(D[b][k] * chi[b][k] * hP[b] for b in range(N))[None]
+        for a, _ in spatial_axes(p):
+            ML = _sub(M, nd, {a: slice(0, -1)})[0]
+            MR = _sub(M, nd, {a: slice(1, None)})[0]
+            muL = _sub(Pmu[k:k + 1], nd, {a: slice(0, -1)})[0]
+            muR = _sub(Pmu[k:k + 1], nd, {a: slice(1, None)})[0]
+            J = 0.5 * (ML + MR) * (muR - muL) / p.dx
+            div[k] = div[k] + (_along(J, a, slice(1, None)) - _along(J, a, slice(0, -1))) / p.dx
+    h0 = h(phi)
+    h1 = h(phin)
+    ca = c_phase(mu, p)
+    mun = []
+    for k in range(p.nmu):
+        src = sum(ca[b][k] * (h1[b] - h0[b]) for b in range(N))
+        chik = sum(h1[b] * chi[b][k] for b in range(N))
+        mun.append(mu[k] + (p.dt * div[k] - src) / chik)
+    return phin, np.stack(mun)
+
+
+def rhs_phi(phi, mu, n, p):
+    """R_a of the phase-field equation before the Lagrange multiplier (full grid)."""
+    return _rhs_padded(pad(phi, p), pad(mu, p), n, p)
+
+
+def step(phi, mu, n, p):
+    """One step from time level n: returns (phi^{n+1}, mu^{n+1})."""
+    return _step_padded(pad(phi, p), pad(mu, p), n, p)
+
+
+def run(phi, mu, n0, nsteps, p):
+    """nsteps steps starting at time level n0."""
+    for i in range(nsteps):
+        phi, mu = step(phi, mu, n0 + i, p)
+    return phi, mu
+
+
+def step_window(phi, mu, n, p, lo, hi):
+    """One step evaluated only on the box lo <= index < hi (array order, spatial axes).
+
+    Uses the full fields for the neighbourhood, so the result equals the same
+    cells of ``step`` while costing only the window.  ``lo``/``hi`` are tuples
+    in array order ((z,) y, x).
+    """
+    nd = p.dim
+    Pphi = pad(phi, p)
+    Pmu = pad(mu, p)
+    sl = tuple(slice(l, h_ + 2) for l, h_ in zip(lo, hi))
+    y_origin = lo[-2]
+    return _step_padded(Pphi[(slice(None),) + sl], Pmu[(slice(None),) + sl], n, p, y_origin)
+
+
+# ----------------------------------------------------------------------------
+# Energy and diagnostics
+# ----------------------------------------------------------------------------
+
+def energy(phi, mu, n, p):
+    """Discrete grand potential of the isotropic scheme (used as a brute-force pin).
+
+    Omega_h = dx^d [ sum_faces eps sum_{a<b} gamma_ab q_n^2
+                    + sum_cells (w(phi)/eps + sum_a h_a(phi) psi^a(mu, T)) ]
+    (Eq. grand_eqn with a from Eq. Eqn_a and a_c = 1), each physical face once.
+    """
+    nd = p.dim
+    N = p.nphases
+    Pphi = pad(phi, p)
+    Eg = 0.0
+    for a, _ in spatial_axes(p):
+        # faces 1..n of the padded set: each physical face once
+        L = _along(_sub(Pphi, nd, {a: slice(0, -1)}), a, slice(1, None))
+        R = _along(_sub(Pphi, nd, {a: slice(1, None)}), a, slice(1, None))
+        pb = 0.5 * (L + R)
+        g = (R - L) / p.dx
+        for i in range(N):
+            for j in range(i + 1, N):
+                q = pb[i] * g[j] - pb[j] * g[i]
+                Eg = Eg + np.sum(p.gamma[i][j] * q * q)
+    T = temperature(p, n, phi.shape[1:])
+    bulk = w(phi, p) / p.eps + np.sum(h(phi) * psi_phase(mu, T, p), axis=0)
+    return p.dx ** nd * (p.eps * Eg + np.sum(bulk))
+
+
+def composition(phi, mu, p):
+    """Mixture composition c_k = sum_a h_a(phi) c^a_k(mu) (the composition constraint of Sec. 2.1)."""
+    hh = h(phi)
+    ca = c_phase(mu, p)
+    return np.stack([sum(hh[a] * ca[a][k] for a in range(p.nphases)) for k in range(p.nmu)])
+
+
+def diagnostics(phi, mu, p):
+    """Reference values of the diagnostics reductions (plain FP64 sums)."""
+    vol = p.dx ** p.dim
+    c = composition(phi, mu, p)
+    hh = h(phi)
+    chi = chi_phase(p)
+    chik = np.stack([sum(hh[a] * chi[a][k] for a in range(p.nphases)) for k in range(p.nmu)])
+    finite = np.isfinite(phi).all(axis=0) & np.isfinite(mu).all(axis=0)
+    return {
+        "max_sum_dev": float(np.max(np.abs(phi.sum(axis=0) - 1.0))),
+        "mass": [float(np.sum(c[k]) * vol) for k in range(p.nmu)],
+        "volume": [float(np.sum(phi[a]) * vol) for a in range(p.nphases)],
+        "min_chi": float(np.min(chik)),
+        "nonfinite": int(np.size(finite) - np.count_nonzero(finite)),
+    }

@@ -1,0 +1,356 @@
+"""Seeded synthetic workloads for the grand-potential phase-field step.
+
+This module only builds inputs: parameter sets and initial fields.  It holds no
+part of the time step itself, so both the HIP path and the FP64 reference
+stepper can consume what it produces.
+
+Parameter meaning follows the grand-potential model of MICROSIM
+(arXiv 2404.01035, Sec. 2.1 and Sec. 3):
+
+* ``gamma[a][b]``  interface energy of the a-b interface (Eq. Obstacle / Eq. Well)
+* ``gamma3``       third-order coefficient gamma_abd (same equations, N = 3 only)
+* ``delta[a][b]``  four-fold anisotropy strength delta_ab (anisotropy function a_c)
+* ``eps``, ``tau`` interface width and relaxation constant (Eq. phi_eqn)
+* ``A, B, C``      diagonal parabolic free-energy coefficients per phase and
+                   independent component, f^a(c) = sum_k A_k c_k^2 + B_k c_k + C
+                   (Eq. free_energy_density with V_m = 1)
+* ``s``            slope of C^a with temperature, C^a(T) = C^a + s^a (T - Te)
+* ``D``            diagonal diffusivity per phase and component (Eq. Mass_conservation)
+* ``Te``           temperature at which C^a is given (Equilibrium_temperature, Sec. 5)
+* ``T0, G, V, y0`` frozen, translating temperature field
+                   T(y, t) = T0 + G (y - y0 - V t) (the Tempgrady input of Sec. 5:
+                   base temperature, gradient, offset, velocity)
+
+Arrays use the layout of the C ABI: ``phi`` has shape ``(N, ny, nx)`` in 2D and
+``(N, nz, ny, nx)`` in 3D, ``mu`` has shape ``(K-1, ...)`` likewise; x is the
+fastest axis.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+BC_PERIODIC = 0
+BC_NOFLUX = 1
+
+MAX_PHASES = 3
+MAX_MU = 2
+
+
+def _z33():
+    return np.zeros((MAX_PHASES, MAX_PHASES))
+
+
+@dataclass
+class Params:
+    """One simulation: grid, model sizes and coefficients (all FP64 on the host)."""
+
+    dim: int = 2
+    n: tuple = (64, 64, 1)          # (nx, ny, nz); nz = 1 in 2D
+    dx: float = 1.0
+    bc: tuple = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
+    nphases: int = 2                # N, the liquid is the last phase
+    ncomp: int = 2                  # K, components; K - 1 independent mu fields
+    precision: str = "f64"          # "f64" | "f32"
+    potential: str = "well"         # "well" | "obstacle"
+    eps: float = 4.0
+    tau: float = 1.0
+    dt: float = 0.05
+    gamma: np.ndarray = field(default_factory=_z33)
+    gamma3: float = 0.0
+    delta: np.ndarray = field(default_factory=_z33)
+    A: np.ndarray = field(default_factory=lambda: np.ones((MAX_PHASES, MAX_MU)))
+    B: np.ndarray = field(default_factory=lambda: np.zeros((MAX_PHASES, MAX_MU)))
+    C: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    s: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    D: np.ndarray = field(default_factory=lambda: np.zeros((MAX_PHASES, MAX_MU)))
+    Te: float = 1.0
+    T0: float = 1.0
+    G: float = 0.0
+    V: float = 0.0
+    y0: float = 0.0
+
+    @property
+    def nmu(self) -> int:
+        return self.ncomp - 1
+
+    @property
+    def nfields(self) -> int:
+        return self.nphases + self.nmu
+
+    @property
+    def spatial(self) -> tuple:
+        nx, ny, nz = self.n
+        return (nz, ny, nx) if self.dim == 3 else (ny, nx)
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.spatial))
+
+    def copy(self, **kw) -> "Params":
+        p = replace(self, **kw)
+        for name in ("gamma", "delta", "A", "B", "C", "s", "D"):
+            if name not in kw:
+                setattr(p, name, np.array(getattr(self, name), dtype=np.float64))
+        return p
+
+
+# ----------------------------------------------------------------------------
+# Thermodynamic inputs
+# ----------------------------------------------------------------------------
+
+def parabolic_coefficients(A, ceq, liquid):
+    """B and C of the parabolic free energies from curvatures and equilibrium compositions.
+
+    Follows Eq. Coeff_B and Eq. Coeff_C (Sec. 3) for a diagonal A: with the
+    liquid as reference (B^l = C^l = 0), each solid a gets
+    B^a_j = 2 (A^l_j c^l_j - A^a_j c^a_j) and C^a = sum_j (A^a_j (c^a_j)^2 - A^l_j (c^l_j)^2),
+    so that every solid is in equilibrium with the liquid at mu_j = 2 A^l_j c^l_j.
+    The common linear term -mu_e . c is then subtracted from every phase (a pure
+    gauge: it shifts mu by mu_e and leaves the physics unchanged), which puts the
+    equilibrium point at mu = 0.  A and ceq have shape (N, K-1).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    ceq = np.asarray(ceq, dtype=np.float64)
+    npha = A.shape[0]
+    B = np.zeros_like(A)
+    C = np.zeros(npha)
+    for a in range(npha):
+        if a == liquid:
+            continue
+        B[a] = 2.0 * (A[liquid] * ceq[liquid] - A[a] * ceq[a])
+        C[a] = np.sum(A[a] * ceq[a] ** 2 - A[liquid] * ceq[liquid] ** 2)
+    mu_e = 2.0 * A[liquid] * ceq[liquid]
+    B = B - mu_e[None, :]
+    return B, C
+
+
+def dt_limit(p: Params) -> float:
+    """Explicit (forward Euler) stability limit used to size dt.
+
+    Phase fields: the projected gradient term acts like diffusion with
+    coefficient at most 2 gamma_max (N-1)/N / tau, raised by a margin of
+    (1 + 20 delta_max) for the anisotropic stiffness.  Diffusion potentials: the
+    mu equation is a diffusion with coefficient M/chi <= max_a(D^a chi^a) / min_a chi^a.
+    The FTCS bound dx^2 / (2 d coefficient) applies to both.
+    """
+    N, K1, d = p.nphases, p.nmu, p.dim
+    g = np.asarray(p.gamma)[:N, :N]
+    dl = np.asarray(p.delta)[:N, :N]
+    gmax = float(np.max(g[np.triu_indices(N, 1)]))
+    dmax = float(np.max(np.abs(dl[np.triu_indices(N, 1)])))
+    base = p.dx * p.dx / (2.0 * d)
+    lim = math.inf
+    if gmax > 0:
+        lim = base * p.tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax))
+    chi = 1.0 / (2.0 * np.asarray(p.A)[:N, :K1])
+    Dm = np.asarray(p.D)[:N, :K1]
+    for k in range(K1):
+        top = float(np.max(Dm[:, k] * chi[:, k]))
+        if top > 0:
+            lim = min(lim, base * float(np.min(chi[:, k])) / top)
+    return lim
+
+
+# ----------------------------------------------------------------------------
+# Initial-condition building blocks (the FILL* shapes of Sec. 5, made diffuse)
+# ----------------------------------------------------------------------------
+
+def diffuse_step(dist, eps):
+    """Solid fraction across a diffuse front: 1 inside (dist < 0), 0 outside.
+
+    The tanh width 2 eps / 3 matches the planar multi-well profile, so a seed
+    starts close to its relaxed shape instead of a sharp FILL* edge.
+    """
+    return 0.5 * (1.0 - np.tanh(3.0 * dist / (2.0 * eps)))
+
+
+def grid_coords(p: Params):
+    """Cell-centre coordinates (x, y[, z]) at integer multiples of dx, array layout."""
+    nx, ny, nz = p.n
+    if p.dim == 3:
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        return x * p.dx, y * p.dx, z * p.dx
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return x * p.dx, y * p.dx
+
+
+def fields_from_solid(p: Params, solid_frac, solid_phase_of_cell, mu_value=0.0):
+    """Assemble phi (N, ...) and mu (K-1, ...) from a solid fraction field.
+
+    ``solid_phase_of_cell`` gives, per cell, which solid phase (0..N-2) the solid
+    fraction belongs to; the liquid (phase N-1) takes the rest.
+    """
+    N, K1 = p.nphases, p.nmu
+    phi = np.zeros((N,) + p.spatial)
+    for a in range(N - 1):
+        phi[a] = np.where(solid_phase_of_cell == a, solid_frac, 0.0)
+    phi[N - 1] = 1.0 - solid_frac
+    mu = np.full((K1,) + p.spatial, float(mu_value))
+    return phi, mu
+
+
+# ----------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------
+
+def binary_two_phase(dim=2, n=(64, 64, 1), bc=(0, 0, 0), precision="f64",
+                     potential="well", delta=0.0, gamma=1.0, undercooling=0.0,
+                     c_solid=0.2, c_liquid=0.8, A=1.0, D_solid=0.0, D_liquid=1.0,
+                     eps=4.0, tau=1.0, dt_frac=0.2) -> Params:
+    """Two phases (solid, liquid), one independent component."""
+    p = Params(dim=dim, n=tuple(n), bc=tuple(bc), nphases=2, ncomp=2,
+               precision=precision, potential=potential, eps=eps, tau=tau)
+    p.gamma[0, 1] = p.gamma[1, 0] = gamma
+    p.delta[0, 1] = p.delta[1, 0] = delta
+    Am = np.full((2, 1), float(A))
+    ceq = np.array([[c_solid], [c_liquid]])
+    B, C = parabolic_coefficients(Am, ceq, liquid=1)
+    p.A[:2, :1] = Am
+    p.B[:2, :1] = B
+    p.C[:2] = C
+    p.s[:2] = (1.0, 0.0)
+    p.D[:2, 0] = (D_solid, D_liquid)
+    # uniform undercooling: T = Te - dT everywhere (no gradient)
+    p.Te = 1.0
+    p.T0 = 1.0 - float(undercooling)
+    p.G, p.V, p.y0 = 0.0, 0.0, 0.0
+    p.dt = dt_frac * dt_limit(p)
+    return p
+
+
+def config_c1(seed: int = 0):
+    """2D 64x64 periodic, 2 phases, binary alloy, FP64; circular nucleus R=10 plus noise.
+
+    f_a(c) = A (c - c_a)^2 with A = 1, c_solid = 0.2, c_liquid = 0.8; gamma = 1,
+    eps = 4 dx, tau = 1, D = (0, 1), dt = 0.2 of the explicit limit.  Noise:
+    U(-0.01, 0.01) on phi_solid (liquid takes 1 - phi_solid), then on mu, drawn
+    in that order from numpy's default_rng(seed).
+    """
+    p = binary_two_phase(dim=2, n=(64, 64, 1), bc=(0, 0, 0))
+    x, y = grid_coords(p)
+    r = np.hypot(x - 32.0, y - 32.0)
+    sol = diffuse_step(r - 10.0, p.eps)
+    rng = np.random.default_rng(seed)
+    sol = sol + rng.uniform(-0.01, 0.01, size=sol.shape)
+    phi, mu = fields_from_solid(p, sol, np.zeros(sol.shape, dtype=int))
+    mu = mu + rng.uniform(-0.01, 0.01, size=mu.shape)
+    return p, phi, mu
+
+
+def eutectic_params(n=(4096, 4096, 1), seed=1, precision="f64", G=1e-3, V=0.01,
+                    y0=64.0, eps=4.0, tau=1.0, dt_frac=0.2) -> Params:
+    """Three phases (alpha, beta, liquid), ternary (2 independent mu), directional growth.
+
+    A ~ U[0.5, 2] and c_eq ~ U[0.1, 0.9] per phase and component (seeded),
+    B and C from Eq. Coeff_B / Eq. Coeff_C against the liquid, so alpha, beta and
+    liquid coexist at mu = 0 and T = Te.  Temperature T = Te + G (y - y0 - V t),
+    x periodic, y no-flux, D = (0, 0, 1), s = (1, 1, 0).
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(0.5, 2.0, size=(3, 2))
+    ceq = rng.uniform(0.1, 0.9, size=(3, 2))
+    p = Params(dim=2, n=tuple(n), bc=(BC_PERIODIC, BC_NOFLUX, BC_PERIODIC),
+               nphases=3, ncomp=3, precision=precision, eps=eps, tau=tau)
+    for a in range(3):
+        for b in range(3):
+            if a != b:
+                p.gamma[a, b] = 1.0
+    B, C = parabolic_coefficients(A, ceq, liquid=2)
+    p.A[:3, :2] = A
+    p.B[:3, :2] = B
+    p.C[:3] = C
+    p.s[:3] = (1.0, 1.0, 0.0)
+    p.D[2, :2] = 1.0
+    p.Te, p.T0, p.G, p.V, p.y0 = 1.0, 1.0, G, V, y0
+    p.dt = dt_frac * dt_limit(p)
+    return p
+
+
+def eutectic_initial(p: Params, slab=64, wmin=16, wmax=48, seed=1):
+    """Bottom slab ``slab`` cells thick of alternating alpha/beta lamellae in melt at mu = 0.
+
+    Lamella widths are integers drawn uniformly from [wmin, wmax] (the last one
+    is cut at the domain edge); the slab top is diffuse (tanh across y = slab),
+    lamella-lamella boundaries are sharp.
+    """
+    rng = np.random.default_rng(seed + 1000)
+    nx = p.n[0]
+    owner = np.zeros(nx, dtype=int)
+    x0, k = 0, 0
+    while x0 < nx:
+        w = int(rng.integers(wmin, wmax + 1))
+        owner[x0:x0 + w] = k % 2
+        x0 += w
+        k += 1
+    x, y = grid_coords(p)
+    sol = diffuse_step(y - (slab - 0.5), p.eps)
+    which = np.broadcast_to(owner[None, :], sol.shape)
+    return fields_from_solid(p, sol, which)
+
+
+def config_c2(precision="f64", n=(4096, 4096, 1), seed=1):
+    """2D 4096x4096 directional eutectic solidification (3 phases, ternary)."""
+    scale = n[0] / 4096.0
+    p = eutectic_params(n=n, seed=seed, precision=precision,
+                        y0=max(8.0, 64.0 * scale))
+    slab = int(round(p.y0))
+    wmin = max(4, int(round(16 * scale)))
+    wmax = max(wmin + 2, int(round(48 * scale)))
+    phi, mu = eutectic_initial(p, slab=slab, wmin=wmin, wmax=wmax, seed=seed)
+    return p, phi, mu
+
+
+def dendrite_params(n=(512, 512, 512), precision="f32", gamma0=0.5, delta=0.02,
+                    undercooling=0.3, eps=4.0, dt_frac=0.2) -> Params:
+    """3D binary dendrite: 2 phases, cubic anisotropy, no-flux on every face."""
+    return binary_two_phase(dim=3, n=n, bc=(BC_NOFLUX,) * 3, precision=precision,
+                            delta=delta, gamma=gamma0, undercooling=undercooling,
+                            eps=eps, dt_frac=dt_frac)
+
+
+def config_c3(precision="f32", n=(512, 512, 512), radius=8.0):
+    """3D 512^3 octant dendrite seed (sphere of radius 8 at the mirrored corner)."""
+    p = dendrite_params(n=n, precision=precision)
+    x, y, z = grid_coords(p)
+    # the mirror plane of the no-flux ghost lies half a cell before cell 0
+    r = np.sqrt((x + 0.5) ** 2 + (y + 0.5) ** 2 + (z + 0.5) ** 2)
+    sol = diffuse_step(r - radius, p.eps)
+    phi, mu = fields_from_solid(p, sol, np.zeros(sol.shape, dtype=int))
+    return p, phi, mu
+
+
+def nuclei_initial(p: Params, centres, radii, phases, mu_value=0.0):
+    """Solid nuclei (discs or spheres) in melt; overlapping seeds keep the larger fraction."""
+    coords = grid_coords(p)
+    sol = np.zeros(p.spatial)
+    which = np.zeros(p.spatial, dtype=int)
+    L = [p.n[i] * p.dx for i in range(p.dim)]
+    for c, R, ph in zip(centres, radii, phases):
+        d2 = np.zeros(p.spatial)
+        for i in range(p.dim):
+            dd = coords[i] - c[i]
+            if p.bc[i] == BC_PERIODIC:  # nearest periodic image
+                dd = dd - L[i] * np.round(dd / L[i])
+            d2 = d2 + dd * dd
+        f = diffuse_step(np.sqrt(d2) - R, p.eps)
+        take = f > sol
+        sol = np.where(take, f, sol)
+        which = np.where(take, ph, which)
+    return fields_from_solid(p, sol, which, mu_value=mu_value)
+
+
+def random_multiphase(p: Params, seed: int, amp: float = 1.0):
+    """Random phase fields on the simplex plus random mu: a harsh parity input.
+
+    Used for one-step and few-step checks where large gradients everywhere
+    exercise every term of the update.
+    """
+    rng = np.random.default_rng(seed)
+    raw = rng.uniform(0.0, 1.0, size=(p.nphases,) + p.spatial)
+    phi = raw / raw.sum(axis=0, keepdims=True)
+    phi = (1 - amp) / p.nphases + amp * phi
+    mu = rng.uniform(-0.05, 0.05, size=(p.nmu,) + p.spatial)
+    return phi, mu

@@ -1,0 +1,530 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Each test ties the oracle to something other than its own formulas: hand
+values of the paper's functions, complex-step derivatives of an independently
+written functional, exact discrete solutions (Fourier modes of the heat
+equation), equilibrium profiles and conservation laws.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gp
+from paper_2404_01035_amd import inputs
+
+CS = 1e-30  # complex-step size
+
+
+def small_params(N=2, dim=2, n=(6, 5, 1), bc=(0, 0, 0), potential="well", delta=0.0,
+                 seed=0, G=0.0, gamma3=0.0):
+    rng = np.random.default_rng(seed)
+    p = inputs.Params(dim=dim, n=tuple(n), bc=tuple(bc), nphases=N, ncomp=N,
+                      potential=potential, eps=2.5, tau=1.3, dx=0.9)
+    for a in range(N):
+        for b in range(a + 1, N):
+            p.gamma[a, b] = p.gamma[b, a] = rng.uniform(0.5, 2.0)
+            p.delta[a, b] = p.delta[b, a] = delta
+    p.gamma3 = gamma3
+    K1 = N - 1
+    A = rng.uniform(0.5, 2.0, size=(N, K1))
+    ceq = rng.uniform(0.1, 0.9, size=(N, K1))
+    B, C = inputs.parabolic_coefficients(A, ceq, liquid=N - 1)
+    p.A[:N, :K1], p.B[:N, :K1], p.C[:N] = A, B, C
+    p.s[:N] = rng.uniform(0.2, 1.0, size=N)
+    p.s[N - 1] = 0.0
+    p.D[:N, :K1] = rng.uniform(0.1, 1.0, size=(N, K1))
+    p.Te, p.T0, p.G, p.V, p.y0 = 1.0, 0.93, G, 0.3, 1.7
+    p.dt = 0.2 * inputs.dt_limit(p)
+    return p
+
+
+def random_state(p, seed=1, simplex=False):
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(-0.1, 1.1, size=(p.nphases,) + p.spatial)
+    if simplex:
+        phi = np.abs(phi)
+        phi = phi / phi.sum(axis=0, keepdims=True)
+    mu = rng.uniform(-0.3, 0.3, size=(p.nmu,) + p.spatial)
+    return phi, mu
+
+
+# ----------------------------------------------------------------------------
+# Interpolation, potential, thermodynamics
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_h_partition_of_unity(N):
+    rng = np.random.default_rng(N)
+    phi = rng.uniform(0, 1, size=(N, 1000))
+    phi /= phi.sum(axis=0, keepdims=True)
+    assert np.max(np.abs(gp.h(phi).sum(axis=0) - 1.0)) < 1e-15
+
+
+def test_h_hand_values():
+    # Eq. hphi by hand: N=2, phi=(1/2,1/2): 3/4 - 2/8 = 1/2.
+    assert np.allclose(gp.h(np.array([[0.5], [0.5]]))[:, 0], [0.5, 0.5], rtol=0, atol=1e-16)
+    # N=3 at the centre: 3/9 - 2/27 + 2 (1/3)(1/9) = 1/3.
+    third = np.full((3, 1), 1.0 / 3.0)
+    assert np.allclose(gp.h(third)[:, 0], 1.0 / 3.0, rtol=0, atol=1e-15)
+    # N=2, phi_solid = 0.3: 3(0.09) - 2(0.027) = 0.216; the liquid at 0.7: 0.784.
+    assert np.allclose(gp.h(np.array([[0.3], [0.7]]))[:, 0], [0.216, 0.784], rtol=0, atol=1e-15)
+    # pure phases
+    assert np.array_equal(gp.h(np.array([[1.0], [0.0], [0.0]]))[:, 0], [1.0, 0.0, 0.0])
+
+
+@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("potential", ["well", "obstacle"])
+def test_dh_dw_match_complex_step(N, potential):
+    p = small_params(N=N, potential=potential, gamma3=0.7 if N == 3 else 0.0)
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(-0.2, 1.2, size=(N, 7))
+    dhm = gp.dh(phi)
+    dwm = gp.dw(phi, p)
+    for a in range(N):
+        e = np.zeros((N, 1))
+        e[a] = 1.0
+        pc = phi + 1j * CS * e
+        num_h = gp.h(pc).imag / CS
+        num_w = gp.w(pc, p).imag / CS
+        for b in range(N):
+            assert np.allclose(dhm[b][a], num_h[b], rtol=1e-14, atol=1e-14)
+        assert np.allclose(dwm[a], num_w, rtol=1e-14, atol=1e-14)
+
+
+def test_psi_is_legendre_transform():
+    """psi^a(mu) = min_c f^a(c) - mu c, checked by brute-force minimisation over a fine grid."""
+    p = small_params(N=3)
+    mu = np.array([[0.137], [-0.21]])
+    T = np.full((1,), p.Te)
+    psi = gp.psi_phase(mu, T, p)[:, 0]
+    for a in range(3):
+        # separable in components for diagonal A: minimise each term on its own
+        total = p.C[a]
+        for k in range(2):
+            cgrid = np.linspace(-3, 3, 600001)
+            val = p.A[a][k] * cgrid ** 2 + p.B[a][k] * cgrid - mu[k, 0] * cgrid
+            total += val.min()
+        assert abs(psi[a] - total) < 1e-9
+
+
+def test_common_tangent_at_zero_mu():
+    """Eq. Coeff_B / Coeff_C: all phases coexist at mu = 0 with c^a = c_eq^a."""
+    rng = np.random.default_rng(11)
+    A = rng.uniform(0.5, 2.0, size=(3, 2))
+    ceq = rng.uniform(0.1, 0.9, size=(3, 2))
+    B, C = inputs.parabolic_coefficients(A, ceq, liquid=2)
+    p = inputs.Params(nphases=3, ncomp=3)
+    p.A[:3, :2], p.B[:3, :2], p.C[:3] = A, B, C
+    mu0 = np.zeros((2, 1))
+    ca = gp.c_phase(mu0, p)[:, :, 0]
+    assert np.allclose(ca, ceq, rtol=0, atol=1e-14)
+    psi = gp.psi_phase(mu0, np.array([p.Te]), p)[:, 0]
+    assert np.ptp(psi) < 1e-14
+    # equal slopes: mu = df/dc at each phase's equilibrium composition
+    for a in range(3):
+        for k in range(2):
+            assert abs(2 * A[a, k] * ceq[a, k] + B[a, k]) < 1e-14
+
+
+def test_c1_coefficients_match_config_formula():
+    """C1 states f_a(c) = A (c - c_a)^2: same B, and C up to a common constant."""
+    p, _, _ = inputs.config_c1()
+    assert np.allclose(p.B[:2, 0], [-0.4, -1.6], atol=1e-15)
+    assert abs((p.C[0] - p.C[1]) - (0.2 ** 2 - 0.8 ** 2)) < 1e-15
+    assert abs(p.dt - 0.05) < 1e-15
+
+
+def test_temperature_hand_values():
+    p = inputs.Params(T0=1.0, G=1e-3, V=0.01, y0=64.0, dt=0.1, dx=1.0)
+    T = gp.temperature(p, 1000, (200, 3))
+    # T0 + G (y - y0 - V t) at y = 100, t = 100: 1 + 1e-3 (100 - 64 - 1)
+    assert abs(T[100, 1] - 1.035) < 1e-15
+    assert abs(T[64, 0] - (1.0 - 1e-3)) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# Gradient term: variational identity and anisotropy
+# ----------------------------------------------------------------------------
+
+def _grad_energy_complex_step(phi, mu, p):
+    grad = np.zeros_like(phi)
+    for idx in np.ndindex(phi.shape):
+        pc = phi.astype(complex)
+        pc[idx] += 1j * CS
+        grad[idx] = gp.energy(pc, mu, 3, p).imag / CS
+    return grad
+
+
+@pytest.mark.parametrize("case", [
+    dict(N=2, dim=2, n=(5, 4, 1), bc=(0, 0, 0), potential="well"),
+    dict(N=3, dim=2, n=(4, 5, 1), bc=(0, 1, 0), potential="well", gamma3=0.6, G=0.05),
+    dict(N=3, dim=2, n=(4, 4, 1), bc=(1, 0, 0), potential="obstacle", gamma3=0.4),
+    dict(N=2, dim=3, n=(3, 4, 3), bc=(1, 0, 1), potential="well"),
+    dict(N=3, dim=3, n=(3, 3, 4), bc=(0, 1, 0), potential="well", G=0.1),
+])
+def test_rhs_is_negative_energy_gradient(case):
+    """With a_c = 1: R_a = -(1/dx^d) dOmega_h/dphi_a (the scheme is variational)."""
+    p = small_params(**case)
+    phi, mu = random_state(p, seed=3)
+    R = gp.rhs_phi(phi, mu, 3, p)
+    num = -_grad_energy_complex_step(phi, mu, p) / p.dx ** p.dim
+    assert np.allclose(R, num, rtol=1e-12, atol=1e-12)
+
+
+def _ac_sq_q2(q, delta):
+    """a_c(q)^2 |q|^2 written directly from the four-fold a_c of Sec. 2.1."""
+    q2 = sum(c * c for c in q)
+    ac = 1.0 - delta * (3.0 - 4.0 * sum(c ** 4 for c in q) / q2 ** 2)
+    return ac * ac * q2
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_anisotropic_G_complex_step(dim):
+    rng = np.random.default_rng(dim)
+    for _ in range(50):
+        q = rng.normal(size=dim) * 10 ** rng.uniform(-3, 1)
+        delta = rng.uniform(0.0, 0.05)
+        qc = q.astype(complex)
+        qc[0] += 1j * CS
+        num = _ac_sq_q2(list(qc), delta).imag / CS
+        got = gp.G_normal(np.array(q[0]), [np.array(t) for t in q[1:]], delta)
+        assert abs(got - num) <= 1e-12 * max(1.0, abs(num))
+
+
+def test_anisotropic_G_limits():
+    # delta = 0 is exactly the isotropic 2 q_n
+    q = np.array([0.3, -1.7])
+    assert gp.G_normal(np.array(q[0]), [np.array(q[1])], 0.0) == 2.0 * q[0]
+    # below the guard the isotropic limit with a_c(axis) ... (1 - 3 delta)^2
+    tiny = np.array(1e-16)
+    assert gp.G_normal(tiny, [np.array(0.0)], 0.02) == 2.0 * (1 - 0.06) ** 2 * tiny
+    # along an axis a_c = 1 + delta, so G_n = 2 (1 + delta)^2 q_n
+    got = gp.G_normal(np.array(0.8), [np.array(0.0), np.array(0.0)], 0.03)
+    assert abs(got - 2 * 1.03 ** 2 * 0.8) < 1e-15
+
+
+def _gradient_energy_density(phis, grads, p):
+    """a(phi, grad phi) = sum_{a<b} gamma_ab a_c(q_ab)^2 |q_ab|^2 (Eq. Eqn_a)."""
+    N = len(phis)
+    out = 0.0
+    for a in range(N):
+        for b in range(a + 1, N):
+            q = [phis[a] * grads[b][i] - phis[b] * grads[a][i] for i in range(len(grads[0]))]
+            if p.delta[a][b] != 0.0:
+                out = out + p.gamma[a][b] * _ac_sq_q2(q, p.delta[a][b])
+            else:
+                out = out + p.gamma[a][b] * sum(c * c for c in q)
+    return out
+
+
+@pytest.mark.parametrize("dim,N", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_face_flux_equals_continuum_derivative_on_bilinear_fields(dim, N):
+    """On (bi)linear fields face averages and differences are exact, so the face flux
+    must equal da/d(d_n phi_a) of the continuum density, anisotropy included."""
+    n = (7, 6, 5) if dim == 3 else (7, 6, 1)
+    p = small_params(N=N, dim=dim, n=n, bc=(1, 1, 1), delta=0.03)
+    rng = np.random.default_rng(7)
+    base = rng.uniform(0.2, 0.5, size=N)
+    slope = rng.uniform(-0.05, 0.05, size=(N, dim))
+    # bilinear x_i x_j terms keep face means, normal differences and the mean of the
+    # two cells' central differences exact, while one cell's difference alone is not
+    bil = rng.uniform(-0.01, 0.01, size=(N, dim, dim))
+
+    def field(a, xyz):
+        v = base[a] + sum(slope[a][i] * xyz[i] for i in range(dim))
+        for i in range(dim):
+            for j in range(i + 1, dim):
+                v = v + bil[a][i][j] * xyz[i] * xyz[j]
+        return v
+
+    def gradient(a, xyz):
+        g = [slope[a][i] for i in range(dim)]
+        for i in range(dim):
+            for j in range(i + 1, dim):
+                g[i] = g[i] + bil[a][i][j] * xyz[j]
+                g[j] = g[j] + bil[a][i][j] * xyz[i]
+        return g
+
+    coords = inputs.grid_coords(p)
+    phi = np.stack([field(a, coords) for a in range(N)])
+    Pphi = gp.pad(phi, p)
+    axes = [a for a, _ in gp.spatial_axes(p)]
+    for ax_i, (a, F, S) in enumerate(gp._faces(Pphi, p)):
+        # face k along this axis sits between cells k-1 and k; take faces whose
+        # neighbourhood holds no ghost cells
+        shape = F.shape[1:]
+        for idx in np.ndindex(shape):
+            ok = True
+            pos = []
+            for d_arr in range(len(shape)):
+                ax_neg = d_arr - len(shape)
+                i = idx[d_arr]
+                if ax_neg == a:
+                    ok &= 2 <= i <= shape[d_arr] - 2
+                    pos.append((i - 0.5) * p.dx)
+                else:
+                    ok &= 1 <= i <= shape[d_arr] - 2
+                    pos.append(i * p.dx)
+            if not ok:
+                continue
+            # pos is in array order ((z,) y, x); slope columns are (x, y, z)
+            xyz = pos[::-1]
+            vals = [field(b, xyz) for b in range(N)]
+            for b in range(N):
+                g = [[complex(v) for v in gradient(c, xyz)] for c in range(N)]
+                g[b][ax_i] += 1j * CS
+                dens = _gradient_energy_density([complex(v) for v in vals], g, p)
+                assert abs(F[(b,) + idx] - dens.imag / CS) < 1e-12
+
+
+@pytest.mark.parametrize("dim,N,delta", [(2, 3, 0.0), (2, 3, 0.04), (3, 2, 0.02), (3, 3, 0.03)])
+def test_face_source_identity(dim, N, delta):
+    """q_n is bilinear in (phi_bar, g): sum_a phi_bar_a s_a = sum_a g_a F_a on every face."""
+    n = (5, 4, 3) if dim == 3 else (5, 4, 1)
+    p = small_params(N=N, dim=dim, n=n, bc=(0, 1, 0), delta=delta)
+    phi, _ = random_state(p, seed=9)
+    Pphi = gp.pad(phi, p)
+    for a, F, S in gp._faces(Pphi, p):
+        L = gp._sub(Pphi, p.dim, {a: slice(0, -1)})
+        R = gp._sub(Pphi, p.dim, {a: slice(1, None)})
+        pb = 0.5 * (L + R)
+        g = (R - L) / p.dx
+        lhs = (pb * S).sum(axis=0)
+        rhs = (g * F).sum(axis=0)
+        assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Diffusion of mu: exact discrete Fourier modes
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mixture", [False, True])
+def test_heat_equation_mode_decay(dim, mixture):
+    """Frozen single phase (or frozen uniform mixture): the mu update is FTCS diffusion
+    with coefficient M/chi, so a Fourier mode is multiplied by
+    1 - 4 (dt M / (chi dx^2)) sum_i sin^2(pi m_i / n_i) each step."""
+    n = (8, 6, 5) if dim == 3 else (8, 6, 1)
+    p = small_params(N=2, dim=dim, n=n, bc=(0, 0, 0))
+    p.D[:2, 0] = (0.4, 1.3)
+    chi_s, chi_l = 1 / (2 * p.A[0, 0]), 1 / (2 * p.A[1, 0])
+    if mixture:
+        fs = 0.3
+        hs, hl = 0.216, 0.784  # Eq. hphi at 0.3 / 0.7, by hand
+        p.tau = math.inf      # freeze phi so h(phi^{n+1}) = h(phi^n)
+    else:
+        fs, hs, hl = 0.0, 0.0, 1.0
+    M = p.D[0, 0] * chi_s * hs + p.D[1, 0] * chi_l * hl
+    chi = chi_s * hs + chi_l * hl
+    phi = np.stack([np.full(p.spatial, fs), np.full(p.spatial, 1 - fs)])
+    coords = inputs.grid_coords(p)
+    m = (1, 2, 1)
+    mode = np.ones(p.spatial)
+    sin2 = 0.0
+    for i in range(dim):
+        L = p.n[i] * p.dx
+        mode = mode * np.cos(2 * np.pi * m[i] * coords[i] / L)
+        sin2 += math.sin(math.pi * m[i] / p.n[i]) ** 2
+    mu = 0.01 * mode[None]
+    g = 1 - 4 * p.dt * M / chi / p.dx ** 2 * sin2
+    f, m1 = gp.step(phi, mu, 0, p)
+    assert np.array_equal(f, phi) or np.max(np.abs(f - phi)) < 1e-16
+    assert np.allclose(m1, g * mu, rtol=0, atol=1e-15)
+
+
+def test_noflux_boundary_keeps_cosine_mode():
+    """Zero-flux (mirror) ghosts: cos(pi m (j + 1/2)/n) is an exact discrete mode."""
+    p = small_params(N=2, n=(10, 7, 1), bc=(1, 1, 0))
+    p.D[:2, 0] = (0.0, 1.0)
+    phi = np.stack([np.zeros(p.spatial), np.ones(p.spatial)])
+    j = np.arange(10)
+    mode = np.cos(np.pi * 3 * (j + 0.5) / 10)[None, :] * np.ones((7, 1))
+    mu = 0.02 * mode[None]
+    g = 1 - 4 * p.dt * p.D[1, 0] / p.dx ** 2 * math.sin(math.pi * 3 / 20) ** 2
+    _, m1 = gp.step(phi, mu, 0, p)
+    assert np.allclose(m1, g * mu, rtol=0, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# Planar interface: equilibrium profile, interface energy, convergence
+# ----------------------------------------------------------------------------
+
+def _slab(p, profile):
+    nx = p.n[0]
+    x = (np.arange(nx) + 0.5) * p.dx
+    x1, x2 = 0.25 * nx * p.dx, 0.75 * nx * p.dx
+    if profile == "well":
+        s = 0.5 * (np.tanh(3 * (x - x1) / (2 * p.eps)) - np.tanh(3 * (x - x2) / (2 * p.eps)))
+    else:
+        half = np.pi ** 2 * p.eps / 8
+
+        def up(u):
+            return np.where(u < -half, 0.0, np.where(u > half, 1.0,
+                            0.5 * (1 + np.sin(4 * u / (np.pi * p.eps)))))
+        s = up(x - x1) * up(x2 - x)
+    s = np.broadcast_to(s[None, :], p.spatial)
+    return np.stack([s, 1 - s])
+
+
+def _planar_params(k, potential="well"):
+    p = small_params(N=2, n=(32 * k, 1, 1), bc=(0, 0, 0), potential=potential)
+    p.eps = 1.0
+    p.dx = 1.0 / k
+    p.gamma[0, 1] = p.gamma[1, 0] = 1.3
+    p.T0 = p.Te  # mu = 0 and T = Te: equal grand potentials, no driving force
+    p.dt = 0.2 * inputs.dt_limit(p)
+    return p
+
+
+def test_planar_profile_second_order():
+    """The tanh profile of the multi-well potential is stationary in the continuum;
+    the discrete rate on it shrinks like (dx/eps)^2."""
+    errs = []
+    for k in (4, 8, 16):
+        p = _planar_params(k)
+        phi = _slab(p, "well")
+        mu = np.zeros((1,) + p.spatial)
+        R = gp.rhs_phi(phi, mu, 0, p)
+        rate = 0.5 * (R[0] - R[1]) / (p.tau * p.eps)
+        errs.append(np.max(np.abs(rate)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.3 for o in orders), (errs, orders)
+
+
+@pytest.mark.parametrize("potential,tol", [("well", 3e-3), ("obstacle", 2e-2)])
+def test_interface_energy_equals_gamma(potential, tol):
+    """Both normalisations (9 gamma and 16 gamma / pi^2) give interface energy gamma."""
+    p = _planar_params(16, potential)
+    phi = _slab(p, potential)
+    mu = np.zeros((1,) + p.spatial)
+    # psi^a(0) at T = Te equals the common value C^l = 0 here, so Omega_h is the interface part
+    E = gp.energy(phi, mu, 0, p)
+    bulk_psi = gp.psi_phase(mu, np.full(p.spatial, p.Te), p)[1].sum() * p.dx ** p.dim
+    per_interface = (E - bulk_psi) / (2 * p.dx)  # two interfaces, cross-section dx (ny = 1)
+    assert abs(per_interface / p.gamma[0, 1] - 1.0) < tol
+
+
+def test_symmetric_slab_does_not_drift():
+    p = _planar_params(4)
+    phi = _slab(p, "well")
+    mu = np.zeros((1,) + p.spatial)
+    f, m = gp.run(phi, mu, 0, 400, p)
+    s = f[0, 0]
+    assert np.max(np.abs(s - s[::-1])) < 1e-12  # mirror symmetry kept, so no net drift
+    assert np.max(np.abs(f - phi)) < 0.02
+
+
+# ----------------------------------------------------------------------------
+# Conservation, constraints and symmetry
+# ----------------------------------------------------------------------------
+
+def test_c1_conserves_solute_and_sum_phi():
+    p, phi, mu = inputs.config_c1()
+    m0 = gp.diagnostics(phi, mu, p)["mass"][0]
+    f, m = gp.run(phi, mu, 0, 1000, p)
+    d = gp.diagnostics(f, m, p)
+    assert abs(d["mass"][0] - m0) / abs(m0) < 1e-13
+    assert d["max_sum_dev"] < 1e-12
+
+
+@pytest.mark.parametrize("bc", [(0, 1, 0), (1, 1, 0)])
+def test_ternary_three_phase_conserves_mass(bc):
+    p, phi, mu = inputs.config_c2(n=(96, 80, 1))
+    p = p.copy(bc=bc)
+    p.D[:3, :2] = [[0.2, 0.1], [0.05, 0.3], [1.0, 1.0]]
+    p.dt = 0.2 * inputs.dt_limit(p)
+    d0 = gp.diagnostics(phi, mu, p)
+    f, m = gp.run(phi, mu, 0, 300, p)
+    d1 = gp.diagnostics(f, m, p)
+    for k in range(2):
+        assert abs(d1["mass"][k] - d0["mass"][k]) / abs(d0["mass"][k]) < 1e-13
+    assert d1["max_sum_dev"] < 1e-12
+
+
+def test_translation_equivariance_is_bitwise():
+    p = small_params(N=3, n=(12, 10, 1), bc=(0, 0, 0), G=0.0, gamma3=0.2)
+    phi, mu = random_state(p, seed=4, simplex=True)
+    f, m = gp.run(phi, mu, 0, 5, p)
+    sh = (3, -4)
+    f2, m2 = gp.run(np.roll(phi, sh, axis=(1, 2)), np.roll(mu, sh, axis=(1, 2)), 0, 5, p)
+    assert np.array_equal(np.roll(f, sh, axis=(1, 2)), f2)
+    assert np.array_equal(np.roll(m, sh, axis=(1, 2)), m2)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_transpose_equivariance(dim):
+    """Swapping x and y on a square periodic grid swaps the result (cubic a_c included)."""
+    n = (7, 7, 4) if dim == 3 else (9, 9, 1)
+    p = small_params(N=3, dim=dim, n=n, bc=(0, 0, 0), delta=0.03, G=0.0)
+    phi, mu = random_state(p, seed=8, simplex=True)
+    f, m = gp.run(phi, mu, 0, 3, p)
+    tr = (lambda a: np.swapaxes(a, -1, -2))
+    f2, m2 = gp.run(tr(phi), tr(mu), 0, 3, p)
+    assert np.max(np.abs(tr(f) - f2)) <= 1e-15
+    assert np.max(np.abs(tr(m) - m2)) <= 1e-15
+
+
+def test_energy_decays_for_pure_phase_field_flow():
+    """Equal compositions and mu = 0: mu stays put and the phase fields follow a
+    projected gradient flow of Omega_h, which must not increase."""
+    p = small_params(N=3, n=(24, 20, 1), bc=(0, 0, 0))
+    p.B[:3, :2] = 0.0
+    p.C[:3] = 0.0
+    p.s[:3] = 0.0
+    p.D[:3, :2] = 0.0
+    p.dt = 0.2 * inputs.dt_limit(p)
+    rng = np.random.default_rng(2)
+    raw = rng.uniform(0, 1, size=(3, 5, 6))
+    raw = np.kron(raw, np.ones((1, 4, 4)))  # blocky start with sharp edges
+    phi = raw / raw.sum(axis=0, keepdims=True)
+    mu = np.zeros((2,) + p.spatial)
+    E = [gp.energy(phi, mu, 0, p)]
+    for i in range(200):
+        phi, mu = gp.step(phi, mu, i, p)
+        E.append(gp.energy(phi, mu, i + 1, p))
+    dE = np.diff(E)
+    assert np.all(dE <= 1e-12 * abs(E[0])), dE.max()
+    assert E[-1] < 0.9 * E[0]
+
+
+@pytest.mark.parametrize("factor,grows", [(1.4, True), (0.6, False)])
+def test_gibbs_thomson_critical_radius(factor, grows):
+    """A disc grows above and shrinks below R* = gamma / (s dT) (2D sharp-interface limit)."""
+    dT = 0.1
+    p = inputs.binary_two_phase(dim=2, n=(96, 96, 1), bc=(0, 0, 0), undercooling=dT,
+                                D_solid=1.0, D_liquid=1.0, A=20.0)
+    Rs = p.gamma[0, 1] / (p.s[0] * dT)
+    phi, mu = inputs.nuclei_initial(p, [(48.0, 48.0)], [factor * Rs], [0])
+    v0 = phi[0].sum()
+    f, m = gp.run(phi, mu, 0, 400, p)
+    assert (f[0].sum() > v0) == grows
+
+
+def test_step_window_matches_full_step():
+    p, phi, mu = inputs.config_c2(n=(64, 48, 1))
+    p.G = 2e-3
+    f, m = gp.step(phi, mu, 17, p)
+    lo, hi = (40, 5), (48, 20)
+    fw, mw = gp.step_window(phi, mu, 17, p, lo, hi)
+    assert np.array_equal(fw, f[:, 40:48, 5:20])
+    assert np.array_equal(mw, m[:, 40:48, 5:20])
+
+
+def test_obstacle_keeps_bounds_and_sum():
+    p = small_params(N=3, n=(16, 12, 1), potential="obstacle", gamma3=0.3)
+    phi, mu = random_state(p, seed=12, simplex=True)
+    f, m = gp.run(phi, mu, 0, 50, p)
+    assert f.min() >= 0.0 and f.max() <= 1.0
+    assert np.max(np.abs(f.sum(axis=0) - 1)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [(1, 5, 1), (2, 3, 1), (3, 1, 1)])
+def test_degenerate_tiny_grids_are_finite_and_conservative(n):
+    p = small_params(N=2, n=n, bc=(0, 0, 0))
+    phi, mu = random_state(p, seed=1, simplex=True)
+    d0 = gp.diagnostics(phi, mu, p)
+    f, m = gp.run(phi, mu, 0, 20, p)
+    d1 = gp.diagnostics(f, m, p)
+    assert d1["nonfinite"] == 0
+    assert abs(d1["mass"][0] - d0["mass"][0]) <= 1e-13 * max(1.0, abs(d0["mass"][0]))
