@@ -1,0 +1,165 @@
+/*
+ * mp.h - C ABI of the explicit grand-potential phase-field step (libmpstep.so).
+ *
+ * The library advances N phase fields phi_a and K-1 diffusion potentials mu_k
+ * of the multiphase, multicomponent grand-potential model of MICROSIM
+ * (arXiv 2404.01035, Sec. 2.1) by forward-Euler steps on a regular 2D or 3D
+ * grid, one fused HIP kernel per step on gfx950:
+ *
+ *   phi: Eq. phi_eqn (Allen-Cahn with the gradient energy of Eq. Eqn_a and the
+ *        four-fold a_c, the potential of Eq. Well or Eq. Obstacle, the driving
+ *        force sum_b psi^b dh_b/dphi_a with h of Eq. hphi, and the Lagrange
+ *        multiplier that keeps sum_a phi_a = 1; no elastic term);
+ *   mu : Eq. Mu_explicit_temperature with M of Eq. Mass_conservation and the
+ *        diagonal parabolic free energies of Eq. free_energy_density (no
+ *        anti-trapping current).
+ *
+ * Conventions for every call:
+ *   - Return value: MP_OK (0) or a negative MP_E_* code; mp_last_error()
+ *     gives a message for the calling thread.  No call aborts or throws.
+ *   - Device memory is owned by the caller.  The library only borrows the
+ *     pointers given to mp_bind and never allocates or frees device memory
+ *     itself (mp_destroy frees host-side state only).
+ *   - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
+ *     mp_step is asynchronous; faults inside a kernel surface at the next
+ *     synchronising call (mp_diagnostics, or the caller's own sync).
+ *
+ * State layout (one state buffer): structure of arrays, field-major,
+ *   [N phase fields][K-1 mu fields] x [nz][ny][nx], x fastest, contiguous,
+ * elements double (MP_FP64) or float (MP_FP32).  A torch tensor of shape
+ * (N + K - 1, nz, ny, nx) (2D: (N + K - 1, ny, nx)) maps onto it 1:1.  Two such
+ * buffers are used as ping-pong; after mp_step the current one is reported by
+ * mp_current.
+ */
+#ifndef MPSTEP_MP_H
+#define MPSTEP_MP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_MAX_PHASES 3
+#define MP_MAX_MU 2
+
+enum {
+    MP_OK = 0,
+    MP_E_PARAM = -1,     /* a size, code or coefficient is outside what the library supports */
+    MP_E_UNSTABLE = -2,  /* dt above the explicit stability limit (mp_dt_limit) */
+    MP_E_NULLPTR = -3,   /* a required pointer is NULL */
+    MP_E_UNBOUND = -4,   /* mp_step / mp_diagnostics before mp_bind */
+    MP_E_HIP = -5,       /* a HIP runtime call failed (message holds hipGetErrorString) */
+    MP_E_NONFINITE = -6, /* mp_diagnostics found NaN/Inf in the state */
+    MP_E_STATE = -7      /* call not valid for this state (e.g. batch vs single) */
+};
+
+enum { MP_BC_PERIODIC = 0, MP_BC_NOFLUX = 1 };   /* BOUNDARY codes 3 and 1 of Sec. 5 */
+enum { MP_FP64 = 0, MP_FP32 = 1 };
+enum { MP_WELL = 0, MP_OBSTACLE = 1 };           /* Function_W of Sec. 5: Eq. Well / Eq. Obstacle */
+
+typedef struct mp_state mp_state; /* opaque */
+
+/* Regular grid.  dim = 2 or 3; n = (nx, ny, nz) with nz = 1 in 2D; each n >= 1.
+ * bc per axis (x, y, z): MP_BC_PERIODIC wraps, MP_BC_NOFLUX mirrors the edge
+ * cell into the ghost (zero normal flux).  Cell j of an axis sits at j*dx. */
+typedef struct {
+    int32_t dim;
+    int32_t bc[3];
+    int64_t n[3];
+    double dx;
+} mp_grid;
+
+/* Model coefficients (host FP64; converted once to the run precision).
+ * Only entries [a][b] with a, b < N and [a][k] with k < K-1 are read.
+ *   gamma[a][b]  interface energy gamma_ab (symmetric), Eq. Well / Eq. Obstacle
+ *   gamma3       third-order gamma_abd of the same equations (N = 3)
+ *   delta[a][b]  four-fold anisotropy strength delta_ab (symmetric; 0 = isotropic)
+ *   eps, tau     interface width and relaxation constant of Eq. phi_eqn
+ *   dt           time step; must satisfy dt <= mp_dt_limit(...)
+ *   A, B, C      f^a(c) = sum_k A[a][k] c_k^2 + B[a][k] c_k + C[a]   (A > 0)
+ *   s            C^a(T) = C[a] + s[a] (T - Te)
+ *   D            diffusivity per phase and component, >= 0 (Eq. Mass_conservation)
+ *   Te, T0, G, V, y0  temperature T(y,t) = T0 + G (y - y0 - V t), t = step * dt
+ *                (the Tempgrady key of Sec. 5) */
+typedef struct {
+    int32_t precision; /* MP_FP64 | MP_FP32 */
+    int32_t potential; /* MP_WELL | MP_OBSTACLE */
+    double eps, tau, dt;
+    double gamma[3][3];
+    double gamma3;
+    double delta[3][3];
+    double A[3][2], B[3][2], C[3];
+    double s[3];
+    double D[3][2];
+    double Te, T0, G, V, y0;
+} mp_params;
+
+/* Global diagnostics of the current state, reduced in FP64 with Neumaier
+ * compensation in a fixed order (bitwise reproducible run to run). */
+typedef struct {
+    int64_t step;          /* time level of the state */
+    int64_t nonfinite;     /* cells holding a NaN or Inf in any field */
+    double max_sum_dev;    /* max over cells of |sum_a phi_a - 1| (Sec. 2.1 constraint) */
+    double mass[2];        /* sum over cells of c_k dx^d, c_k = sum_a h_a c^a_k(mu) */
+    double volume[3];      /* sum over cells of phi_a dx^d */
+    double min_chi[2];     /* min over cells of sum_a h_a dc^a_k/dmu_k */
+} mp_diag;
+
+/* Explicit stability limit used by mp_create (host only, no GPU needed):
+ * dx^2/(2d) * min( tau / (2 gamma_max (N-1)/N (1 + 20 delta_max)),
+ *                  min_k min_a chi^a_k / max_a (D^a_k chi^a_k) ), chi = 1/(2A).
+ * Returns a negative value for invalid input. */
+double mp_dt_limit(const mp_grid* grid, int nphases, int ncomp, const mp_params* params);
+
+/* Validate the problem and build a solver state (host only, no GPU needed).
+ * nphases N in {2, 3}; ncomp K in {2, 3} (K - 1 diffusion potentials).
+ * Errors: MP_E_NULLPTR, MP_E_PARAM (dim, n, bc, dx, N, K, precision,
+ * potential, eps, tau, A, D, gamma, delta out of range), MP_E_UNSTABLE. */
+int mp_create(const mp_grid* grid, int nphases, int ncomp, const mp_params* params,
+              mp_state** out);
+
+/* Bytes of one state buffer, and of the workspace mp_bind needs. */
+size_t mp_state_bytes(const mp_state* st);
+size_t mp_workspace_bytes(const mp_state* st);
+
+/* Attach caller-owned device buffers: buf0 and buf1 each mp_state_bytes()
+ * long, 256-byte aligned; workspace mp_workspace_bytes() long (FP64 partial
+ * sums of the reductions).  buf0 is the current buffer afterwards and the
+ * time level is reset to 0 (use mp_set_step to resume). */
+int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
+
+/* Advance nsteps >= 0 forward-Euler steps on ``stream`` (asynchronous).
+ * Each step reads the current buffer and writes the other; the current
+ * buffer flips nsteps mod 2 times; the time level advances by nsteps. */
+int mp_step(mp_state* st, int64_t nsteps, void* stream);
+
+/* Which bound buffer (0 or 1) holds the current state, and its time level. */
+int mp_current(const mp_state* st, int* which_buf, int64_t* step);
+
+/* Declare that buffer ``which_buf`` holds the state at time level ``step``. */
+int mp_set_step(mp_state* st, int64_t step, int which_buf);
+
+/* Reduce the current state into *out (synchronises ``stream``).
+ * Returns MP_E_NONFINITE (with *out filled) when a NaN/Inf is present. */
+int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
+
+/* Tile shape of the step kernel: block width bx (cells along x; 64, 128 or
+ * 256 in 2D, 64 in 3D) and march length seg (planes per block along the
+ * slowest axis, >= 1).  0 keeps the current value.  Results do not depend on
+ * the tile shape (bitwise). */
+int mp_set_tile(mp_state* st, int bx, int seg);
+int mp_get_tile(const mp_state* st, int* bx, int* seg);
+
+/* Free host-side state (device buffers stay with the caller). NULL is a no-op. */
+void mp_destroy(mp_state* st);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPSTEP_MP_H */

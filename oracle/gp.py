@@ -350,19 +350,30 @@ def run(phi, mu, n0, nsteps, p):
     return phi, mu
 
 
+def _ghost_index(lo, hi, n, bc):
+    """Source indices of cells lo-1 .. hi along one axis with the ghost rule of ``pad``."""
+    idx = np.arange(lo - 1, hi + 1)
+    if bc == PERIODIC:
+        return np.mod(idx, n)
+    return np.clip(idx, 0, n - 1)
+
+
 def step_window(phi, mu, n, p, lo, hi):
     """One step evaluated only on the box lo <= index < hi (array order, spatial axes).
 
-    Uses the full fields for the neighbourhood, so the result equals the same
-    cells of ``step`` while costing only the window.  ``lo``/``hi`` are tuples
-    in array order ((z,) y, x).
+    Gathers the box plus a one-cell rim with the same ghost rule as ``pad`` and
+    runs the padded step on it, so the result equals the same cells of ``step``
+    while costing only the window.  ``lo``/``hi`` are tuples in array order
+    ((z,) y, x).
     """
     nd = p.dim
-    Pphi = pad(phi, p)
-    Pmu = pad(mu, p)
-    sl = tuple(slice(l, h_ + 2) for l, h_ in zip(lo, hi))
-    y_origin = lo[-2]
-    return _step_padded(Pphi[(slice(None),) + sl], Pmu[(slice(None),) + sl], n, p, y_origin)
+    bcs = [bc for _, bc in spatial_axes(p)][::-1]  # array order
+    shape = phi.shape[1:]
+    ix = [_ghost_index(lo[i], hi[i], shape[i], bcs[i]) for i in range(nd)]
+    grid = np.ix_(*ix)
+    Pphi = phi[(slice(None),) + grid]
+    Pmu = mu[(slice(None),) + grid]
+    return _step_padded(Pphi, Pmu, n, p, y_origin=lo[-2])
 
 
 # ----------------------------------------------------------------------------
@@ -414,6 +425,6 @@ def diagnostics(phi, mu, p):
         "max_sum_dev": float(np.max(np.abs(phi.sum(axis=0) - 1.0))),
         "mass": [float(np.sum(c[k]) * vol) for k in range(p.nmu)],
         "volume": [float(np.sum(phi[a]) * vol) for a in range(p.nphases)],
-        "min_chi": float(np.min(chik)),
+        "min_chi": [float(np.min(chik[k])) for k in range(p.nmu)],
         "nonfinite": int(np.size(finite) - np.count_nonzero(finite)),
     }

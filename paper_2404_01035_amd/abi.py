@@ -1,0 +1,214 @@
+"""ctypes binding of libmpstep.so: the calls of include/mp.h under the same names.
+
+Argument marshalling only; every step of the path runs in the library's HIP
+kernels.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmpstep.so")
+
+MP_OK = 0
+MP_E_PARAM, MP_E_UNSTABLE, MP_E_NULLPTR, MP_E_UNBOUND, MP_E_HIP, MP_E_NONFINITE, MP_E_STATE = (
+    -1, -2, -3, -4, -5, -6, -7)
+MP_BC_PERIODIC, MP_BC_NOFLUX = 0, 1
+MP_FP64, MP_FP32 = 0, 1
+MP_WELL, MP_OBSTACLE = 0, 1
+
+ERROR_NAMES = {
+    MP_E_PARAM: "MP_E_PARAM", MP_E_UNSTABLE: "MP_E_UNSTABLE", MP_E_NULLPTR: "MP_E_NULLPTR",
+    MP_E_UNBOUND: "MP_E_UNBOUND", MP_E_HIP: "MP_E_HIP", MP_E_NONFINITE: "MP_E_NONFINITE",
+    MP_E_STATE: "MP_E_STATE",
+}
+
+# Every symbol the header declares (checked by the ABI test).
+EXPORTS = [
+    "mp_dt_limit", "mp_create", "mp_state_bytes", "mp_workspace_bytes", "mp_bind", "mp_step",
+    "mp_current", "mp_set_step", "mp_diagnostics", "mp_set_tile", "mp_get_tile", "mp_destroy",
+    "mp_last_error",
+]
+
+
+class mp_grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("bc", C.c_int32 * 3), ("n", C.c_int64 * 3), ("dx", C.c_double)]
+
+
+class mp_params(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("potential", C.c_int32),
+        ("eps", C.c_double), ("tau", C.c_double), ("dt", C.c_double),
+        ("gamma", (C.c_double * 3) * 3), ("gamma3", C.c_double), ("delta", (C.c_double * 3) * 3),
+        ("A", (C.c_double * 2) * 3), ("B", (C.c_double * 2) * 3), ("C", C.c_double * 3),
+        ("s", C.c_double * 3), ("D", (C.c_double * 2) * 3),
+        ("Te", C.c_double), ("T0", C.c_double), ("G", C.c_double), ("V", C.c_double),
+        ("y0", C.c_double),
+    ]
+
+
+class mp_diag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("nonfinite", C.c_int64), ("max_sum_dev", C.c_double),
+        ("mass", C.c_double * 2), ("volume", C.c_double * 3), ("min_chi", C.c_double * 2),
+    ]
+
+
+class MPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2404_01035_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.mp_dt_limit.restype = C.c_double
+        L.mp_dt_limit.argtypes = [C.POINTER(mp_grid), C.c_int, C.c_int, C.POINTER(mp_params)]
+        L.mp_create.restype = C.c_int
+        L.mp_create.argtypes = [C.POINTER(mp_grid), C.c_int, C.c_int, C.POINTER(mp_params),
+                                C.POINTER(vp)]
+        L.mp_state_bytes.restype = C.c_size_t
+        L.mp_state_bytes.argtypes = [vp]
+        L.mp_workspace_bytes.restype = C.c_size_t
+        L.mp_workspace_bytes.argtypes = [vp]
+        L.mp_bind.restype = C.c_int
+        L.mp_bind.argtypes = [vp, vp, vp, vp]
+        L.mp_step.restype = C.c_int
+        L.mp_step.argtypes = [vp, C.c_int64, vp]
+        L.mp_current.restype = C.c_int
+        L.mp_current.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int64)]
+        L.mp_set_step.restype = C.c_int
+        L.mp_set_step.argtypes = [vp, C.c_int64, C.c_int]
+        L.mp_diagnostics.restype = C.c_int
+        L.mp_diagnostics.argtypes = [vp, C.POINTER(mp_diag), vp]
+        L.mp_set_tile.restype = C.c_int
+        L.mp_set_tile.argtypes = [vp, C.c_int, C.c_int]
+        L.mp_get_tile.restype = C.c_int
+        L.mp_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mp_destroy.restype = None
+        L.mp_destroy.argtypes = [vp]
+        L.mp_last_error.restype = C.c_char_p
+        L.mp_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MP_OK:
+        raise MPError(rc, lib().mp_last_error().decode())
+    return rc
+
+
+def mp_last_error() -> str:
+    return lib().mp_last_error().decode()
+
+
+def to_grid(p) -> mp_grid:
+    g = mp_grid()
+    g.dim = int(p.dim)
+    for i in range(3):
+        g.bc[i] = int(p.bc[i])
+        g.n[i] = int(p.n[i])
+    g.dx = float(p.dx)
+    return g
+
+
+def to_params(p) -> mp_params:
+    c = mp_params()
+    c.precision = MP_FP64 if p.precision == "f64" else MP_FP32
+    c.potential = MP_WELL if p.potential == "well" else MP_OBSTACLE
+    c.eps, c.tau, c.dt = float(p.eps), float(p.tau), float(p.dt)
+    c.gamma3 = float(p.gamma3)
+    g = np.asarray(p.gamma, dtype=np.float64)
+    d = np.asarray(p.delta, dtype=np.float64)
+    A, B, Dm = (np.asarray(x, dtype=np.float64) for x in (p.A, p.B, p.D))
+    for a in range(3):
+        c.C[a] = float(p.C[a])
+        c.s[a] = float(p.s[a])
+        for b in range(3):
+            c.gamma[a][b] = float(g[a, b])
+            c.delta[a][b] = float(d[a, b])
+        for k in range(2):
+            c.A[a][k] = float(A[a, k])
+            c.B[a][k] = float(B[a, k])
+            c.D[a][k] = float(Dm[a, k])
+    c.Te, c.T0, c.G, c.V, c.y0 = (float(x) for x in (p.Te, p.T0, p.G, p.V, p.y0))
+    return c
+
+
+def mp_dt_limit(p) -> float:
+    g, c = to_grid(p), to_params(p)
+    return lib().mp_dt_limit(C.byref(g), int(p.nphases), int(p.ncomp), C.byref(c))
+
+
+def mp_create(p) -> int:
+    """Validate and create a state for the problem ``p`` (an inputs.Params); returns a handle."""
+    g, c = to_grid(p), to_params(p)
+    h = C.c_void_p()
+    _check(lib().mp_create(C.byref(g), int(p.nphases), int(p.ncomp), C.byref(c), C.byref(h)))
+    return h.value
+
+
+def mp_state_bytes(st) -> int:
+    return int(lib().mp_state_bytes(st))
+
+
+def mp_workspace_bytes(st) -> int:
+    return int(lib().mp_workspace_bytes(st))
+
+
+def mp_bind(st, buf0: int, buf1: int, workspace: int):
+    _check(lib().mp_bind(st, buf0, buf1, workspace))
+
+
+def mp_step(st, nsteps: int, stream: int = 0):
+    _check(lib().mp_step(st, int(nsteps), stream))
+
+
+def mp_current(st):
+    w, s = C.c_int(), C.c_int64()
+    _check(lib().mp_current(st, C.byref(w), C.byref(s)))
+    return w.value, s.value
+
+
+def mp_set_step(st, step: int, which_buf: int):
+    _check(lib().mp_set_step(st, int(step), int(which_buf)))
+
+
+def mp_diagnostics(st, stream: int = 0, allow_nonfinite: bool = False) -> dict:
+    d = mp_diag()
+    rc = lib().mp_diagnostics(st, C.byref(d), stream)
+    if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
+        _check(rc)
+    return {
+        "step": d.step, "nonfinite": d.nonfinite, "max_sum_dev": d.max_sum_dev,
+        "mass": list(d.mass), "volume": list(d.volume), "min_chi": list(d.min_chi),
+    }
+
+
+def mp_set_tile(st, bx: int = 0, seg: int = 0):
+    _check(lib().mp_set_tile(st, int(bx), int(seg)))
+
+
+def mp_get_tile(st):
+    bx, seg = C.c_int(), C.c_int()
+    _check(lib().mp_get_tile(st, C.byref(bx), C.byref(seg)))
+    return bx.value, seg.value
+
+
+def mp_destroy(st):
+    if st:
+        lib().mp_destroy(st)

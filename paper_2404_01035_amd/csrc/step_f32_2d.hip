@@ -1,0 +1,6 @@
+// Kernel instances of the fused step: precision float, 2d.
+#include "step_kernel.hpp"
+
+namespace mp {
+template int launch_step_dim<float, false>(const StepLaunch&, const Coef<float>&, hipStream_t);
+}  // namespace mp

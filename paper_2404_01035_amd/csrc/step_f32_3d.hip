@@ -1,0 +1,6 @@
+// Kernel instances of the fused step: precision float, 3d.
+#include "step_kernel.hpp"
+
+namespace mp {
+template int launch_step_dim<float, true>(const StepLaunch&, const Coef<float>&, hipStream_t);
+}  // namespace mp

@@ -1,0 +1,74 @@
+"""Torch-owned device buffers bound to one library state.
+
+PyTorch only allocates device memory and supplies the stream; every step runs
+in libmpstep.so's kernels through the C ABI (``abi``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+class Solver:
+    """One simulation on cuda:0: two ping-pong state buffers plus the reduction workspace."""
+
+    def __init__(self, p, device: str = "cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (torch.cuda.is_available() is False)")
+        self.p = p
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if p.precision == "f64" else torch.float32
+        self.st = abi.mp_create(p)
+        shape = (p.nfields,) + tuple(p.spatial)
+        self.bufs = [torch.empty(shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        nws = abi.mp_workspace_bytes(self.st)
+        self.ws = torch.empty(nws, dtype=torch.uint8, device=self.device)
+        assert abi.mp_state_bytes(self.st) == self.bufs[0].numel() * self.bufs[0].element_size()
+        abi.mp_bind(self.st, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(), self.ws.data_ptr())
+
+    @staticmethod
+    def stream() -> int:
+        return torch.cuda.current_stream().cuda_stream
+
+    def load(self, phi, mu, step: int = 0):
+        """Upload (phi, mu) host arrays into buffer 0 and declare it the state at ``step``."""
+        host = np.concatenate([np.asarray(phi), np.asarray(mu)], axis=0)
+        self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(host)).to(self.dtype))
+        torch.cuda.synchronize()
+        abi.mp_set_step(self.st, step, 0)
+
+    def step(self, nsteps: int):
+        abi.mp_step(self.st, nsteps, self.stream())
+
+    def current(self) -> torch.Tensor:
+        w, _ = abi.mp_current(self.st)
+        return self.bufs[w]
+
+    @property
+    def time_level(self) -> int:
+        return abi.mp_current(self.st)[1]
+
+    def fields(self):
+        """(phi, mu) of the current state as float64 numpy arrays."""
+        torch.cuda.synchronize()
+        a = self.current().double().cpu().numpy()
+        return a[: self.p.nphases], a[self.p.nphases:]
+
+    def diagnostics(self, allow_nonfinite: bool = False) -> dict:
+        return abi.mp_diagnostics(self.st, self.stream(), allow_nonfinite)
+
+    def set_tile(self, bx: int = 0, seg: int = 0):
+        abi.mp_set_tile(self.st, bx, seg)
+
+    def close(self):
+        if self.st:
+            abi.mp_destroy(self.st)
+            self.st = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

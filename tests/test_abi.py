@@ -1,0 +1,133 @@
+"""Host-side checks of the C ABI (no GPU needed: these calls make no HIP call)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_01035_amd import abi, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    with open(os.path.join(ROOT, "include", "mp.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(mp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = abi.lib()
+    declared = _header_symbols()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(abi.EXPORTS) == declared
+
+
+def test_create_and_query_without_gpu():
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        assert abi.mp_state_bytes(st) == p.ncells * p.nfields * 8
+        assert abi.mp_workspace_bytes(st) > 0
+        assert abi.mp_current(st) == (0, 0)
+        abi.mp_set_step(st, 7, 1)
+        assert abi.mp_current(st) == (1, 7)
+        abi.mp_set_tile(st, 128, 8)
+        assert abi.mp_get_tile(st) == (128, 8)
+    finally:
+        abi.mp_destroy(st)
+
+
+def test_fp32_state_bytes():
+    p, _, _ = inputs.config_c2(n=(96, 80, 1), precision="f32")
+    st = abi.mp_create(p)
+    assert abi.mp_state_bytes(st) == p.ncells * 5 * 4
+    abi.mp_destroy(st)
+
+
+def test_dt_limit_matches_input_formula():
+    for p in [inputs.config_c1()[0], inputs.config_c2(n=(64, 64, 1))[0],
+              inputs.dendrite_params(n=(16, 16, 16))]:
+        assert math.isclose(abi.mp_dt_limit(p), inputs.dt_limit(p), rel_tol=1e-14)
+
+
+def _expect(code, p, match=None):
+    with pytest.raises(abi.MPError) as ei:
+        abi.mp_create(p)
+    assert ei.value.code == code, str(ei.value)
+    if match:
+        assert re.search(match, str(ei.value)), str(ei.value)
+
+
+def test_create_rejects_bad_input():
+    p, _, _ = inputs.config_c1()
+    _expect(abi.MP_E_UNSTABLE, p.copy(dt=1.01 * inputs.dt_limit(p)), "stability")
+    _expect(abi.MP_E_PARAM, p.copy(nphases=4), "nphases")
+    _expect(abi.MP_E_PARAM, p.copy(ncomp=4), "ncomp")
+    _expect(abi.MP_E_PARAM, p.copy(dim=4), "dim")
+    _expect(abi.MP_E_PARAM, p.copy(n=(0, 64, 1)), "n\\[0\\]")
+    _expect(abi.MP_E_PARAM, p.copy(n=(8, 8, 2)), "2D grid")
+    _expect(abi.MP_E_PARAM, p.copy(bc=(2, 0, 0)), "bc")
+    _expect(abi.MP_E_PARAM, p.copy(dx=-1.0), "dx")
+    _expect(abi.MP_E_PARAM, p.copy(eps=0.0), "eps")
+    _expect(abi.MP_E_PARAM, p.copy(tau=-1.0), "tau")
+    q = p.copy()
+    q.A[0, 0] = 0.0
+    _expect(abi.MP_E_PARAM, q, "A\\[0\\]\\[0\\]")
+    q = p.copy()
+    q.D[1, 0] = -1.0
+    _expect(abi.MP_E_PARAM, q, "D\\[1\\]\\[0\\]")
+    q = p.copy()
+    q.gamma[0, 1] = 2.0  # asymmetric
+    _expect(abi.MP_E_PARAM, q, "symmetric")
+    q = p.copy()
+    q.delta[0, 1] = q.delta[1, 0] = 0.5
+    _expect(abi.MP_E_PARAM, q, "delta")
+    q = p.copy()
+    q.C[0] = float("nan")
+    _expect(abi.MP_E_PARAM, q, "finite")
+    import ctypes as C
+    g, c = abi.to_grid(p), abi.to_params(p)
+    h = C.c_void_p()
+    for field in ("precision", "potential"):
+        c2 = abi.to_params(p)
+        setattr(c2, field, 7)
+        assert abi.lib().mp_create(C.byref(g), 2, 2, C.byref(c2), C.byref(h)) == abi.MP_E_PARAM
+        assert field in abi.mp_last_error()
+    assert abi.lib().mp_create(C.byref(g), 2, 2, C.byref(c), C.byref(h)) == abi.MP_OK
+    abi.mp_destroy(h.value)
+
+
+def test_calls_reject_null_and_unbound():
+    L = abi.lib()
+    assert L.mp_bind(None, None, None, None) == abi.MP_E_NULLPTR
+    assert L.mp_step(None, 1, None) == abi.MP_E_NULLPTR
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        assert L.mp_step(st, 1, None) == abi.MP_E_UNBOUND
+        assert "before mp_bind" in abi.mp_last_error()
+        assert L.mp_bind(st, None, None, None) == abi.MP_E_NULLPTR
+        assert L.mp_bind(st, 256, 256, 512) == abi.MP_E_PARAM      # same buffer twice
+        assert L.mp_bind(st, 256, 520, 1024) == abi.MP_E_PARAM     # misaligned
+        assert L.mp_set_step(st, -1, 0) == abi.MP_E_PARAM
+        assert L.mp_set_step(st, 0, 2) == abi.MP_E_PARAM
+        assert L.mp_set_tile(st, 100, 0) == abi.MP_E_PARAM
+        assert L.mp_set_tile(st, 0, -3) == abi.MP_E_PARAM
+    finally:
+        abi.mp_destroy(st)
+    abi.mp_destroy(None)
+
+
+def test_create_rejects_null_pointers():
+    import ctypes as C
+    L = abi.lib()
+    h = C.c_void_p()
+    assert L.mp_create(None, 2, 2, None, C.byref(h)) == abi.MP_E_NULLPTR
+    p, _, _ = inputs.config_c1()
+    g = abi.to_grid(p)
+    assert L.mp_create(C.byref(g), 2, 2, None, C.byref(h)) == abi.MP_E_NULLPTR
+    assert L.mp_create(C.byref(g), 2, 2, C.byref(abi.to_params(p)), None) == abi.MP_E_NULLPTR

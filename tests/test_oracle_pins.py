@@ -501,14 +501,26 @@ def test_gibbs_thomson_critical_radius(factor, grows):
     assert (f[0].sum() > v0) == grows
 
 
-def test_step_window_matches_full_step():
+@pytest.mark.parametrize("lo,hi", [((40, 5), (48, 20)), ((0, 0), (7, 9)), ((41, 55), (48, 64))])
+def test_step_window_matches_full_step(lo, hi):
     p, phi, mu = inputs.config_c2(n=(64, 48, 1))
     p.G = 2e-3
     f, m = gp.step(phi, mu, 17, p)
-    lo, hi = (40, 5), (48, 20)
     fw, mw = gp.step_window(phi, mu, 17, p, lo, hi)
-    assert np.array_equal(fw, f[:, 40:48, 5:20])
-    assert np.array_equal(mw, m[:, 40:48, 5:20])
+    sl = (slice(None), slice(lo[0], hi[0]), slice(lo[1], hi[1]))
+    assert np.array_equal(fw, f[sl])
+    assert np.array_equal(mw, m[sl])
+
+
+def test_step_window_matches_full_step_3d():
+    p = small_params(N=3, dim=3, n=(9, 7, 6), bc=(0, 1, 0), delta=0.02, G=0.01)
+    phi, mu = random_state(p, seed=21, simplex=True)
+    f, m = gp.step(phi, mu, 4, p)
+    for lo, hi in [((0, 0, 0), (2, 3, 4)), ((4, 5, 7), (6, 7, 9)), ((1, 2, 3), (5, 6, 8))]:
+        fw, mw = gp.step_window(phi, mu, 4, p, lo, hi)
+        sl = (slice(None),) + tuple(slice(a, b) for a, b in zip(lo, hi))
+        assert np.array_equal(fw, f[sl])
+        assert np.array_equal(mw, m[sl])
 
 
 def test_obstacle_keeps_bounds_and_sum():
