@@ -32,7 +32,33 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--tile", type=str, default="", help="bx,seg override")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of one FP64 state buffer instead")
     return ap.parse_args()
+
+
+def copy_calibration(n, steps):
+    """Plain device-to-device copy of one FP64 C2 state buffer (5 fields x n x n):
+    the practical HBM ceiling, and the known-size reference for traffic counters."""
+    import torch
+
+    nbytes = 5 * n * n * 8
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    print(json.dumps({"copy_bytes_each_way": nbytes, "ms_per_copy": ms, "GBs_read_plus_write": gbs,
+                      "frac_of_8TBs": gbs / HBM_PEAK_GBS}), flush=True)
 
 
 def time_precision(precision, n, steps, warmup, tile):
@@ -110,6 +136,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.copy_calibration:
+        copy_calibration(a.n, a.steps)
+        return
     print(f"[bench] FP64 {a.n}x{a.n}: warmup {a.warmup}, timed {a.steps} steps", file=sys.stderr,
           flush=True)
     r64 = time_precision("f64", a.n, a.steps, a.warmup, a.tile)

@@ -1,0 +1,251 @@
+// Device arithmetic of one grand-potential step (MICROSIM, arXiv 2404.01035,
+// Sec. 2.1), shared by the 2D and 3D step kernels.
+//
+// Faces.  On a face normal to axis n between cells L and R, with
+// sigma_a = phi_L,a + phi_R,a and delta_a = phi_R,a - phi_L,a, the pair term of
+// Eq. Eqn_a has q_n = (sigma_a delta_b - sigma_b delta_a) / (2 dx).  The
+// gradient term of Eq. phi_eqn at a cell is
+//   eps [ sum_axes (F_hi - F_lo)/dx - (s_hi + s_lo)/2 ],
+// F_a = d(a)/d(d_n phi_a), s_a = the face's share of d(a)/d(phi_a).  Writing
+// U = 2F - dx s (what the face contributes to the cell below it) and
+// W = 2F + dx s (to the cell above it) this is eps/(2 dx) sum_axes (U_hi - W_lo),
+// and for each pair, with g = 2 gamma G_n (G_n = d(a_c^2|q|^2)/dq_n):
+//   U_a -= g phi_R,b,  U_b += g phi_R,a,  W_a -= g phi_L,b,  W_b += g phi_L,a.
+// a_c depends only on the direction of q and G_n is homogeneous of degree one,
+// so the anisotropic G_n is evaluated on the rescaled q~ = 2 dx q (the guard
+// |q|^2 <= 1e-30 is rescaled with it).  The mu flux uses
+// M~ = dt/(2 dx^2) M, so that dt div(M grad mu) = sum_axes (J_hi - J_lo) with
+// J = (M~_L + M~_R)(mu_R - mu_L).
+//
+// Cells.  psi^b = C^b + s^b (T - Te) - sum_k (mu_k - B^b_k)^2 / (4 A^b_k);
+// with P_a = phi_b phi_c (N = 3) the driving force of Eq. phi_eqn is
+// sum_b psi^b dh_b/dphi_a = 6 psi_a phi_a (1 - phi_a) + 2 P_a sum_b psi_b, and
+// h_a = phi_a^2 (3 - 2 phi_a) + 2 phi_a P_a (Eq. hphi).  lambda is the mean of
+// the N right-hand sides, accumulated in FP64 in both precisions.
+#pragma once
+
+#include "mp_internal.hpp"
+
+namespace mp {
+
+// Ghost index map: -1 and n are the ghosts (wrap or mirror); indices further
+// out only occur in the unused rim of a ragged tile and are clamped.
+__device__ __forceinline__ int gmap(int i, int n, bool periodic) {
+    if (i < 0) return periodic ? n - 1 : 0;
+    if (i >= n) return (i == n && periodic) ? 0 : n - 1;
+    return i;
+}
+
+__device__ __forceinline__ int pair_index(int i, int j) { return i + j - 1; }  // (0,1)->0 (0,2)->1 (1,2)->2
+
+// Normal component of d(a_c^2 |q|^2)/dq for the four-fold a_c, on the rescaled q.
+template <typename R, int NTG>
+__device__ __forceinline__ R g_aniso(R qn, const R (&qt)[NTG], R d, R guard) {
+    R Q2 = qn * qn;
+#pragma unroll
+    for (int t = 0; t < NTG; ++t) Q2 = Q2 + qt[t] * qt[t];
+    if (Q2 <= guard) {
+        R a0 = R(1) - R(3) * d;
+        return R(2) * a0 * a0 * qn;
+    }
+    R rq = sqrt(Q2);
+    R mn = qn / rq;
+    R mn2 = mn * mn;
+    R S4 = mn2 * mn2;
+#pragma unroll
+    for (int t = 0; t < NTG; ++t) {
+        R mt = qt[t] / rq;
+        R mt2 = mt * mt;
+        S4 = S4 + mt2 * mt2;
+    }
+    R ac = R(1) - d * (R(3) - R(4) * S4);
+    return R(2) * ac * ac * qn + R(32) * d * ac * rq * (mn2 * mn - mn * S4);
+}
+
+// One face: U, W (gradient term) and J (mu flux).  tau[t][a] is the unscaled
+// sum of the two cells' central differences along tangential axis t
+// (= 4 dx times the face's tangential gradient); unused when !ANISO.
+template <typename R, int NP, int NM, bool ANISO, int NTG>
+__device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
+                                          const R (&tau)[NTG > 0 ? NTG : 1][NP],
+                                          const R (&mL)[NM], const R (&mR)[NM],
+                                          const R (&uL)[NM], const R (&uR)[NM], const Coef<R>& c,
+                                          R (&U)[NP], R (&W)[NP], R (&J)[NM]) {
+    R sg[NP], dl[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        sg[a] = pL[a] + pR[a];
+        dl[a] = pR[a] - pL[a];
+        U[a] = R(0);
+        W[a] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+#pragma unroll
+        for (int j = i + 1; j < NP; ++j) {
+            const int pi = pair_index(i, j);
+            R q = sg[i] * dl[j] - sg[j] * dl[i];
+            R gh;
+            if constexpr (ANISO) {
+                R d = c.del[pi];
+                if (d != R(0)) {
+                    R qt[NTG];
+#pragma unroll
+                    for (int t = 0; t < NTG; ++t)
+                        qt[t] = R(0.25) * (sg[i] * tau[t][j] - sg[j] * tau[t][i]);
+                    gh = c.gd[pi] * g_aniso<R, NTG>(q, qt, d, c.qguard);
+                } else {
+                    gh = c.g2d[pi] * q;
+                }
+            } else {
+                gh = c.g2d[pi] * q;
+            }
+            U[i] = U[i] - gh * pR[j];
+            U[j] = U[j] + gh * pR[i];
+            W[i] = W[i] - gh * pL[j];
+            W[j] = W[j] + gh * pL[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NM; ++k) J[k] = (mL[k] + mR[k]) * (uR[k] - uL[k]);
+}
+
+// Interpolation functions h_a of Eq. hphi.
+template <typename R, int NP>
+__device__ __forceinline__ void interp_h(const R (&phi)[NP], R (&h)[NP]) {
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        R sq = phi[a] * phi[a];
+        h[a] = sq * (R(3) - R(2) * phi[a]);
+        if constexpr (NP == 3) {
+            const int b = a == 0 ? 1 : 0, g = a == 2 ? 1 : 2;
+            h[a] = h[a] + R(2) * phi[a] * (phi[b] * phi[g]);
+        }
+    }
+}
+
+// Scaled cell mobility M~_k = sum_a (D^a_k chi^a_k dt / (2 dx^2)) h_a.
+template <typename R, int NP, int NM>
+__device__ __forceinline__ void mobility(const R (&h)[NP], const Coef<R>& c, R (&Mt)[NM]) {
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        R m = R(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) m = m + c.Dt[a][k] * h[a];
+        Mt[k] = m;
+    }
+}
+
+// Reciprocal to within a few ulp: hardware estimate plus Newton steps.
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
+// Cell update from the face sums Gs_a = sum_axes (U_hi - W_lo) and
+// Js_k = sum_axes (J_hi - J_lo); h0 = h(phi^n) of the cell; tt = T - Te.
+template <typename R, int NP, int NM, bool OBST>
+__device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM],
+                                            const R (&h0)[NP], const R (&Gs)[NP],
+                                            const R (&Js)[NM], R tt, const Coef<R>& c,
+                                            R (&phin)[NP], R (&mun)[NM]) {
+    R dmu[NP][NM];
+    R psi[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+        R v = c.C[b] + c.s[b] * tt;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            dmu[b][k] = mu[k] - c.B[b][k];
+            v = v - c.halfchi[b][k] * dmu[b][k] * dmu[b][k];
+        }
+        psi[b] = v;
+    }
+    R sq[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) sq[a] = phi[a] * phi[a];
+    R P[NP];
+    if constexpr (NP == 3) {
+        P[0] = phi[1] * phi[2];
+        P[1] = phi[0] * phi[2];
+        P[2] = phi[0] * phi[1];
+    }
+    R psum = R(0);
+    if constexpr (NP == 3) psum = psi[0] + psi[1] + psi[2];
+
+    R Rr[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        R dw = R(0);
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            if (b == a) continue;
+            const R wc = c.wc[pair_index(a < b ? a : b, a < b ? b : a)];
+            if constexpr (OBST)
+                dw = dw + wc * phi[b];
+            else
+                dw = dw + wc * sq[b];
+        }
+        if constexpr (!OBST) dw = dw * phi[a];
+        R dps = R(6) * psi[a] * (phi[a] * (R(1) - phi[a]));
+        if constexpr (NP == 3) {
+            dw = dw + c.gamma3 * P[a];
+            dps = dps + R(2) * P[a] * psum;
+        }
+        Rr[a] = c.cE * Gs[a] - (c.inv_eps * dw + dps);
+    }
+
+    double lam = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) lam = lam + (double)Rr[a];
+    lam = lam * (1.0 / NP);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) phin[a] = phi[a] + c.kphi * (R)((double)Rr[a] - lam);
+    if constexpr (OBST) {
+        R sum = R(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            phin[a] = fmin(fmax(phin[a], R(0)), R(1));
+            sum = sum + phin[a];
+        }
+        const R inv = R(1) / sum;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) phin[a] = phin[a] * inv;
+    }
+
+    R h1[NP], dh[NP];
+    interp_h<R, NP>(phin, h1);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) dh[a] = h1[a] - h0[a];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        R src = R(0), chik = R(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            src = src + (dmu[a][k] * c.chi[a][k]) * dh[a];
+            chik = chik + h1[a] * c.chi[a][k];
+        }
+        mun[k] = mu[k] + (Js[k] - src) * fast_rcp(chik);
+    }
+}
+
+// Whole-wave lane shuffle: value of lane (addr / 4).
+__device__ __forceinline__ float lane_get(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_get(double v, int addr) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+}  // namespace mp

@@ -17,20 +17,26 @@ struct Geom {
     int64_t fstride;        // elements per field = nx * ny * nz
 };
 
-// Model coefficients in the run precision R, derived once on the host.
+// Model coefficients in the run precision R, derived once on the host in
+// FP64 and folded for the face/cell arithmetic of gp_device.hpp.
+// Pair index: (0,1) -> 0, (0,2) -> 1, (1,2) -> 2.
 template <typename R>
 struct Coef {
-    R dt, inv_dx, half_inv_dx, eps, inv_eps, kphi;  // kphi = dt / (tau eps)
-    R gam[3][3];     // gamma_ab
-    R wcoef[3][3];   // 18 gamma_ab (multi-well) or 16/pi^2 gamma_ab (obstacle)
-    R gamma3;        // gamma_abd
-    R delta[3][3];   // anisotropy strength
-    R chi[3][2];     // 1 / (2 A)
-    R halfchi[3][2]; // 1 / (4 A)
+    R cE;          // eps / (2 dx)
+    R inv_eps;     // 1 / eps
+    R kphi;        // dt / (tau eps)
+    R qguard;      // (2 dx)^2 * 1e-30, the |q|^2 guard on the rescaled q
+    R g2d[3];      // 2 gamma_ab / dx (isotropic pair factor)
+    R gd[3];       // gamma_ab / dx (anisotropic pair factor)
+    R del[3];      // delta_ab
+    R wc[3];       // 18 gamma_ab (multi-well) or 16/pi^2 gamma_ab (obstacle)
+    R gamma3;      // gamma_abd
+    R chi[3][2];   // 1 / (2 A)
+    R halfchi[3][2];  // 1 / (4 A)
     R B[3][2];
     R C[3];
     R s[3];
-    R Dchi[3][2];    // D chi, the per-phase weight of the mobility M
+    R Dt[3][2];    // D chi dt / (2 dx^2)
 };
 
 // Coefficients the FP64 diagnostics reduction needs.
@@ -57,6 +63,8 @@ constexpr int DV_MASS = 0, DV_VOL = 4, DV_MAXDEV = 10, DV_MINCHI = 11, DV_NONFIN
 
 int launch_step_f64(const StepLaunch& L, const Coef<double>& c, hipStream_t s);
 int launch_step_f32(const StepLaunch& L, const Coef<float>& c, hipStream_t s);
+template <typename R, bool D3>
+int launch_step_dim(const StepLaunch& L, const Coef<R>& c, hipStream_t s);
 
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
                 const DiagCoef& dc, double* ws, hipStream_t s);

@@ -1,0 +1,228 @@
+// 3D fused phi + mu step: xy tiles staged in an LDS ring of z planes.
+//
+// A block owns a 64 (x) by 4 (y) tile and walks a segment of z planes.  A
+// 4-slot LDS ring holds planes m-1, m, m+1 (plus the slot being filled): the
+// loads of plane m+2 are issued into registers before plane m is computed and
+// land in the free slot afterwards, so one barrier per plane suffices.  Each
+// staged cell also stores its scaled mobility M~ so that faces never recompute
+// h of a neighbour.  The z face between planes m and m+1 stays in registers
+// (its W, J) and becomes the lower face of plane m+1; in-plane faces are
+// evaluated by both of their cells with identical code and inputs.  Blocks are
+// dealt XCD-aware so that a band of tiles shares one XCD's L2.
+#pragma once
+
+#include "gp_device.hpp"
+
+namespace mp {
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY>
+__global__ void __launch_bounds__(BX * BY)
+k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, double tbase,
+         double tslope, int seg, int ntx, int nty) {
+    constexpr int NF = NP + NM;
+    constexpr int PW = BX + 2;
+    constexpr int PH = BY + 2;
+    constexpr int PP = PW * PH;
+    constexpr int NT = BX * BY;
+    constexpr int NPOS = (PP + NT - 1) / NT;
+    constexpr int NS = 4;
+    __shared__ R sv[NS][NF][PP];
+    __shared__ R sm[NS][NM][PP];
+
+    const int nb = gridDim.x;
+    const int q8 = nb / 8;
+    const int b = blockIdx.x;
+    const int tile = (b < 8 * q8) ? (b % 8) * q8 + b / 8 : b;
+    const int tx_i = tile % ntx;
+    const int rest = tile / ntx;
+    const int ty_i = rest % nty;
+    const int sg_i = rest / nty;
+
+    const int x0 = tx_i * BX;
+    const int y0 = ty_i * BY;
+    const int m0 = sg_i * seg;
+    const int m1 = min(m0 + seg, g.nz);
+    const bool perx = g.bcx == MP_BC_PERIODIC;
+    const bool pery = g.bcy == MP_BC_PERIODIC;
+    const bool perz = g.bcz == MP_BC_PERIODIC;
+    const int64_t sy = g.nx;
+    const int64_t sz = (int64_t)g.nx * g.ny;
+    const int64_t fs = g.fstride;
+
+    const int tid = threadIdx.x;
+    const int lx = tid % BX;
+    const int ly = tid / BX;
+
+    int64_t poff[NPOS];
+#pragma unroll
+    for (int k = 0; k < NPOS; ++k) {
+        int p = tid + k * NT;
+        if (p >= PP) p = PP - 1;
+        const int ix = p % PW, iy = p / PW;
+        poff[k] = gmap(x0 - 1 + ix, g.nx, perx) + gmap(y0 - 1 + iy, g.ny, pery) * sy;
+    }
+
+    R reg[NPOS][NF];
+    auto fetch = [&](int m) {
+        const int64_t mo = (int64_t)gmap(m, g.nz, perz) * sz;
+#pragma unroll
+        for (int k = 0; k < NPOS; ++k) {
+            if (tid + k * NT < PP) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) reg[k][f] = in[f * fs + mo + poff[k]];
+            }
+        }
+    };
+    auto stage = [&](int m) {
+        const int sl = (m + NS) & (NS - 1);
+#pragma unroll
+        for (int k = 0; k < NPOS; ++k) {
+            const int p = tid + k * NT;
+            if (p < PP) {
+                R ph[NP], hh[NP], Mt[NM];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) sv[sl][f][p] = reg[k][f];
+#pragma unroll
+                for (int a = 0; a < NP; ++a) ph[a] = reg[k][a];
+                interp_h<R, NP>(ph, hh);
+                mobility<R, NP, NM>(hh, c, Mt);
+#pragma unroll
+                for (int kk = 0; kk < NM; ++kk) sm[sl][kk][p] = Mt[kk];
+            }
+        }
+    };
+
+    // Face between (sL, pL) and (sR, pR); tangential axes given as (slot, offset)
+    // steps: dS*[t] is the slot step, dP*[t] the in-plane position step.
+    auto face = [&](int sL, int pL, int sR, int pR, const int (&tS)[2], const int (&tP)[2],
+                    R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
+        R phL[NP], phR[NP], uL[NM], uR[NM], mL[NM], mR[NM];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            phL[a] = sv[sL][a][pL];
+            phR[a] = sv[sR][a][pR];
+        }
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            uL[k] = sv[sL][NP + k][pL];
+            uR[k] = sv[sR][NP + k][pR];
+            mL[k] = sm[sL][k][pL];
+            mR[k] = sm[sR][k][pR];
+        }
+        R tau[2][NP];
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int sLp = (sL + tS[t] + NS) & (NS - 1), sLm = (sL - tS[t] + NS) & (NS - 1);
+                const int sRp = (sR + tS[t] + NS) & (NS - 1), sRm = (sR - tS[t] + NS) & (NS - 1);
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+                    tau[t][a] = (sv[sLp][a][pL + tP[t]] - sv[sLm][a][pL - tP[t]]) +
+                                (sv[sRp][a][pR + tP[t]] - sv[sRm][a][pR - tP[t]]);
+            }
+        }
+        face_core<R, NP, NM, ANISO, 2>(phL, phR, tau, mL, mR, uL, uR, c, U, Wf, J);
+    };
+
+    fetch(m0 - 1);
+    stage(m0 - 1);
+    fetch(m0);
+    stage(m0);
+    fetch(m0 + 1);
+    stage(m0 + 1);
+    __syncthreads();
+
+    const int pc = (ly + 1) * PW + (lx + 1);
+    const int gx = x0 + lx;
+    const int gy = y0 + ly;
+    const bool valid = gx < g.nx && gy < g.ny;
+    const R tt = (R)(tbase + tslope * (double)gy);  // T - Te depends on y only
+
+    // tangential steps: x faces see (y, z), y faces see (x, z), z faces see (x, y)
+    const int tSx[2] = {0, 1}, tPx[2] = {PW, 0};
+    const int tSy[2] = {0, 1}, tPy[2] = {1, 0};
+    const int tSz[2] = {0, 0}, tPz[2] = {1, PW};
+
+    R Wlo[NP], Jlo[NM];  // z face between planes m-1 and m
+    {
+        R Ud[NP];
+        const int s0 = (m0 + NS) & (NS - 1), sm1 = (m0 - 1 + NS) & (NS - 1);
+        face(sm1, pc, s0, pc, tSz, tPz, Ud, Wlo, Jlo);
+    }
+
+    for (int m = m0; m < m1; ++m) {
+        if (m + 2 <= m1) fetch(m + 2);
+        const int s0 = (m + NS) & (NS - 1);
+        const int sp1 = (m + 1) & (NS - 1);
+
+        R Gs[NP], Js[NM];
+        {
+            R Ul[NP], Wl[NP], Jl[NM], Uh[NP], Wh[NP], Jh[NM];
+            face(s0, pc - 1, s0, pc, tSx, tPx, Ul, Wl, Jl);
+            face(s0, pc, s0, pc + 1, tSx, tPx, Uh, Wh, Jh);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) Gs[a] = Uh[a] - Wl[a];
+#pragma unroll
+            for (int k = 0; k < NM; ++k) Js[k] = Jh[k] - Jl[k];
+        }
+        {
+            R Ul[NP], Wl[NP], Jl[NM], Uh[NP], Wh[NP], Jh[NM];
+            face(s0, pc - PW, s0, pc, tSy, tPy, Ul, Wl, Jl);
+            face(s0, pc, s0, pc + PW, tSy, tPy, Uh, Wh, Jh);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) Gs[a] = Gs[a] + (Uh[a] - Wl[a]);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) Js[k] = Js[k] + (Jh[k] - Jl[k]);
+        }
+        {
+            R Uh[NP], Wh[NP], Jh[NM];
+            face(s0, pc, sp1, pc, tSz, tPz, Uh, Wh, Jh);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                Gs[a] = Gs[a] + (Uh[a] - Wlo[a]);
+                Wlo[a] = Wh[a];
+            }
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                Js[k] = Js[k] + (Jh[k] - Jlo[k]);
+                Jlo[k] = Jh[k];
+            }
+        }
+
+        R phi[NP], mu[NM], h0[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) phi[a] = sv[s0][a][pc];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) mu[k] = sv[s0][NP + k][pc];
+        interp_h<R, NP>(phi, h0);
+        R phin[NP], mun[NM];
+        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, tt, c, phin, mun);
+
+        if (valid) {
+            const int64_t o = (int64_t)gx + (int64_t)gy * sy + (int64_t)m * sz;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) out[a * fs + o] = phin[a];
+#pragma unroll
+            for (int k = 0; k < NM; ++k) out[(NP + k) * fs + o] = mun[k];
+        }
+
+        if (m + 2 <= m1) stage(m + 2);
+        __syncthreads();
+    }
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int launch_3d(const StepLaunch& L, const Coef<R>& c, hipStream_t s) {
+    constexpr int BX = 64, BY = 4;
+    const int ntx = (L.g.nx + BX - 1) / BX;
+    const int nty = (L.g.ny + BY - 1) / BY;
+    const int nseg = (L.g.nz + L.seg - 1) / L.seg;
+    const long long nblocks = (long long)ntx * nty * nseg;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
+    hipLaunchKernelGGL((k_step3d<R, NP, NM, ANISO, OBST, BX, BY>), dim3((unsigned)nblocks),
+                       dim3(BX * BY), 0, s, (const R*)L.in, (R*)L.out, L.g, c, L.tbase, L.tslope,
+                       L.seg, ntx, nty);
+    return MP_OK;
+}
+
+}  // namespace mp

@@ -1,5 +1,5 @@
 // Kernel instances of the fused step: precision double, 3d.
-#include "step_kernel.hpp"
+#include "step_dispatch.hpp"
 
 namespace mp {
 template int launch_step_dim<double, true>(const StepLaunch&, const Coef<double>&, hipStream_t);
