@@ -125,9 +125,11 @@ size_t mp_state_bytes(const mp_state* st);
 size_t mp_workspace_bytes(const mp_state* st);
 
 /* Attach caller-owned device buffers: buf0 and buf1 each mp_state_bytes()
- * long, 256-byte aligned; workspace mp_workspace_bytes() long (FP64 partial
- * sums of the reductions).  buf0 is the current buffer afterwards and the
- * time level is reset to 0 (use mp_set_step to resume). */
+ * long, 256-byte aligned; workspace mp_workspace_bytes() long (reduction
+ * partial sums, the device copy of the time level and, for a batch, the
+ * instance table).  buf0 is the current buffer afterwards and the time level
+ * is reset to 0 (use mp_set_step to resume).  Needs the GPU: it writes the
+ * workspace with a synchronous copy. */
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
 
 /* Advance nsteps >= 0 forward-Euler steps on ``stream`` (asynchronous).
@@ -138,19 +140,51 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream);
 /* Which bound buffer (0 or 1) holds the current state, and its time level. */
 int mp_current(const mp_state* st, int* which_buf, int64_t* step);
 
-/* Declare that buffer ``which_buf`` holds the state at time level ``step``. */
+/* Declare that buffer ``which_buf`` holds the state at time level ``step``
+ * (updates the device copy of the time level synchronously when bound). */
 int mp_set_step(mp_state* st, int64_t step, int which_buf);
 
 /* Reduce the current state into *out (synchronises ``stream``).
- * Returns MP_E_NONFINITE (with *out filled) when a NaN/Inf is present. */
+ * Returns MP_E_NONFINITE (with *out filled) when a NaN/Inf is present, and
+ * MP_E_STATE for a batched state (use mp_diagnostics_batch). */
 int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
 
-/* Tile shape of the step kernel: block width bx (cells along x; 64, 128 or
- * 256 in 2D, 64 in 3D) and march length seg (planes per block along the
- * slowest axis, >= 1).  0 keeps the current value.  Results do not depend on
- * the tile shape (bitwise). */
+/* Tile shape of the step kernel.  2D: bx = threads per block (64, 128 or
+ * 256: 1, 2 or 4 independent strip waves) and seg = rows per strip segment.
+ * 3D: bx = 64 (64 x 4 tiles) and seg = z planes per block.  0 keeps the
+ * current value.  Results do not depend on the tile shape (bitwise). */
 int mp_set_tile(mp_state* st, int bx, int seg);
 int mp_get_tile(const mp_state* st, int* bx, int* seg);
+
+/* Replay steps as a HIP graph: chunk = steps per graph (even, >= 2), or 0 to
+ * launch kernel by kernel (the default).  The graph is built explicitly (no
+ * stream capture), so any stream works, the null stream included; it is
+ * rebuilt after mp_bind or mp_set_tile.  Results are bitwise those of the
+ * kernel-by-kernel path. */
+int mp_set_graph(mp_state* st, int chunk);
+
+/* Batched states (many independent 2D simulations stepped together by one
+ * persistent kernel launch per step; the north-star "batched ensemble").
+ * Instance i has grid grids[i] (dim must be 2), nphases[i] phases, ncomp[i]
+ * components and coefficients params[i], each validated as by mp_create
+ * (including its own dt limit).  All instances share precision and
+ * potential.  One state buffer holds every instance's state, each at a
+ * 256-byte aligned offset (mp_instance_offset) in the single-state layout.
+ * mp_step advances every instance by the same number of steps, each with its
+ * own dt; mp_diagnostics_batch reduces each instance.  Errors: as mp_create,
+ * plus MP_E_PARAM for ninst < 1, a 3D grid, or mixed precision/potential. */
+int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const int* ncomp,
+                    const mp_params* params, mp_state** out);
+
+/* Number of instances (1 for a state made by mp_create). */
+int mp_instance_count(const mp_state* st, int* ninst);
+
+/* Byte offset and size of instance i's state inside each state buffer. */
+int mp_instance_offset(const mp_state* st, int i, size_t* offset_bytes, size_t* nbytes);
+
+/* Per-instance diagnostics: out[i] for i < ninst (synchronises ``stream``).
+ * Returns MP_E_NONFINITE (with out filled) if any instance holds NaN/Inf. */
+int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream);
 
 /* Free host-side state (device buffers stay with the caller). NULL is a no-op. */
 void mp_destroy(mp_state* st);

@@ -371,8 +371,9 @@ def step_window(phi, mu, n, p, lo, hi):
     shape = phi.shape[1:]
     ix = [_ghost_index(lo[i], hi[i], shape[i], bcs[i]) for i in range(nd)]
     grid = np.ix_(*ix)
-    Pphi = phi[(slice(None),) + grid]
-    Pmu = mu[(slice(None),) + grid]
+    # promote (e.g. an FP32 state) so the window is stepped in FP64 or complex
+    Pphi = np.asarray(phi[(slice(None),) + grid], dtype=np.result_type(phi, np.float64))
+    Pmu = np.asarray(mu[(slice(None),) + grid], dtype=np.result_type(mu, np.float64))
     return _step_padded(Pphi, Pmu, n, p, y_origin=lo[-2])
 
 

@@ -30,7 +30,8 @@ ERROR_NAMES = {
 EXPORTS = [
     "mp_dt_limit", "mp_create", "mp_state_bytes", "mp_workspace_bytes", "mp_bind", "mp_step",
     "mp_current", "mp_set_step", "mp_diagnostics", "mp_set_tile", "mp_get_tile", "mp_destroy",
-    "mp_last_error",
+    "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
+    "mp_diagnostics_batch",
 ]
 
 
@@ -102,6 +103,17 @@ def lib():
         L.mp_destroy.argtypes = [vp]
         L.mp_last_error.restype = C.c_char_p
         L.mp_last_error.argtypes = []
+        L.mp_set_graph.restype = C.c_int
+        L.mp_set_graph.argtypes = [vp, C.c_int]
+        L.mp_create_batch.restype = C.c_int
+        L.mp_create_batch.argtypes = [C.c_int, C.POINTER(mp_grid), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int), C.POINTER(mp_params), C.POINTER(vp)]
+        L.mp_instance_count.restype = C.c_int
+        L.mp_instance_count.argtypes = [vp, C.POINTER(C.c_int)]
+        L.mp_instance_offset.restype = C.c_int
+        L.mp_instance_offset.argtypes = [vp, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.mp_diagnostics_batch.restype = C.c_int
+        L.mp_diagnostics_batch.argtypes = [vp, C.POINTER(mp_diag), vp]
         _lib = L
     return _lib
 
@@ -188,15 +200,56 @@ def mp_set_step(st, step: int, which_buf: int):
     _check(lib().mp_set_step(st, int(step), int(which_buf)))
 
 
+def _diag_dict(d) -> dict:
+    return {
+        "step": d.step, "nonfinite": d.nonfinite, "max_sum_dev": d.max_sum_dev,
+        "mass": list(d.mass), "volume": list(d.volume), "min_chi": list(d.min_chi),
+    }
+
+
 def mp_diagnostics(st, stream: int = 0, allow_nonfinite: bool = False) -> dict:
     d = mp_diag()
     rc = lib().mp_diagnostics(st, C.byref(d), stream)
     if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
         _check(rc)
-    return {
-        "step": d.step, "nonfinite": d.nonfinite, "max_sum_dev": d.max_sum_dev,
-        "mass": list(d.mass), "volume": list(d.volume), "min_chi": list(d.min_chi),
-    }
+    return _diag_dict(d)
+
+
+def mp_diagnostics_batch(st, stream: int = 0, allow_nonfinite: bool = False) -> list:
+    n = mp_instance_count(st)
+    arr = (mp_diag * n)()
+    rc = lib().mp_diagnostics_batch(st, arr, stream)
+    if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
+        _check(rc)
+    return [_diag_dict(arr[i]) for i in range(n)]
+
+
+def mp_create_batch(plist) -> int:
+    """One batched state for a list of 2D problems (inputs.Params); returns a handle."""
+    n = len(plist)
+    grids = (mp_grid * n)(*[to_grid(p) for p in plist])
+    params = (mp_params * n)(*[to_params(p) for p in plist])
+    nph = (C.c_int * n)(*[int(p.nphases) for p in plist])
+    ncp = (C.c_int * n)(*[int(p.ncomp) for p in plist])
+    h = C.c_void_p()
+    _check(lib().mp_create_batch(n, grids, nph, ncp, params, C.byref(h)))
+    return h.value
+
+
+def mp_instance_count(st) -> int:
+    n = C.c_int()
+    _check(lib().mp_instance_count(st, C.byref(n)))
+    return n.value
+
+
+def mp_instance_offset(st, i: int):
+    off, nb = C.c_size_t(), C.c_size_t()
+    _check(lib().mp_instance_offset(st, int(i), C.byref(off), C.byref(nb)))
+    return off.value, nb.value
+
+
+def mp_set_graph(st, chunk: int):
+    _check(lib().mp_set_graph(st, int(chunk)))
 
 
 def mp_set_tile(st, bx: int = 0, seg: int = 0):

@@ -1,8 +1,10 @@
 // Host side of the C ABI declared in include/mp.h: validation, coefficient
-// derivation, buffer bookkeeping and kernel dispatch.  mp_dt_limit,
-// mp_create, mp_state_bytes, mp_workspace_bytes, mp_set_tile/mp_get_tile,
-// mp_current/mp_set_step, mp_destroy and mp_last_error make no HIP call, so
-// they work on a machine without a GPU.
+// derivation, buffer bookkeeping, kernel dispatch, graph replay and batching.
+// mp_dt_limit, mp_create, mp_create_batch, mp_state_bytes,
+// mp_workspace_bytes, mp_get_tile, mp_set_graph, mp_current,
+// mp_instance_count/offset, mp_destroy and mp_last_error make no HIP call, so
+// they work on a machine without a GPU; mp_set_step and mp_set_tile touch the
+// device only once the state is bound.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -11,21 +13,43 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "mp_internal.hpp"
 
-struct mp_state {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Inst {
     mp_grid grid;
-    int N, K;  // phases, components (K - 1 diffusion potentials)
+    int N, K;
     mp_params prm;
-    double dt_lim;
+    bool aniso;
+    size_t off_bytes, bytes;  // within each state buffer
+};
+
+}  // namespace
+
+struct mp_state {
+    bool batch;
+    std::vector<Inst> inst;
+    int precision, potential;
+    bool aniso;
     void* buf[2];
     void* ws;
     bool bound;
     int cur;
     int64_t step;
     int bx, seg;
-    bool aniso;
+    int graph_chunk;
+    hipGraphExec_t gexec[2];  // by starting buffer
+    std::vector<mp::KernelCall> gcalls[2];  // argument records of each graph's nodes, kept alive
+    std::vector<int> item_inst;  // batch work list (host copy) for the current seg
+    int nitems;
+    int batch_blocks;
 };
 
 namespace {
@@ -49,10 +73,9 @@ int ok() {
 
 bool finite(double x) { return std::isfinite(x); }
 
-int nmu_of(const mp_state* st) { return st->K - 1; }
-int nfields_of(const mp_state* st) { return st->N + st->K - 1; }
-
 int64_t ncells_of(const mp_grid& g) { return g.n[0] * g.n[1] * g.n[2]; }
+
+size_t elem_of(int precision) { return precision == MP_FP64 ? sizeof(double) : sizeof(float); }
 
 int check_grid(const mp_grid* g) {
     if (!g) return fail(MP_E_NULLPTR, "grid is NULL");
@@ -129,10 +152,39 @@ double dt_limit_of(const mp_grid* g, int N, int K, const mp_params* p) {
     return lim;
 }
 
+// Full validation of one problem, as mp_create does it.
+int validate(const mp_grid* grid, int N, int K, const mp_params* p, const char* who) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    rc = check_params(N, K, p);
+    if (rc) return rc;
+    const double lim = dt_limit_of(grid, N, K, p);
+    if (p->dt > lim * (1.0 + 1e-12))
+        return fail(MP_E_UNSTABLE, "%sdt = %.17g exceeds the explicit stability limit %.17g", who,
+                    p->dt, lim);
+    if (ncells_of(*grid) * (N + K - 1) > ((int64_t)1 << 40)) return fail(MP_E_PARAM, "grid too large");
+    return MP_OK;
+}
+
+Inst make_inst(const mp_grid* g, int N, int K, const mp_params* p) {
+    Inst I;
+    I.grid = *g;
+    I.N = N;
+    I.K = K;
+    I.prm = *p;
+    I.aniso = false;
+    for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; ++b)
+            if (p->delta[a][b] != 0.0) I.aniso = true;
+    I.bytes = (size_t)ncells_of(*g) * (size_t)(N + K - 1) * elem_of(p->precision);
+    I.off_bytes = 0;
+    return I;
+}
+
 template <typename R>
-mp::Coef<R> make_coef(const mp_state* st) {
-    const mp_params& p = st->prm;
-    const double dx = st->grid.dx;
+mp::Coef<R> make_coef(const Inst& I) {
+    const mp_params& p = I.prm;
+    const double dx = I.grid.dx;
     mp::Coef<R> c;
     std::memset(&c, 0, sizeof c);
     c.cE = (R)(p.eps / (2.0 * dx));
@@ -150,10 +202,10 @@ mp::Coef<R> make_coef(const mp_state* st) {
     }
     c.gamma3 = (R)p.gamma3;
     const double dtf = p.dt / (2.0 * dx * dx);
-    for (int a = 0; a < st->N; ++a) {
+    for (int a = 0; a < I.N; ++a) {
         c.C[a] = (R)p.C[a];
         c.s[a] = (R)p.s[a];
-        for (int k = 0; k < st->K - 1; ++k) {
+        for (int k = 0; k < I.K - 1; ++k) {
             const double chi = 1.0 / (2.0 * p.A[a][k]);
             c.chi[a][k] = (R)chi;
             c.halfchi[a][k] = (R)(0.5 * chi);
@@ -164,16 +216,24 @@ mp::Coef<R> make_coef(const mp_state* st) {
     return c;
 }
 
-mp::Geom make_geom(const mp_state* st) {
+mp::Geom make_geom(const mp_grid& gr) {
     mp::Geom g;
-    g.nx = (int32_t)st->grid.n[0];
-    g.ny = (int32_t)st->grid.n[1];
-    g.nz = (int32_t)st->grid.n[2];
-    g.bcx = st->grid.bc[0];
-    g.bcy = st->grid.bc[1];
-    g.bcz = st->grid.bc[2];
-    g.fstride = ncells_of(st->grid);
+    g.nx = (int32_t)gr.n[0];
+    g.ny = (int32_t)gr.n[1];
+    g.nz = (int32_t)gr.n[2];
+    g.bcx = gr.bc[0];
+    g.bcy = gr.bc[1];
+    g.bcz = gr.bc[2];
+    g.fstride = ncells_of(gr);
     return g;
+}
+
+// T - Te at row j and step n: T0 + G (j dx - y0 - V n dt) - Te = tb0 + tdn n + tslope j
+void temperature_law(const Inst& I, double& tb0, double& tdn, double& tslope) {
+    const mp_params& p = I.prm;
+    tb0 = p.T0 - p.Te - p.G * p.y0;
+    tdn = -p.G * p.V * p.dt;
+    tslope = p.G * I.grid.dx;
 }
 
 int hip_check(hipError_t e, const char* what) {
@@ -181,14 +241,279 @@ int hip_check(hipError_t e, const char* what) {
     return MP_OK;
 }
 
+int strips_of(const Inst& I) { return (int)((I.grid.n[0] + mp::W2D_OUT_HOST - 1) / mp::W2D_OUT_HOST); }
+
+// ---- workspace layout -------------------------------------------------------
+// [diag partials + one result record per instance][time level][instance table][work list]
+size_t ws_diag_bytes(const mp_state* st) {
+    return align_up((size_t)(mp::DIAG_BLOCKS_MAX + st->inst.size()) * mp::DIAG_VALS * sizeof(double));
+}
+size_t ws_ctr_off(const mp_state* st) { return ws_diag_bytes(st); }
+size_t ws_table_off(const mp_state* st) { return ws_ctr_off(st) + kAlign; }
+size_t table_bytes(const mp_state* st) {
+    const size_t one =
+        st->precision == MP_FP64 ? sizeof(mp::InstDesc<double>) : sizeof(mp::InstDesc<float>);
+    return st->batch ? align_up(one * st->inst.size()) : 0;
+}
+size_t ws_items_off(const mp_state* st) { return ws_table_off(st) + table_bytes(st); }
+size_t items_capacity(const mp_state* st) {
+    if (!st->batch) return 0;
+    size_t n = 0;  // the work list is longest at seg = 1: one item per strip and row
+    for (const Inst& I : st->inst) n += (size_t)strips_of(I) * (size_t)I.grid.n[1];
+    return n;
+}
+
+int64_t* dev_ctr(mp_state* st) { return (int64_t*)((char*)st->ws + ws_ctr_off(st)); }
+
+void drop_graphs(mp_state* st) {
+    for (int p = 0; p < 2; ++p) {
+        if (st->gexec[p]) {
+            (void)hipGraphExecDestroy(st->gexec[p]);
+            st->gexec[p] = nullptr;
+        }
+        st->gcalls[p].clear();
+    }
+}
+
+void build_items(mp_state* st) {
+    st->item_inst.clear();
+    for (size_t i = 0; i < st->inst.size(); ++i) {
+        const Inst& I = st->inst[i];
+        const int nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
+        st->item_inst.insert(st->item_inst.end(), (size_t)strips_of(I) * nseg, (int)i);
+    }
+    st->nitems = (int)st->item_inst.size();
+}
+
+template <typename R>
+int upload_table(mp_state* st) {
+    std::vector<mp::InstDesc<R>> tab(st->inst.size());
+    int item0 = 0;
+    for (size_t i = 0; i < st->inst.size(); ++i) {
+        const Inst& I = st->inst[i];
+        mp::InstDesc<R>& d = tab[i];
+        std::memset(&d, 0, sizeof d);
+        d.g = make_geom(I.grid);
+        d.np = I.N;
+        d.nm = I.K - 1;
+        d.ntx = strips_of(I);
+        d.seg = st->seg;
+        d.nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
+        d.item0 = item0;
+        item0 += d.ntx * d.nseg;
+        d.off = (int64_t)(I.off_bytes / sizeof(R));
+        temperature_law(I, d.tb0, d.tdn, d.tslope);
+        d.c = make_coef<R>(I);
+    }
+    char* ws = (char*)st->ws;
+    int rc = hip_check(hipMemcpy(ws + ws_table_off(st), tab.data(),
+                                 sizeof(mp::InstDesc<R>) * tab.size(), hipMemcpyHostToDevice),
+                       "instance table upload");
+    if (rc) return rc;
+    return hip_check(hipMemcpy(ws + ws_items_off(st), st->item_inst.data(),
+                               sizeof(int) * st->item_inst.size(), hipMemcpyHostToDevice),
+                     "work list upload");
+}
+
+int choose_batch_blocks(mp_state* st) {
+    int dev = 0, cus = 0, per = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (rc) return rc;
+    mp::BatchLaunch L;
+    std::memset(&L, 0, sizeof L);
+    L.potential = st->potential;
+    L.aniso = st->aniso ? 1 : 0;
+    L.nblocks = 8;
+    mp::KernelCall k;
+    rc = st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
+    if (rc) return fail(rc, "no batched kernel instance");
+    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k.func, (int)k.block.x, 0),
+                   "occupancy query");
+    if (rc) return rc;
+    if (per < 1) per = 1;
+    long long nb = (long long)cus * per;
+    const long long need = (st->nitems + mp::BATCH_WPB_HOST - 1) / mp::BATCH_WPB_HOST;
+    if (nb > need) nb = need;
+    nb = (nb + 7) / 8 * 8;
+    if (nb < 8) nb = 8;
+    st->batch_blocks = (int)nb;
+    return MP_OK;
+}
+
+int sync_batch(mp_state* st) {
+    build_items(st);
+    if (!st->bound) return MP_OK;
+    const int rc = st->precision == MP_FP64 ? upload_table<double>(st) : upload_table<float>(st);
+    if (rc) return rc;
+    return choose_batch_blocks(st);
+}
+
+// One step launch; kstep is the launch's offset from the device time level.
+int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
+    if (st->batch) {
+        mp::BatchLaunch L;
+        L.in = st->buf[from];
+        L.out = st->buf[1 - from];
+        L.table = (const char*)st->ws + ws_table_off(st);
+        L.item_inst = (const int*)((const char*)st->ws + ws_items_off(st));
+        L.nitems = st->nitems;
+        L.potential = st->potential;
+        L.aniso = st->aniso ? 1 : 0;
+        L.nblocks = st->batch_blocks;
+        L.stepctr = dev_ctr(st);
+        L.kstep = kstep;
+        return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
+    }
+    const Inst& I = st->inst[0];
+    mp::StepLaunch L;
+    L.in = st->buf[from];
+    L.out = st->buf[1 - from];
+    L.g = make_geom(I.grid);
+    L.nphases = I.N;
+    L.nmu = I.K - 1;
+    L.dim = I.grid.dim;
+    L.potential = I.prm.potential;
+    L.aniso = I.aniso ? 1 : 0;
+    L.bx = st->bx;
+    L.seg = st->seg;
+    L.stepctr = dev_ctr(st);
+    L.kstep = kstep;
+    temperature_law(I, L.tb0, L.tdn, L.tslope);
+    if (st->precision == MP_FP64) return mp::call_step_f64(L, make_coef<double>(I), k);
+    return mp::call_step_f32(L, make_coef<float>(I), k);
+}
+
+int launch(const mp::KernelCall& k, hipStream_t s) {
+    return hip_check(hipLaunchKernel(k.func, k.grid, k.block, (void**)k.args, 0, s), "kernel launch");
+}
+
+// Graph of graph_chunk steps starting from buffer `from`, then the time-level advance.
+int build_graph(mp_state* st, int from, hipGraphExec_t* out) {
+    std::vector<mp::KernelCall>& calls = st->gcalls[from];
+    calls.assign((size_t)st->graph_chunk + 1, mp::KernelCall());
+    for (int i = 0; i <= st->graph_chunk; ++i) {
+        if (i < st->graph_chunk) {
+            const int rc = make_step_call(st, i, (from + i) & 1, calls[i]);
+            if (rc) return fail(rc, "no kernel instance for this configuration");
+        } else {
+            mp::call_advance(dev_ctr(st), st->graph_chunk, calls[i]);
+        }
+    }
+    hipGraph_t g = nullptr;
+    int rc = hip_check(hipGraphCreate(&g, 0), "hipGraphCreate");
+    if (rc) return rc;
+    hipGraphNode_t prev = nullptr;
+    for (size_t i = 0; i < calls.size() && rc == MP_OK; ++i) {
+        const mp::KernelCall& k = calls[i];
+        hipKernelNodeParams np;
+        std::memset(&np, 0, sizeof np);
+        np.func = (void*)k.func;
+        np.gridDim = k.grid;
+        np.blockDim = k.block;
+        np.sharedMemBytes = 0;
+        np.kernelParams = (void**)k.args;
+        np.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        rc = hip_check(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np),
+                       "hipGraphAddKernelNode");
+        prev = node;
+    }
+    if (rc == MP_OK)
+        rc = hip_check(hipGraphInstantiate(out, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(g);
+    return rc;
+}
+
+void init_state(mp_state* st) {
+    st->buf[0] = st->buf[1] = nullptr;
+    st->ws = nullptr;
+    st->bound = false;
+    st->cur = 0;
+    st->step = 0;
+    st->graph_chunk = 0;
+    st->gexec[0] = st->gexec[1] = nullptr;
+    st->nitems = 0;
+    st->batch_blocks = 0;
+    st->aniso = false;
+    for (const Inst& I : st->inst) st->aniso = st->aniso || I.aniso;
+    st->precision = st->inst[0].prm.precision;
+    st->potential = st->inst[0].prm.potential;
+    if (st->inst[0].grid.dim == 3) {
+        st->bx = 64;
+        st->seg = 16;
+    } else {
+        // measured best on 4096^2 (both precisions): short segments keep enough
+        // waves in flight to cover HBM latency
+        st->bx = st->batch ? 64 * mp::BATCH_WPB_HOST : 256;
+        st->seg = 16;
+    }
+}
+
+int diag_instance(mp_state* st, int i, hipStream_t s) {
+    const Inst& I = st->inst[i];
+    mp::DiagCoef dc;
+    std::memset(&dc, 0, sizeof dc);
+    for (int a = 0; a < I.N; ++a)
+        for (int k = 0; k < I.K - 1; ++k) {
+            dc.chi[a][k] = 1.0 / (2.0 * I.prm.A[a][k]);
+            dc.B[a][k] = I.prm.B[a][k];
+        }
+    dc.vol = std::pow(I.grid.dx, I.grid.dim);
+    double* ws = (double*)st->ws;
+    const void* state = (const char*)st->buf[st->cur] + I.off_bytes;
+    int rc = mp::launch_diag(state, st->precision, make_geom(I.grid), I.N, I.K - 1, dc, ws,
+                             ws + (size_t)(mp::DIAG_BLOCKS_MAX + i) * mp::DIAG_VALS, s);
+    if (rc) return fail(rc, "no diagnostics instance");
+    return hip_check(hipGetLastError(), "diagnostics launch");
+}
+
+void unpack_diag(const mp_state* st, int i, const double* r, mp_diag* out) {
+    const Inst& I = st->inst[i];
+    std::memset(out, 0, sizeof *out);
+    out->step = st->step;
+    for (int k = 0; k < I.K - 1; ++k) {
+        out->mass[k] = r[mp::DV_MASS + 2 * k] + r[mp::DV_MASS + 2 * k + 1];
+        out->min_chi[k] = r[mp::DV_MINCHI + k];
+    }
+    for (int a = 0; a < I.N; ++a) out->volume[a] = r[mp::DV_VOL + 2 * a] + r[mp::DV_VOL + 2 * a + 1];
+    out->max_sum_dev = r[mp::DV_MAXDEV];
+    out->nonfinite = (int64_t)r[mp::DV_NONFIN];
+}
+
+int diag_many(mp_state* st, mp_diag* out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)st->inst.size();
+    for (int i = 0; i < n; ++i) {
+        const int rc = diag_instance(st, i, s);
+        if (rc) return rc;
+    }
+    std::vector<double> r((size_t)n * mp::DIAG_VALS);
+    int rc = hip_check(hipMemcpyAsync(r.data(),
+                                      (double*)st->ws + (size_t)mp::DIAG_BLOCKS_MAX * mp::DIAG_VALS,
+                                      sizeof(double) * r.size(), hipMemcpyDeviceToHost, s),
+                       "diagnostics copy");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(s), "diagnostics sync");
+    if (rc) return rc;
+    int64_t bad = 0;
+    for (int i = 0; i < n; ++i) {
+        unpack_diag(st, i, &r[(size_t)i * mp::DIAG_VALS], &out[i]);
+        bad += out[i].nonfinite;
+    }
+    if (bad > 0) return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)bad);
+    return ok();
+}
+
 }  // namespace
 
 namespace mp {
-int launch_step_f64(const StepLaunch& L, const Coef<double>& c, hipStream_t s) {
-    return L.dim == 3 ? launch_step_dim<double, true>(L, c, s) : launch_step_dim<double, false>(L, c, s);
+int call_step_f64(const StepLaunch& L, const Coef<double>& c, KernelCall& k) {
+    return L.dim == 3 ? call_step_dim<double, true>(L, c, k) : call_step_dim<double, false>(L, c, k);
 }
-int launch_step_f32(const StepLaunch& L, const Coef<float>& c, hipStream_t s) {
-    return L.dim == 3 ? launch_step_dim<float, true>(L, c, s) : launch_step_dim<float, false>(L, c, s);
+int call_step_f32(const StepLaunch& L, const Coef<float>& c, KernelCall& k) {
+    return L.dim == 3 ? call_step_dim<float, true>(L, c, k) : call_step_dim<float, false>(L, c, k);
 }
 }  // namespace mp
 
@@ -204,69 +529,84 @@ double mp_dt_limit(const mp_grid* grid, int nphases, int ncomp, const mp_params*
 int mp_create(const mp_grid* grid, int nphases, int ncomp, const mp_params* params, mp_state** out) {
     if (!out) return fail(MP_E_NULLPTR, "out is NULL");
     *out = nullptr;
-    int rc = check_grid(grid);
+    const int rc = validate(grid, nphases, ncomp, params, "");
     if (rc) return rc;
-    rc = check_params(nphases, ncomp, params);
-    if (rc) return rc;
-    const double lim = dt_limit_of(grid, nphases, ncomp, params);
-    if (params->dt > lim * (1.0 + 1e-12))
-        return fail(MP_E_UNSTABLE, "dt = %.17g exceeds the explicit stability limit %.17g",
-                    params->dt, lim);
-    const int64_t nc = ncells_of(*grid);
-    if (nc * (nphases + ncomp - 1) > ((int64_t)1 << 40))
-        return fail(MP_E_PARAM, "grid too large");
     mp_state* st = new (std::nothrow) mp_state();
     if (!st) return fail(MP_E_PARAM, "out of host memory");
-    st->grid = *grid;
-    st->N = nphases;
-    st->K = ncomp;
-    st->prm = *params;
-    st->dt_lim = lim;
-    st->buf[0] = st->buf[1] = nullptr;
-    st->ws = nullptr;
-    st->bound = false;
-    st->cur = 0;
-    st->step = 0;
-    st->aniso = false;
-    for (int a = 0; a < nphases; ++a)
-        for (int b = a + 1; b < nphases; ++b)
-            if (params->delta[a][b] != 0.0) st->aniso = true;
-    if (grid->dim == 3) {
-        st->bx = 64;
-        st->seg = 16;
-    } else {
-        // measured best on 4096^2 (both precisions): short segments keep enough
-        // waves in flight to cover HBM latency
-        st->bx = 256;
-        st->seg = 16;
+    st->batch = false;
+    st->inst.push_back(make_inst(grid, nphases, ncomp, params));
+    init_state(st);
+    *out = st;
+    return ok();
+}
+
+int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const int* ncomp,
+                    const mp_params* params, mp_state** out) {
+    if (!out) return fail(MP_E_NULLPTR, "out is NULL");
+    *out = nullptr;
+    if (ninst < 1) return fail(MP_E_PARAM, "ninst must be >= 1");
+    if (!grids || !nphases || !ncomp || !params) return fail(MP_E_NULLPTR, "batch array is NULL");
+    mp_state* st = new (std::nothrow) mp_state();
+    if (!st) return fail(MP_E_PARAM, "out of host memory");
+    st->batch = true;
+    size_t off = 0;
+    for (int i = 0; i < ninst; ++i) {
+        char who[64];
+        snprintf(who, sizeof who, "instance %d: ", i);
+        int rc = validate(&grids[i], nphases[i], ncomp[i], &params[i], who);
+        if (rc == MP_OK && grids[i].dim != 2) rc = fail(MP_E_PARAM, "%sbatched grids must be 2D", who);
+        if (rc == MP_OK && i > 0 && params[i].precision != params[0].precision)
+            rc = fail(MP_E_PARAM, "%sall instances must share one precision", who);
+        if (rc == MP_OK && i > 0 && params[i].potential != params[0].potential)
+            rc = fail(MP_E_PARAM, "%sall instances must share one potential", who);
+        if (rc) {
+            delete st;
+            return rc;
+        }
+        Inst I = make_inst(&grids[i], nphases[i], ncomp[i], &params[i]);
+        I.off_bytes = off;
+        off = align_up(off + I.bytes);
+        st->inst.push_back(I);
     }
+    init_state(st);
+    build_items(st);
     *out = st;
     return ok();
 }
 
 size_t mp_state_bytes(const mp_state* st) {
     if (!st) return 0;
-    const size_t el = st->prm.precision == MP_FP64 ? sizeof(double) : sizeof(float);
-    return (size_t)ncells_of(st->grid) * (size_t)nfields_of(st) * el;
+    if (!st->batch) return st->inst[0].bytes;
+    const Inst& L = st->inst.back();
+    return align_up(L.off_bytes + L.bytes);
 }
 
 size_t mp_workspace_bytes(const mp_state* st) {
     if (!st) return 0;
-    return (size_t)(mp::DIAG_BLOCKS_MAX + 1) * mp::DIAG_VALS * sizeof(double);
+    return ws_items_off(st) + align_up(sizeof(int) * items_capacity(st));
 }
 
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (!buf0 || !buf1 || !workspace) return fail(MP_E_NULLPTR, "buffer pointer is NULL");
     if (buf0 == buf1) return fail(MP_E_PARAM, "buf0 and buf1 must differ");
-    if (((uintptr_t)buf0 | (uintptr_t)buf1 | (uintptr_t)workspace) & 255u)
+    if (((uintptr_t)buf0 | (uintptr_t)buf1 | (uintptr_t)workspace) & (kAlign - 1))
         return fail(MP_E_PARAM, "buffers must be 256-byte aligned");
+    drop_graphs(st);
     st->buf[0] = buf0;
     st->buf[1] = buf1;
     st->ws = workspace;
     st->bound = true;
     st->cur = 0;
     st->step = 0;
+    int64_t zero = 0;
+    int rc = hip_check(hipMemcpy(dev_ctr(st), &zero, sizeof zero, hipMemcpyHostToDevice),
+                       "time level upload");
+    if (rc == MP_OK && st->batch) rc = sync_batch(st);
+    if (rc) {
+        st->bound = false;
+        return rc;
+    }
     return ok();
 }
 
@@ -275,36 +615,34 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_step before mp_bind");
     if (nsteps < 0) return fail(MP_E_PARAM, "nsteps must be >= 0");
     hipStream_t s = (hipStream_t)stream;
-    mp::StepLaunch L;
-    L.g = make_geom(st);
-    L.nphases = st->N;
-    L.nmu = nmu_of(st);
-    L.dim = st->grid.dim;
-    L.potential = st->prm.potential;
-    L.aniso = st->aniso ? 1 : 0;
-    L.bx = st->bx;
-    L.seg = st->seg;
-    const mp_params& p = st->prm;
-    const bool f64 = p.precision == MP_FP64;
-    mp::Coef<double> cd;
-    mp::Coef<float> cf;
-    if (f64)
-        cd = make_coef<double>(st);
-    else
-        cf = make_coef<float>(st);
-    for (int64_t i = 0; i < nsteps; ++i) {
-        const double t = (double)(st->step) * p.dt;
-        // T(y) - Te = T0 + G (j dx - y0 - V t) - Te
-        L.tbase = p.T0 - p.Te - p.G * (p.y0 + p.V * t);
-        L.tslope = p.G * st->grid.dx;
-        L.in = st->buf[st->cur];
-        L.out = st->buf[1 - st->cur];
-        const int rc = f64 ? mp::launch_step_f64(L, cd, s) : mp::launch_step_f32(L, cf, s);
+    int64_t left = nsteps;
+    const int C = st->graph_chunk;
+    if (C > 0) {
+        while (left >= C) {
+            if (!st->gexec[st->cur]) {
+                const int rc = build_graph(st, st->cur, &st->gexec[st->cur]);
+                if (rc) return rc;
+            }
+            const int rc = hip_check(hipGraphLaunch(st->gexec[st->cur], s), "hipGraphLaunch");
+            if (rc) return rc;
+            left -= C;  // C is even: the current buffer is unchanged
+            st->step += C;
+        }
+    }
+    for (int64_t i = 0; i < left; ++i) {
+        mp::KernelCall k;
+        int rc = make_step_call(st, (int)i, st->cur, k);
         if (rc) return fail(rc, "no kernel instance for this configuration");
-        const int hr = hip_check(hipGetLastError(), "step kernel launch");
-        if (hr) return hr;
+        rc = launch(k, s);
+        if (rc) return rc;
         st->cur = 1 - st->cur;
-        st->step += 1;
+    }
+    if (left > 0) {
+        mp::KernelCall k;
+        mp::call_advance(dev_ctr(st), left, k);
+        const int rc = launch(k, s);
+        if (rc) return rc;
+        st->step += left;
     }
     return ok();
 }
@@ -320,6 +658,11 @@ int mp_set_step(mp_state* st, int64_t step, int which_buf) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (which_buf != 0 && which_buf != 1) return fail(MP_E_PARAM, "which_buf must be 0 or 1");
     if (step < 0) return fail(MP_E_PARAM, "step must be >= 0");
+    if (st->bound) {
+        const int rc = hip_check(hipMemcpy(dev_ctr(st), &step, sizeof step, hipMemcpyHostToDevice),
+                                 "time level upload");
+        if (rc) return rc;
+    }
     st->step = step;
     st->cur = which_buf;
     return ok();
@@ -327,53 +670,34 @@ int mp_set_step(mp_state* st, int64_t step, int which_buf) {
 
 int mp_diagnostics(mp_state* st, mp_diag* out, void* stream) {
     if (!st || !out) return fail(MP_E_NULLPTR, "state or out is NULL");
+    if (st->batch) return fail(MP_E_STATE, "batched state: use mp_diagnostics_batch");
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_diagnostics before mp_bind");
-    hipStream_t s = (hipStream_t)stream;
-    mp::DiagCoef dc;
-    std::memset(&dc, 0, sizeof dc);
-    for (int a = 0; a < st->N; ++a)
-        for (int k = 0; k < st->K - 1; ++k) {
-            dc.chi[a][k] = 1.0 / (2.0 * st->prm.A[a][k]);
-            dc.B[a][k] = st->prm.B[a][k];
-        }
-    dc.vol = std::pow(st->grid.dx, st->grid.dim);
-    mp::Geom g = make_geom(st);
-    double* ws = (double*)st->ws;
-    int rc = mp::launch_diag(st->buf[st->cur], st->prm.precision, g, st->N, nmu_of(st), dc, ws, s);
-    if (rc) return fail(rc, "no diagnostics instance");
-    rc = hip_check(hipGetLastError(), "diagnostics launch");
-    if (rc) return rc;
-    double r[mp::DIAG_VALS];
-    rc = hip_check(hipMemcpyAsync(r, ws + (size_t)mp::DIAG_BLOCKS_MAX * mp::DIAG_VALS, sizeof r,
-                                  hipMemcpyDeviceToHost, s),
-                   "diagnostics copy");
-    if (rc) return rc;
-    rc = hip_check(hipStreamSynchronize(s), "diagnostics sync");
-    if (rc) return rc;
-    std::memset(out, 0, sizeof *out);
-    out->step = st->step;
-    for (int k = 0; k < nmu_of(st); ++k) {
-        out->mass[k] = r[mp::DV_MASS + 2 * k] + r[mp::DV_MASS + 2 * k + 1];
-        out->min_chi[k] = r[mp::DV_MINCHI + k];
-    }
-    for (int a = 0; a < st->N; ++a) out->volume[a] = r[mp::DV_VOL + 2 * a] + r[mp::DV_VOL + 2 * a + 1];
-    out->max_sum_dev = r[mp::DV_MAXDEV];
-    out->nonfinite = (int64_t)r[mp::DV_NONFIN];
-    if (out->nonfinite > 0)
-        return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)out->nonfinite);
-    return ok();
+    return diag_many(st, out, stream);
+}
+
+int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream) {
+    if (!st || !out) return fail(MP_E_NULLPTR, "state or out is NULL");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_diagnostics_batch before mp_bind");
+    return diag_many(st, out, stream);
 }
 
 int mp_set_tile(mp_state* st, int bx, int seg) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    const bool d3 = st->inst[0].grid.dim == 3;
     if (bx) {
-        const bool okbx = st->grid.dim == 3 ? bx == 64 : (bx == 64 || bx == 128 || bx == 256);
+        bool okbx = d3 ? bx == 64 : (bx == 64 || bx == 128 || bx == 256);
+        if (st->batch) okbx = bx == 64 * mp::BATCH_WPB_HOST;
         if (!okbx) return fail(MP_E_PARAM, "unsupported tile width %d", bx);
-        st->bx = bx;
     }
+    if (seg < 0) return fail(MP_E_PARAM, "seg must be >= 1");
+    drop_graphs(st);
+    if (bx) st->bx = bx;
     if (seg) {
-        if (seg < 1) return fail(MP_E_PARAM, "seg must be >= 1");
         st->seg = seg;
+        if (st->batch) {
+            const int rc = sync_batch(st);
+            if (rc) return rc;
+        }
     }
     return ok();
 }
@@ -385,7 +709,34 @@ int mp_get_tile(const mp_state* st, int* bx, int* seg) {
     return ok();
 }
 
-void mp_destroy(mp_state* st) { delete st; }
+int mp_set_graph(mp_state* st, int chunk) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (chunk < 0 || (chunk > 0 && (chunk < 2 || chunk % 2)))
+        return fail(MP_E_PARAM, "graph chunk must be 0 or an even number >= 2 (got %d)", chunk);
+    drop_graphs(st);
+    st->graph_chunk = chunk;
+    return ok();
+}
+
+int mp_instance_count(const mp_state* st, int* ninst) {
+    if (!st || !ninst) return fail(MP_E_NULLPTR, "state or ninst is NULL");
+    *ninst = (int)st->inst.size();
+    return ok();
+}
+
+int mp_instance_offset(const mp_state* st, int i, size_t* offset_bytes, size_t* nbytes) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (i < 0 || i >= (int)st->inst.size()) return fail(MP_E_PARAM, "instance %d out of range", i);
+    if (offset_bytes) *offset_bytes = st->inst[i].off_bytes;
+    if (nbytes) *nbytes = st->inst[i].bytes;
+    return ok();
+}
+
+void mp_destroy(mp_state* st) {
+    if (!st) return;
+    drop_graphs(st);
+    delete st;
+}
 
 const char* mp_last_error(void) { return g_err.c_str(); }
 

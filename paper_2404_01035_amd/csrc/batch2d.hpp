@@ -1,0 +1,79 @@
+// Batched 2D step: many independent simulations in one persistent launch.
+//
+// The work list holds one item per (instance, 62-column strip, row segment),
+// instance by instance; item_inst[i] names the instance of item i and the
+// instance table (InstDesc) carries its grid, sizes, coefficients, state
+// offset and temperature law.  The grid is sized to what stays resident; each
+// wave walks items with a fixed stride (deterministic), inside the contiguous
+// slice of the list given to its XCD, so a strip's neighbours tend to share an
+// L2.  Each item runs the same strip function as the single-grid kernel, so a
+// batched instance is stepped bit for bit like a single one.
+#pragma once
+
+#include "step2d.hpp"
+
+namespace mp {
+
+constexpr int BATCH_WPB = BATCH_WPB_HOST;  // waves per block
+
+template <typename R, bool ANISO, bool OBST>
+__global__ void __launch_bounds__(64 * BATCH_WPB)
+k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __restrict__ tab,
+          const int* __restrict__ item_inst, int nitems, const int64_t* __restrict__ stepctr,
+          int kstep) {
+    const int nb = gridDim.x;  // a multiple of 8
+    const int b = blockIdx.x;
+    const int xcd = b % 8;
+    const int wpx = (nb / 8) * BATCH_WPB;  // waves per XCD
+    const int rank = __builtin_amdgcn_readfirstlane((b / 8) * BATCH_WPB + (threadIdx.x >> 6));
+    const int lo = (int)((long long)nitems * xcd / 8);
+    const int hi = (int)((long long)nitems * (xcd + 1) / 8);
+    const int64_t n = *stepctr + kstep;
+    for (int it = lo + rank; it < hi; it += wpx) {
+        const int inst = __builtin_amdgcn_readfirstlane(item_inst[it]);
+        const InstDesc<R>& d = tab[inst];
+        const int local = it - d.item0;
+        const int tx = local % d.ntx;
+        const int m0 = (local / d.ntx) * d.seg;
+        const int m1 = min(m0 + d.seg, d.g.ny);
+        const double tbase = d.tb0 + d.tdn * (double)n;
+        const R* src = in + d.off;
+        R* dst = out + d.off;
+        switch (d.np * 4 + d.nm) {
+            case 2 * 4 + 1:
+                strip2d<R, 2, 1, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+                break;
+            case 2 * 4 + 2:
+                strip2d<R, 2, 2, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+                break;
+            case 3 * 4 + 1:
+                strip2d<R, 3, 1, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+                break;
+            default:
+                strip2d<R, 3, 2, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+                break;
+        }
+    }
+}
+
+template <typename R>
+int call_batch(const BatchLaunch& L, KernelCall& k) {
+    const bool obst = L.potential == MP_OBSTACLE;
+    if (L.aniso)
+        k.func = obst ? (const void*)&k_batch2d<R, true, true> : (const void*)&k_batch2d<R, true, false>;
+    else
+        k.func = obst ? (const void*)&k_batch2d<R, false, true> : (const void*)&k_batch2d<R, false, false>;
+    if (L.nblocks <= 0 || L.nblocks % 8) return MP_E_PARAM;
+    k.grid = dim3((unsigned)L.nblocks);
+    k.block = dim3(64 * BATCH_WPB);
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg((const InstDesc<R>*)L.table);
+    k.arg(L.item_inst);
+    k.arg(L.nitems);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    return MP_OK;
+}
+
+}  // namespace mp

@@ -161,22 +161,22 @@ __global__ void __launch_bounds__(DT) k_diag_final(const double* __restrict__ pa
 }
 
 template <typename R, int NP, int NM>
-int launch_diag_t(const void* state, const Geom& g, const DiagCoef& dc, double* ws, hipStream_t s) {
+int launch_diag_t(const void* state, const Geom& g, const DiagCoef& dc, double* partials,
+                  double* result, hipStream_t s) {
     const int64_t n = g.fstride;
     const int nb = diag_blocks(n);
-    hipLaunchKernelGGL((k_diag<R, NP, NM>), dim3(nb), dim3(DT), 0, s, (const R*)state, n, dc, ws);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DT), 0, s, (const double*)ws, nb,
-                       ws + (int64_t)DIAG_BLOCKS_MAX * DIAG_VALS);
+    hipLaunchKernelGGL((k_diag<R, NP, NM>), dim3(nb), dim3(DT), 0, s, (const R*)state, n, dc, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DT), 0, s, (const double*)partials, nb, result);
     return MP_OK;
 }
 
 template <typename R>
-int launch_diag_r(const void* state, const Geom& g, int np, int nm, const DiagCoef& dc, double* ws,
-                  hipStream_t s) {
-    if (np == 2 && nm == 1) return launch_diag_t<R, 2, 1>(state, g, dc, ws, s);
-    if (np == 2 && nm == 2) return launch_diag_t<R, 2, 2>(state, g, dc, ws, s);
-    if (np == 3 && nm == 1) return launch_diag_t<R, 3, 1>(state, g, dc, ws, s);
-    if (np == 3 && nm == 2) return launch_diag_t<R, 3, 2>(state, g, dc, ws, s);
+int launch_diag_r(const void* state, const Geom& g, int np, int nm, const DiagCoef& dc,
+                  double* partials, double* result, hipStream_t s) {
+    if (np == 2 && nm == 1) return launch_diag_t<R, 2, 1>(state, g, dc, partials, result, s);
+    if (np == 2 && nm == 2) return launch_diag_t<R, 2, 2>(state, g, dc, partials, result, s);
+    if (np == 3 && nm == 1) return launch_diag_t<R, 3, 1>(state, g, dc, partials, result, s);
+    if (np == 3 && nm == 2) return launch_diag_t<R, 3, 2>(state, g, dc, partials, result, s);
     return MP_E_PARAM;
 }
 
@@ -190,9 +190,10 @@ int diag_blocks(int64_t ncells) {
 }
 
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
-                const DiagCoef& dc, double* ws, hipStream_t s) {
-    if (precision == MP_FP64) return launch_diag_r<double>(state, g, nphases, nmu, dc, ws, s);
-    return launch_diag_r<float>(state, g, nphases, nmu, dc, ws, s);
+                const DiagCoef& dc, double* partials, double* result, hipStream_t s) {
+    if (precision == MP_FP64)
+        return launch_diag_r<double>(state, g, nphases, nmu, dc, partials, result, s);
+    return launch_diag_r<float>(state, g, nphases, nmu, dc, partials, result, s);
 }
 
 }  // namespace mp

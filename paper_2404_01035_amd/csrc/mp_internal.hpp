@@ -46,14 +46,60 @@ struct DiagCoef {
     double vol;      // dx^d
 };
 
-// One launch of the fused step kernel.
+// One launch of the fused step kernel.  The time level of the launch is
+// *stepctr + kstep (the counter lives in device memory so that a replayed
+// graph of launches stays correct); T - Te at row j is
+// tb0 + tdn * n + tslope * j.
 struct StepLaunch {
     const void* in;
     void* out;
     Geom g;
     int nphases, nmu, dim, potential, aniso;
     int bx, seg;
-    double tbase, tslope;  // T(y) - Te = tbase + tslope * j for row j at this step
+    const int64_t* stepctr;
+    int kstep;
+    double tb0, tdn, tslope;
+};
+
+// A kernel launch described as data: launched directly or added to a graph.
+struct KernelCall {
+    const void* func = nullptr;
+    dim3 grid, block;
+    alignas(16) unsigned char store[1024];
+    size_t used = 0;
+    void* args[16];
+    int nargs = 0;
+    template <typename T>
+    void arg(const T& v) {
+        used = (used + alignof(T) - 1) / alignof(T) * alignof(T);
+        __builtin_memcpy(store + used, &v, sizeof(T));
+        args[nargs++] = store + used;
+        used += sizeof(T);
+    }
+};
+
+// One instance of a batch, as the batched kernel reads it from device memory.
+template <typename R>
+struct InstDesc {
+    Geom g;
+    int32_t np, nm;
+    int32_t ntx, nseg, seg, item0;  // work items item0 .. item0 + ntx*nseg - 1
+    int64_t off;                    // element offset of the instance's state
+    double tb0, tdn, tslope;        // T - Te = tb0 + tdn * n + tslope * j
+    Coef<R> c;
+};
+
+// One launch of the batched 2D kernel.
+struct BatchLaunch {
+    const void* in;
+    void* out;
+    const void* table;     // InstDesc<R>[ninst] in device memory
+    const int* item_inst;  // instance of each work item, in device memory
+    int nitems;
+    int potential, aniso;
+    int nblocks;
+    const int64_t* stepctr;
+    int kstep;
 };
 
 constexpr int DIAG_BLOCKS_MAX = 1024;
@@ -61,13 +107,22 @@ constexpr int DIAG_VALS = 16;  // per-block partial record, doubles
 // record layout: mass (sum, comp) x2, volume (sum, comp) x3, max_dev, min_chi x2, nonfinite
 constexpr int DV_MASS = 0, DV_VOL = 4, DV_MAXDEV = 10, DV_MINCHI = 11, DV_NONFIN = 13;
 
-int launch_step_f64(const StepLaunch& L, const Coef<double>& c, hipStream_t s);
-int launch_step_f32(const StepLaunch& L, const Coef<float>& c, hipStream_t s);
+int call_step_f64(const StepLaunch& L, const Coef<double>& c, KernelCall& k);
+int call_step_f32(const StepLaunch& L, const Coef<float>& c, KernelCall& k);
 template <typename R, bool D3>
-int launch_step_dim(const StepLaunch& L, const Coef<R>& c, hipStream_t s);
+int call_step_dim(const StepLaunch& L, const Coef<R>& c, KernelCall& k);
+template <typename R>
+int call_batch(const BatchLaunch& L, KernelCall& k);
+void call_advance(int64_t* ctr, int64_t by, KernelCall& k);
+
+// Tile constants shared with the host: columns written per 2D strip wave,
+// waves per block of the batched kernel.
+constexpr int W2D_OUT_HOST = 62;
+constexpr int BATCH_WPB_HOST = 4;
+inline int batch_waves_per_block_host() { return BATCH_WPB_HOST; }
 
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
-                const DiagCoef& dc, double* ws, hipStream_t s);
+                const DiagCoef& dc, double* partials, double* result, hipStream_t s);
 int diag_blocks(int64_t ncells);
 
 }  // namespace mp

@@ -27,32 +27,21 @@ struct Cell2d {
     R cdx[ANISO ? NP : 1];  // phi(x+1) - phi(x-1) on this row
 };
 
-constexpr int W2D_OUT = 62;  // columns written per wave
+constexpr int W2D_OUT = W2D_OUT_HOST;  // columns written per wave
 
+// One wave's strip: columns tx*62-1 .. tx*62+62 of a 2D field, rows [m0, m1).
+// Called with wave-uniform arguments by the single-grid and the batched kernel.
 template <typename R, int NP, int NM, bool ANISO, bool OBST>
-__global__ void __launch_bounds__(256)
-k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, double tbase,
-         double tslope, int seg, int ntx, int nseg) {
+__device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
+                                        const Coef<R>& c, double tbase, double tslope, int tx,
+                                        int m0, int m1) {
     constexpr int NF = NP + NM;
     typedef Cell2d<R, NP, NM, ANISO> CellT;
     const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int nb = gridDim.x;
-    const int q8 = nb / 8;
-    const int b = blockIdx.x;
-    const int blk = (b < 8 * q8) ? (b % 8) * q8 + b / 8 : b;
-    // wave-uniform by construction; readfirstlane tells the compiler so, which
-    // keeps every row-loop branch scalar and lets loads stay in flight across rows
-    const int wid = __builtin_amdgcn_readfirstlane(blk * wpb + (threadIdx.x >> 6));
-    if (wid >= ntx * nseg) return;  // whole wave leaves; nothing below synchronises
-    const int tx = wid % ntx;
-    const int sg = wid / ntx;
     const int gx = tx * W2D_OUT - 1 + lane;
     const bool perx = g.bcx == MP_BC_PERIODIC;
     const bool pery = g.bcy == MP_BC_PERIODIC;
     const int col = gmap(gx, g.nx, perx);
-    const int m0 = sg * seg;
-    const int m1 = min(m0 + seg, g.ny);
     const int64_t fs = g.fstride;
     const int64_t nx = g.nx;
     const int aR = ((lane + 1) & 63) << 2;
@@ -195,15 +184,49 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, doubl
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST>
-int launch_2d(const StepLaunch& L, const Coef<R>& c, hipStream_t s) {
+__global__ void __launch_bounds__(256)
+k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+         const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+         int seg, int ntx, int nseg) {
+    const int wpb = blockDim.x >> 6;
+    const int nb = gridDim.x;
+    const int q8 = nb / 8;
+    const int b = blockIdx.x;
+    const int blk = (b < 8 * q8) ? (b % 8) * q8 + b / 8 : b;
+    // wave-uniform by construction; readfirstlane tells the compiler so, which
+    // keeps every row-loop branch scalar
+    const int wid = __builtin_amdgcn_readfirstlane(blk * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;  // whole wave leaves; nothing below synchronises
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
+    strip2d<R, NP, NM, ANISO, OBST>(in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int call_2d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     const int ntx = (L.g.nx + W2D_OUT - 1) / W2D_OUT;
     const int nseg = (L.g.ny + L.seg - 1) / L.seg;
     const int wpb = L.bx / 64;
     const long long waves = (long long)ntx * nseg;
     const long long nblocks = (waves + wpb - 1) / wpb;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
-    hipLaunchKernelGGL((k_step2d<R, NP, NM, ANISO, OBST>), dim3((unsigned)nblocks), dim3(L.bx), 0, s,
-                       (const R*)L.in, (R*)L.out, L.g, c, L.tbase, L.tslope, L.seg, ntx, nseg);
+    k.func = (const void*)&k_step2d<R, NP, NM, ANISO, OBST>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(L.bx);
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nseg);
     return MP_OK;
 }
 

@@ -17,8 +17,9 @@ namespace mp {
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY)
-k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, double tbase,
-         double tslope, int seg, int ntx, int nty) {
+k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+         const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+         int seg, int ntx, int nty) {
     constexpr int NF = NP + NM;
     constexpr int PW = BX + 2;
     constexpr int PH = BY + 2;
@@ -136,6 +137,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, doubl
     const int gx = x0 + lx;
     const int gy = y0 + ly;
     const bool valid = gx < g.nx && gy < g.ny;
+    const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
     const R tt = (R)(tbase + tslope * (double)gy);  // T - Te depends on y only
 
     // tangential steps: x faces see (y, z), y faces see (x, z), z faces see (x, y)
@@ -212,16 +214,28 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, doubl
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST>
-int launch_3d(const StepLaunch& L, const Coef<R>& c, hipStream_t s) {
+int call_3d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     constexpr int BX = 64, BY = 4;
     const int ntx = (L.g.nx + BX - 1) / BX;
     const int nty = (L.g.ny + BY - 1) / BY;
     const int nseg = (L.g.nz + L.seg - 1) / L.seg;
     const long long nblocks = (long long)ntx * nty * nseg;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
-    hipLaunchKernelGGL((k_step3d<R, NP, NM, ANISO, OBST, BX, BY>), dim3((unsigned)nblocks),
-                       dim3(BX * BY), 0, s, (const R*)L.in, (R*)L.out, L.g, c, L.tbase, L.tslope,
-                       L.seg, ntx, nty);
+    k.func = (const void*)&k_step3d<R, NP, NM, ANISO, OBST, BX, BY>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(BX * BY);
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nty);
     return MP_OK;
 }
 

@@ -2,5 +2,5 @@
 #include "step_dispatch.hpp"
 
 namespace mp {
-template int launch_step_dim<float, true>(const StepLaunch&, const Coef<float>&, hipStream_t);
+template int call_step_dim<float, true>(const StepLaunch&, const Coef<float>&, KernelCall&);
 }  // namespace mp

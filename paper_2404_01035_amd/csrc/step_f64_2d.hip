@@ -2,5 +2,5 @@
 #include "step_dispatch.hpp"
 
 namespace mp {
-template int launch_step_dim<double, false>(const StepLaunch&, const Coef<double>&, hipStream_t);
+template int call_step_dim<double, false>(const StepLaunch&, const Coef<double>&, KernelCall&);
 }  // namespace mp

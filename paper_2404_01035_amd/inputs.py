@@ -168,13 +168,12 @@ def diffuse_step(dist, eps):
 
 
 def grid_coords(p: Params):
-    """Cell-centre coordinates (x, y[, z]) at integer multiples of dx, array layout."""
+    """Cell-centre coordinates (x, y[, z]) at integer multiples of dx, as broadcastable axes."""
     nx, ny, nz = p.n
     if p.dim == 3:
-        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-        return x * p.dx, y * p.dx, z * p.dx
-    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
-    return x * p.dx, y * p.dx
+        return (np.arange(nx).reshape(1, 1, nx) * p.dx, np.arange(ny).reshape(1, ny, 1) * p.dx,
+                np.arange(nz).reshape(nz, 1, 1) * p.dx)
+    return np.arange(nx).reshape(1, nx) * p.dx, np.arange(ny).reshape(ny, 1) * p.dx
 
 
 def fields_from_solid(p: Params, solid_frac, solid_phase_of_cell, mu_value=0.0):
@@ -286,7 +285,7 @@ def eutectic_initial(p: Params, slab=64, wmin=16, wmax=48, seed=1):
         x0 += w
         k += 1
     x, y = grid_coords(p)
-    sol = diffuse_step(y - (slab - 0.5), p.eps)
+    sol = np.broadcast_to(diffuse_step(y - (slab - 0.5), p.eps), p.spatial)
     which = np.broadcast_to(owner[None, :], sol.shape)
     return fields_from_solid(p, sol, which)
 
@@ -354,3 +353,53 @@ def random_multiphase(p: Params, seed: int, amp: float = 1.0):
     phi = (1 - amp) / p.nphases + amp * phi
     mu = rng.uniform(-0.05, 0.05, size=(p.nmu,) + p.spatial)
     return phi, mu
+
+
+def random_instance(rng, nx, ny, N, K, precision="f32", undercooling=None, nuclei=None):
+    """One batched-ensemble member: seeded sizes, coefficients and nuclei in melt.
+
+    Interface energies gamma_ab ~ U[0.5, 2], liquid diffusivities log-uniform in
+    [0.1, 10] (solids 0), parabolic coefficients drawn as in the eutectic
+    workload, undercooling ~ U[0.1, 0.5], 1-16 nuclei of radius 10 at uniform
+    positions, each of a random solid phase; periodic boundaries; dt = 0.2 of
+    the instance's own explicit limit.
+    """
+    p = Params(dim=2, n=(int(nx), int(ny), 1), bc=(BC_PERIODIC, BC_PERIODIC, BC_PERIODIC),
+               nphases=int(N), ncomp=int(K), precision=precision)
+    for a in range(N):
+        for b in range(a + 1, N):
+            p.gamma[a, b] = p.gamma[b, a] = rng.uniform(0.5, 2.0)
+    K1 = K - 1
+    A = rng.uniform(0.5, 2.0, size=(N, K1))
+    ceq = rng.uniform(0.1, 0.9, size=(N, K1))
+    B, C = parabolic_coefficients(A, ceq, liquid=N - 1)
+    p.A[:N, :K1], p.B[:N, :K1], p.C[:N] = A, B, C
+    p.s[:N] = 1.0
+    p.s[N - 1] = 0.0
+    p.D[N - 1, :K1] = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=K1))
+    dT = rng.uniform(0.1, 0.5) if undercooling is None else undercooling
+    p.Te, p.T0 = 1.0, 1.0 - dT
+    p.dt = 0.2 * dt_limit(p)
+    count = int(rng.integers(1, 17)) if nuclei is None else nuclei
+    centres = [(rng.uniform(0, nx), rng.uniform(0, ny)) for _ in range(count)]
+    phases = [int(rng.integers(0, N - 1)) for _ in range(count)]
+    phi, mu = nuclei_initial(p, centres, [10.0] * count, phases)
+    return p, phi, mu
+
+
+def config_c4(ninst=256, seed=4, precision="f32", side=(64, 1024)):
+    """Batched ensemble: ninst independent 2D simulations of uneven size and parameters.
+
+    Grid sides ~ U{64..1024} independently (non-square allowed), N ~ U{2,3},
+    K - 1 ~ U{1,2}, per-instance coefficients and nuclei as in random_instance.
+    Returns a list of (params, phi, mu).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(ninst):
+        nx = int(rng.integers(side[0], side[1] + 1))
+        ny = int(rng.integers(side[0], side[1] + 1))
+        N = int(rng.integers(2, 4))
+        K = 1 + int(rng.integers(1, 3))
+        out.append(random_instance(rng, nx, ny, N, K, precision=precision))
+    return out

@@ -62,6 +62,81 @@ class Solver:
     def set_tile(self, bx: int = 0, seg: int = 0):
         abi.mp_set_tile(self.st, bx, seg)
 
+    def set_graph(self, chunk: int):
+        """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
+        abi.mp_set_graph(self.st, chunk)
+
+    def close(self):
+        if self.st:
+            abi.mp_destroy(self.st)
+            self.st = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Many independent 2D simulations stepped together (one persistent launch per step).
+
+    Every instance lives in the same pair of state buffers at the offsets the
+    library reports; ``load``/``fields`` move one instance at a time.
+    """
+
+    def __init__(self, plist, device: str = "cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("BatchSolver needs a GPU (torch.cuda.is_available() is False)")
+        self.plist = list(plist)
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if self.plist[0].precision == "f64" else torch.float32
+        self.esize = 8 if self.dtype == torch.float64 else 4
+        self.st = abi.mp_create_batch(self.plist)
+        nbytes = abi.mp_state_bytes(self.st)
+        self.bufs = [torch.empty(nbytes // self.esize, dtype=self.dtype, device=self.device)
+                     for _ in range(2)]
+        self.ws = torch.empty(abi.mp_workspace_bytes(self.st), dtype=torch.uint8, device=self.device)
+        abi.mp_bind(self.st, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(), self.ws.data_ptr())
+        self.offsets = [abi.mp_instance_offset(self.st, i) for i in range(len(self.plist))]
+
+    def _view(self, buf, i):
+        off, nb = self.offsets[i]
+        p = self.plist[i]
+        return buf[off // self.esize:(off + nb) // self.esize].view((p.nfields,) + tuple(p.spatial))
+
+    def load(self, i, phi, mu):
+        host = np.concatenate([np.asarray(phi), np.asarray(mu)], axis=0)
+        self._view(self.bufs[0], i).copy_(torch.from_numpy(np.ascontiguousarray(host)).to(self.dtype))
+
+    def start(self, step: int = 0):
+        """Declare buffer 0 (as filled by ``load``) the state at ``step``."""
+        torch.cuda.synchronize()
+        abi.mp_set_step(self.st, step, 0)
+
+    def step(self, nsteps: int):
+        abi.mp_step(self.st, nsteps, Solver.stream())
+
+    def fields(self, i):
+        torch.cuda.synchronize()
+        w, _ = abi.mp_current(self.st)
+        a = self._view(self.bufs[w], i).double().cpu().numpy()
+        n = self.plist[i].nphases
+        return a[:n], a[n:]
+
+    def diagnostics(self, allow_nonfinite: bool = False):
+        return abi.mp_diagnostics_batch(self.st, Solver.stream(), allow_nonfinite)
+
+    def set_tile(self, seg: int):
+        abi.mp_set_tile(self.st, 0, seg)
+
+    def set_graph(self, chunk: int):
+        abi.mp_set_graph(self.st, chunk)
+
+    @property
+    def time_level(self) -> int:
+        return abi.mp_current(self.st)[1]
+
     def close(self):
         if self.st:
             abi.mp_destroy(self.st)

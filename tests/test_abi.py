@@ -131,3 +131,51 @@ def test_create_rejects_null_pointers():
     g = abi.to_grid(p)
     assert L.mp_create(C.byref(g), 2, 2, None, C.byref(h)) == abi.MP_E_NULLPTR
     assert L.mp_create(C.byref(g), 2, 2, C.byref(abi.to_params(p)), None) == abi.MP_E_NULLPTR
+
+
+def test_batch_create_validation_and_layout_without_gpu():
+    members = inputs.config_c4(ninst=5, seed=2, side=(64, 96))
+    plist = [m[0] for m in members]
+    st = abi.mp_create_batch(plist)
+    try:
+        assert abi.mp_instance_count(st) == 5
+        prev_end = 0
+        for i, p in enumerate(plist):
+            off, nb = abi.mp_instance_offset(st, i)
+            assert off % 256 == 0 and off >= prev_end
+            assert nb == p.ncells * p.nfields * 4
+            prev_end = off + nb
+        assert abi.mp_state_bytes(st) >= prev_end
+        with pytest.raises(abi.MPError):
+            abi.mp_instance_offset(st, 5)
+    finally:
+        abi.mp_destroy(st)
+    bad = [p.copy() for p in plist]
+    bad[2] = bad[2].copy(dt=2 * inputs.dt_limit(bad[2]))
+    with pytest.raises(abi.MPError) as ei:
+        abi.mp_create_batch(bad)
+    assert ei.value.code == abi.MP_E_UNSTABLE and "instance 2" in str(ei.value)
+    mixed = [p.copy() for p in plist]
+    mixed[1] = mixed[1].copy(precision="f64")
+    with pytest.raises(abi.MPError) as ei:
+        abi.mp_create_batch(mixed)
+    assert ei.value.code == abi.MP_E_PARAM and "precision" in str(ei.value)
+    d3 = [inputs.dendrite_params(n=(8, 8, 8))]
+    with pytest.raises(abi.MPError) as ei:
+        abi.mp_create_batch(d3)
+    assert "2D" in str(ei.value)
+    assert abi.lib().mp_create_batch(0, None, None, None, None, None) == abi.MP_E_NULLPTR
+
+
+def test_graph_chunk_validation_without_gpu():
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        for bad in (-2, 1, 3, 7):
+            assert abi.lib().mp_set_graph(st, bad) == abi.MP_E_PARAM
+        for good in (0, 2, 8, 100):
+            abi.mp_set_graph(st, good)
+        assert abi.mp_instance_count(st) == 1
+        assert abi.mp_instance_offset(st, 0) == (0, abi.mp_state_bytes(st))
+    finally:
+        abi.mp_destroy(st)
