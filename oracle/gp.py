@@ -429,3 +429,226 @@ def diagnostics(phi, mu, p):
         "min_chi": [float(np.min(chik[k])) for k in range(p.nmu)],
         "nonfinite": int(np.size(finite) - np.count_nonzero(finite)),
     }
+
+
+# ----------------------------------------------------------------------------
+# Discrete adjoint (isotropic gradient term, multi-well potential)
+# ----------------------------------------------------------------------------
+
+def unpad_add(Pf, p):
+    """Transpose of ``pad``: fold the ghost layer's values onto the cells it copies."""
+    f = Pf
+    for a, bc in reversed(spatial_axes(p)):
+        n = f.shape[a] - 2
+        core = _along(f, a, slice(1, -1)).copy()
+        lo = _along(f, a, slice(0, 1))
+        hi = _along(f, a, slice(n + 1, n + 2))
+        first = [slice(None)] * core.ndim
+        last = [slice(None)] * core.ndim
+        first[core.ndim + a] = slice(0, 1)
+        last[core.ndim + a] = slice(n - 1, n)
+        if bc == PERIODIC:
+            core[tuple(last)] += lo
+            core[tuple(first)] += hi
+        else:
+            core[tuple(first)] += lo
+            core[tuple(last)] += hi
+        f = core
+    return f
+
+
+def _zpad_along(x, a):
+    """Zero cell on both ends of axis a (cotangents of the ghost cells are zero)."""
+    z = np.zeros_like(_along(x, a, slice(0, 1)))
+    return np.concatenate([z, x, z], axis=a)
+
+
+PAIRS = [(0, 1), (0, 2), (1, 2)]
+
+
+def adjoint_step(phi, mu, n, p, lphi1, lmu1):
+    """Transpose of one step: from dL/d(phi^{n+1}, mu^{n+1}) to dL/d(phi^n, mu^n).
+
+    Also returns this step's contribution to the parameter gradient, a dict
+    with 'gamma' (3 pairs: 01, 02, 12), 'D' (3 x 2, per phase and component)
+    and 'tau'.  Written by hand, term by term, from the forward scheme of
+    ``step``; only the isotropic multi-well variant is differentiable here.
+    """
+    if p.potential != "well":
+        raise ValueError("adjoint: the obstacle projection is not differentiable")
+    N, K1, nd = p.nphases, p.nmu, p.dim
+    if any(p.delta[i][j] != 0.0 for i in range(N) for j in range(i + 1, N)):
+        raise ValueError("adjoint: anisotropic gradient energy not supported")
+    dx, eps, tau, dt = p.dx, p.eps, p.tau, p.dt
+    A = np.asarray(p.A)
+    Dm = np.asarray(p.D)
+    chi = chi_phase(p)
+    Pphi, Pmu = pad(phi, p), pad(mu, p)
+
+    # ---- forward recomputation of the cell quantities ------------------------
+    R = _rhs_padded(Pphi, Pmu, n, p)
+    lam = sum(R[a] for a in range(N)) / N
+    phin = phi + dt * (R - lam) / (tau * eps)
+    hP = h(Pphi)
+    div = [0.0 * mu[k] for k in range(K1)]
+    M = [sum(Dm[b][k] * chi[b][k] * hP[b] for b in range(N))[None] for k in range(K1)]
+    for k in range(K1):
+        for a, _ in spatial_axes(p):
+            ML = _sub(M[k], nd, {a: slice(0, -1)})[0]
+            MR = _sub(M[k], nd, {a: slice(1, None)})[0]
+            muL = _sub(Pmu[k:k + 1], nd, {a: slice(0, -1)})[0]
+            muR = _sub(Pmu[k:k + 1], nd, {a: slice(1, None)})[0]
+            J = 0.5 * (ML + MR) * (muR - muL) / dx
+            div[k] = div[k] + (_along(J, a, slice(1, None)) - _along(J, a, slice(0, -1))) / dx
+    h0, h1 = h(phi), h(phin)
+    ca = c_phase(mu, p)
+    T = temperature(p, n, phi.shape[1:])
+    psi = psi_phase(mu, T, p)
+
+    g_gamma = np.zeros(3)
+    g_D = np.zeros((3, 2))
+
+    # ---- mu update ------------------------------------------------------------
+    lmu = [lmu1[k].copy() for k in range(K1)]
+    lh1 = [0.0 * phi[0] for _ in range(N)]
+    lh0 = [0.0 * phi[0] for _ in range(N)]
+    ldiv = []
+    for k in range(K1):
+        src = sum(ca[b][k] * (h1[b] - h0[b]) for b in range(N))
+        chik = sum(h1[b] * chi[b][k] for b in range(N))
+        Q = dt * div[k] - src
+        lQ = lmu1[k] / chik
+        lchi = -lmu1[k] * Q / chik ** 2
+        ldiv.append(dt * lQ)
+        lsrc = -lQ
+        for b in range(N):
+            lh1[b] = lh1[b] + lsrc * ca[b][k] + lchi * chi[b][k]
+            lh0[b] = lh0[b] - lsrc * ca[b][k]
+            lmu[k] = lmu[k] + lsrc * (h1[b] - h0[b]) / (2.0 * A[b][k])   # through c^b_k(mu)
+
+    # ---- phi update: phin = phi + dt (R - lam) / (tau eps) -----------------------
+    dh1 = dh(phin)
+    lphin = [lphi1[a] + sum(lh1[b] * dh1[b][a] for b in range(N)) for a in range(N)]
+    dh0 = dh(phi)
+    lphi = [lphin[a] + sum(lh0[b] * dh0[b][a] for b in range(N)) for a in range(N)]
+    kk = dt / (tau * eps)
+    lmean = sum(lphin) / N
+    lR = [kk * (lphin[a] - lmean) for a in range(N)]
+    g_tau = float(np.sum(sum(lphin[a] * (-(dt * (R[a] - lam)) / (tau ** 2 * eps)) for a in range(N))))
+
+    # R_a = eps grad_a - dw_a / eps - sum_b psi_b dh_b/dphi_a
+    lgrad = [eps * lR[a] for a in range(N)]
+    # potential: dw_c = sum_{b != c} 18 g_cb phi_c phi_b^2 + g3 prod_{b != c} phi_b
+    for c in range(N):
+        for a in range(N):
+            if a == c:
+                d = sum(18.0 * p.gamma[c][b] * phi[b] ** 2 for b in range(N) if b != c)
+            else:
+                d = 36.0 * p.gamma[c][a] * phi[c] * phi[a]
+                if N == 3:
+                    d = d + p.gamma3 * phi[3 - a - c]
+            lphi[a] = lphi[a] - lR[c] * d / eps
+    for c in range(N):
+        for b in range(N):
+            if b != c:
+                q = PAIRS.index((min(b, c), max(b, c)))
+                g_gamma[q] += float(np.sum(-lR[c] / eps * 18.0 * phi[c] * phi[b] ** 2))
+    # driving force: second derivatives of h (differentiated by hand from Eq. hphi)
+    for c in range(N):
+        for a in range(N):
+            acc = 0.0
+            for b in range(N):
+                if N == 2:
+                    d2 = (6.0 - 12.0 * phi[b]) if (a == b and c == b) else 0.0
+                else:
+                    if a == b and c == b:
+                        d2 = 6.0 - 12.0 * phi[b]
+                    elif a == c:
+                        d2 = 0.0
+                    elif a == b or c == b:
+                        d2 = 2.0 * phi[3 - a - c]
+                    else:
+                        d2 = 2.0 * phi[b]
+                acc = acc + psi[b] * d2
+            lphi[a] = lphi[a] - lR[c] * acc
+    lpsi = [-sum(lR[c] * dh0[b][c] for c in range(N)) for b in range(N)]
+    for k in range(K1):
+        for b in range(N):
+            lmu[k] = lmu[k] - lpsi[b] * ca[b][k]   # dpsi_b/dmu_k = -c^b_k
+
+    # ---- faces: gradient term and mu flux ------------------------------------
+    lPphi = np.zeros_like(Pphi)
+    lPmu = np.zeros_like(Pmu)
+    lPM = [np.zeros_like(M[k]) for k in range(K1)]
+    for a, _ in spatial_axes(p):
+        sL = {a: slice(0, -1)}
+        sR = {a: slice(1, None)}
+        L = _sub(Pphi, nd, sL)
+        Rf = _sub(Pphi, nd, sR)
+        pb = 0.5 * (L + Rf)
+        g = (Rf - L) / dx
+        lgz = [_zpad_along(lgrad[c], a) for c in range(N)]
+        lF = [(_along(lgz[c], a, slice(0, -1)) - _along(lgz[c], a, slice(1, None))) / dx for c in range(N)]
+        lS = [-0.5 * (_along(lgz[c], a, slice(0, -1)) + _along(lgz[c], a, slice(1, None))) for c in range(N)]
+        lpb = [0.0 * pb[0] for _ in range(N)]
+        lg = [0.0 * pb[0] for _ in range(N)]
+        for i in range(N):
+            for j in range(i + 1, N):
+                qn = pb[i] * g[j] - pb[j] * g[i]
+                Gn = 2.0 * qn
+                gG = p.gamma[i][j] * Gn
+                lgG = -lF[i] * pb[j] + lF[j] * pb[i] + lS[i] * g[j] - lS[j] * g[i]
+                lpb[j] = lpb[j] - lF[i] * gG
+                lpb[i] = lpb[i] + lF[j] * gG
+                lg[j] = lg[j] + lS[i] * gG
+                lg[i] = lg[i] - lS[j] * gG
+                g_gamma[PAIRS.index((i, j))] += float(np.sum(lgG * Gn))
+                lqn = 2.0 * p.gamma[i][j] * lgG
+                lpb[i] = lpb[i] + lqn * g[j]
+                lg[j] = lg[j] + lqn * pb[i]
+                lpb[j] = lpb[j] - lqn * g[i]
+                lg[i] = lg[i] - lqn * pb[j]
+        lL = np.stack([0.5 * lpb[c] - lg[c] / dx for c in range(N)])
+        lRr = np.stack([0.5 * lpb[c] + lg[c] / dx for c in range(N)])
+        _sub(lPphi, nd, sL)[...] += lL
+        _sub(lPphi, nd, sR)[...] += lRr
+        for k in range(K1):
+            ML = _sub(M[k], nd, sL)[0]
+            MR = _sub(M[k], nd, sR)[0]
+            muL = _sub(Pmu[k:k + 1], nd, sL)[0]
+            muR = _sub(Pmu[k:k + 1], nd, sR)[0]
+            ldz = _zpad_along(ldiv[k], a)
+            lJ = (_along(ldz, a, slice(0, -1)) - _along(ldz, a, slice(1, None))) / dx
+            lMf = lJ * 0.5 * (muR - muL) / dx
+            lmuf = lJ * 0.5 * (ML + MR) / dx
+            _sub(lPM[k], nd, sL)[0] += lMf
+            _sub(lPM[k], nd, sR)[0] += lMf
+            _sub(lPmu[k:k + 1], nd, sL)[0] -= lmuf
+            _sub(lPmu[k:k + 1], nd, sR)[0] += lmuf
+    # cell mobility M_k = sum_b D_bk chi_bk h_b(phi) on the padded cells
+    dhP = dh(Pphi)
+    for k in range(K1):
+        for b in range(N):
+            g_D[b][k] += float(np.sum(lPM[k][0] * chi[b][k] * hP[b]))
+            for a in range(N):
+                lPphi[a] = lPphi[a] + lPM[k][0] * Dm[b][k] * chi[b][k] * dhP[b][a]
+    lphi_faces = unpad_add(lPphi, p)
+    lmu_faces = unpad_add(lPmu, p)
+    lphi0 = np.stack(lphi) + lphi_faces
+    lmu0 = np.stack(lmu) + lmu_faces
+    return lphi0, lmu0, {"gamma": g_gamma, "D": g_D, "tau": g_tau}
+
+
+def adjoint_run(phi0, mu0, n0, nsteps, p, lphiN, lmuN):
+    """Adjoint of ``run``: stores every forward state (small grids only) and sweeps back."""
+    states = [(phi0, mu0)]
+    for i in range(nsteps):
+        states.append(step(*states[-1], n0 + i, p))
+    lphi, lmu = lphiN, lmuN
+    tot = {"gamma": np.zeros(3), "D": np.zeros((3, 2)), "tau": 0.0}
+    for i in reversed(range(nsteps)):
+        lphi, lmu, g = adjoint_step(states[i][0], states[i][1], n0 + i, p, lphi, lmu)
+        tot["gamma"] += g["gamma"]
+        tot["D"] += g["D"]
+        tot["tau"] += g["tau"]
+    return lphi, lmu, tot
