@@ -186,6 +186,34 @@ int mp_instance_offset(const mp_state* st, int i, size_t* offset_bytes, size_t* 
  * Returns MP_E_NONFINITE (with out filled) if any instance holds NaN/Inf. */
 int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream);
 
+/* Checkpointed forward run (single 2D or 3D state): before every chunk of
+ * ``every`` steps the current state is copied into checkpoint slot c of
+ * ckpt_buf (slot stride = mp_state_bytes rounded up to 256 bytes;
+ * ceil(nsteps / every) slots), then the chunk is stepped as by mp_step.  The
+ * checkpoints are the forward states at time levels n0, n0 + every, ... where
+ * n0 is the time level on entry.  The adjoint's recomputation reproduces the
+ * stepped states bit for bit from them. */
+int mp_step_ckpt(mp_state* st, int64_t nsteps, int64_t every, void* ckpt_buf, void* stream);
+
+/* Bytes of the caller-owned work buffer mp_adjoint needs for ``every``
+ * (cotangent staging, two adjoint buffers, one segment of recomputed states,
+ * per-block gradient partial sums); 0 for unsupported states. */
+size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
+
+/* Discrete adjoint of nsteps steps recorded by mp_step_ckpt starting at time
+ * level n0 (2D, isotropic, multi-well only; the obstacle projection is not
+ * differentiable).  lam_final holds dL/ds at the final state (state layout);
+ * lam_initial receives dL/ds at the initial state.  grad_theta (host, 10
+ * doubles) receives dL/dtheta with theta = (gamma_01, gamma_02, gamma_12,
+ * D[0][0], D[0][1], D[1][0], D[1][1], D[2][0], D[2][1], tau) and dt held
+ * fixed.  Each segment between checkpoints is recomputed from its checkpoint
+ * into the work buffer and swept backwards; results do not depend on
+ * ``every`` (bitwise).  Synchronises ``stream``.  Errors: MP_E_STATE (batched
+ * state), MP_E_PARAM (3D, obstacle, anisotropy, bad sizes or alignment). */
+int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,
+               const void* lam_final, void* lam_initial, double* grad_theta, void* work,
+               void* stream);
+
 /* Free host-side state (device buffers stay with the caller). NULL is a no-op. */
 void mp_destroy(mp_state* st);
 

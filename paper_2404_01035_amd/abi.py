@@ -31,8 +31,11 @@ EXPORTS = [
     "mp_dt_limit", "mp_create", "mp_state_bytes", "mp_workspace_bytes", "mp_bind", "mp_step",
     "mp_current", "mp_set_step", "mp_diagnostics", "mp_set_tile", "mp_get_tile", "mp_destroy",
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
-    "mp_diagnostics_batch",
+    "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
 ]
+
+# Layout of the parameter gradient filled by mp_adjoint.
+GRAD_NAMES = ["gamma01", "gamma02", "gamma12", "D00", "D01", "D10", "D11", "D20", "D21", "tau"]
 
 
 class mp_grid(C.Structure):
@@ -114,6 +117,13 @@ def lib():
         L.mp_instance_offset.argtypes = [vp, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.mp_diagnostics_batch.restype = C.c_int
         L.mp_diagnostics_batch.argtypes = [vp, C.POINTER(mp_diag), vp]
+        L.mp_step_ckpt.restype = C.c_int
+        L.mp_step_ckpt.argtypes = [vp, C.c_int64, C.c_int64, vp, vp]
+        L.mp_adjoint_work_bytes.restype = C.c_size_t
+        L.mp_adjoint_work_bytes.argtypes = [vp, C.c_int64]
+        L.mp_adjoint.restype = C.c_int
+        L.mp_adjoint.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int64, vp, vp,
+                                 C.POINTER(C.c_double), vp, vp]
         _lib = L
     return _lib
 
@@ -265,3 +275,20 @@ def mp_get_tile(st):
 def mp_destroy(st):
     if st:
         lib().mp_destroy(st)
+
+
+def mp_step_ckpt(st, nsteps: int, every: int, ckpt_buf: int, stream: int = 0):
+    _check(lib().mp_step_ckpt(st, int(nsteps), int(every), ckpt_buf, stream))
+
+
+def mp_adjoint_work_bytes(st, every: int) -> int:
+    return int(lib().mp_adjoint_work_bytes(st, int(every)))
+
+
+def mp_adjoint(st, ckpt_buf: int, nsteps: int, every: int, n0: int, lam_final: int,
+               lam_initial: int, work: int, stream: int = 0) -> dict:
+    """Adjoint sweep; returns the parameter gradient as a dict keyed by GRAD_NAMES."""
+    g = (C.c_double * 10)()
+    _check(lib().mp_adjoint(st, ckpt_buf, int(nsteps), int(every), int(n0), lam_final,
+                            lam_initial, g, work, stream))
+    return dict(zip(GRAD_NAMES, list(g)))

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint2d.hpp"
 #include "mp_internal.hpp"
 
 namespace {
@@ -350,6 +351,9 @@ int sync_batch(mp_state* st) {
     return choose_batch_blocks(st);
 }
 
+int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
+                     mp::KernelCall& k);
+
 // One step launch; kstep is the launch's offset from the device time level.
 int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
     if (st->batch) {
@@ -366,10 +370,16 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
         L.kstep = kstep;
         return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
     }
+    return make_single_call(st, st->buf[from], st->buf[1 - from], dev_ctr(st), kstep, k);
+}
+
+// Single-grid step from ``in`` to ``out`` at time level *ctr + kstep.
+int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
+                     mp::KernelCall& k) {
     const Inst& I = st->inst[0];
     mp::StepLaunch L;
-    L.in = st->buf[from];
-    L.out = st->buf[1 - from];
+    L.in = in;
+    L.out = out;
     L.g = make_geom(I.grid);
     L.nphases = I.N;
     L.nmu = I.K - 1;
@@ -378,7 +388,7 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
     L.aniso = I.aniso ? 1 : 0;
     L.bx = st->bx;
     L.seg = st->seg;
-    L.stepctr = dev_ctr(st);
+    L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
     if (st->precision == MP_FP64) return mp::call_step_f64(L, make_coef<double>(I), k);
@@ -504,6 +514,80 @@ int diag_many(mp_state* st, mp_diag* out, void* stream) {
     }
     if (bad > 0) return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)bad);
     return ok();
+}
+
+// ---- adjoint driver -----------------------------------------------------------
+template <typename R>
+mp::AdjCoef<R> make_adj_coef(const Inst& I) {
+    const mp_params& p = I.prm;
+    mp::AdjCoef<R> c;
+    std::memset(&c, 0, sizeof c);
+    c.inv_dx = (R)(1.0 / I.grid.dx);
+    c.eps = (R)p.eps;
+    c.inv_eps = (R)(1.0 / p.eps);
+    c.kphi = (R)(p.dt / (p.tau * p.eps));
+    c.dt = (R)p.dt;
+    c.ktau = (R)(p.dt / (p.tau * p.tau * p.eps));
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int q = 0; q < 3; ++q) {
+        c.gam[q] = (R)p.gamma[pa[q]][pb[q]];
+        c.w18[q] = (R)(18.0 * p.gamma[pa[q]][pb[q]]);
+    }
+    c.gamma3 = (R)p.gamma3;
+    for (int a = 0; a < I.N; ++a) {
+        c.C[a] = (R)p.C[a];
+        c.s[a] = (R)p.s[a];
+        for (int k = 0; k < I.K - 1; ++k) {
+            const double chi = 1.0 / (2.0 * p.A[a][k]);
+            c.chi[a][k] = (R)chi;
+            c.halfchi[a][k] = (R)(0.5 * chi);
+            c.B[a][k] = (R)p.B[a][k];
+            c.Dchi[a][k] = (R)(p.D[a][k] * chi);
+        }
+    }
+    return c;
+}
+
+struct AdjLayout {
+    size_t X, lamA, lamB, seg, acc, ctr, grad, total;
+    size_t state;
+    int nrows;
+};
+
+AdjLayout adj_layout(const mp_state* st, int64_t every) {
+    const Inst& I = st->inst[0];
+    AdjLayout L;
+    L.state = align_up(I.bytes);
+    mp::AdjGeom g;
+    g.nx = (int)I.grid.n[0];
+    g.ny = (int)I.grid.n[1];
+    L.nrows = mp::adj_blocks(g);
+    size_t o = 0;
+    L.X = o;
+    o += L.state;
+    L.lamA = o;
+    o += L.state;
+    L.lamB = o;
+    o += L.state;
+    L.seg = o;
+    o += L.state * (size_t)every;
+    L.acc = o;
+    o += align_up(sizeof(double) * mp::ADJ_NPAR * (size_t)L.nrows);
+    L.ctr = o;
+    o += kAlign;
+    L.grad = o;
+    o += kAlign;
+    L.total = o;
+    return L;
+}
+
+int adj_supported(const mp_state* st) {
+    if (st->batch) return fail(MP_E_STATE, "adjoint: batched states are not supported");
+    const Inst& I = st->inst[0];
+    if (I.grid.dim != 2) return fail(MP_E_PARAM, "adjoint: 2D grids only");
+    if (I.prm.potential != MP_WELL) return fail(MP_E_PARAM, "adjoint: the obstacle projection is not differentiable");
+    if (I.aniso) return fail(MP_E_PARAM, "adjoint: anisotropic gradient energy not supported");
+    return MP_OK;
 }
 
 }  // namespace
@@ -730,6 +814,108 @@ int mp_instance_offset(const mp_state* st, int i, size_t* offset_bytes, size_t* 
     if (offset_bytes) *offset_bytes = st->inst[i].off_bytes;
     if (nbytes) *nbytes = st->inst[i].bytes;
     return ok();
+}
+
+size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every) {
+    if (!st || every < 1 || st->batch) return 0;
+    return adj_layout(st, every).total;
+}
+
+int mp_step_ckpt(mp_state* st, int64_t nsteps, int64_t every, void* ckpt_buf, void* stream) {
+    if (!st || !ckpt_buf) return fail(MP_E_NULLPTR, "state or checkpoint buffer is NULL");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_step_ckpt before mp_bind");
+    if (st->batch) return fail(MP_E_STATE, "checkpointing: batched states are not supported");
+    if (nsteps < 0 || every < 1) return fail(MP_E_PARAM, "nsteps must be >= 0 and every >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t sb = st->inst[0].bytes;
+    const size_t stride = align_up(sb);
+    for (int64_t done = 0, c = 0; done < nsteps; done += every, ++c) {
+        int rc = hip_check(hipMemcpyAsync((char*)ckpt_buf + (size_t)c * stride, st->buf[st->cur], sb,
+                                          hipMemcpyDeviceToDevice, s),
+                           "checkpoint copy");
+        if (rc) return rc;
+        const int64_t len = nsteps - done < every ? nsteps - done : every;
+        rc = mp_step(st, len, stream);
+        if (rc) return rc;
+    }
+    return ok();
+}
+
+int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,
+               const void* lam_final, void* lam_initial, double* grad_theta, void* work, void* stream) {
+    if (!st || !ckpt_buf || !lam_final || !lam_initial || !grad_theta || !work)
+        return fail(MP_E_NULLPTR, "mp_adjoint: NULL argument");
+    int rc = adj_supported(st);
+    if (rc) return rc;
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_adjoint before mp_bind");
+    if (nsteps < 0 || every < 1 || n0 < 0) return fail(MP_E_PARAM, "nsteps, n0 must be >= 0 and every >= 1");
+    if (((uintptr_t)work | (uintptr_t)ckpt_buf) & (kAlign - 1))
+        return fail(MP_E_PARAM, "work and checkpoint buffers must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const Inst& I = st->inst[0];
+    const AdjLayout L = adj_layout(st, every);
+    char* w = (char*)work;
+    const size_t sb = I.bytes;
+    void* lam[2] = {w + L.lamA, w + L.lamB};
+    double* acc = (double*)(w + L.acc);
+    int64_t* zctr = (int64_t*)(w + L.ctr);
+    double* gdev = (double*)(w + L.grad);
+    rc = hip_check(hipMemcpyAsync(lam[0], lam_final, sb, hipMemcpyDeviceToDevice, s), "lambda copy");
+    if (rc) return rc;
+    mp::adj_fill(acc, (int64_t)L.nrows * mp::ADJ_NPAR, 0.0, s);
+    mp::adj_fill((double*)zctr, 1, 0.0, s);  // all-zero bits: the int64 time-level base 0
+    mp::AdjLaunch A;
+    A.g.nx = (int)I.grid.n[0];
+    A.g.ny = (int)I.grid.n[1];
+    A.g.perx = I.grid.bc[0] == MP_BC_PERIODIC;
+    A.g.pery = I.grid.bc[1] == MP_BC_PERIODIC;
+    A.g.fs = ncells_of(I.grid);
+    A.nphases = I.N;
+    A.nmu = I.K - 1;
+    A.X = w + L.X;
+    A.acc = acc;
+    double tb0, tdn, tslope;
+    temperature_law(I, tb0, tdn, tslope);
+    const mp::AdjCoef<double> cd = make_adj_coef<double>(I);
+    const mp::AdjCoef<float> cf = make_adj_coef<float>(I);
+    int cur = 0;
+    const int64_t nseg = (nsteps + every - 1) / every;
+    for (int64_t k = nseg - 1; k >= 0; --k) {
+        const int64_t base = n0 + k * every;
+        const int64_t len = (nsteps - k * every) < every ? (nsteps - k * every) : every;
+        char* seg = w + L.seg;
+        rc = hip_check(hipMemcpyAsync(seg, (const char*)ckpt_buf + (size_t)k * L.state, sb,
+                                      hipMemcpyDeviceToDevice, s),
+                       "checkpoint restore");
+        if (rc) return rc;
+        for (int64_t i = 0; i + 1 < len; ++i) {  // recompute the segment's states
+            mp::KernelCall kc;
+            rc = make_single_call(st, seg + (size_t)i * L.state, seg + (size_t)(i + 1) * L.state, zctr,
+                                  (int)(base + i), kc);
+            if (rc) return fail(rc, "no kernel instance for this configuration");
+            rc = launch(kc, s);
+            if (rc) return rc;
+        }
+        for (int64_t i = len - 1; i >= 0; --i) {  // reverse sweep
+            A.s = seg + (size_t)i * L.state;
+            A.lam1 = lam[cur];
+            A.out = lam[1 - cur];
+            A.tt_row0 = tb0 + tdn * (double)(base + i);
+            A.tt_slope = tslope;
+            rc = st->precision == MP_FP64 ? mp::adj_launch<double>(A, cd, s) : mp::adj_launch<float>(A, cf, s);
+            if (rc) return fail(rc, "no adjoint instance for this configuration");
+            rc = hip_check(hipGetLastError(), "adjoint launch");
+            if (rc) return rc;
+            cur = 1 - cur;
+        }
+    }
+    rc = hip_check(hipMemcpyAsync(lam_initial, lam[cur], sb, hipMemcpyDeviceToDevice, s), "lambda copy");
+    if (rc) return rc;
+    mp::adj_reduce(acc, L.nrows, gdev, s);
+    rc = hip_check(hipMemcpyAsync(grad_theta, gdev, sizeof(double) * mp::ADJ_NPAR, hipMemcpyDeviceToHost, s),
+                   "gradient copy");
+    if (rc) return rc;
+    return hip_check(hipStreamSynchronize(s), "adjoint sync");
 }
 
 void mp_destroy(mp_state* st) {

@@ -115,6 +115,15 @@ template <typename R>
 int call_batch(const BatchLaunch& L, KernelCall& k);
 void call_advance(int64_t* ctr, int64_t by, KernelCall& k);
 
+// Adjoint (adjoint2d.hpp): plain coefficients and one reverse step.
+template <typename R>
+struct AdjCoef;
+struct AdjLaunch;
+template <typename R>
+int adj_launch(const AdjLaunch& L, const AdjCoef<R>& c, hipStream_t s);
+void adj_fill(double* p, int64_t n, double v, hipStream_t s);
+void adj_reduce(const double* acc, int nrows, double* out, hipStream_t s);
+
 // Tile constants shared with the host: columns written per 2D strip wave,
 // waves per block of the batched kernel.
 constexpr int W2D_OUT_HOST = 62;

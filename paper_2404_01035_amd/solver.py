@@ -66,6 +66,26 @@ class Solver:
         """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
         abi.mp_set_graph(self.st, chunk)
 
+    # ---- checkpointed run and adjoint -------------------------------------
+    def checkpoint_buffer(self, nsteps: int, every: int) -> torch.Tensor:
+        """Device buffer for ceil(nsteps / every) checkpoints (256-byte slots)."""
+        slot = (abi.mp_state_bytes(self.st) + 255) // 256 * 256
+        nslots = max(1, -(-int(nsteps) // int(every)))
+        return torch.empty(slot * nslots, dtype=torch.uint8, device=self.device)
+
+    def step_ckpt(self, nsteps: int, every: int, ckpt: torch.Tensor):
+        abi.mp_step_ckpt(self.st, nsteps, every, ckpt.data_ptr(), self.stream())
+
+    def adjoint(self, lam_final: torch.Tensor, ckpt: torch.Tensor, nsteps: int, every: int, n0: int):
+        """dL/d(initial state) and dL/dtheta from dL/d(final state) (state layout)."""
+        lam0 = torch.empty_like(self.bufs[0])
+        work = torch.empty(abi.mp_adjoint_work_bytes(self.st, every), dtype=torch.uint8,
+                           device=self.device)
+        lam_final = lam_final.to(self.dtype).contiguous()
+        g = abi.mp_adjoint(self.st, ckpt.data_ptr(), nsteps, every, n0, lam_final.data_ptr(),
+                           lam0.data_ptr(), work.data_ptr(), self.stream())
+        return lam0, g
+
     def close(self):
         if self.st:
             abi.mp_destroy(self.st)

@@ -179,3 +179,40 @@ def test_graph_chunk_validation_without_gpu():
         assert abi.mp_instance_offset(st, 0) == (0, abi.mp_state_bytes(st))
     finally:
         abi.mp_destroy(st)
+
+
+def test_adjoint_rejects_unsupported_variants_without_gpu():
+    import ctypes as C
+    L = abi.lib()
+    cases = []
+    p, _, _ = inputs.config_c1()
+    cases.append((p.copy(potential="obstacle"), abi.MP_E_PARAM, "obstacle"))
+    q = p.copy()
+    q.delta[0, 1] = q.delta[1, 0] = 0.02
+    q.dt = 0.2 * inputs.dt_limit(q)
+    cases.append((q, abi.MP_E_PARAM, "anisotropic"))
+    cases.append((inputs.dendrite_params(n=(8, 8, 8), delta=0.0), abi.MP_E_PARAM, "2D"))
+    buf = C.c_void_p(256)
+    g = (C.c_double * 10)()
+    for prm, code, word in cases:
+        st = abi.mp_create(prm)
+        try:
+            rc = L.mp_adjoint(st, buf, 10, 5, 0, buf, buf, g, buf, None)
+            assert rc == code and word in abi.mp_last_error(), (rc, abi.mp_last_error())
+        finally:
+            abi.mp_destroy(st)
+    st = abi.mp_create(p)
+    try:
+        assert L.mp_adjoint(st, None, 10, 5, 0, buf, buf, g, buf, None) == abi.MP_E_NULLPTR
+        assert L.mp_adjoint(st, buf, 10, 5, 0, buf, buf, g, buf, None) == abi.MP_E_UNBOUND
+        assert abi.mp_adjoint_work_bytes(st, 0) == 0
+        assert abi.mp_adjoint_work_bytes(st, 10) > 10 * abi.mp_state_bytes(st)
+    finally:
+        abi.mp_destroy(st)
+    members = inputs.config_c4(ninst=2, side=(64, 70))
+    bst = abi.mp_create_batch([m[0] for m in members])
+    try:
+        assert L.mp_adjoint(bst, buf, 10, 5, 0, buf, buf, g, buf, None) == abi.MP_E_STATE
+        assert abi.mp_adjoint_work_bytes(bst, 5) == 0
+    finally:
+        abi.mp_destroy(bst)
