@@ -1,13 +1,22 @@
 """Benchmark of the fused phi + mu step on one MI355X.
 
-Workload: 2D 4096 x 4096 directional eutectic (3 phases, ternary: 2 mu fields),
-x periodic / y no-flux, seeded synthetic initial state (lamellae slab in melt).
-A benchmark step is one forward-Euler time step of the whole field (one launch
-of the fused kernel).  The timed region runs exactly --steps steps in FP64
-(``value``) and, separately, in FP32 (``fp32``), with the state resident in HBM.
+Headline workload: 2D 4096 x 4096 directional eutectic (3 phases, ternary: 2 mu
+fields), x periodic / y no-flux, seeded synthetic initial state (lamellae slab
+in melt).  A benchmark step is one forward-Euler time step of the whole field
+(one launch of the fused kernel).  The timed region runs exactly --steps steps
+in FP64 (``value``) and, separately, in FP32 (``fp32``), with the state
+resident in HBM; the tile shape is picked by the autotuner first.
 
-Prints one JSON line.  Options: --gpus (only 1 is supported), --steps, --warmup,
---no-cpu (skip the CPU oracle leg), --no-fp32, --n (grid side, default 4096).
+Further legs, each a block of the same JSON line:
+  dendrite_3d  3D 512^3 binary dendrite with cubic anisotropy, FP32
+  batched      256 uneven 2D instances in one persistent launch per step,
+               replayed as HIP graphs, FP32
+  adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
+               (every 100 steps) and the adjoint sweep; their cost ratio
+cpu_baseline   the FP64 oracle on one full 4096^2 step, on the host.
+
+Prints one JSON line.  Options: --gpus (only 1 is supported), --steps,
+--warmup, --legs, --no-cpu, --n (2D grid side), --tile bx,seg (skips tuning).
 """
 from __future__ import annotations
 
@@ -21,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
+ALL_LEGS = ("c2", "c3", "c4", "c5")
 
 
 def parse():
@@ -29,16 +40,52 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--legs", type=str, default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--tile", type=str, default="", help="bx,seg override")
+    ap.add_argument("--tile", type=str, default="", help="bx,seg for the 2D legs (no tuning)")
+    ap.add_argument("--steps3d", type=int, default=100)
+    ap.add_argument("--n3d", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=400)
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of one FP64 state buffer instead")
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def roofline(bytes_per_step, ms_step):
+    gbs = bytes_per_step / (ms_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+
+
+class Timer:
+    """HIP events on torch's current stream, the stream every library call here runs on."""
+
+    def __init__(self):
+        import torch
+
+        self.torch = torch
+        self.stream = torch.cuda.current_stream()
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.torch.cuda.synchronize()
+        self.e0.record(self.stream)
+        return self
+
+    def __exit__(self, *exc):
+        self.e1.record(self.stream)
+        self.torch.cuda.synchronize()
+        self.ms = self.e0.elapsed_time(self.e1)
+
+
 def copy_calibration(n, steps):
-    """Plain device-to-device copy of one FP64 C2 state buffer (5 fields x n x n):
+    """Plain device-to-device copy of one FP64 C2-sized state buffer (5 fields x n x n):
     the practical HBM ceiling, and the known-size reference for traffic counters."""
     import torch
 
@@ -47,68 +94,158 @@ def copy_calibration(n, steps):
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    with Timer() as t:
+        for _ in range(steps):
+            dst.copy_(src)
+    ms = t.ms / steps
     gbs = 2 * nbytes / (ms * 1e-3) / 1e9
     print(json.dumps({"copy_bytes_each_way": nbytes, "ms_per_copy": ms, "GBs_read_plus_write": gbs,
                       "frac_of_8TBs": gbs / HBM_PEAK_GBS}), flush=True)
 
 
-def time_precision(precision, n, steps, warmup, tile):
-    import torch
-
+def leg_c2(precision, n, steps, warmup, tile):
     from paper_2404_01035_amd import inputs
     from paper_2404_01035_amd.solver import Solver
 
     p, phi, mu = inputs.config_c2(precision=precision, n=(n, n, 1))
     s = Solver(p)
+    s.load(phi, mu)
+    del phi, mu
     if tile:
         bx, seg = (int(v) for v in tile.split(","))
         s.set_tile(bx, seg)
-    s.load(phi, mu)
-    del phi, mu
+        tuned = {"bx": bx, "seg": seg, "source": "--tile"}
+    else:
+        tuned = s.autotune(reps=10, force=True)
     s.step(warmup)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    s.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    with Timer() as t:
+        s.step(steps)
     d = s.diagnostics()
     s.close()
-    ncells = p.ncells
     elem = 8 if precision == "f64" else 4
-    bytes_per_step = ncells * p.nfields * 2 * elem  # read + write of every field once
-    ms_step = ms / steps
-    gbs = bytes_per_step / (ms_step * 1e-3) / 1e9
+    bpc = p.nfields * 2 * elem  # read + write of every field once
+    ms_step = t.ms / steps
     return {
-        "value": ncells * steps / (ms * 1e-3),
+        "value": p.ncells * steps / (t.ms * 1e-3),
         "ms_per_step": ms_step,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
-        },
-        "bytes_per_cell_update": p.nfields * 2 * elem,
+        "roofline": roofline(p.ncells * bpc, ms_step),
+        "bytes_per_cell_update": bpc,
+        "tile": {"bx": tuned["bx"], "seg": tuned["seg"], "source": tuned["source"]},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
 
+def leg_c3(n, steps, warmup):
+    from paper_2404_01035_amd import inputs
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu = inputs.config_c3(n=(n, n, n))
+    s = Solver(p)
+    s.load(phi, mu)
+    del phi, mu
+    tuned = s.autotune(reps=5, force=True)
+    s.step(warmup)
+    with Timer() as t:
+        s.step(steps)
+    d = s.diagnostics()
+    s.close()
+    bpc = p.nfields * 2 * 4
+    ms_step = t.ms / steps
+    return {
+        "workload": f"3D {n}^3 binary dendrite, cubic anisotropy delta=0.02, no-flux, FP32",
+        "value": p.ncells * steps / (t.ms * 1e-3),
+        "unit": "cell-updates/s",
+        "steps": steps,
+        "ms_per_step": ms_step,
+        "roofline": roofline(p.ncells * bpc, ms_step),
+        "bytes_per_cell_update": bpc,
+        "tile": {"bx": tuned["bx"], "seg": tuned["seg"]},
+        "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
+    }
+
+
+def leg_c4(steps, warmup, graph_chunk=50):
+    from paper_2404_01035_amd import inputs
+    from paper_2404_01035_amd.solver import BatchSolver
+
+    members = inputs.config_c4()
+    b = BatchSolver([m[0] for m in members])
+    for i, (_, phi, mu) in enumerate(members):
+        b.load(i, phi, mu)
+    b.start(0)
+    cells = sum(m[0].ncells for m in members)
+    bytes_step = sum(m[0].ncells * m[0].nfields * 2 * 4 for m in members)
+    del members
+    tuned = b.autotune(reps=5, force=True)
+    b.set_graph(graph_chunk)
+    b.step(warmup)
+    with Timer() as t:
+        b.step(steps)
+    diags = b.diagnostics()
+    b.close()
+    ms_step = t.ms / steps
+    return {
+        "workload": "256 independent 2D instances, sides U{64..1024}, N in {2,3}, 1-2 mu fields, "
+                    "periodic, FP32, one persistent launch per step, HIP graphs of "
+                    f"{graph_chunk} steps",
+        "value": cells * steps / (t.ms * 1e-3),
+        "unit": "cell-updates/s",
+        "steps": steps,
+        "cells": cells,
+        "ms_per_step": ms_step,
+        "roofline": roofline(bytes_step, ms_step),
+        "tile": {"seg": tuned["seg"]},
+        "nonfinite_instances": sum(1 for d in diags if d["nonfinite"]),
+    }
+
+
+def leg_c5(nsteps, every=100, n=512):
+    """Checkpointed forward run and adjoint sweep at nominal theta; loss = 1/2 |phi^N - phi*|^2."""
+    import numpy as np
+    import torch
+
+    from paper_2404_01035_amd import inputs
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu, theta_star = inputs.config_c5(n=n)
+    # target from the hidden parameters (untimed)
+    s = Solver(inputs.theta_into(p, theta_star))
+    s.load(phi, mu)
+    s.step(nsteps)
+    target = s.current()[: p.nphases].clone()
+    s.close()
+
+    s = Solver(p)
+    s.load(phi, mu)
+    ckpt = s.checkpoint_buffer(nsteps, every)
+    s.step_ckpt(2, 1, s.checkpoint_buffer(2, 1))  # warm the kernels
+    s.load(phi, mu)
+    with Timer() as tf:
+        s.step_ckpt(nsteps, every, ckpt)
+    lam = torch.zeros_like(s.current())
+    lam[: p.nphases] = s.current()[: p.nphases] - target
+    loss = 0.5 * float((lam[: p.nphases].double() ** 2).sum())
+    s.adjoint(lam, ckpt, 2 * every, every, 0)  # warm
+    with Timer() as ta:
+        _, g = s.adjoint(lam, ckpt, nsteps, every, 0)
+    s.close()
+    grads = [g["gamma01"], g["gamma02"], g["gamma12"], g["D20"], g["D21"], g["tau"]]
+    return {
+        "workload": f"2D {n}x{n}, 3 phases, ternary, periodic, FP32 forward + FP32 adjoint, "
+                    f"{nsteps} steps, checkpoints every {every}",
+        "forward_ms": tf.ms,
+        "adjoint_ms": ta.ms,
+        "adjoint_over_forward": ta.ms / tf.ms,
+        "forward_cell_updates_per_s": p.ncells * nsteps / (tf.ms * 1e-3),
+        "loss": loss,
+        "grad_theta": dict(zip(["gamma01", "gamma02", "gamma12", "Dliq1", "Dliq2", "tau"],
+                               [float(v) for v in grads])),
+        "theta_star": [float(v) for v in np.asarray(theta_star)],
+    }
+
+
 def cpu_baseline(n):
-    """The FP64 oracle (numpy, one thread) on one full-grid step of the same workload."""
+    """The FP64 oracle (numpy, one thread) on one full-grid step of the headline workload."""
     from oracle import gp
     from paper_2404_01035_amd import inputs
 
@@ -139,19 +276,11 @@ def main():
     if a.copy_calibration:
         copy_calibration(a.n, a.steps)
         return
-    print(f"[bench] FP64 {a.n}x{a.n}: warmup {a.warmup}, timed {a.steps} steps", file=sys.stderr,
-          flush=True)
-    r64 = time_precision("f64", a.n, a.steps, a.warmup, a.tile)
-    r32 = None
-    if not a.no_fp32:
-        print(f"[bench] FP32 {a.n}x{a.n}", file=sys.stderr, flush=True)
-        r32 = time_precision("f32", a.n, a.steps, a.warmup, a.tile)
-    cpu = None
-    if not a.no_cpu:
-        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(a.n)
+    legs = [x for x in a.legs.split(",") if x]
+    log(f"FP64 {a.n}x{a.n}: warmup {a.warmup}, timed {a.steps} steps")
+    r64 = leg_c2("f64", a.n, a.steps, a.warmup, a.tile)
     out = {
-        "metric": "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost",
+        "metric": METRIC,
         "value": r64["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -172,16 +301,27 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r64["roofline"],
-        "cpu_baseline": cpu,
+        "tile": r64["tile"],
+        "diag": r64["diag"],
+        "cpu_baseline": None,
     }
-    if r32:
-        out["fp32"] = {
-            "value": r32["value"],
-            "ms_per_step": r32["ms_per_step"],
-            "roofline": r32["roofline"],
-            "dtype": "f32 (FP64 Lagrange multiplier and reductions)",
-        }
+    if "c2" in legs:
+        log(f"FP32 {a.n}x{a.n}")
+        r32 = leg_c2("f32", a.n, a.steps, a.warmup, a.tile)
+        out["fp32"] = dict(r32, dtype="f32 (FP64 Lagrange multiplier and reductions)")
         out["speedup_fp32_over_fp64"] = r32["value"] / r64["value"]
+    if "c3" in legs:
+        log(f"3D {a.n3d}^3 FP32")
+        out["dendrite_3d"] = leg_c3(a.n3d, a.steps3d, 5)
+    if "c4" in legs:
+        log("batched ensemble FP32")
+        out["batched"] = leg_c4(a.batch_steps, 50)
+    if "c5" in legs:
+        log("checkpointed forward + adjoint FP32")
+        out["adjoint"] = leg_c5(a.adjoint_steps)
+    if not a.no_cpu:
+        log("CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(a.n)
     print(json.dumps(out), flush=True)
 
 

@@ -156,6 +156,21 @@ int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
 int mp_set_tile(mp_state* st, int bx, int seg);
 int mp_get_tile(const mp_state* st, int* bx, int* seg);
 
+/* Autotuning support.  mp_tune_candidates writes up to ``cap`` (bx, seg)
+ * pairs that are valid for this state into cand[2*i], cand[2*i+1] and
+ * returns how many there are (a negative MP_E_* on error); cand may be NULL
+ * to query the count.  mp_tune times each of the ncand pairs in ``cand``:
+ * one untimed launch, then ``reps`` launches of one step from the current
+ * buffer into the other one, bracketed by events on ``stream``, and stores
+ * the mean milliseconds per launch in ms[i] (-1 for a pair the state
+ * rejects).  The current buffer and the time level are untouched; the other
+ * buffer is overwritten.  The fastest pair is set (as by mp_set_tile) and its
+ * index stored in *best.  Synchronises ``stream``.  Errors: MP_E_NULLPTR,
+ * MP_E_UNBOUND, MP_E_PARAM (ncand < 1, reps < 1 or no valid pair), MP_E_HIP. */
+int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap);
+int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, int* best,
+            void* stream);
+
 /* Replay steps as a HIP graph: chunk = steps per graph (even, >= 2), or 0 to
  * launch kernel by kernel (the default).  The graph is built explicitly (no
  * stream capture), so any stream works, the null stream included; it is
@@ -164,7 +179,8 @@ int mp_get_tile(const mp_state* st, int* bx, int* seg);
 int mp_set_graph(mp_state* st, int chunk);
 
 /* Batched states (many independent 2D simulations stepped together by one
- * persistent kernel launch per step; the north-star "batched ensemble").
+ * persistent kernel launch per step: an ensemble of uneven runs, which the
+ * paper itself does not have; its nearest notion is a set of boxes).
  * Instance i has grid grids[i] (dim must be 2), nphases[i] phases, ncomp[i]
  * components and coefficients params[i], each validated as by mp_create
  * (including its own dt limit).  All instances share precision and

@@ -32,6 +32,7 @@ EXPORTS = [
     "mp_current", "mp_set_step", "mp_diagnostics", "mp_set_tile", "mp_get_tile", "mp_destroy",
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
+    "mp_tune_candidates", "mp_tune",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -124,6 +125,11 @@ def lib():
         L.mp_adjoint.restype = C.c_int
         L.mp_adjoint.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int64, vp, vp,
                                  C.POINTER(C.c_double), vp, vp]
+        L.mp_tune_candidates.restype = C.c_int
+        L.mp_tune_candidates.argtypes = [vp, C.POINTER(C.c_int32), C.c_int]
+        L.mp_tune.restype = C.c_int
+        L.mp_tune.argtypes = [vp, C.POINTER(C.c_int32), C.c_int, C.c_int, C.POINTER(C.c_double),
+                              C.POINTER(C.c_int), vp]
         _lib = L
     return _lib
 
@@ -292,3 +298,23 @@ def mp_adjoint(st, ckpt_buf: int, nsteps: int, every: int, n0: int, lam_final: i
     _check(lib().mp_adjoint(st, ckpt_buf, int(nsteps), int(every), int(n0), lam_final,
                             lam_initial, g, work, stream))
     return dict(zip(GRAD_NAMES, list(g)))
+
+
+def mp_tune_candidates(st):
+    """The (bx, seg) tile pairs the library accepts for this state."""
+    L = lib()
+    n = L.mp_tune_candidates(st, None, 0)
+    _check(min(n, 0))
+    buf = (C.c_int32 * (2 * n))()
+    _check(min(L.mp_tune_candidates(st, buf, n), 0))
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(n)]
+
+
+def mp_tune(st, cand, reps: int, stream: int = 0):
+    """Time each (bx, seg) pair; returns (ms per launch list, index of the fastest, now set)."""
+    n = len(cand)
+    buf = (C.c_int32 * (2 * n))(*[int(v) for pair in cand for v in pair])
+    ms = (C.c_double * n)()
+    best = C.c_int(-1)
+    _check(lib().mp_tune(st, buf, n, int(reps), ms, C.byref(best), stream))
+    return list(ms), best.value

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import torch
 
-from . import abi
+from . import abi, inputs
 from .solver import Solver
 
 THETA_NAMES = ["gamma01", "gamma02", "gamma12", "Dliq1", "Dliq2", "tau"]
@@ -17,15 +17,7 @@ THETA_NAMES = ["gamma01", "gamma02", "gamma12", "Dliq1", "Dliq2", "tau"]
 
 def params_with_theta(p, theta):
     """A copy of p with theta written in (theta is a length-6 sequence of floats)."""
-    q = p.copy()
-    N = q.nphases
-    for idx, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
-        if b < N:
-            q.gamma[a, b] = q.gamma[b, a] = float(theta[idx])
-    for k in range(q.nmu):
-        q.D[N - 1, k] = float(theta[3 + k])
-    q.tau = float(theta[5])
-    return q
+    return inputs.theta_into(p, theta)
 
 
 def theta_of(p):

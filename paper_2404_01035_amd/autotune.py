@@ -1,0 +1,91 @@
+"""Tile-shape autotuner for the step kernels, with an on-disk cache.
+
+The library times each candidate (bx, seg) pair on the bound state itself
+(``mp_tune``: one step from the current buffer into the other, repeated, with
+events on the stream) and keeps the fastest.  The choice is cached per
+workload signature -- grid, phases, components, precision, potential,
+anisotropy, batch composition and device name -- in a JSON file, so later runs
+of the same workload set the tile without timing.  Results never depend on the
+tile (bitwise), only speed does.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import tempfile
+
+from . import abi
+
+CACHE_ENV = "MP_TUNE_CACHE"
+
+
+def default_cache_path() -> str:
+    p = os.environ.get(CACHE_ENV)
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_2404_01035_amd", "tiles.json")
+
+
+def _one(p) -> list:
+    return [p.dim, list(p.n), p.nphases, p.ncomp, bool(abs(p.delta).max() > 0)]
+
+
+def signature(plist, device: str) -> str:
+    """Cache key of a single (len 1) or batched workload on ``device``."""
+    p0 = plist[0]
+    body = {
+        "kind": "batch" if len(plist) > 1 else "single",
+        "precision": p0.precision,
+        "potential": p0.potential,
+        "device": device,
+    }
+    if len(plist) == 1:
+        body["grid"] = _one(p0)
+    else:
+        h = hashlib.sha1(json.dumps([_one(p) for p in plist]).encode()).hexdigest()[:16]
+        body["members"] = f"{len(plist)}:{h}"
+    return json.dumps(body, sort_keys=True)
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d or ".", prefix=".tiles.")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(st, plist, stream: int, device: str, reps: int = 10, cache: str | None = None,
+         force: bool = False) -> dict:
+    """Pick and set the tile of bound state ``st`` (built from ``plist``).
+
+    Returns {"bx", "seg", "source": "cache" | "timed", "ms": {"bx,seg": ms}}.
+    """
+    path = cache or default_cache_path()
+    key = signature(plist, device)
+    data = _load(path)
+    hit = data.get(key)
+    if hit and not force:
+        abi.mp_set_tile(st, hit["bx"], hit["seg"])
+        return dict(hit, source="cache")
+    cand = abi.mp_tune_candidates(st)
+    ms, best = abi.mp_tune(st, cand, reps, stream)
+    rec = {
+        "bx": cand[best][0],
+        "seg": cand[best][1],
+        "ms": {f"{b},{s}": t for (b, s), t in zip(cand, ms)},
+    }
+    data[key] = rec
+    _store(path, data)
+    return dict(rec, source="timed")

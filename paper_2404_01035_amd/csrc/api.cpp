@@ -793,6 +793,69 @@ int mp_get_tile(const mp_state* st, int* bx, int* seg) {
     return ok();
 }
 
+int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (cap < 0) return fail(MP_E_PARAM, "cap must be >= 0");
+    std::vector<int32_t> v;
+    const bool d3 = st->inst[0].grid.dim == 3;
+    if (d3) {
+        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64, seg});
+    } else if (st->batch) {
+        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg});
+    } else {
+        for (int bx : {64, 128, 256})
+            for (int seg : {8, 16, 32, 64, 128}) v.insert(v.end(), {bx, seg});
+    }
+    const int n = (int)(v.size() / 2);
+    if (cand)
+        for (int i = 0; i < n && i < cap; ++i) {
+            cand[2 * i] = v[2 * i];
+            cand[2 * i + 1] = v[2 * i + 1];
+        }
+    ok();
+    return n;
+}
+
+int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, int* best,
+            void* stream) {
+    if (!st || !cand || !ms || !best) return fail(MP_E_NULLPTR, "state, cand, ms or best is NULL");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_tune before mp_bind");
+    if (ncand < 1 || reps < 1) return fail(MP_E_PARAM, "ncand and reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const int bx0 = st->bx, seg0 = st->seg;
+    hipEvent_t e[2] = {nullptr, nullptr};
+    int rc = hip_check(hipEventCreate(&e[0]), "hipEventCreate");
+    if (rc == MP_OK) rc = hip_check(hipEventCreate(&e[1]), "hipEventCreate");
+    int bi = -1;
+    for (int i = 0; i < ncand && rc == MP_OK; ++i) {
+        ms[i] = -1.0;
+        if (mp_set_tile(st, cand[2 * i], cand[2 * i + 1]) != MP_OK) continue;
+        mp::KernelCall k;
+        if (make_step_call(st, 0, st->cur, k) != MP_OK) continue;
+        rc = launch(k, s);
+        if (rc == MP_OK) rc = hip_check(hipEventRecord(e[0], s), "hipEventRecord");
+        for (int r = 0; r < reps && rc == MP_OK; ++r) rc = launch(k, s);
+        if (rc == MP_OK) rc = hip_check(hipEventRecord(e[1], s), "hipEventRecord");
+        if (rc == MP_OK) rc = hip_check(hipEventSynchronize(e[1]), "hipEventSynchronize");
+        float t = 0.0f;
+        if (rc == MP_OK) rc = hip_check(hipEventElapsedTime(&t, e[0], e[1]), "hipEventElapsedTime");
+        if (rc != MP_OK) break;
+        ms[i] = (double)t / reps;
+        if (bi < 0 || ms[i] < ms[bi]) bi = i;
+    }
+    for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    if (rc != MP_OK || bi < 0) {
+        const std::string why = rc != MP_OK ? g_err : std::string("no valid tile candidate");
+        (void)mp_set_tile(st, bx0, seg0);
+        return fail(rc != MP_OK ? rc : MP_E_PARAM, "mp_tune: %s", why.c_str());
+    }
+    rc = mp_set_tile(st, cand[2 * bi], cand[2 * bi + 1]);
+    if (rc) return rc;
+    *best = bi;
+    return ok();
+}
+
 int mp_set_graph(mp_state* st, int chunk) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (chunk < 0 || (chunk > 0 && (chunk < 2 || chunk % 2)))

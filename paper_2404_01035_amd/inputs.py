@@ -403,3 +403,35 @@ def config_c4(ninst=256, seed=4, precision="f32", side=(64, 1024)):
         K = 1 + int(rng.integers(1, 3))
         out.append(random_instance(rng, nx, ny, N, K, precision=precision))
     return out
+
+
+def theta_into(p: Params, theta) -> Params:
+    """Copy of p with theta = (gamma_01, gamma_02, gamma_12, D^liq_1, D^liq_2, tau) written in."""
+    q = p.copy()
+    N = q.nphases
+    for idx, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
+        if b < N:
+            q.gamma[a, b] = q.gamma[b, a] = float(theta[idx])
+    for k in range(q.nmu):
+        q.D[N - 1, k] = float(theta[3 + k])
+    q.tau = float(theta[5])
+    return q
+
+
+def config_c5(n=512, seed=5, precision="f32", nuclei=8, undercooling=0.3):
+    """Differentiable run: 2D n x n, 3 phases, ternary, periodic.
+
+    Returns (p_nominal, phi0, mu0, theta_star).  theta_star = (three gamma_ab ~
+    U[0.5, 2], two liquid diffusivities log-uniform in [0.1, 10], tau ~ U[0.5, 2])
+    drives the target run; gradients are taken at the nominal theta = all ones.
+    dt is one value for both (0.2 of the smaller of the two explicit limits), so
+    that it stays fixed under perturbations of theta.
+    """
+    rng = np.random.default_rng(seed)
+    p, phi, mu = random_instance(rng, n, n, 3, 3, precision=precision,
+                                 undercooling=undercooling, nuclei=nuclei)
+    theta_star = list(rng.uniform(0.5, 2.0, size=3)) + \
+        list(np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=2))) + [rng.uniform(0.5, 2.0)]
+    p = theta_into(p, [1.0] * 6)
+    p.dt = 0.2 * min(dt_limit(p), dt_limit(theta_into(p, theta_star)))
+    return p, phi, mu, theta_star

@@ -66,6 +66,13 @@ class Solver:
         """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
         abi.mp_set_graph(self.st, chunk)
 
+    def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:
+        """Pick the fastest tile for this workload (cached on disk); the state is unchanged."""
+        from . import autotune
+
+        return autotune.tune(self.st, [self.p], self.stream(), torch.cuda.get_device_name(self.device),
+                             reps, cache, force)
+
     # ---- checkpointed run and adjoint -------------------------------------
     def checkpoint_buffer(self, nsteps: int, every: int) -> torch.Tensor:
         """Device buffer for ceil(nsteps / every) checkpoints (256-byte slots)."""
@@ -152,6 +159,13 @@ class BatchSolver:
 
     def set_graph(self, chunk: int):
         abi.mp_set_graph(self.st, chunk)
+
+    def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:
+        """Pick the fastest strip segment for this ensemble (cached on disk)."""
+        from . import autotune
+
+        return autotune.tune(self.st, self.plist, Solver.stream(),
+                             torch.cuda.get_device_name(self.device), reps, cache, force)
 
     @property
     def time_level(self) -> int:

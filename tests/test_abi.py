@@ -216,3 +216,38 @@ def test_adjoint_rejects_unsupported_variants_without_gpu():
         assert abi.mp_adjoint_work_bytes(bst, 5) == 0
     finally:
         abi.mp_destroy(bst)
+
+
+def test_tune_candidates_and_errors_without_gpu():
+    import ctypes as C
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        cand = abi.mp_tune_candidates(st)
+        assert len(cand) >= 4 and all(b in (64, 128, 256) and s >= 1 for b, s in cand)
+        for b, s in cand:  # every candidate is a tile the state accepts
+            abi.mp_set_tile(st, b, s)
+        L = abi.lib()
+        buf = (C.c_int32 * 2)(64, 16)
+        ms = (C.c_double * 1)()
+        best = C.c_int()
+        assert L.mp_tune(st, buf, 1, 3, ms, C.byref(best), None) == abi.MP_E_UNBOUND
+        assert L.mp_tune(st, None, 1, 3, ms, C.byref(best), None) == abi.MP_E_NULLPTR
+    finally:
+        abi.mp_destroy(st)
+    st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
+    try:
+        assert {b for b, _ in abi.mp_tune_candidates(st)} == {64}
+    finally:
+        abi.mp_destroy(st)
+
+
+def test_autotune_signature_distinguishes_workloads():
+    from paper_2404_01035_amd import autotune
+    p, _, _ = inputs.config_c1()
+    q = p.copy(precision="f32")
+    a = autotune.signature([p], "dev")
+    assert a == autotune.signature([p.copy()], "dev")
+    assert a != autotune.signature([q], "dev") and a != autotune.signature([p], "other")
+    members = [m[0] for m in inputs.config_c4(ninst=3, side=(64, 80))]
+    assert autotune.signature(members, "dev") != autotune.signature(members[:2], "dev")

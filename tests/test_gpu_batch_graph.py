@@ -123,3 +123,48 @@ def test_batch_diagnostics_match_single():
         d = s.diagnostics()
         s.close()
         assert d == dg[i], i
+
+
+def test_autotuner_keeps_results_and_caches(tmp_path):
+    from paper_2404_01035_amd.solver import BatchSolver, Solver
+
+    cache = str(tmp_path / "tiles.json")
+    p, phi, mu = inputs.config_c2(n=(300, 200, 1), precision="f64")
+    ref = _single(p, phi, mu, 9)
+    s = Solver(p)
+    try:
+        s.load(phi, mu)
+        r = s.autotune(reps=2, cache=cache)
+        assert r["source"] == "timed" and all(t > 0 for t in r["ms"].values())
+        assert abi_tile(s) == (r["bx"], r["seg"])
+        assert s.time_level == 0
+        s.step(9)
+        got = s.fields()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    finally:
+        s.close()
+    s = Solver(p)
+    try:
+        assert s.autotune(cache=cache)["source"] == "cache"
+    finally:
+        s.close()
+    members = _batch_members(5, seed=19, precision="f32")
+    bref, _ = _run_batch(members, 6)
+    b = BatchSolver([m[0] for m in members])
+    try:
+        for i, (_, phi, mu) in enumerate(members):
+            b.load(i, phi, mu)
+        b.start(0)
+        assert b.autotune(reps=2, cache=cache)["source"] == "timed"
+        b.step(6)
+        for i in range(len(members)):
+            f = b.fields(i)
+            assert np.array_equal(f[0], bref[i][0]) and np.array_equal(f[1], bref[i][1])
+    finally:
+        b.close()
+
+
+def abi_tile(s):
+    from paper_2404_01035_amd import abi
+
+    return abi.mp_get_tile(s.st)
