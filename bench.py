@@ -16,7 +16,7 @@ Further legs, each a block of the same JSON line:
 cpu_baseline   the FP64 oracle on one full 4096^2 step, on the host.
 
 Prints one JSON line.  Options: --gpus (only 1 is supported), --steps,
---warmup, --legs, --no-cpu, --n (2D grid side), --tile bx,seg (skips tuning).
+--warmup, --legs, --no-cpu, --n (2D grid side), --tile bx,seg,vec (skips tuning).
 """
 from __future__ import annotations
 
@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--legs", type=str, default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tile", type=str, default="", help="bx,seg for the 2D legs (no tuning)")
+    ap.add_argument("--tile", type=str, default="", help="bx,seg,vec for the 2D legs (no tuning)")
     ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--n3d", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=400)
@@ -112,9 +112,9 @@ def leg_c2(precision, n, steps, warmup, tile):
     s.load(phi, mu)
     del phi, mu
     if tile:
-        bx, seg = (int(v) for v in tile.split(","))
-        s.set_tile(bx, seg)
-        tuned = {"bx": bx, "seg": seg, "source": "--tile"}
+        bx, seg, vec = (int(v) for v in tile.split(","))
+        s.set_tile(bx, seg, vec)
+        tuned = {"bx": bx, "seg": seg, "vec": vec, "source": "--tile"}
     else:
         tuned = s.autotune(reps=10, force=True)
     s.step(warmup)
@@ -130,7 +130,7 @@ def leg_c2(precision, n, steps, warmup, tile):
         "ms_per_step": ms_step,
         "roofline": roofline(p.ncells * bpc, ms_step),
         "bytes_per_cell_update": bpc,
-        "tile": {"bx": tuned["bx"], "seg": tuned["seg"], "source": tuned["source"]},
+        "tile": {k: tuned[k] for k in ("bx", "seg", "vec", "source")},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
@@ -159,7 +159,7 @@ def leg_c3(n, steps, warmup):
         "ms_per_step": ms_step,
         "roofline": roofline(p.ncells * bpc, ms_step),
         "bytes_per_cell_update": bpc,
-        "tile": {"bx": tuned["bx"], "seg": tuned["seg"]},
+        "tile": {"bx": tuned["bx"], "seg": tuned["seg"], "vec": tuned["vec"]},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
@@ -194,7 +194,7 @@ def leg_c4(steps, warmup, graph_chunk=50):
         "cells": cells,
         "ms_per_step": ms_step,
         "roofline": roofline(bytes_step, ms_step),
-        "tile": {"seg": tuned["seg"]},
+        "tile": {"seg": tuned["seg"], "vec": tuned["vec"]},
         "nonfinite_instances": sum(1 for d in diags if d["nonfinite"]),
     }
 

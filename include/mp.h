@@ -150,23 +150,26 @@ int mp_set_step(mp_state* st, int64_t step, int which_buf);
 int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
 
 /* Tile shape of the step kernel.  2D: bx = threads per block (64, 128 or
- * 256: 1, 2 or 4 independent strip waves) and seg = rows per strip segment.
- * 3D: bx = 64 (64 x 4 tiles) and seg = z planes per block.  0 keeps the
- * current value.  Results do not depend on the tile shape (bitwise). */
-int mp_set_tile(mp_state* st, int bx, int seg);
-int mp_get_tile(const mp_state* st, int* bx, int* seg);
+ * 256: 1, 2 or 4 independent strip waves), seg = rows per strip segment and
+ * vec = the most cells one lane holds (1, 2, or 4 in FP32 only; each lane
+ * takes the largest power of two <= vec that divides nx; -1 = the widest the
+ * precision allows, which is the default).  3D: bx = 64 (64 x 4 tiles), seg =
+ * z planes per block, vec must be 0 or 1.  0 keeps the current value of a
+ * field.  Results do not depend on the tile shape (bitwise). */
+int mp_set_tile(mp_state* st, int bx, int seg, int vec);
+int mp_get_tile(const mp_state* st, int* bx, int* seg, int* vec);
 
-/* Autotuning support.  mp_tune_candidates writes up to ``cap`` (bx, seg)
- * pairs that are valid for this state into cand[2*i], cand[2*i+1] and
- * returns how many there are (a negative MP_E_* on error); cand may be NULL
- * to query the count.  mp_tune times each of the ncand pairs in ``cand``:
+/* Autotuning support.  mp_tune_candidates writes up to ``cap`` (bx, seg, vec)
+ * triples that are valid for this state into cand[3*i .. 3*i+2] and returns
+ * how many there are (a negative MP_E_* on error); cand may be NULL to query
+ * the count.  mp_tune times each of the ncand triples in ``cand``:
  * one untimed launch, then ``reps`` launches of one step from the current
  * buffer into the other one, bracketed by events on ``stream``, and stores
- * the mean milliseconds per launch in ms[i] (-1 for a pair the state
+ * the mean milliseconds per launch in ms[i] (-1 for a triple the state
  * rejects).  The current buffer and the time level are untouched; the other
- * buffer is overwritten.  The fastest pair is set (as by mp_set_tile) and its
+ * buffer is overwritten.  The fastest one is set (as by mp_set_tile) and its
  * index stored in *best.  Synchronises ``stream``.  Errors: MP_E_NULLPTR,
- * MP_E_UNBOUND, MP_E_PARAM (ncand < 1, reps < 1 or no valid pair), MP_E_HIP. */
+ * MP_E_UNBOUND, MP_E_PARAM (ncand < 1, reps < 1 or no valid triple), MP_E_HIP. */
 int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap);
 int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, int* best,
             void* stream);

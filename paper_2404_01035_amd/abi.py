@@ -100,9 +100,9 @@ def lib():
         L.mp_diagnostics.restype = C.c_int
         L.mp_diagnostics.argtypes = [vp, C.POINTER(mp_diag), vp]
         L.mp_set_tile.restype = C.c_int
-        L.mp_set_tile.argtypes = [vp, C.c_int, C.c_int]
+        L.mp_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mp_get_tile.restype = C.c_int
-        L.mp_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mp_get_tile.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mp_destroy.restype = None
         L.mp_destroy.argtypes = [vp]
         L.mp_last_error.restype = C.c_char_p
@@ -268,14 +268,14 @@ def mp_set_graph(st, chunk: int):
     _check(lib().mp_set_graph(st, int(chunk)))
 
 
-def mp_set_tile(st, bx: int = 0, seg: int = 0):
-    _check(lib().mp_set_tile(st, int(bx), int(seg)))
+def mp_set_tile(st, bx: int = 0, seg: int = 0, vec: int = 0):
+    _check(lib().mp_set_tile(st, int(bx), int(seg), int(vec)))
 
 
 def mp_get_tile(st):
-    bx, seg = C.c_int(), C.c_int()
-    _check(lib().mp_get_tile(st, C.byref(bx), C.byref(seg)))
-    return bx.value, seg.value
+    bx, seg, vec = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().mp_get_tile(st, C.byref(bx), C.byref(seg), C.byref(vec)))
+    return bx.value, seg.value, vec.value
 
 
 def mp_destroy(st):
@@ -301,19 +301,19 @@ def mp_adjoint(st, ckpt_buf: int, nsteps: int, every: int, n0: int, lam_final: i
 
 
 def mp_tune_candidates(st):
-    """The (bx, seg) tile pairs the library accepts for this state."""
+    """The (bx, seg, vec) tile triples the library accepts for this state."""
     L = lib()
     n = L.mp_tune_candidates(st, None, 0)
     _check(min(n, 0))
-    buf = (C.c_int32 * (2 * n))()
+    buf = (C.c_int32 * (3 * n))()
     _check(min(L.mp_tune_candidates(st, buf, n), 0))
-    return [(buf[2 * i], buf[2 * i + 1]) for i in range(n)]
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(n)]
 
 
 def mp_tune(st, cand, reps: int, stream: int = 0):
-    """Time each (bx, seg) pair; returns (ms per launch list, index of the fastest, now set)."""
+    """Time each (bx, seg, vec) triple; returns (ms per launch list, index of the fastest, now set)."""
     n = len(cand)
-    buf = (C.c_int32 * (2 * n))(*[int(v) for pair in cand for v in pair])
+    buf = (C.c_int32 * (3 * n))(*[int(v) for tri in cand for v in tri])
     ms = (C.c_double * n)()
     best = C.c_int(-1)
     _check(lib().mp_tune(st, buf, n, int(reps), ms, C.byref(best), stream))

@@ -1,6 +1,6 @@
 """Tile-shape autotuner for the step kernels, with an on-disk cache.
 
-The library times each candidate (bx, seg) pair on the bound state itself
+The library times each candidate (bx, seg, vec) tile on the bound state itself
 (``mp_tune``: one step from the current buffer into the other, repeated, with
 events on the stream) and keeps the fastest.  The choice is cached per
 workload signature -- grid, phases, components, precision, potential,
@@ -70,21 +70,22 @@ def tune(st, plist, stream: int, device: str, reps: int = 10, cache: str | None 
          force: bool = False) -> dict:
     """Pick and set the tile of bound state ``st`` (built from ``plist``).
 
-    Returns {"bx", "seg", "source": "cache" | "timed", "ms": {"bx,seg": ms}}.
+    Returns {"bx", "seg", "vec", "source": "cache" | "timed", "ms": {"bx,seg,vec": ms}}.
     """
     path = cache or default_cache_path()
     key = signature(plist, device)
     data = _load(path)
     hit = data.get(key)
     if hit and not force:
-        abi.mp_set_tile(st, hit["bx"], hit["seg"])
+        abi.mp_set_tile(st, hit["bx"], hit["seg"], hit["vec"])
         return dict(hit, source="cache")
     cand = abi.mp_tune_candidates(st)
     ms, best = abi.mp_tune(st, cand, reps, stream)
     rec = {
         "bx": cand[best][0],
         "seg": cand[best][1],
-        "ms": {f"{b},{s}": t for (b, s), t in zip(cand, ms)},
+        "vec": cand[best][2],
+        "ms": {f"{b},{s},{v}": t for (b, s, v), t in zip(cand, ms)},
     }
     data[key] = rec
     _store(path, data)

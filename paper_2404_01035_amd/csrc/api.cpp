@@ -44,7 +44,7 @@ struct mp_state {
     bool bound;
     int cur;
     int64_t step;
-    int bx, seg;
+    int bx, seg, vec;  // vec: cap on cells per lane of the 2D strips (-1: none)
     int graph_chunk;
     hipGraphExec_t gexec[2];  // by starting buffer
     std::vector<mp::KernelCall> gcalls[2];  // argument records of each graph's nodes, kept alive
@@ -242,7 +242,14 @@ int hip_check(hipError_t e, const char* what) {
     return MP_OK;
 }
 
-int strips_of(const Inst& I) { return (int)((I.grid.n[0] + mp::W2D_OUT_HOST - 1) / mp::W2D_OUT_HOST); }
+// Strip waves across one row of a 2D instance (62 written lanes of vec_of cells each).
+int vec_of(const mp_state* st, const Inst& I) {
+    return mp::vec2d_width(I.grid.n[0], (int)elem_of(I.prm.precision), st->vec);
+}
+int strips_of(const mp_state* st, const Inst& I) {
+    const int64_t w = mp::W2D_LANES_OUT_HOST * vec_of(st, I);
+    return (int)((I.grid.n[0] + w - 1) / w);
+}
 
 // ---- workspace layout -------------------------------------------------------
 // [diag partials + one result record per instance][time level][instance table][work list]
@@ -260,7 +267,7 @@ size_t ws_items_off(const mp_state* st) { return ws_table_off(st) + table_bytes(
 size_t items_capacity(const mp_state* st) {
     if (!st->batch) return 0;
     size_t n = 0;  // the work list is longest at seg = 1: one item per strip and row
-    for (const Inst& I : st->inst) n += (size_t)strips_of(I) * (size_t)I.grid.n[1];
+    for (const Inst& I : st->inst) n += (size_t)strips_of(st, I) * (size_t)I.grid.n[1];
     return n;
 }
 
@@ -281,7 +288,7 @@ void build_items(mp_state* st) {
     for (size_t i = 0; i < st->inst.size(); ++i) {
         const Inst& I = st->inst[i];
         const int nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
-        st->item_inst.insert(st->item_inst.end(), (size_t)strips_of(I) * nseg, (int)i);
+        st->item_inst.insert(st->item_inst.end(), (size_t)strips_of(st, I) * nseg, (int)i);
     }
     st->nitems = (int)st->item_inst.size();
 }
@@ -297,7 +304,8 @@ int upload_table(mp_state* st) {
         d.g = make_geom(I.grid);
         d.np = I.N;
         d.nm = I.K - 1;
-        d.ntx = strips_of(I);
+        d.ntx = strips_of(st, I);
+        d.vec = vec_of(st, I);
         d.seg = st->seg;
         d.nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
         d.item0 = item0;
@@ -388,6 +396,7 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.aniso = I.aniso ? 1 : 0;
     L.bx = st->bx;
     L.seg = st->seg;
+    L.vec = st->vec;
     L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
@@ -449,15 +458,18 @@ void init_state(mp_state* st) {
     st->aniso = false;
     for (const Inst& I : st->inst) st->aniso = st->aniso || I.aniso;
     st->precision = st->inst[0].prm.precision;
+    st->vec = -1;
     st->potential = st->inst[0].prm.potential;
     if (st->inst[0].grid.dim == 3) {
         st->bx = 64;
         st->seg = 16;
     } else {
-        // measured best on 4096^2 (both precisions): short segments keep enough
-        // waves in flight to cover HBM latency
-        st->bx = st->batch ? 64 * mp::BATCH_WPB_HOST : 256;
-        st->seg = 16;
+        // measured best on 4096^2: short segments keep enough waves in flight
+        // to cover HBM latency; one FP64 cell per lane keeps two waves per
+        // SIMD without spills, two FP32 cells per lane give 8-byte accesses
+        st->bx = st->batch ? 64 * mp::BATCH_WPB_HOST : (st->precision == MP_FP64 ? 128 : 64);
+        st->seg = st->batch ? 4 : 8;
+        st->vec = st->precision == MP_FP64 ? 1 : 2;
     }
 }
 
@@ -765,7 +777,7 @@ int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream) {
     return diag_many(st, out, stream);
 }
 
-int mp_set_tile(mp_state* st, int bx, int seg) {
+int mp_set_tile(mp_state* st, int bx, int seg, int vec) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     const bool d3 = st->inst[0].grid.dim == 3;
     if (bx) {
@@ -774,22 +786,27 @@ int mp_set_tile(mp_state* st, int bx, int seg) {
         if (!okbx) return fail(MP_E_PARAM, "unsupported tile width %d", bx);
     }
     if (seg < 0) return fail(MP_E_PARAM, "seg must be >= 1");
+    if (vec) {
+        const int vmax = st->precision == MP_FP64 ? 2 : 4;
+        const bool okv = d3 ? vec == 1 : (vec == -1 || vec == 1 || vec == 2 || vec == 4);
+        if (!okv || vec > vmax) return fail(MP_E_PARAM, "unsupported cells per lane %d", vec);
+    }
     drop_graphs(st);
     if (bx) st->bx = bx;
-    if (seg) {
-        st->seg = seg;
-        if (st->batch) {
-            const int rc = sync_batch(st);
-            if (rc) return rc;
-        }
+    if (vec) st->vec = d3 ? -1 : vec;
+    if (seg) st->seg = seg;
+    if ((seg || vec) && st->batch) {
+        const int rc = sync_batch(st);
+        if (rc) return rc;
     }
     return ok();
 }
 
-int mp_get_tile(const mp_state* st, int* bx, int* seg) {
+int mp_get_tile(const mp_state* st, int* bx, int* seg, int* vec) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (bx) *bx = st->bx;
     if (seg) *seg = st->seg;
+    if (vec) *vec = st->vec;
     return ok();
 }
 
@@ -798,20 +815,21 @@ int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap) {
     if (cap < 0) return fail(MP_E_PARAM, "cap must be >= 0");
     std::vector<int32_t> v;
     const bool d3 = st->inst[0].grid.dim == 3;
+    const int vmax = st->precision == MP_FP64 ? 2 : 4;
     if (d3) {
-        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64, seg});
+        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64, seg, 1});
     } else if (st->batch) {
-        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg});
+        for (int vec = 1; vec <= vmax; vec *= 2)
+            for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg, vec});
     } else {
-        for (int bx : {64, 128, 256})
-            for (int seg : {8, 16, 32, 64, 128}) v.insert(v.end(), {bx, seg});
+        for (int vec = 1; vec <= vmax; vec *= 2)
+            for (int bx : {64, 128, 256})
+                for (int seg : {8, 16, 32, 64, 128}) v.insert(v.end(), {bx, seg, vec});
     }
-    const int n = (int)(v.size() / 2);
+    const int n = (int)(v.size() / 3);
     if (cand)
-        for (int i = 0; i < n && i < cap; ++i) {
-            cand[2 * i] = v[2 * i];
-            cand[2 * i + 1] = v[2 * i + 1];
-        }
+        for (int i = 0; i < n && i < cap; ++i)
+            for (int j = 0; j < 3; ++j) cand[3 * i + j] = v[3 * i + j];
     ok();
     return n;
 }
@@ -822,14 +840,14 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_tune before mp_bind");
     if (ncand < 1 || reps < 1) return fail(MP_E_PARAM, "ncand and reps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    const int bx0 = st->bx, seg0 = st->seg;
+    const int bx0 = st->bx, seg0 = st->seg, vec0 = st->vec;
     hipEvent_t e[2] = {nullptr, nullptr};
     int rc = hip_check(hipEventCreate(&e[0]), "hipEventCreate");
     if (rc == MP_OK) rc = hip_check(hipEventCreate(&e[1]), "hipEventCreate");
     int bi = -1;
     for (int i = 0; i < ncand && rc == MP_OK; ++i) {
         ms[i] = -1.0;
-        if (mp_set_tile(st, cand[2 * i], cand[2 * i + 1]) != MP_OK) continue;
+        if (mp_set_tile(st, cand[3 * i], cand[3 * i + 1], cand[3 * i + 2]) != MP_OK) continue;
         mp::KernelCall k;
         if (make_step_call(st, 0, st->cur, k) != MP_OK) continue;
         rc = launch(k, s);
@@ -847,10 +865,10 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
         if (x) (void)hipEventDestroy(x);
     if (rc != MP_OK || bi < 0) {
         const std::string why = rc != MP_OK ? g_err : std::string("no valid tile candidate");
-        (void)mp_set_tile(st, bx0, seg0);
+        (void)mp_set_tile(st, bx0, seg0, vec0);
         return fail(rc != MP_OK ? rc : MP_E_PARAM, "mp_tune: %s", why.c_str());
     }
-    rc = mp_set_tile(st, cand[2 * bi], cand[2 * bi + 1]);
+    rc = mp_set_tile(st, cand[3 * bi], cand[3 * bi + 1], cand[3 * bi + 2]);
     if (rc) return rc;
     *best = bi;
     return ok();

@@ -1,6 +1,6 @@
 // Batched 2D step: many independent simulations in one persistent launch.
 //
-// The work list holds one item per (instance, 62-column strip, row segment),
+// The work list holds one item per (instance, column strip, row segment),
 // instance by instance; item_inst[i] names the instance of item i and the
 // instance table (InstDesc) carries its grid, sizes, coefficients, state
 // offset and temperature law.  The grid is sized to what stays resident; each
@@ -16,8 +16,40 @@ namespace mp {
 
 constexpr int BATCH_WPB = BATCH_WPB_HOST;  // waves per block
 
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+__device__ __forceinline__ void run_vec(const R* src, R* dst, const InstDesc<R>& d, double tbase,
+                                        int tx, int m0, int m1) {
+    if (d.vec == 1) {
+        strip2d<R, NP, NM, ANISO, OBST, 1>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+    } else if (sizeof(R) == 8 || d.vec == 2) {
+        strip2d<R, NP, NM, ANISO, OBST, 2>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+    } else {
+        strip2d<R, NP, NM, ANISO, OBST, 16 / sizeof(R)>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0,
+                                                        m1);
+    }
+}
+
 template <typename R, bool ANISO, bool OBST>
-__global__ void __launch_bounds__(64 * BATCH_WPB)
+__device__ __forceinline__ void run_item(const R* src, R* dst, const InstDesc<R>& d, double tbase,
+                                         int tx, int m0, int m1) {
+    switch (d.np * 4 + d.nm) {
+        case 2 * 4 + 1:
+            run_vec<R, 2, 1, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            break;
+        case 2 * 4 + 2:
+            run_vec<R, 2, 2, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            break;
+        case 3 * 4 + 1:
+            run_vec<R, 3, 1, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            break;
+        default:
+            run_vec<R, 3, 2, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            break;
+    }
+}
+
+template <typename R, bool ANISO, bool OBST>
+__global__ void __launch_bounds__(64 * BATCH_WPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __restrict__ tab,
           const int* __restrict__ item_inst, int nitems, const int64_t* __restrict__ stepctr,
           int kstep) {
@@ -39,20 +71,7 @@ k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __re
         const double tbase = d.tb0 + d.tdn * (double)n;
         const R* src = in + d.off;
         R* dst = out + d.off;
-        switch (d.np * 4 + d.nm) {
-            case 2 * 4 + 1:
-                strip2d<R, 2, 1, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-                break;
-            case 2 * 4 + 2:
-                strip2d<R, 2, 2, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-                break;
-            case 3 * 4 + 1:
-                strip2d<R, 3, 1, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-                break;
-            default:
-                strip2d<R, 3, 2, ANISO, OBST>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-                break;
-        }
+        run_item<R, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
     }
 }
 

@@ -55,7 +55,7 @@ struct StepLaunch {
     void* out;
     Geom g;
     int nphases, nmu, dim, potential, aniso;
-    int bx, seg;
+    int bx, seg, vec;
     const int64_t* stepctr;
     int kstep;
     double tb0, tdn, tslope;
@@ -84,6 +84,7 @@ struct InstDesc {
     Geom g;
     int32_t np, nm;
     int32_t ntx, nseg, seg, item0;  // work items item0 .. item0 + ntx*nseg - 1
+    int32_t vec;                    // cells per lane of the strip kernel (vec2d_width)
     int64_t off;                    // element offset of the instance's state
     double tb0, tdn, tslope;        // T - Te = tb0 + tdn * n + tslope * j
     Coef<R> c;
@@ -124,9 +125,21 @@ int adj_launch(const AdjLaunch& L, const AdjCoef<R>& c, hipStream_t s);
 void adj_fill(double* p, int64_t n, double v, hipStream_t s);
 void adj_reduce(const double* acc, int nrows, double* out, hipStream_t s);
 
-// Tile constants shared with the host: columns written per 2D strip wave,
+// Cells per lane of the 2D strip kernel: the widest power of two up to
+// min(16 / elem, cap) (cap <= 0: no cap) that divides the row length, so that
+// each lane's cells form one aligned vector.  A strip wave writes
+// W2D_LANES_OUT_HOST lanes' worth of columns.
+__host__ __device__ inline int vec2d_width(int64_t nx, int elem, int cap) {
+    int v = 16 / elem;
+    while (cap > 0 && v > cap) v /= 2;
+    for (; v > 1; v /= 2)
+        if (nx % v == 0) return v;
+    return 1;
+}
+
+// Written lanes per 2D strip wave (lanes 1..62; 0 and 63 hold the halo),
 // waves per block of the batched kernel.
-constexpr int W2D_OUT_HOST = 62;
+constexpr int W2D_LANES_OUT_HOST = 62;
 constexpr int BATCH_WPB_HOST = 4;
 inline int batch_waves_per_block_host() { return BATCH_WPB_HOST; }
 

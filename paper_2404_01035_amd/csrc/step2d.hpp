@@ -1,190 +1,360 @@
 // 2D fused phi + mu step: one wave per column strip, no LDS, no barriers.
 //
-// A wave owns 64 consecutive columns, x0-1 .. x0+62, and writes the 62 inner
-// ones (lanes 1..62); neighbouring waves overlap by two columns.  It walks a
-// segment of rows (y, the slowest axis) keeping its own column's cells of
-// rows m-1 (anisotropy only), m and m+1 in registers; the x neighbours come
-// from the adjacent lanes through ds_bpermute.  Every face is evaluated once:
-// lane t computes the x face (t, t+1) and passes its W, J to lane t+1; the y
-// face (m, m+1) is kept and becomes the lower face of row m+1.  Rows are
-// loaded two at a time, two rows ahead of use, with one wait per pair (see the
-// row loop).  Waves are independent, so there is
-// no block-level synchronisation at all; consecutive waves of a block take
-// neighbouring strips, and blocks are dealt XCD-aware so that a band of strips
-// shares one XCD's L2.
+// A lane owns V consecutive cells of a row (V * sizeof(R) <= 16 bytes, so a
+// lane moves one aligned vector per field; V divides nx).  A wave's 64 lanes
+// cover the 64 V columns xs .. xs + 64 V - 1, xs = tx * 62 V - V: lanes 1..62
+// hold the strip's 62 V cells and are the ones written; lane 0 and lane 63
+// hold the columns just outside it (only lane 0's last and lane 63's first
+// cell matter), so neighbouring strips overlap by 2 V columns.  The wave
+// walks a segment of rows [m0, m1) of the slowest axis y, keeping the cell
+// records of rows m and m+1 in registers.  Every face is evaluated once per
+// wave: lane t evaluates the V x faces to the right of its cells (the last one
+// with lane t+1's first cell, fetched through ds_bpermute) and passes the last
+// face's W, J to lane t+1; the y face (m, m+1) is kept and becomes the lower
+// face of row m+1.  Out-of-range columns come from the boundary map: a lane
+// lying wholly outside the grid loads the aligned vector holding its ghost
+// column and, for a mirror boundary, moves that value into the slot the
+// neighbouring lane reads.  Consecutive waves of a block take neighbouring
+// strips; blocks are dealt XCD-aware so that a band of strips shares one
+// XCD's L2.
 #pragma once
 
 #include "gp_device.hpp"
 
 namespace mp {
 
-template <typename R, int NP, int NM, bool ANISO>
-struct Cell2d {
-    R phi[NP];
-    R mu[NM];
-    R Mt[NM];
-    R h[NP];
-    R cdx[ANISO ? NP : 1];  // phi(x+1) - phi(x-1) on this row
+template <typename R, int V>
+struct Vec;
+template <>
+struct Vec<double, 1> {
+    typedef double T;
+};
+template <>
+struct Vec<double, 2> {
+    typedef double T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<float, 1> {
+    typedef float T;
+};
+template <>
+struct Vec<float, 2> {
+    typedef float T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec<float, 4> {
+    typedef float T __attribute__((ext_vector_type(4)));
 };
 
-constexpr int W2D_OUT = W2D_OUT_HOST;  // columns written per wave
+template <typename R, int V>
+__device__ __forceinline__ void vload(const R* p, R (&v)[V]) {
+    if constexpr (V == 1) {
+        v[0] = *p;
+    } else {
+        const typename Vec<R, V>::T t = *reinterpret_cast<const typename Vec<R, V>::T*>(p);
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = t[i];
+    }
+}
 
-// One wave's strip: columns tx*62-1 .. tx*62+62 of a 2D field, rows [m0, m1).
-// Called with wave-uniform arguments by the single-grid and the batched kernel.
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+template <typename R, int V>
+__device__ __forceinline__ void vstore(R* p, const R (&v)[V]) {
+    if constexpr (V == 1) {
+        *p = v[0];
+    } else {
+        typename Vec<R, V>::T t;
+#pragma unroll
+        for (int i = 0; i < V; ++i) t[i] = v[i];
+        *reinterpret_cast<typename Vec<R, V>::T*>(p) = t;
+    }
+}
+
+constexpr int W2D_LANES_OUT = W2D_LANES_OUT_HOST;  // written lanes per strip wave
+
+// Raw row as loaded: the lane's V cells of every field.
+template <typename R, int NF, int V>
+struct Raw2d {
+    R v[NF][V];
+};
+
+// Cell record of one row (cell-major); for anisotropy also the x central
+// differences phi(x+1) - phi(x-1).
+template <typename R, int NP, int NM, int V, bool ANISO>
+struct Row2d {
+    R phi[V][NP];
+    R mu[V][NM];
+    R Mt[V][NM];
+    R cdx[ANISO ? V : 1][NP];
+};
+
+#ifndef MP_STRIP_DEPTH
+#define MP_STRIP_DEPTH 2
+#endif
+
+// One wave's strip: columns tx*62V .. tx*62V + 62V - 1 (lanes 1..62), rows
+// [m0, m1).  Called with wave-uniform arguments by the single-grid and the
+// batched kernel.  Requires nx % V == 0.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int DEPTH = MP_STRIP_DEPTH>
 __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                         const Coef<R>& c, double tbase, double tslope, int tx,
                                         int m0, int m1) {
     constexpr int NF = NP + NM;
-    typedef Cell2d<R, NP, NM, ANISO> CellT;
+    typedef Raw2d<R, NF, V> RawT;
+    typedef Row2d<R, NP, NM, V, ANISO> RowT;
     const int lane = threadIdx.x & 63;
-    const int gx = tx * W2D_OUT - 1 + lane;
     const bool perx = g.bcx == MP_BC_PERIODIC;
     const bool pery = g.bcy == MP_BC_PERIODIC;
-    const int col = gmap(gx, g.nx, perx);
+    const int nx = g.nx;
     const int64_t fs = g.fstride;
-    const int64_t nx = g.nx;
+    const int cs = (tx * W2D_LANES_OUT - 1 + lane) * V;  // first column of the lane
+    // load column: the lane's own, or the aligned vector holding its ghost
+    int col = cs;
+    bool fixL = false, fixR = false;  // mirror ghosts: move the ghost value into the read slot
+    if (cs < 0) {
+        col = perx ? nx - V : 0;
+        fixL = !perx;
+    } else if (cs >= nx) {
+        col = perx ? 0 : nx - V;
+        fixR = !perx;
+    }
+    const bool writes = lane >= 1 && lane <= W2D_LANES_OUT && cs < nx;
     const int aR = ((lane + 1) & 63) << 2;
     const int aL = ((lane + 63) & 63) << 2;
-    const bool writes = lane >= 1 && lane <= W2D_OUT && gx < g.nx;
 
-    auto load = [&](int m, R (&v)[NF]) {
+    auto load = [&](int m, RawT& r) {
         const int64_t o = (int64_t)gmap(m, g.ny, pery) * nx + col;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[f] = in[f * fs + o];
+        for (int f = 0; f < NF; ++f) vload<R, V>(in + f * fs + o, r.v[f]);
     };
-    auto process = [&](const R (&v)[NF], CellT& P) {
+    auto process = [&](const RawT& r, RowT& P) {
 #pragma unroll
-        for (int a = 0; a < NP; ++a) P.phi[a] = v[a];
+        for (int i = 0; i < V; ++i) {
 #pragma unroll
-        for (int k = 0; k < NM; ++k) P.mu[k] = v[NP + k];
-        interp_h<R, NP>(P.phi, P.h);
-        mobility<R, NP, NM>(P.h, c, P.Mt);
-        if constexpr (ANISO) {
+            for (int a = 0; a < NP; ++a) P.phi[i][a] = r.v[a][i];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) P.cdx[a] = lane_get(P.phi[a], aR) - lane_get(P.phi[a], aL);
+            for (int k = 0; k < NM; ++k) P.mu[i][k] = r.v[NP + k][i];
         }
-    };
-    R Wlo0[NP], Jlo0[NM], Wlo1[NP], Jlo1[NM];  // lower y faces, alternating per row
-    auto yface = [&](const CellT& A, const CellT& B, R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
-        R tau[1][NP];
-        if constexpr (ANISO) {
+        if constexpr (V > 1) {
+            // a mirror ghost lane on the left is read at its last slot, one on
+            // the right at its first slot
 #pragma unroll
-            for (int a = 0; a < NP; ++a) tau[0][a] = A.cdx[a] + B.cdx[a];
+            for (int a = 0; a < NP; ++a) {
+                P.phi[V - 1][a] = fixL ? P.phi[0][a] : P.phi[V - 1][a];
+                P.phi[0][a] = fixR ? P.phi[V - 1][a] : P.phi[0][a];
+            }
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                P.mu[V - 1][k] = fixL ? P.mu[0][k] : P.mu[V - 1][k];
+                P.mu[0][k] = fixR ? P.mu[V - 1][k] : P.mu[0][k];
+            }
         }
-        face_core<R, NP, NM, ANISO, 1>(A.phi, B.phi, tau, A.Mt, B.Mt, A.mu, B.mu, c, U, Wf, J);
-    };
-
-    // Prologue: rows m0-1, m0, m0+1 processed, rows m0+2 and m0+3 in flight.
-    R v0[NF], v1[NF], v2[NF], ldA[NF], ldB[NF], ldC[NF], ldD[NF];
-    load(m0 - 1, v0);
-    load(m0, v1);
-    load(m0 + 1, v2);
-    if (m0 + 2 <= m1) load(m0 + 2, ldA);
-    if (m0 + 3 <= m1) load(m0 + 3, ldB);
-    CellT cA, cB;
-    R prvphi[ANISO ? NP : 1];
-    {
-        CellT prv;
-        process(v0, prv);
-        process(v1, cA);
-        process(v2, cB);
-        if constexpr (ANISO) {
 #pragma unroll
-            for (int a = 0; a < NP; ++a) prvphi[a] = prv.phi[a];
+        for (int i = 0; i < V; ++i) {
+            R hh[NP];
+            interp_h<R, NP>(P.phi[i], hh);
+            mobility<R, NP, NM>(hh, c, P.Mt[i]);
         }
-        R Ud[NP];
-        yface(prv, cA, Ud, Wlo0, Jlo0);
-    }
-
-    // One row.  On entry cur = row m, nxt = row m+1 and ldX holds the raw row
-    // m+2; the call ends by turning ldX into the cell record of row m+2 in
-    // cur's storage, so the next row is computed with the roles swapped.
-    auto row = [&](int m, CellT& cur, CellT& nxt, const R (&ldX)[NF], const R (&Wlo)[NP],
-                   const R (&Jlo)[NM], R (&Wy)[NP], R (&Jy)[NM]) {
-        // x face (t, t+1) on row m
-        R pR[NP], uR[NM], MR[NM];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) pR[a] = lane_get(cur.phi[a], aR);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            uR[k] = lane_get(cur.mu[k], aR);
-            MR[k] = lane_get(cur.Mt[k], aR);
-        }
-        R taux[1][NP];
         if constexpr (ANISO) {
 #pragma unroll
             for (int a = 0; a < NP; ++a) {
-                R cdy = nxt.phi[a] - prvphi[a];
-                taux[0][a] = cdy + lane_get(cdy, aR);
+                const R left = lane_get(P.phi[V - 1][a], aL);
+                const R right = lane_get(P.phi[0][a], aR);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    P.cdx[i][a] = (i + 1 < V ? P.phi[i + 1][a] : right) - (i > 0 ? P.phi[i - 1][a] : left);
             }
         }
-        R Ux[NP], Wx[NP], Jx[NM];
-        face_core<R, NP, NM, ANISO, 1>(cur.phi, pR, taux, cur.Mt, MR, cur.mu, uR, c, Ux, Wx, Jx);
-        R Wxl[NP], Jxl[NM];  // face (t-1, t), computed by the lane on the left
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Wxl[a] = lane_get(Wx[a], aL);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) Jxl[k] = lane_get(Jx[k], aL);
-
-        // y face (m, m+1)
-        R Uy[NP];
-        yface(cur, nxt, Uy, Wy, Jy);
-
-        R Gs[NP], Js[NM];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - Wlo[a]);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) Js[k] = (Jx[k] - Jxl[k]) + (Jy[k] - Jlo[k]);
-
-        const R tt = (R)(tbase + tslope * (double)m);
-        R phin[NP], mun[NM];
-        cell_update<R, NP, NM, OBST>(cur.phi, cur.mu, cur.h, Gs, Js, tt, c, phin, mun);
-        if (writes) {
-            const int64_t o = (int64_t)m * nx + gx;
-#pragma unroll
-            for (int a = 0; a < NP; ++a) out[a * fs + o] = phin[a];
-#pragma unroll
-            for (int k = 0; k < NM; ++k) out[(NP + k) * fs + o] = mun[k];
-        }
-
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int a = 0; a < NP; ++a) prvphi[a] = cur.phi[a];
-        }
-        if (m + 2 <= m1) process(ldX, cur);
     };
 
-    // Rows go in pairs.  Before a pair, one explicit wait drains every
-    // outstanding access (the two raw rows the pair consumes, and earlier
-    // stores); the loads of the next pair's rows are issued right after it, so
-    // each load has two rows of arithmetic to land in.  Waiting any finer would
-    // not help: with loads and stores both pending the counter completes out of
-    // order and any wait on a load becomes a wait for zero.
+    R Wlo[V][NP], Jlo[V][NM];  // lower y faces of the current row's cells
+    R prvphi[ANISO ? V : 1][NP];
+
+    auto yface = [&](const RowT& A, const RowT& B, int i, R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
+        R tau[1][NP];
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) tau[0][a] = A.cdx[i][a] + B.cdx[i][a];
+        }
+        face_core<R, NP, NM, ANISO, 1>(A.phi[i], B.phi[i], tau, A.Mt[i], B.Mt[i], A.mu[i], B.mu[i], c,
+                                       U, Wf, J);
+    };
+
+    // Row m from cur (row m) and nxt (row m+1); stores row m.
+    auto row = [&](int m, const RowT& cur, const RowT& nxt) {
+        R cdy[ANISO ? V : 1][NP];
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int a = 0; a < NP; ++a) cdy[i][a] = nxt.phi[i][a] - prvphi[i][a];
+        }
+        // x face to the right of the last cell, with lane t+1's first cell
+        R Ur[NP], Wr[NP], Jr[NM];
+        {
+            R pR[NP], uR[NM], MR[NM], tau[1][NP];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) pR[a] = lane_get(cur.phi[0][a], aR);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                uR[k] = lane_get(cur.mu[0][k], aR);
+                MR[k] = lane_get(cur.Mt[0][k], aR);
+            }
+            if constexpr (ANISO) {
+#pragma unroll
+                for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_get(cdy[0][a], aR);
+            }
+            face_core<R, NP, NM, ANISO, 1>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR,
+                                           c, Ur, Wr, Jr);
+        }
+        // the face on the left of the first cell is lane t-1's last face
+        R Wxl[NP], Jxl[NM];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) Wxl[a] = lane_get(Wr[a], aL);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) Jxl[k] = lane_get(Jr[k], aL);
+
+        const R tt = (R)(tbase + tslope * (double)m);
+        R phin[NP][V], mun[NM][V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            // x face (i, i+1) inside the lane, or the right face for the last cell
+            R Ux[NP], Wx[NP], Jx[NM];
+            if (i + 1 < V) {
+                R tau[1][NP];
+                if constexpr (ANISO) {
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) tau[0][a] = cdy[i][a] + cdy[i + 1][a];
+                }
+                face_core<R, NP, NM, ANISO, 1>(cur.phi[i], cur.phi[i + 1], tau, cur.Mt[i], cur.Mt[i + 1],
+                                               cur.mu[i], cur.mu[i + 1], c, Ux, Wx, Jx);
+            } else {
+#pragma unroll
+                for (int a = 0; a < NP; ++a) {
+                    Ux[a] = Ur[a];
+                    Wx[a] = Wr[a];
+                }
+#pragma unroll
+                for (int k = 0; k < NM; ++k) Jx[k] = Jr[k];
+            }
+            // y face (m, m+1) above cell i
+            R Uy[NP], Wy[NP], Jy[NM];
+            yface(cur, nxt, i, Uy, Wy, Jy);
+            R Gs[NP], Js[NM];
+#pragma unroll
+            for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - Wlo[i][a]);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) Js[k] = (Jx[k] - Jxl[k]) + (Jy[k] - Jlo[i][k]);
+            R pn[NP], un[NM], h0[NP];
+            interp_h<R, NP>(cur.phi[i], h0);
+            cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, tt, c, pn, un);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                phin[a][i] = pn[a];
+                Wlo[i][a] = Wy[a];
+                Wxl[a] = Wx[a];
+            }
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                mun[k][i] = un[k];
+                Jlo[i][k] = Jy[k];
+                Jxl[k] = Jx[k];
+            }
+        }
+        if (writes) {
+            const int64_t o = (int64_t)m * nx + cs;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) vstore<R, V>(out + a * fs + o, phin[a]);
+#pragma unroll
+            for (int k = 0; k < NM; ++k) vstore<R, V>(out + (NP + k) * fs + o, mun[k]);
+        }
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int a = 0; a < NP; ++a) prvphi[i][a] = cur.phi[i][a];
+        }
+    };
+
+    // Prologue: rows m0-1, m0 and m0+1 processed.
+    RowT cA, cB;
+    {
+        RawT r0, r1, r2;
+        load(m0 - 1, r0);
+        load(m0, r1);
+        load(m0 + 1, r2);
+        RowT prv;
+        process(r0, prv);
+        process(r1, cA);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            R Ud[NP];
+            yface(prv, cA, i, Ud, Wlo[i], Jlo[i]);
+        }
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+#pragma unroll
+                for (int a = 0; a < NP; ++a) prvphi[i][a] = prv.phi[i][a];
+        }
+        process(r2, cB);
+    }
+
+    // Loads and stores share one counter and may complete out of order with
+    // respect to each other, so the only wait that covers a load issued before
+    // a store is a wait for everything.  The loop therefore waits once per
+    // DEPTH rows and issues the loads of the next DEPTH rows right after that
+    // wait, giving every load DEPTH rows of arithmetic to land in; a raw row
+    // is turned into a cell record just before the row that needs it.
     constexpr unsigned kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt/lgkmcnt untouched
     int m = m0;
-    while (true) {
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        if (m + 4 <= m1) load(m + 4, ldC);
-        if (m + 5 <= m1) load(m + 5, ldD);
-        if (m >= m1) break;
-        row(m, cA, cB, ldA, Wlo0, Jlo0, Wlo1, Jlo1);
-        if (m + 1 >= m1) break;
-        row(m + 1, cB, cA, ldB, Wlo1, Jlo1, Wlo0, Jlo0);
-        m += 2;
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        if (m + 4 <= m1) load(m + 4, ldA);
-        if (m + 5 <= m1) load(m + 5, ldB);
-        if (m >= m1) break;
-        row(m, cA, cB, ldC, Wlo0, Jlo0, Wlo1, Jlo1);
-        if (m + 1 >= m1) break;
-        row(m + 1, cB, cA, ldD, Wlo1, Jlo1, Wlo0, Jlo0);
-        m += 2;
+    if constexpr (DEPTH == 1) {
+        RawT ld;
+        if (m0 + 2 <= m1) load(m0 + 2, ld);
+        while (true) {
+            row(m, cA, cB);
+            if (++m >= m1) break;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            process(ld, cA);
+            if (m + 2 <= m1) load(m + 2, ld);
+            row(m, cB, cA);
+            if (++m >= m1) break;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            process(ld, cB);
+            if (m + 2 <= m1) load(m + 2, ld);
+        }
+    } else {
+        RawT X1, X2, Y1, Y2;
+        if (m0 + 2 <= m1) load(m0 + 2, X1);
+        if (m0 + 3 <= m1) load(m0 + 3, X2);
+        while (true) {
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            if (m + 4 <= m1) load(m + 4, Y1);
+            if (m + 5 <= m1) load(m + 5, Y2);
+            row(m, cA, cB);
+            if (++m >= m1) break;
+            process(X1, cA);
+            row(m, cB, cA);
+            if (++m >= m1) break;
+            process(X2, cB);
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            if (m + 4 <= m1) load(m + 4, X1);
+            if (m + 5 <= m1) load(m + 5, X2);
+            row(m, cA, cB);
+            if (++m >= m1) break;
+            process(Y1, cA);
+            row(m, cB, cA);
+            if (++m >= m1) break;
+            process(Y2, cB);
+        }
     }
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
-__global__ void __launch_bounds__(256)
+#ifndef MP_WAVES_PER_EU
+#define MP_WAVES_PER_EU 2
+#endif
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
 k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
          const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
          int seg, int ntx, int nseg) {
@@ -201,18 +371,18 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     const int sg = wid / ntx;
     const int m0 = sg * seg;
     const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
-    strip2d<R, NP, NM, ANISO, OBST>(in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
+    strip2d<R, NP, NM, ANISO, OBST, V>(in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
-int call_2d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
-    const int ntx = (L.g.nx + W2D_OUT - 1) / W2D_OUT;
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+int call_2d_v(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
+    const int ntx = (L.g.nx + W2D_LANES_OUT * V - 1) / (W2D_LANES_OUT * V);
     const int nseg = (L.g.ny + L.seg - 1) / L.seg;
     const int wpb = L.bx / 64;
     const long long waves = (long long)ntx * nseg;
     const long long nblocks = (waves + wpb - 1) / wpb;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
-    k.func = (const void*)&k_step2d<R, NP, NM, ANISO, OBST>;
+    k.func = (const void*)&k_step2d<R, NP, NM, ANISO, OBST, V>;
     k.grid = dim3((unsigned)nblocks);
     k.block = dim3(L.bx);
     k.arg((const R*)L.in);
@@ -228,6 +398,17 @@ int call_2d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     k.arg(ntx);
     k.arg(nseg);
     return MP_OK;
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int call_2d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
+    const int v = vec2d_width(L.g.nx, (int)sizeof(R), L.vec);
+    if (v == 1) return call_2d_v<R, NP, NM, ANISO, OBST, 1>(L, c, k);
+    if (v == 2) return call_2d_v<R, NP, NM, ANISO, OBST, 2>(L, c, k);
+    if constexpr (sizeof(R) == 4) {
+        if (v == 4) return call_2d_v<R, NP, NM, ANISO, OBST, 4>(L, c, k);
+    }
+    return MP_E_PARAM;
 }
 
 }  // namespace mp

@@ -59,8 +59,8 @@ class Solver:
     def diagnostics(self, allow_nonfinite: bool = False) -> dict:
         return abi.mp_diagnostics(self.st, self.stream(), allow_nonfinite)
 
-    def set_tile(self, bx: int = 0, seg: int = 0):
-        abi.mp_set_tile(self.st, bx, seg)
+    def set_tile(self, bx: int = 0, seg: int = 0, vec: int = 0):
+        abi.mp_set_tile(self.st, bx, seg, vec)
 
     def set_graph(self, chunk: int):
         """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
@@ -154,8 +154,8 @@ class BatchSolver:
     def diagnostics(self, allow_nonfinite: bool = False):
         return abi.mp_diagnostics_batch(self.st, Solver.stream(), allow_nonfinite)
 
-    def set_tile(self, seg: int):
-        abi.mp_set_tile(self.st, 0, seg)
+    def set_tile(self, seg: int, vec: int = 0):
+        abi.mp_set_tile(self.st, 0, seg, vec)
 
     def set_graph(self, chunk: int):
         abi.mp_set_graph(self.st, chunk)

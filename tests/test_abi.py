@@ -35,8 +35,11 @@ def test_create_and_query_without_gpu():
         assert abi.mp_current(st) == (0, 0)
         abi.mp_set_step(st, 7, 1)
         assert abi.mp_current(st) == (1, 7)
-        abi.mp_set_tile(st, 128, 8)
-        assert abi.mp_get_tile(st) == (128, 8)
+        assert abi.mp_get_tile(st) == (128, 8, 1)
+        abi.mp_set_tile(st, 256, 16)
+        assert abi.mp_get_tile(st) == (256, 16, 1)
+        abi.mp_set_tile(st, 0, 0, -1)
+        assert abi.mp_get_tile(st) == (256, 16, -1)
     finally:
         abi.mp_destroy(st)
 
@@ -115,8 +118,10 @@ def test_calls_reject_null_and_unbound():
         assert L.mp_bind(st, 256, 520, 1024) == abi.MP_E_PARAM     # misaligned
         assert L.mp_set_step(st, -1, 0) == abi.MP_E_PARAM
         assert L.mp_set_step(st, 0, 2) == abi.MP_E_PARAM
-        assert L.mp_set_tile(st, 100, 0) == abi.MP_E_PARAM
-        assert L.mp_set_tile(st, 0, -3) == abi.MP_E_PARAM
+        assert L.mp_set_tile(st, 100, 0, 0) == abi.MP_E_PARAM
+        assert L.mp_set_tile(st, 0, -3, 0) == abi.MP_E_PARAM
+        assert L.mp_set_tile(st, 0, 0, 4) == abi.MP_E_PARAM   # FP64: at most 2 cells per lane
+        assert L.mp_set_tile(st, 0, 0, 3) == abi.MP_E_PARAM
     finally:
         abi.mp_destroy(st)
     abi.mp_destroy(None)
@@ -224,11 +229,12 @@ def test_tune_candidates_and_errors_without_gpu():
     st = abi.mp_create(p)
     try:
         cand = abi.mp_tune_candidates(st)
-        assert len(cand) >= 4 and all(b in (64, 128, 256) and s >= 1 for b, s in cand)
-        for b, s in cand:  # every candidate is a tile the state accepts
-            abi.mp_set_tile(st, b, s)
+        assert len(cand) >= 4 and all(b in (64, 128, 256) and s >= 1 and v in (1, 2)
+                                      for b, s, v in cand)
+        for b, s, v in cand:  # every candidate is a tile the state accepts
+            abi.mp_set_tile(st, b, s, v)
         L = abi.lib()
-        buf = (C.c_int32 * 2)(64, 16)
+        buf = (C.c_int32 * 3)(64, 16, 1)
         ms = (C.c_double * 1)()
         best = C.c_int()
         assert L.mp_tune(st, buf, 1, 3, ms, C.byref(best), None) == abi.MP_E_UNBOUND
@@ -237,7 +243,8 @@ def test_tune_candidates_and_errors_without_gpu():
         abi.mp_destroy(st)
     st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
     try:
-        assert {b for b, _ in abi.mp_tune_candidates(st)} == {64}
+        assert {(b, v) for b, _, v in abi.mp_tune_candidates(st)} == {(64, 1)}
+        assert abi.lib().mp_set_tile(st, 0, 0, 2) == abi.MP_E_PARAM
     finally:
         abi.mp_destroy(st)
 

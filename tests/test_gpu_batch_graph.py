@@ -136,7 +136,7 @@ def test_autotuner_keeps_results_and_caches(tmp_path):
         s.load(phi, mu)
         r = s.autotune(reps=2, cache=cache)
         assert r["source"] == "timed" and all(t > 0 for t in r["ms"].values())
-        assert abi_tile(s) == (r["bx"], r["seg"])
+        assert abi_tile(s) == (r["bx"], r["seg"], r["vec"])
         assert s.time_level == 0
         s.step(9)
         got = s.fields()
