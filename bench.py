@@ -16,7 +16,8 @@ Further legs, each a block of the same JSON line:
 cpu_baseline   the FP64 oracle on one full 4096^2 step, on the host.
 
 Prints one JSON line.  Options: --gpus (only 1 is supported), --steps,
---warmup, --legs, --no-cpu, --n (2D grid side), --tile bx,seg,vec (skips tuning).
+--warmup, --legs, --no-cpu, --n (2D grid side), --tile / --tile32 bx,seg,vec
+(fixed FP64 / FP32 tiles instead of tuning).
 """
 from __future__ import annotations
 
@@ -42,7 +43,8 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--legs", type=str, default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tile", type=str, default="", help="bx,seg,vec for the 2D legs (no tuning)")
+    ap.add_argument("--tile", type=str, default="", help="bx,seg,vec of the FP64 leg (no tuning)")
+    ap.add_argument("--tile32", type=str, default="", help="bx,seg,vec of the FP32 leg (no tuning)")
     ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--n3d", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=400)
@@ -307,7 +309,7 @@ def main():
     }
     if "c2" in legs:
         log(f"FP32 {a.n}x{a.n}")
-        r32 = leg_c2("f32", a.n, a.steps, a.warmup, a.tile)
+        r32 = leg_c2("f32", a.n, a.steps, a.warmup, a.tile32)
         out["fp32"] = dict(r32, dtype="f32 (FP64 Lagrange multiplier and reductions)")
         out["speedup_fp32_over_fp64"] = r32["value"] / r64["value"]
     if "c3" in legs:

@@ -153,7 +153,8 @@ int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
  * 256: 1, 2 or 4 independent strip waves), seg = rows per strip segment and
  * vec = the most cells one lane holds (1, 2, or 4 in FP32 only; each lane
  * takes the largest power of two <= vec that divides nx; -1 = the widest the
- * precision allows, which is the default).  3D: bx = 64 (64 x 4 tiles), seg =
+ * precision allows).  A batched state takes bx = 256 and vec in {-1, 1, 2}
+ * (-1 acts as 2).  3D: bx = 64 (64 x 4 tiles), seg =
  * z planes per block, vec must be 0 or 1.  0 keeps the current value of a
  * field.  Results do not depend on the tile shape (bitwise). */
 int mp_set_tile(mp_state* st, int bx, int seg, int vec);

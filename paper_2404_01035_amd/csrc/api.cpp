@@ -243,8 +243,14 @@ int hip_check(hipError_t e, const char* what) {
 }
 
 // Strip waves across one row of a 2D instance (62 written lanes of vec_of cells each).
+// Cap on cells per lane: the tile's, at most 2 in a batch (the batched kernel
+// is built for 1 or 2).
+int vec_cap(const mp_state* st) {
+    if (!st->batch) return st->vec;
+    return st->vec == 1 ? 1 : 2;
+}
 int vec_of(const mp_state* st, const Inst& I) {
-    return mp::vec2d_width(I.grid.n[0], (int)elem_of(I.prm.precision), st->vec);
+    return mp::vec2d_width(I.grid.n[0], (int)elem_of(I.prm.precision), vec_cap(st));
 }
 int strips_of(const mp_state* st, const Inst& I) {
     const int64_t w = mp::W2D_LANES_OUT_HOST * vec_of(st, I);
@@ -334,6 +340,7 @@ int choose_batch_blocks(mp_state* st) {
     std::memset(&L, 0, sizeof L);
     L.potential = st->potential;
     L.aniso = st->aniso ? 1 : 0;
+    L.vmax = vec_cap(st);
     L.nblocks = 8;
     mp::KernelCall k;
     rc = st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
@@ -373,6 +380,7 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
         L.nitems = st->nitems;
         L.potential = st->potential;
         L.aniso = st->aniso ? 1 : 0;
+        L.vmax = vec_cap(st);
         L.nblocks = st->batch_blocks;
         L.stepctr = dev_ctr(st);
         L.kstep = kstep;
@@ -469,7 +477,7 @@ void init_state(mp_state* st) {
         // SIMD without spills, two FP32 cells per lane give 8-byte accesses
         st->bx = st->batch ? 64 * mp::BATCH_WPB_HOST : (st->precision == MP_FP64 ? 128 : 64);
         st->seg = st->batch ? 4 : 8;
-        st->vec = st->precision == MP_FP64 ? 1 : 2;
+        st->vec = (st->batch || st->precision == MP_FP64) ? 1 : 2;
     }
 }
 
@@ -789,7 +797,8 @@ int mp_set_tile(mp_state* st, int bx, int seg, int vec) {
     if (vec) {
         const int vmax = st->precision == MP_FP64 ? 2 : 4;
         const bool okv = d3 ? vec == 1 : (vec == -1 || vec == 1 || vec == 2 || vec == 4);
-        if (!okv || vec > vmax) return fail(MP_E_PARAM, "unsupported cells per lane %d", vec);
+        if (!okv || vec > vmax || (st->batch && vec > 2))
+            return fail(MP_E_PARAM, "unsupported cells per lane %d", vec);
     }
     drop_graphs(st);
     if (bx) st->bx = bx;
@@ -819,7 +828,7 @@ int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap) {
     if (d3) {
         for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64, seg, 1});
     } else if (st->batch) {
-        for (int vec = 1; vec <= vmax; vec *= 2)
+        for (int vec = 1; vec <= 2; vec *= 2)
             for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg, vec});
     } else {
         for (int vec = 1; vec <= vmax; vec *= 2)

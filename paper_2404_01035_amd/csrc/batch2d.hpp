@@ -16,39 +16,38 @@ namespace mp {
 
 constexpr int BATCH_WPB = BATCH_WPB_HOST;  // waves per block
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+// Cells per lane of a batched item: 1, or up to VMAX = 2 where nx is even.
+// Every variant is inlined into the one kernel, whose register budget is that
+// of the widest, so the kernel is instantiated per VMAX.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int VMAX>
 __device__ __forceinline__ void run_vec(const R* src, R* dst, const InstDesc<R>& d, double tbase,
                                         int tx, int m0, int m1) {
-    if (d.vec == 1) {
+    if (VMAX == 1 || d.vec == 1)
         strip2d<R, NP, NM, ANISO, OBST, 1>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-    } else if (sizeof(R) == 8 || d.vec == 2) {
+    else
         strip2d<R, NP, NM, ANISO, OBST, 2>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
-    } else {
-        strip2d<R, NP, NM, ANISO, OBST, 16 / sizeof(R)>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0,
-                                                        m1);
-    }
 }
 
-template <typename R, bool ANISO, bool OBST>
+template <typename R, bool ANISO, bool OBST, int VMAX>
 __device__ __forceinline__ void run_item(const R* src, R* dst, const InstDesc<R>& d, double tbase,
                                          int tx, int m0, int m1) {
     switch (d.np * 4 + d.nm) {
         case 2 * 4 + 1:
-            run_vec<R, 2, 1, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 2, 1, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
             break;
         case 2 * 4 + 2:
-            run_vec<R, 2, 2, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 2, 2, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
             break;
         case 3 * 4 + 1:
-            run_vec<R, 3, 1, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 3, 1, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
             break;
         default:
-            run_vec<R, 3, 2, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 3, 2, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
             break;
     }
 }
 
-template <typename R, bool ANISO, bool OBST>
+template <typename R, bool ANISO, bool OBST, int VMAX>
 __global__ void __launch_bounds__(64 * BATCH_WPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __restrict__ tab,
           const int* __restrict__ item_inst, int nitems, const int64_t* __restrict__ stepctr,
@@ -71,17 +70,21 @@ k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __re
         const double tbase = d.tb0 + d.tdn * (double)n;
         const R* src = in + d.off;
         R* dst = out + d.off;
-        run_item<R, ANISO, OBST>(src, dst, d, tbase, tx, m0, m1);
+        run_item<R, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
     }
+}
+
+template <typename R, int VMAX>
+const void* batch_func(bool aniso, bool obst) {
+    if (aniso)
+        return obst ? (const void*)&k_batch2d<R, true, true, VMAX> : (const void*)&k_batch2d<R, true, false, VMAX>;
+    return obst ? (const void*)&k_batch2d<R, false, true, VMAX> : (const void*)&k_batch2d<R, false, false, VMAX>;
 }
 
 template <typename R>
 int call_batch(const BatchLaunch& L, KernelCall& k) {
     const bool obst = L.potential == MP_OBSTACLE;
-    if (L.aniso)
-        k.func = obst ? (const void*)&k_batch2d<R, true, true> : (const void*)&k_batch2d<R, true, false>;
-    else
-        k.func = obst ? (const void*)&k_batch2d<R, false, true> : (const void*)&k_batch2d<R, false, false>;
+    k.func = L.vmax == 1 ? batch_func<R, 1>(L.aniso, obst) : batch_func<R, 2>(L.aniso, obst);
     if (L.nblocks <= 0 || L.nblocks % 8) return MP_E_PARAM;
     k.grid = dim3((unsigned)L.nblocks);
     k.block = dim3(64 * BATCH_WPB);

@@ -38,28 +38,41 @@ __device__ __forceinline__ int gmap(int i, int n, bool periodic) {
 
 __device__ __forceinline__ int pair_index(int i, int j) { return i + j - 1; }  // (0,1)->0 (0,2)->1 (1,2)->2
 
-// Normal component of d(a_c^2 |q|^2)/dq for the four-fold a_c, on the rescaled q.
+// 1/sqrt(x), x > 0 and normal: hardware estimate (about 1 ulp in FP32), two
+// Newton steps in FP64.
+__device__ __forceinline__ float rsqrt_ok(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_ok(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    return y * fma(-hx * y, y, 1.5);
+}
+
+// Normal component of d(a_c^2 |q|^2)/dq for the four-fold a_c, on the rescaled
+// q.  m = q/|q| comes from one reciprocal square root; the |q|^2 <= guard
+// limit is selected at the end, so lanes do not diverge.
 template <typename R, int NTG>
 __device__ __forceinline__ R g_aniso(R qn, const R (&qt)[NTG], R d, R guard) {
     R Q2 = qn * qn;
 #pragma unroll
     for (int t = 0; t < NTG; ++t) Q2 = Q2 + qt[t] * qt[t];
-    if (Q2 <= guard) {
-        R a0 = R(1) - R(3) * d;
-        return R(2) * a0 * a0 * qn;
-    }
-    R rq = sqrt(Q2);
-    R mn = qn / rq;
-    R mn2 = mn * mn;
+    const bool small = Q2 <= guard;
+    const R Q2s = small ? R(1) : Q2;
+    const R inv = rsqrt_ok(Q2s);
+    const R rq = Q2s * inv;
+    const R mn = qn * inv;
+    const R mn2 = mn * mn;
     R S4 = mn2 * mn2;
 #pragma unroll
     for (int t = 0; t < NTG; ++t) {
-        R mt = qt[t] / rq;
-        R mt2 = mt * mt;
+        const R mt = qt[t] * inv;
+        const R mt2 = mt * mt;
         S4 = S4 + mt2 * mt2;
     }
-    R ac = R(1) - d * (R(3) - R(4) * S4);
-    return R(2) * ac * ac * qn + R(32) * d * ac * rq * (mn2 * mn - mn * S4);
+    const R ac = R(1) - d * (R(3) - R(4) * S4);
+    const R gen = R(2) * ac * ac * qn + R(32) * d * ac * rq * (mn2 * mn - mn * S4);
+    const R a0 = R(1) - R(3) * d;
+    return small ? R(2) * a0 * a0 * qn : gen;
 }
 
 // One face: U, W (gradient term) and J (mu flux).  tau[t][a] is the unscaled

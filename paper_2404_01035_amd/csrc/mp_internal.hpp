@@ -98,6 +98,7 @@ struct BatchLaunch {
     const int* item_inst;  // instance of each work item, in device memory
     int nitems;
     int potential, aniso;
+    int vmax;  // widest cells-per-lane among the items (1 or 2)
     int nblocks;
     const int64_t* stepctr;
     int kstep;
