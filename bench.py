@@ -5,7 +5,8 @@ fields), x periodic / y no-flux, seeded synthetic initial state (lamellae slab
 in melt).  A benchmark step is one forward-Euler time step of the whole field
 (one launch of the fused kernel).  The timed region runs exactly --steps steps
 in FP64 (``value``) and, separately, in FP32 (``fp32``), with the state
-resident in HBM; the tile shape is picked by the autotuner first.
+resident in HBM, at the library's default tiles (the autotuner's picks for this
+workload; --tune re-tunes).
 
 Further legs, each a block of the same JSON line:
   dendrite_3d  3D 512^3 binary dendrite with cubic anisotropy, FP32
@@ -13,15 +14,16 @@ Further legs, each a block of the same JSON line:
                replayed as HIP graphs, FP32
   adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
                (every 100 steps) and the adjoint sweep; their cost ratio
-cpu_baseline   the FP64 oracle on one full 4096^2 step, on the host.
+cpu_baseline   the FP64 oracle on two full 4096^2 steps, on the host.
 
 Prints one JSON line.  Options: --gpus (only 1 is supported), --steps,
---warmup, --legs, --no-cpu, --n (2D grid side), --tile / --tile32 bx,seg,vec
-(fixed FP64 / FP32 tiles instead of tuning).
+--warmup, --legs, --no-cpu, --n (2D grid side), --tune, --tile / --tile32 /
+--tile3d bx,seg,vec and --tile-batch seg,vec (fixed tiles).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +33,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
+
+# HBM bytes per launch of each leg's step kernel, from rocprofv3 counter runs:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
+# counters read for a plain device copy of known size.  A figure holds only
+# for the tile it was taken at and for the kernel sources it was taken on
+# (sha256 over csrc/); otherwise the leg reports traffic null.
+TRAFFIC = {}
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5")
 
@@ -43,8 +53,13 @@ def parse():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--legs", type=str, default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--tile", type=str, default="", help="bx,seg,vec of the FP64 leg (no tuning)")
-    ap.add_argument("--tile32", type=str, default="", help="bx,seg,vec of the FP32 leg (no tuning)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the 2D legs instead of using the library's default tiles")
+    ap.add_argument("--tile", type=str, default="", help="bx,seg,vec of the FP64 leg")
+    ap.add_argument("--tile32", type=str, default="", help="bx,seg,vec of the FP32 leg")
+    ap.add_argument("--tile3d", type=str, default="", help="bx,seg,vec of the 3D leg (no tuning)")
+    ap.add_argument("--tile-batch", type=str, default="",
+                    help="seg,vec of the batched leg (no tuning)")
     ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--n3d", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=400)
@@ -58,10 +73,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def roofline(bytes_per_step, ms_step):
+def source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_of(leg, tile):
+    t = TRAFFIC.get(leg)
+    if not t or list(t["tile"]) != list(tile) or t["src"] != source_hash():
+        return None
+    return t["bytes"]
+
+
+def roofline(bytes_per_step, ms_step, traffic=None):
     gbs = bytes_per_step / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def parse_tile(text):
+    return [int(v) for v in text.split(",")] if text else None
 
 
 class Timer:
@@ -105,8 +139,8 @@ def copy_calibration(n, steps):
                       "frac_of_8TBs": gbs / HBM_PEAK_GBS}), flush=True)
 
 
-def leg_c2(precision, n, steps, warmup, tile):
-    from paper_2404_01035_amd import inputs
+def leg_c2(precision, n, steps, warmup, tile, tune):
+    from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import Solver
 
     p, phi, mu = inputs.config_c2(precision=precision, n=(n, n, 1))
@@ -114,11 +148,14 @@ def leg_c2(precision, n, steps, warmup, tile):
     s.load(phi, mu)
     del phi, mu
     if tile:
-        bx, seg, vec = (int(v) for v in tile.split(","))
-        s.set_tile(bx, seg, vec)
-        tuned = {"bx": bx, "seg": seg, "vec": vec, "source": "--tile"}
+        s.set_tile(*tile)
+        source = "fixed"
+    elif tune:
+        s.autotune(reps=10, force=True)
+        source = "tuned"
     else:
-        tuned = s.autotune(reps=10, force=True)
+        source = "default"
+    used = list(abi.mp_get_tile(s.st))
     s.step(warmup)
     with Timer() as t:
         s.step(steps)
@@ -130,22 +167,27 @@ def leg_c2(precision, n, steps, warmup, tile):
     return {
         "value": p.ncells * steps / (t.ms * 1e-3),
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step),
+        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of(f"c2_{precision}", used)),
         "bytes_per_cell_update": bpc,
-        "tile": {k: tuned[k] for k in ("bx", "seg", "vec", "source")},
+        "algorithmic_bytes_per_launch": p.ncells * bpc,
+        "tile": {"bx": used[0], "seg": used[1], "vec": used[2], "source": source},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
 
-def leg_c3(n, steps, warmup):
-    from paper_2404_01035_amd import inputs
+def leg_c3(n, steps, warmup, tile):
+    from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import Solver
 
     p, phi, mu = inputs.config_c3(n=(n, n, n))
     s = Solver(p)
     s.load(phi, mu)
     del phi, mu
-    tuned = s.autotune(reps=5, force=True)
+    if tile:
+        s.set_tile(*tile)
+    else:
+        s.autotune(reps=5, force=True)
+    used = list(abi.mp_get_tile(s.st))
     s.step(warmup)
     with Timer() as t:
         s.step(steps)
@@ -159,15 +201,16 @@ def leg_c3(n, steps, warmup):
         "unit": "cell-updates/s",
         "steps": steps,
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step),
+        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of("c3", used)),
         "bytes_per_cell_update": bpc,
-        "tile": {"bx": tuned["bx"], "seg": tuned["seg"], "vec": tuned["vec"]},
+        "algorithmic_bytes_per_launch": p.ncells * bpc,
+        "tile": {"bx": used[0], "seg": used[1], "vec": used[2]},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
 
-def leg_c4(steps, warmup, graph_chunk=50):
-    from paper_2404_01035_amd import inputs
+def leg_c4(steps, warmup, tile, graph_chunk=50):
+    from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import BatchSolver
 
     members = inputs.config_c4()
@@ -178,7 +221,11 @@ def leg_c4(steps, warmup, graph_chunk=50):
     cells = sum(m[0].ncells for m in members)
     bytes_step = sum(m[0].ncells * m[0].nfields * 2 * 4 for m in members)
     del members
-    tuned = b.autotune(reps=5, force=True)
+    if tile:
+        b.set_tile(*tile)
+    else:
+        b.autotune(reps=5, force=True)
+    used = list(abi.mp_get_tile(b.st))
     b.set_graph(graph_chunk)
     b.step(warmup)
     with Timer() as t:
@@ -195,8 +242,9 @@ def leg_c4(steps, warmup, graph_chunk=50):
         "steps": steps,
         "cells": cells,
         "ms_per_step": ms_step,
-        "roofline": roofline(bytes_step, ms_step),
-        "tile": {"seg": tuned["seg"], "vec": tuned["vec"]},
+        "roofline": roofline(bytes_step, ms_step, traffic_of("c4", used)),
+        "algorithmic_bytes_per_launch": bytes_step,
+        "tile": {"seg": used[1], "vec": used[2]},
         "nonfinite_instances": sum(1 for d in diags if d["nonfinite"]),
     }
 
@@ -246,21 +294,22 @@ def leg_c5(nsteps, every=100, n=512):
     }
 
 
-def cpu_baseline(n):
-    """The FP64 oracle (numpy, one thread) on one full-grid step of the headline workload."""
+def cpu_baseline(n, nsteps=2):
+    """The FP64 oracle (numpy: elementwise array passes, one thread) on ``nsteps``
+    full-grid steps of the headline workload."""
     from oracle import gp
     from paper_2404_01035_amd import inputs
 
     p, phi, mu = inputs.config_c2(precision="f64", n=(n, n, 1))
     t0 = time.perf_counter()
-    gp.step(phi, mu, 0, p)
+    gp.run(phi, mu, 0, nsteps, p)
     dt = time.perf_counter() - t0
     return {
-        "value": p.ncells / dt,
+        "value": p.ncells * nsteps / dt,
         "unit": "cell-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"1 step of the full {n}x{n} grid, FP64 numpy oracle ({dt:.1f} s)",
+        "sample": f"{nsteps} steps of the full {n}x{n} grid, FP64 numpy oracle ({dt:.1f} s)",
     }
 
 
@@ -280,7 +329,7 @@ def main():
         return
     legs = [x for x in a.legs.split(",") if x]
     log(f"FP64 {a.n}x{a.n}: warmup {a.warmup}, timed {a.steps} steps")
-    r64 = leg_c2("f64", a.n, a.steps, a.warmup, a.tile)
+    r64 = leg_c2("f64", a.n, a.steps, a.warmup, parse_tile(a.tile), a.tune)
     out = {
         "metric": METRIC,
         "value": r64["value"],
@@ -303,21 +352,22 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r64["roofline"],
+        "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_launch"],
         "tile": r64["tile"],
         "diag": r64["diag"],
         "cpu_baseline": None,
     }
     if "c2" in legs:
         log(f"FP32 {a.n}x{a.n}")
-        r32 = leg_c2("f32", a.n, a.steps, a.warmup, a.tile32)
+        r32 = leg_c2("f32", a.n, a.steps, a.warmup, parse_tile(a.tile32), a.tune)
         out["fp32"] = dict(r32, dtype="f32 (FP64 Lagrange multiplier and reductions)")
         out["speedup_fp32_over_fp64"] = r32["value"] / r64["value"]
     if "c3" in legs:
         log(f"3D {a.n3d}^3 FP32")
-        out["dendrite_3d"] = leg_c3(a.n3d, a.steps3d, 5)
+        out["dendrite_3d"] = leg_c3(a.n3d, a.steps3d, 5, parse_tile(a.tile3d))
     if "c4" in legs:
         log("batched ensemble FP32")
-        out["batched"] = leg_c4(a.batch_steps, 50)
+        out["batched"] = leg_c4(a.batch_steps, 50, parse_tile(a.tile_batch))
     if "c5" in legs:
         log("checkpointed forward + adjoint FP32")
         out["adjoint"] = leg_c5(a.adjoint_steps)

@@ -154,8 +154,9 @@ int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
  * vec = the most cells one lane holds (1, 2, or 4 in FP32 only; each lane
  * takes the largest power of two <= vec that divides nx; -1 = the widest the
  * precision allows).  A batched state takes bx = 256 and vec in {-1, 1, 2}
- * (-1 acts as 2).  3D: bx = 64 (64 x 4 tiles), seg =
- * z planes per block, vec must be 0 or 1.  0 keeps the current value of a
+ * (-1 acts as 2).  3D: bx = 256 (64 x 4 tiles) or 512 (64 x 8 tiles, where
+ * the tile's LDS ring fits in 64 KiB), seg = z planes per block, vec must be
+ * 0 or 1.  0 keeps the current value of a
  * field.  Results do not depend on the tile shape (bitwise). */
 int mp_set_tile(mp_state* st, int bx, int seg, int vec);
 int mp_get_tile(const mp_state* st, int* bx, int* seg, int* vec);

@@ -453,6 +453,13 @@ int build_graph(mp_state* st, int from, hipGraphExec_t* out) {
     return rc;
 }
 
+// 3D tiles of 64 x 8 exist where their LDS ring fits in 64 KiB.
+bool d3_tall_ok(const mp_state* st) {
+    const Inst& I = st->inst[0];
+    const int elem = (int)elem_of(st->precision);
+    return 4 * (I.N + 2 * (I.K - 1)) * 66 * 10 * elem <= 64 * 1024;
+}
+
 void init_state(mp_state* st) {
     st->buf[0] = st->buf[1] = nullptr;
     st->ws = nullptr;
@@ -469,8 +476,9 @@ void init_state(mp_state* st) {
     st->vec = -1;
     st->potential = st->inst[0].prm.potential;
     if (st->inst[0].grid.dim == 3) {
-        st->bx = 64;
-        st->seg = 16;
+        // measured best on 512^3 FP32: tall tiles, long z segments
+        st->bx = d3_tall_ok(st) ? 512 : 256;
+        st->seg = 64;
     } else {
         // measured best on 4096^2: short segments keep enough waves in flight
         // to cover HBM latency; one FP64 cell per lane keeps two waves per
@@ -789,7 +797,8 @@ int mp_set_tile(mp_state* st, int bx, int seg, int vec) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     const bool d3 = st->inst[0].grid.dim == 3;
     if (bx) {
-        bool okbx = d3 ? bx == 64 : (bx == 64 || bx == 128 || bx == 256);
+        bool okbx = d3 ? (bx == 256 || (bx == 512 && d3_tall_ok(st)))
+                       : (bx == 64 || bx == 128 || bx == 256);
         if (st->batch) okbx = bx == 64 * mp::BATCH_WPB_HOST;
         if (!okbx) return fail(MP_E_PARAM, "unsupported tile width %d", bx);
     }
@@ -826,7 +835,9 @@ int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap) {
     const bool d3 = st->inst[0].grid.dim == 3;
     const int vmax = st->precision == MP_FP64 ? 2 : 4;
     if (d3) {
-        for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64, seg, 1});
+        for (int bx : {256, 512})
+            if (bx == 256 || d3_tall_ok(st))
+                for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {bx, seg, 1});
     } else if (st->batch) {
         for (int vec = 1; vec <= 2; vec *= 2)
             for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg, vec});

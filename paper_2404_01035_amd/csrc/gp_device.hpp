@@ -163,18 +163,25 @@ __device__ __forceinline__ float fast_rcp(float x) {
     return fmaf(r, e, r);
 }
 
+// C^b + s^b (T - Te) for every phase: constant along a row of fixed y.
+template <typename R, int NP>
+__device__ __forceinline__ void psi_const(R tt, const Coef<R>& c, R (&Cs)[NP]) {
+#pragma unroll
+    for (int b = 0; b < NP; ++b) Cs[b] = c.C[b] + c.s[b] * tt;
+}
+
 // Cell update from the face sums Gs_a = sum_axes (U_hi - W_lo) and
-// Js_k = sum_axes (J_hi - J_lo); h0 = h(phi^n) of the cell; tt = T - Te.
+// Js_k = sum_axes (J_hi - J_lo); h0 = h(phi^n) of the cell; Cs from psi_const.
 template <typename R, int NP, int NM, bool OBST>
 __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM],
                                             const R (&h0)[NP], const R (&Gs)[NP],
-                                            const R (&Js)[NM], R tt, const Coef<R>& c,
+                                            const R (&Js)[NM], const R (&Cs)[NP], const Coef<R>& c,
                                             R (&phin)[NP], R (&mun)[NM]) {
     R dmu[NP][NM];
     R psi[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-        R v = c.C[b] + c.s[b] * tt;
+        R v = Cs[b];
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
             dmu[b][k] = mu[k] - c.B[b][k];
@@ -258,6 +265,32 @@ __device__ __forceinline__ double lane_get(double v, int addr) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
     const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value of the next / previous lane of the wave (lane 63's next is lane 0 and
+// lane 0's previous is lane 63).  FP32 goes through the LDS crossbar
+// (ds_bpermute), which leaves the vector ALU -- the FP32 step's limit -- to the
+// arithmetic; FP64 uses DPP wave rotates, two per value, which avoid the LDS
+// round trip.
+__device__ __forceinline__ float lane_next(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)threadIdx.x + 1) & 63) << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ float lane_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)threadIdx.x + 63) & 63) << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ int rot_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false); }
+__device__ __forceinline__ int rot_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false); }
+__device__ __forceinline__ double lane_next(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = rot_next((int)(b & 0xffffffffLL));
+    const int hi = rot_next((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_prev(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = rot_prev((int)(b & 0xffffffffLL));
+    const int hi = rot_prev((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

@@ -9,7 +9,7 @@
 // walks a segment of rows [m0, m1) of the slowest axis y, keeping the cell
 // records of rows m and m+1 in registers.  Every face is evaluated once per
 // wave: lane t evaluates the V x faces to the right of its cells (the last one
-// with lane t+1's first cell, fetched through ds_bpermute) and passes the last
+// with lane t+1's first cell, fetched by a lane rotate) and passes the last
 // face's W, J to lane t+1; the y face (m, m+1) is kept and becomes the lower
 // face of row m+1.  Out-of-range columns come from the boundary map: a lane
 // lying wholly outside the grid loads the aligned vector holding its ghost
@@ -118,8 +118,6 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         fixR = !perx;
     }
     const bool writes = lane >= 1 && lane <= W2D_LANES_OUT && cs < nx;
-    const int aR = ((lane + 1) & 63) << 2;
-    const int aL = ((lane + 63) & 63) << 2;
 
     auto load = [&](int m, RawT& r) {
         const int64_t o = (int64_t)gmap(m, g.ny, pery) * nx + col;
@@ -157,8 +155,8 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         if constexpr (ANISO) {
 #pragma unroll
             for (int a = 0; a < NP; ++a) {
-                const R left = lane_get(P.phi[V - 1][a], aL);
-                const R right = lane_get(P.phi[0][a], aR);
+                const R left = lane_prev(P.phi[V - 1][a]);
+                const R right = lane_next(P.phi[0][a]);
 #pragma unroll
                 for (int i = 0; i < V; ++i)
                     P.cdx[i][a] = (i + 1 < V ? P.phi[i + 1][a] : right) - (i > 0 ? P.phi[i - 1][a] : left);
@@ -193,15 +191,15 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         {
             R pR[NP], uR[NM], MR[NM], tau[1][NP];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) pR[a] = lane_get(cur.phi[0][a], aR);
+            for (int a = 0; a < NP; ++a) pR[a] = lane_next(cur.phi[0][a]);
 #pragma unroll
             for (int k = 0; k < NM; ++k) {
-                uR[k] = lane_get(cur.mu[0][k], aR);
-                MR[k] = lane_get(cur.Mt[0][k], aR);
+                uR[k] = lane_next(cur.mu[0][k]);
+                MR[k] = lane_next(cur.Mt[0][k]);
             }
             if constexpr (ANISO) {
 #pragma unroll
-                for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_get(cdy[0][a], aR);
+                for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_next(cdy[0][a]);
             }
             face_core<R, NP, NM, ANISO, 1>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR,
                                            c, Ur, Wr, Jr);
@@ -209,11 +207,12 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         // the face on the left of the first cell is lane t-1's last face
         R Wxl[NP], Jxl[NM];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) Wxl[a] = lane_get(Wr[a], aL);
+        for (int a = 0; a < NP; ++a) Wxl[a] = lane_prev(Wr[a]);
 #pragma unroll
-        for (int k = 0; k < NM; ++k) Jxl[k] = lane_get(Jr[k], aL);
+        for (int k = 0; k < NM; ++k) Jxl[k] = lane_prev(Jr[k]);
 
-        const R tt = (R)(tbase + tslope * (double)m);
+        R Cs[NP];
+        psi_const<R, NP>((R)(tbase + tslope * (double)m), c, Cs);
         R phin[NP][V], mun[NM][V];
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -246,7 +245,7 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
             for (int k = 0; k < NM; ++k) Js[k] = (Jx[k] - Jxl[k]) + (Jy[k] - Jlo[i][k]);
             R pn[NP], un[NM], h0[NP];
             interp_h<R, NP>(cur.phi[i], h0);
-            cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, tt, c, pn, un);
+            cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un);
 #pragma unroll
             for (int a = 0; a < NP; ++a) {
                 phin[a][i] = pn[a];

@@ -1,6 +1,6 @@
 // 3D fused phi + mu step: xy tiles staged in an LDS ring of z planes.
 //
-// A block owns a 64 (x) by 4 (y) tile and walks a segment of z planes.  A
+// A block owns a 64 (x) by BY (y, 4 or 8) tile and walks a segment of z planes.  A
 // 4-slot LDS ring holds planes m-1, m, m+1 (plus the slot being filled): the
 // loads of plane m+2 are issued into registers before plane m is computed and
 // land in the free slot afterwards, so one barrier per plane suffices.  Each
@@ -138,7 +138,8 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     const int gy = y0 + ly;
     const bool valid = gx < g.nx && gy < g.ny;
     const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
-    const R tt = (R)(tbase + tslope * (double)gy);  // T - Te depends on y only
+    R Cs[NP];  // T - Te depends on y only
+    psi_const<R, NP>((R)(tbase + tslope * (double)gy), c, Cs);
 
     // tangential steps: x faces see (y, z), y faces see (x, z), z faces see (x, y)
     const int tSx[2] = {0, 1}, tPx[2] = {PW, 0};
@@ -198,7 +199,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         for (int k = 0; k < NM; ++k) mu[k] = sv[s0][NP + k][pc];
         interp_h<R, NP>(phi, h0);
         R phin[NP], mun[NM];
-        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, tt, c, phin, mun);
+        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, c, phin, mun);
 
         if (valid) {
             const int64_t o = (int64_t)gx + (int64_t)gy * sy + (int64_t)m * sz;
@@ -213,9 +214,9 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     }
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
-int call_3d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
-    constexpr int BX = 64, BY = 4;
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BY>
+int call_3d_by(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
+    constexpr int BX = 64;
     const int ntx = (L.g.nx + BX - 1) / BX;
     const int nty = (L.g.ny + BY - 1) / BY;
     const int nseg = (L.g.nz + L.seg - 1) / L.seg;
@@ -237,6 +238,24 @@ int call_3d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     k.arg(ntx);
     k.arg(nty);
     return MP_OK;
+}
+
+// LDS bytes of a 64 x BY tile ring (4 planes of the fields and M~, with halo).
+template <typename R, int NP, int NM, int BY>
+constexpr int lds3d_bytes() {
+    return 4 * (NP + 2 * NM) * 66 * (BY + 2) * (int)sizeof(R);
+}
+
+// bx = threads per block: 256 (64 x 4 tiles) or 512 (64 x 8 tiles, taller, so
+// fewer y-halo rows are loaded per cell; only where the LDS ring stays small).
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int call_3d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
+    if (L.bx == 512) {
+        if constexpr (lds3d_bytes<R, NP, NM, 8>() <= 64 * 1024)
+            return call_3d_by<R, NP, NM, ANISO, OBST, 8>(L, c, k);
+        return MP_E_PARAM;
+    }
+    return call_3d_by<R, NP, NM, ANISO, OBST, 4>(L, c, k);
 }
 
 }  // namespace mp

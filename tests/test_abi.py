@@ -243,7 +243,7 @@ def test_tune_candidates_and_errors_without_gpu():
         abi.mp_destroy(st)
     st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
     try:
-        assert {(b, v) for b, _, v in abi.mp_tune_candidates(st)} == {(64, 1)}
+        assert {(b, v) for b, _, v in abi.mp_tune_candidates(st)} == {(256, 1), (512, 1)}
         assert abi.lib().mp_set_tile(st, 0, 0, 2) == abi.MP_E_PARAM
     finally:
         abi.mp_destroy(st)

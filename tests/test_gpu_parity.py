@@ -155,16 +155,25 @@ def test_tile_shape_invariance_bitwise(precision):
             assert np.array_equal(f, ref[0]) and np.array_equal(m, ref[1]), tile
 
 
-def test_tile_shape_invariance_bitwise_3d():
-    p = variant(dim=3, N=3, K=3, n=(70, 13, 40), bc=(0, 1, 1), delta=0.02)
+@pytest.mark.parametrize("case", ["f64_n3k3", "f32_n2k2_tall", "f32_n3k2_tall"])
+def test_tile_shape_invariance_bitwise_3d(case):
+    prec, N, K, tall = {"f64_n3k3": ("f64", 3, 3, False), "f32_n2k2_tall": ("f32", 2, 2, True),
+                        "f32_n3k2_tall": ("f32", 3, 2, True)}[case]
+    p = variant(dim=3, N=N, K=K, n=(70, 13, 40), bc=(0, 1, 1), delta=0.02, precision=prec)
     phi, mu = nuclei_case(p, seed=3)
+    tiles = [(256, 16), (256, 1), (256, 5), (256, 64)]
+    if tall:  # 64 x 8 tiles exist where their LDS ring is small enough
+        tiles += [(512, 3), (512, 16), (512, 64)]
     ref = None
-    for seg in [16, 1, 5, 64]:
-        f, m = run_gpu(p, phi, mu, 10, tile=(64, seg))
+    for tile in tiles:
+        f, m = run_gpu(p, phi, mu, 10, tile=tile)
         if ref is None:
             ref = (f, m)
         else:
-            assert np.array_equal(f, ref[0]) and np.array_equal(m, ref[1]), seg
+            assert np.array_equal(f, ref[0]) and np.array_equal(m, ref[1]), tile
+    if tall:  # and the tall tile against the oracle
+        of, om = gp.run(phi, mu, 0, 10, p)
+        assert np.max(np.abs(f - of)) <= 2e-5 and np.max(np.abs(m - om)) <= 2e-5
 
 
 def test_run_to_run_bitwise():
