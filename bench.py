@@ -40,7 +40,19 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # counters read for a plain device copy of known size.  A figure holds only
 # for the tile it was taken at and for the kernel sources it was taken on
 # (sha256 over csrc/); otherwise the leg reports traffic null.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/k_step2d_eutectic_4096_f64_f32.md
+    "c2_f64": {"tile": [128, 8, 1], "src": "16346d2207d3ad87",
+               "bytes": (2.0 * 345240.4 + 663579.7) * 1024},
+    "c2_f32": {"tile": [64, 8, 2], "src": "16346d2207d3ad87",
+               "bytes": (2.0 * 181914.7 + 329631.4) * 1024},
+    # profiles/k_step3d_dendrite_512_f32.md
+    "c3": {"tile": [512, 64, -1], "src": "16346d2207d3ad87",
+           "bytes": (2.0 * 1094323.8 + 1572864.0) * 1024},
+    # profiles/k_batch2d_ensemble_256_f32.md
+    "c4": {"tile": [256, 8, 1], "src": "16346d2207d3ad87",
+           "bytes": (2.0 * 711766.1 + 1265583.4) * 1024},
+}
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5")
 
@@ -91,7 +103,8 @@ def traffic_of(leg, tile):
 def roofline(bytes_per_step, ms_step, traffic=None):
     gbs = bytes_per_step / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic)}
 
 
 def parse_tile(text):
