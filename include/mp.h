@@ -133,8 +133,11 @@ size_t mp_workspace_bytes(const mp_state* st);
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
 
 /* Advance nsteps >= 0 forward-Euler steps on ``stream`` (asynchronous).
- * Each step reads the current buffer and writes the other; the current
- * buffer flips nsteps mod 2 times; the time level advances by nsteps. */
+ * Each kernel launch reads the current buffer and writes the other one, and
+ * performs one step, or two (mp_set_fusion; an odd remainder is a single
+ * step), so the current buffer flips once per launch: mp_current
+ * reports it.  The time level advances by nsteps.  Results are bitwise the
+ * same either way. */
 int mp_step(mp_state* st, int64_t nsteps, void* stream);
 
 /* Which bound buffer (0 or 1) holds the current state, and its time level. */
@@ -175,6 +178,16 @@ int mp_get_tile(const mp_state* st, int* bx, int* seg, int* vec);
 int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap);
 int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, int* best,
             void* stream);
+
+/* Steps per launch of the 2D step kernels (single grid or batch): 1 or 2
+ * (the default for 2D states; 3D states take 1).
+ * With 2, one launch reads a state, computes the next one in registers and
+ * writes the one after it, so the state crosses HBM once per two steps
+ * (temporal blocking); every cell gets the same arithmetic, and results are
+ * bitwise those of two single steps.  Errors: MP_E_PARAM for other values
+ * and for 3D states. */
+int mp_set_fusion(mp_state* st, int steps);
+int mp_get_fusion(const mp_state* st, int* steps);
 
 /* Replay steps as a HIP graph: chunk = steps per graph (even, >= 2), or 0 to
  * launch kernel by kernel (the default).  The graph is built explicitly (no

@@ -32,7 +32,7 @@ EXPORTS = [
     "mp_current", "mp_set_step", "mp_diagnostics", "mp_set_tile", "mp_get_tile", "mp_destroy",
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
-    "mp_tune_candidates", "mp_tune",
+    "mp_tune_candidates", "mp_tune", "mp_set_fusion", "mp_get_fusion",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -125,6 +125,10 @@ def lib():
         L.mp_adjoint.restype = C.c_int
         L.mp_adjoint.argtypes = [vp, vp, C.c_int64, C.c_int64, C.c_int64, vp, vp,
                                  C.POINTER(C.c_double), vp, vp]
+        L.mp_set_fusion.restype = C.c_int
+        L.mp_set_fusion.argtypes = [vp, C.c_int]
+        L.mp_get_fusion.restype = C.c_int
+        L.mp_get_fusion.argtypes = [vp, C.POINTER(C.c_int)]
         L.mp_tune_candidates.restype = C.c_int
         L.mp_tune_candidates.argtypes = [vp, C.POINTER(C.c_int32), C.c_int]
         L.mp_tune.restype = C.c_int
@@ -262,6 +266,16 @@ def mp_instance_offset(st, i: int):
     off, nb = C.c_size_t(), C.c_size_t()
     _check(lib().mp_instance_offset(st, int(i), C.byref(off), C.byref(nb)))
     return off.value, nb.value
+
+
+def mp_set_fusion(st, steps: int):
+    _check(lib().mp_set_fusion(st, int(steps)))
+
+
+def mp_get_fusion(st) -> int:
+    v = C.c_int()
+    _check(lib().mp_get_fusion(st, C.byref(v)))
+    return v.value
 
 
 def mp_set_graph(st, chunk: int):

@@ -45,8 +45,10 @@ struct mp_state {
     int cur;
     int64_t step;
     int bx, seg, vec;  // vec: cap on cells per lane of the 2D strips (-1: none)
+    int fuse;  // steps per launch of the step kernel: 1, or 2 (2D single grid)
     int graph_chunk;
     hipGraphExec_t gexec[2];  // by starting buffer
+    int gend[2];              // buffer current after a replay, by starting buffer
     std::vector<mp::KernelCall> gcalls[2];  // argument records of each graph's nodes, kept alive
     std::vector<int> item_inst;  // batch work list (host copy) for the current seg
     int nitems;
@@ -242,7 +244,8 @@ int hip_check(hipError_t e, const char* what) {
     return MP_OK;
 }
 
-// Strip waves across one row of a 2D instance (62 written lanes of vec_of cells each).
+// Strip waves across one row of a batched instance (W2X_LANES_OUT written lanes
+// of vec_of cells each, for one and two steps per launch alike).
 // Cap on cells per lane: the tile's, at most 2 in a batch (the batched kernel
 // is built for 1 or 2).
 int vec_cap(const mp_state* st) {
@@ -253,7 +256,7 @@ int vec_of(const mp_state* st, const Inst& I) {
     return mp::vec2d_width(I.grid.n[0], (int)elem_of(I.prm.precision), vec_cap(st));
 }
 int strips_of(const mp_state* st, const Inst& I) {
-    const int64_t w = mp::W2D_LANES_OUT_HOST * vec_of(st, I);
+    const int64_t w = mp::W2X_LANES_OUT_HOST * vec_of(st, I);
     return (int)((I.grid.n[0] + w - 1) / w);
 }
 
@@ -341,6 +344,7 @@ int choose_batch_blocks(mp_state* st) {
     L.potential = st->potential;
     L.aniso = st->aniso ? 1 : 0;
     L.vmax = vec_cap(st);
+    L.fuse = st->fuse;
     L.nblocks = 8;
     mp::KernelCall k;
     rc = st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
@@ -367,10 +371,11 @@ int sync_batch(mp_state* st) {
 }
 
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k);
+                     mp::KernelCall& k, int fuse = 1);
 
-// One step launch; kstep is the launch's offset from the device time level.
-int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
+// One launch of `fuse` steps (1 or 2; a batch always 1); kstep is the
+// launch's offset from the device time level.
+int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fuse = 1) {
     if (st->batch) {
         mp::BatchLaunch L;
         L.in = st->buf[from];
@@ -381,17 +386,19 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k) {
         L.potential = st->potential;
         L.aniso = st->aniso ? 1 : 0;
         L.vmax = vec_cap(st);
+        L.fuse = fuse;
         L.nblocks = st->batch_blocks;
         L.stepctr = dev_ctr(st);
         L.kstep = kstep;
         return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
     }
-    return make_single_call(st, st->buf[from], st->buf[1 - from], dev_ctr(st), kstep, k);
+    return make_single_call(st, st->buf[from], st->buf[1 - from], dev_ctr(st), kstep, k, fuse);
 }
 
-// Single-grid step from ``in`` to ``out`` at time level *ctr + kstep.
+// Single-grid launch of `fuse` steps from ``in`` to ``out`` at time level
+// *ctr + kstep.
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k) {
+                     mp::KernelCall& k, int fuse) {
     const Inst& I = st->inst[0];
     mp::StepLaunch L;
     L.in = in;
@@ -405,6 +412,7 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.bx = st->bx;
     L.seg = st->seg;
     L.vec = st->vec;
+    L.fuse = fuse;
     L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
@@ -416,18 +424,22 @@ int launch(const mp::KernelCall& k, hipStream_t s) {
     return hip_check(hipLaunchKernel(k.func, k.grid, k.block, (void**)k.args, 0, s), "kernel launch");
 }
 
-// Graph of graph_chunk steps starting from buffer `from`, then the time-level advance.
+// Graph of graph_chunk steps starting from buffer `from` (launches of st->fuse
+// steps each), then the time-level advance.  Sets gend[from].
 int build_graph(mp_state* st, int from, hipGraphExec_t* out) {
     std::vector<mp::KernelCall>& calls = st->gcalls[from];
-    calls.assign((size_t)st->graph_chunk + 1, mp::KernelCall());
-    for (int i = 0; i <= st->graph_chunk; ++i) {
-        if (i < st->graph_chunk) {
-            const int rc = make_step_call(st, i, (from + i) & 1, calls[i]);
+    const int F = st->fuse;
+    const int nl = st->graph_chunk / F;  // graph_chunk is even, F is 1 or 2
+    calls.assign((size_t)nl + 1, mp::KernelCall());
+    for (int i = 0; i <= nl; ++i) {
+        if (i < nl) {
+            const int rc = make_step_call(st, i * F, (from + i) & 1, calls[i], F);
             if (rc) return fail(rc, "no kernel instance for this configuration");
         } else {
             mp::call_advance(dev_ctr(st), st->graph_chunk, calls[i]);
         }
     }
+    st->gend[from] = (from + nl) & 1;
     hipGraph_t g = nullptr;
     int rc = hip_check(hipGraphCreate(&g, 0), "hipGraphCreate");
     if (rc) return rc;
@@ -467,7 +479,10 @@ void init_state(mp_state* st) {
     st->cur = 0;
     st->step = 0;
     st->graph_chunk = 0;
+    st->fuse = 1;
     st->gexec[0] = st->gexec[1] = nullptr;
+    st->gend[0] = 0;
+    st->gend[1] = 1;
     st->nitems = 0;
     st->batch_blocks = 0;
     st->aniso = false;
@@ -479,13 +494,22 @@ void init_state(mp_state* st) {
         // measured best on 512^3 FP32: tall tiles, long z segments
         st->bx = d3_tall_ok(st) ? 512 : 256;
         st->seg = 64;
+    } else if (st->batch) {
+        // measured best on the 256-instance ensemble: two steps per launch,
+        // one cell per lane (keeps the batched kernel at 5 waves per SIMD)
+        st->fuse = 2;
+        st->bx = 64 * mp::BATCH_WPB_HOST;
+        st->seg = 32;
+        st->vec = 1;
     } else {
-        // measured best on 4096^2: short segments keep enough waves in flight
-        // to cover HBM latency; one FP64 cell per lane keeps two waves per
-        // SIMD without spills, two FP32 cells per lane give 8-byte accesses
-        st->bx = st->batch ? 64 * mp::BATCH_WPB_HOST : (st->precision == MP_FP64 ? 128 : 64);
-        st->seg = st->batch ? 4 : 8;
-        st->vec = (st->batch || st->precision == MP_FP64) ? 1 : 2;
+        // two steps per launch (the state crosses HBM once per two steps);
+        // tiles measured best for it on 4096^2: one FP64 cell per lane keeps
+        // the kernel at 3 waves per SIMD without spills, two FP32 cells per
+        // lane give 8-byte accesses
+        st->fuse = 2;
+        st->bx = st->precision == MP_FP64 ? 256 : 64;
+        st->seg = st->precision == MP_FP64 ? 32 : 16;
+        st->vec = st->precision == MP_FP64 ? 1 : 2;
     }
 }
 
@@ -737,17 +761,21 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
             }
             const int rc = hip_check(hipGraphLaunch(st->gexec[st->cur], s), "hipGraphLaunch");
             if (rc) return rc;
-            left -= C;  // C is even: the current buffer is unchanged
+            left -= C;
             st->step += C;
+            st->cur = st->gend[st->cur];
         }
     }
-    for (int64_t i = 0; i < left; ++i) {
+    // launches of st->fuse steps, then single steps for the remainder
+    for (int64_t i = 0; i < left;) {
+        const int F = left - i >= st->fuse ? st->fuse : 1;
         mp::KernelCall k;
-        int rc = make_step_call(st, (int)i, st->cur, k);
+        int rc = make_step_call(st, (int)i, st->cur, k, F);
         if (rc) return fail(rc, "no kernel instance for this configuration");
         rc = launch(k, s);
         if (rc) return rc;
         st->cur = 1 - st->cur;
+        i += F;
     }
     if (left > 0) {
         mp::KernelCall k;
@@ -869,7 +897,7 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
         ms[i] = -1.0;
         if (mp_set_tile(st, cand[3 * i], cand[3 * i + 1], cand[3 * i + 2]) != MP_OK) continue;
         mp::KernelCall k;
-        if (make_step_call(st, 0, st->cur, k) != MP_OK) continue;
+        if (make_step_call(st, 0, st->cur, k, st->fuse) != MP_OK) continue;
         rc = launch(k, s);
         if (rc == MP_OK) rc = hip_check(hipEventRecord(e[0], s), "hipEventRecord");
         for (int r = 0; r < reps && rc == MP_OK; ++r) rc = launch(k, s);
@@ -891,6 +919,23 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
     rc = mp_set_tile(st, cand[3 * bi], cand[3 * bi + 1], cand[3 * bi + 2]);
     if (rc) return rc;
     *best = bi;
+    return ok();
+}
+
+int mp_set_fusion(mp_state* st, int steps) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (steps != 1 && steps != 2) return fail(MP_E_PARAM, "steps per launch must be 1 or 2 (got %d)", steps);
+    if (steps == 2 && st->inst[0].grid.dim != 2)
+        return fail(MP_E_PARAM, "two steps per launch exist for 2D grids only");
+    drop_graphs(st);
+    st->fuse = steps;
+    if (st->batch && st->bound) return choose_batch_blocks(st);
+    return ok();
+}
+
+int mp_get_fusion(const mp_state* st, int* steps) {
+    if (!st || !steps) return fail(MP_E_NULLPTR, "state or steps is NULL");
+    *steps = st->fuse;
     return ok();
 }
 

@@ -1,6 +1,8 @@
 // Batched 2D step: many independent simulations in one persistent launch.
 //
 // The work list holds one item per (instance, column strip, row segment),
+// strips W2X_LANES_OUT lanes wide for both the one-step and the two-step
+// variant (so the list does not depend on the steps per launch),
 // instance by instance; item_inst[i] names the instance of item i and the
 // instance table (InstDesc) carries its grid, sizes, coefficients, state
 // offset and temperature law.  The grid is sized to what stays resident; each
@@ -16,38 +18,51 @@ namespace mp {
 
 constexpr int BATCH_WPB = BATCH_WPB_HOST;  // waves per block
 
+constexpr int BATCH_W = W2X_LANES_OUT;  // written lanes per batched strip
+
+// One item with V cells per lane and FUSE (1 or 2) steps.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int FUSE>
+__device__ __forceinline__ void run_strip(const R* src, R* dst, const InstDesc<R>& d, double tb0,
+                                          double tb1, int tx, int m0, int m1) {
+    if constexpr (FUSE == 2)
+        strip2d_x2<R, NP, NM, ANISO, OBST, V>(src, dst, d.g, d.c, tb0, tb1, d.tslope, tx, m0, m1);
+    else
+        strip2d<R, NP, NM, ANISO, OBST, V, MP_STRIP_DEPTH, BATCH_W>(src, dst, d.g, d.c, tb0, d.tslope,
+                                                                    tx, m0, m1);
+}
+
 // Cells per lane of a batched item: 1, or up to VMAX = 2 where nx is even.
 // Every variant is inlined into the one kernel, whose register budget is that
 // of the widest, so the kernel is instantiated per VMAX.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int VMAX>
-__device__ __forceinline__ void run_vec(const R* src, R* dst, const InstDesc<R>& d, double tbase,
-                                        int tx, int m0, int m1) {
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int VMAX, int FUSE>
+__device__ __forceinline__ void run_vec(const R* src, R* dst, const InstDesc<R>& d, double tb0,
+                                        double tb1, int tx, int m0, int m1) {
     if (VMAX == 1 || d.vec == 1)
-        strip2d<R, NP, NM, ANISO, OBST, 1>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+        run_strip<R, NP, NM, ANISO, OBST, 1, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
     else
-        strip2d<R, NP, NM, ANISO, OBST, 2>(src, dst, d.g, d.c, tbase, d.tslope, tx, m0, m1);
+        run_strip<R, NP, NM, ANISO, OBST, 2, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
 }
 
-template <typename R, bool ANISO, bool OBST, int VMAX>
-__device__ __forceinline__ void run_item(const R* src, R* dst, const InstDesc<R>& d, double tbase,
-                                         int tx, int m0, int m1) {
+template <typename R, bool ANISO, bool OBST, int VMAX, int FUSE>
+__device__ __forceinline__ void run_item(const R* src, R* dst, const InstDesc<R>& d, double tb0,
+                                         double tb1, int tx, int m0, int m1) {
     switch (d.np * 4 + d.nm) {
         case 2 * 4 + 1:
-            run_vec<R, 2, 1, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 2, 1, ANISO, OBST, VMAX, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
             break;
         case 2 * 4 + 2:
-            run_vec<R, 2, 2, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 2, 2, ANISO, OBST, VMAX, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
             break;
         case 3 * 4 + 1:
-            run_vec<R, 3, 1, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 3, 1, ANISO, OBST, VMAX, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
             break;
         default:
-            run_vec<R, 3, 2, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
+            run_vec<R, 3, 2, ANISO, OBST, VMAX, FUSE>(src, dst, d, tb0, tb1, tx, m0, m1);
             break;
     }
 }
 
-template <typename R, bool ANISO, bool OBST, int VMAX>
+template <typename R, bool ANISO, bool OBST, int VMAX, int FUSE>
 __global__ void __launch_bounds__(64 * BATCH_WPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __restrict__ tab,
           const int* __restrict__ item_inst, int nitems, const int64_t* __restrict__ stepctr,
@@ -67,24 +82,29 @@ k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __re
         const int tx = local % d.ntx;
         const int m0 = (local / d.ntx) * d.seg;
         const int m1 = min(m0 + d.seg, d.g.ny);
-        const double tbase = d.tb0 + d.tdn * (double)n;
         const R* src = in + d.off;
         R* dst = out + d.off;
-        run_item<R, ANISO, OBST, VMAX>(src, dst, d, tbase, tx, m0, m1);
+        run_item<R, ANISO, OBST, VMAX, FUSE>(src, dst, d, d.tb0 + d.tdn * (double)n,
+                                             d.tb0 + d.tdn * (double)(n + 1), tx, m0, m1);
     }
 }
 
-template <typename R, int VMAX>
+template <typename R, int VMAX, int FUSE>
 const void* batch_func(bool aniso, bool obst) {
     if (aniso)
-        return obst ? (const void*)&k_batch2d<R, true, true, VMAX> : (const void*)&k_batch2d<R, true, false, VMAX>;
-    return obst ? (const void*)&k_batch2d<R, false, true, VMAX> : (const void*)&k_batch2d<R, false, false, VMAX>;
+        return obst ? (const void*)&k_batch2d<R, true, true, VMAX, FUSE>
+                    : (const void*)&k_batch2d<R, true, false, VMAX, FUSE>;
+    return obst ? (const void*)&k_batch2d<R, false, true, VMAX, FUSE>
+                : (const void*)&k_batch2d<R, false, false, VMAX, FUSE>;
 }
 
 template <typename R>
 int call_batch(const BatchLaunch& L, KernelCall& k) {
     const bool obst = L.potential == MP_OBSTACLE;
-    k.func = L.vmax == 1 ? batch_func<R, 1>(L.aniso, obst) : batch_func<R, 2>(L.aniso, obst);
+    if (L.fuse == 2)
+        k.func = L.vmax == 1 ? batch_func<R, 1, 2>(L.aniso, obst) : batch_func<R, 2, 2>(L.aniso, obst);
+    else
+        k.func = L.vmax == 1 ? batch_func<R, 1, 1>(L.aniso, obst) : batch_func<R, 2, 1>(L.aniso, obst);
     if (L.nblocks <= 0 || L.nblocks % 8) return MP_E_PARAM;
     k.grid = dim3((unsigned)L.nblocks);
     k.block = dim3(64 * BATCH_WPB);

@@ -257,17 +257,6 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
     }
 }
 
-// Whole-wave lane shuffle: value of lane (addr / 4).
-__device__ __forceinline__ float lane_get(float v, int addr) {
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
-}
-__device__ __forceinline__ double lane_get(double v, int addr) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
-    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Value of the next / previous lane of the wave (lane 63's next is lane 0 and
 // lane 0's previous is lane 63).  FP32 goes through the LDS crossbar
 // (ds_bpermute), which leaves the vector ALU -- the FP32 step's limit -- to the

@@ -56,6 +56,7 @@ struct StepLaunch {
     Geom g;
     int nphases, nmu, dim, potential, aniso;
     int bx, seg, vec;
+    int fuse;  // steps per launch: 1, or 2 (2D single grid)
     const int64_t* stepctr;
     int kstep;
     double tb0, tdn, tslope;
@@ -99,6 +100,7 @@ struct BatchLaunch {
     int nitems;
     int potential, aniso;
     int vmax;  // widest cells-per-lane among the items (1 or 2)
+    int fuse;  // steps per launch (1 or 2)
     int nblocks;
     const int64_t* stepctr;
     int kstep;
@@ -141,6 +143,7 @@ __host__ __device__ inline int vec2d_width(int64_t nx, int elem, int cap) {
 // Written lanes per 2D strip wave (lanes 1..62; 0 and 63 hold the halo),
 // waves per block of the batched kernel.
 constexpr int W2D_LANES_OUT_HOST = 62;
+constexpr int W2X_LANES_OUT_HOST = 60;  // the two-step strip keeps two halo lanes per side
 constexpr int BATCH_WPB_HOST = 4;
 inline int batch_waves_per_block_host() { return BATCH_WPB_HOST; }
 

@@ -70,6 +70,7 @@ __device__ __forceinline__ void vstore(R* p, const R (&v)[V]) {
 }
 
 constexpr int W2D_LANES_OUT = W2D_LANES_OUT_HOST;  // written lanes per strip wave
+constexpr int W2X_LANES_OUT = W2X_LANES_OUT_HOST;  // written lanes per two-step strip wave
 
 // Raw row as loaded: the lane's V cells of every field.
 template <typename R, int NF, int V>
@@ -87,14 +88,188 @@ struct Row2d {
     R cdx[ANISO ? V : 1][NP];
 };
 
+// What one pass over the rows carries from a row to the next: the W, J of the
+// y faces below the current row's cells and (anisotropy) phi of the row below.
+template <typename R, int NP, int NM, int V, bool ANISO>
+struct Carry2d {
+    R Wlo[V][NP];
+    R Jlo[V][NM];
+    R prvphi[ANISO ? V : 1][NP];
+};
+
+// Cell record from the V values of every field (field-major, as loaded).
+template <typename R, int NP, int NM, bool ANISO, int V>
+__device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, NM, V, ANISO>& P,
+                                         const Coef<R>& c) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) P.phi[i][a] = v[a][i];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) P.mu[i][k] = v[NP + k][i];
+        R hh[NP];
+        interp_h<R, NP>(P.phi[i], hh);
+        mobility<R, NP, NM>(hh, c, P.Mt[i]);
+    }
+    if constexpr (ANISO) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            const R left = lane_prev(P.phi[V - 1][a]);
+            const R right = lane_next(P.phi[0][a]);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                P.cdx[i][a] = (i + 1 < V ? P.phi[i + 1][a] : right) - (i > 0 ? P.phi[i - 1][a] : left);
+        }
+    }
+}
+
+// y face between rows A (below) and B (above) at slot i.
+template <typename R, int NP, int NM, bool ANISO, int V>
+__device__ __forceinline__ void yface(const Row2d<R, NP, NM, V, ANISO>& A, const Row2d<R, NP, NM, V, ANISO>& B,
+                                      int i, const Coef<R>& c, R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
+    R tau[1][NP];
+    if constexpr (ANISO) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) tau[0][a] = A.cdx[i][a] + B.cdx[i][a];
+    }
+    face_core<R, NP, NM, ANISO, 1>(A.phi[i], B.phi[i], tau, A.Mt[i], B.Mt[i], A.mu[i], B.mu[i], c, U, Wf,
+                                   J);
+}
+
+// Carry of the first row of a pass, from the row below it.
+template <typename R, int NP, int NM, bool ANISO, int V>
+__device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO>& prv,
+                                           const Row2d<R, NP, NM, V, ANISO>& cur,
+                                           Carry2d<R, NP, NM, V, ANISO>& k, const Coef<R>& c) {
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        R Ud[NP];
+        yface<R, NP, NM, ANISO, V>(prv, cur, i, c, Ud, k.Wlo[i], k.Jlo[i]);
+    }
+    if constexpr (ANISO) {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int a = 0; a < NP; ++a) k.prvphi[i][a] = prv.phi[i][a];
+    }
+}
+
+// New values of the row `cur` (nxt is the row above) and the carry moved up
+// one row.  Cs = psi_const of the row.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+__device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur,
+                                           const Row2d<R, NP, NM, V, ANISO>& nxt,
+                                           Carry2d<R, NP, NM, V, ANISO>& k, const R (&Cs)[NP],
+                                           const Coef<R>& c, R (&phin)[NP][V], R (&mun)[NM][V]) {
+    R cdy[ANISO ? V : 1][NP];
+    if constexpr (ANISO) {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int a = 0; a < NP; ++a) cdy[i][a] = nxt.phi[i][a] - k.prvphi[i][a];
+    }
+    // x face to the right of the last cell, with the next lane's first cell
+    R Ur[NP], Wr[NP], Jr[NM];
+    {
+        R pR[NP], uR[NM], MR[NM], tau[1][NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) pR[a] = lane_next(cur.phi[0][a]);
+#pragma unroll
+        for (int kk = 0; kk < NM; ++kk) {
+            uR[kk] = lane_next(cur.mu[0][kk]);
+            MR[kk] = lane_next(cur.Mt[0][kk]);
+        }
+        if constexpr (ANISO) {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_next(cdy[0][a]);
+        }
+        face_core<R, NP, NM, ANISO, 1>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR, c,
+                                       Ur, Wr, Jr);
+    }
+    // the face on the left of the first cell is the previous lane's last face
+    R Wxl[NP], Jxl[NM];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) Wxl[a] = lane_prev(Wr[a]);
+#pragma unroll
+    for (int kk = 0; kk < NM; ++kk) Jxl[kk] = lane_prev(Jr[kk]);
+
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        // x face (i, i+1) inside the lane, or the right face for the last cell
+        R Ux[NP], Wx[NP], Jx[NM];
+        if (i + 1 < V) {
+            R tau[1][NP];
+            if constexpr (ANISO) {
+#pragma unroll
+                for (int a = 0; a < NP; ++a) tau[0][a] = cdy[i][a] + cdy[i + 1][a];
+            }
+            face_core<R, NP, NM, ANISO, 1>(cur.phi[i], cur.phi[i + 1], tau, cur.Mt[i], cur.Mt[i + 1],
+                                           cur.mu[i], cur.mu[i + 1], c, Ux, Wx, Jx);
+        } else {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                Ux[a] = Ur[a];
+                Wx[a] = Wr[a];
+            }
+#pragma unroll
+            for (int kk = 0; kk < NM; ++kk) Jx[kk] = Jr[kk];
+        }
+        // y face (m, m+1) above cell i
+        R Uy[NP], Wy[NP], Jy[NM];
+        yface<R, NP, NM, ANISO, V>(cur, nxt, i, c, Uy, Wy, Jy);
+        R Gs[NP], Js[NM];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - k.Wlo[i][a]);
+#pragma unroll
+        for (int kk = 0; kk < NM; ++kk) Js[kk] = (Jx[kk] - Jxl[kk]) + (Jy[kk] - k.Jlo[i][kk]);
+        R pn[NP], un[NM], h0[NP];
+        interp_h<R, NP>(cur.phi[i], h0);
+        cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            phin[a][i] = pn[a];
+            k.Wlo[i][a] = Wy[a];
+            Wxl[a] = Wx[a];
+        }
+#pragma unroll
+        for (int kk = 0; kk < NM; ++kk) {
+            mun[kk][i] = un[kk];
+            k.Jlo[i][kk] = Jy[kk];
+            Jxl[kk] = Jx[kk];
+        }
+    }
+    if constexpr (ANISO) {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int a = 0; a < NP; ++a) k.prvphi[i][a] = cur.phi[i][a];
+    }
+}
+
+// Mirror ghost lane: move its ghost value into the slot the neighbour reads
+// (the last slot for a lane left of the grid, the first for one right of it).
+template <typename R, int NF, int V>
+__device__ __forceinline__ void mirror_fix(R (&v)[NF][V], bool fixL, bool fixR) {
+    if constexpr (V > 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            v[f][V - 1] = fixL ? v[f][0] : v[f][V - 1];
+            v[f][0] = fixR ? v[f][V - 1] : v[f][0];
+        }
+    }
+}
+
 #ifndef MP_STRIP_DEPTH
 #define MP_STRIP_DEPTH 2
 #endif
 
-// One wave's strip: columns tx*62V .. tx*62V + 62V - 1 (lanes 1..62), rows
-// [m0, m1).  Called with wave-uniform arguments by the single-grid and the
-// batched kernel.  Requires nx % V == 0.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int DEPTH = MP_STRIP_DEPTH>
+constexpr unsigned kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt/lgkmcnt untouched
+
+// One wave's strip of one step: columns tx*W*V .. (tx+1)*W*V - 1 (lanes
+// 1..W, W <= 62), rows [m0, m1).  Called with wave-uniform arguments by the
+// single-grid and the batched kernel.  Requires nx % V == 0.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int DEPTH = MP_STRIP_DEPTH,
+          int W = W2D_LANES_OUT>
 __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                         const Coef<R>& c, double tbase, double tslope, int tx,
                                         int m0, int m1) {
@@ -106,10 +281,11 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     const bool pery = g.bcy == MP_BC_PERIODIC;
     const int nx = g.nx;
     const int64_t fs = g.fstride;
-    const int cs = (tx * W2D_LANES_OUT - 1 + lane) * V;  // first column of the lane
+    static_assert(W >= 1 && W <= 62, "strip width");
+    const int cs = (tx * W - 1 + lane) * V;  // first column of the lane
     // load column: the lane's own, or the aligned vector holding its ghost
     int col = cs;
-    bool fixL = false, fixR = false;  // mirror ghosts: move the ghost value into the read slot
+    bool fixL = false, fixR = false;
     if (cs < 0) {
         col = perx ? nx - V : 0;
         fixL = !perx;
@@ -117,160 +293,29 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         col = perx ? 0 : nx - V;
         fixR = !perx;
     }
-    const bool writes = lane >= 1 && lane <= W2D_LANES_OUT && cs < nx;
+    const bool writes = lane >= 1 && lane <= W && cs < nx;
 
     auto load = [&](int m, RawT& r) {
         const int64_t o = (int64_t)gmap(m, g.ny, pery) * nx + col;
 #pragma unroll
         for (int f = 0; f < NF; ++f) vload<R, V>(in + f * fs + o, r.v[f]);
     };
-    auto process = [&](const RawT& r, RowT& P) {
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-#pragma unroll
-            for (int a = 0; a < NP; ++a) P.phi[i][a] = r.v[a][i];
-#pragma unroll
-            for (int k = 0; k < NM; ++k) P.mu[i][k] = r.v[NP + k][i];
-        }
-        if constexpr (V > 1) {
-            // a mirror ghost lane on the left is read at its last slot, one on
-            // the right at its first slot
-#pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                P.phi[V - 1][a] = fixL ? P.phi[0][a] : P.phi[V - 1][a];
-                P.phi[0][a] = fixR ? P.phi[V - 1][a] : P.phi[0][a];
-            }
-#pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                P.mu[V - 1][k] = fixL ? P.mu[0][k] : P.mu[V - 1][k];
-                P.mu[0][k] = fixR ? P.mu[V - 1][k] : P.mu[0][k];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            R hh[NP];
-            interp_h<R, NP>(P.phi[i], hh);
-            mobility<R, NP, NM>(hh, c, P.Mt[i]);
-        }
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                const R left = lane_prev(P.phi[V - 1][a]);
-                const R right = lane_next(P.phi[0][a]);
-#pragma unroll
-                for (int i = 0; i < V; ++i)
-                    P.cdx[i][a] = (i + 1 < V ? P.phi[i + 1][a] : right) - (i > 0 ? P.phi[i - 1][a] : left);
-            }
-        }
+    auto process = [&](RawT& r, RowT& P) {
+        mirror_fix<R, NF, V>(r.v, fixL, fixR);
+        make_row<R, NP, NM, ANISO, V>(r.v, P, c);
     };
-
-    R Wlo[V][NP], Jlo[V][NM];  // lower y faces of the current row's cells
-    R prvphi[ANISO ? V : 1][NP];
-
-    auto yface = [&](const RowT& A, const RowT& B, int i, R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
-        R tau[1][NP];
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int a = 0; a < NP; ++a) tau[0][a] = A.cdx[i][a] + B.cdx[i][a];
-        }
-        face_core<R, NP, NM, ANISO, 1>(A.phi[i], B.phi[i], tau, A.Mt[i], B.Mt[i], A.mu[i], B.mu[i], c,
-                                       U, Wf, J);
-    };
-
-    // Row m from cur (row m) and nxt (row m+1); stores row m.
+    Carry2d<R, NP, NM, V, ANISO> k;
     auto row = [&](int m, const RowT& cur, const RowT& nxt) {
-        R cdy[ANISO ? V : 1][NP];
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int a = 0; a < NP; ++a) cdy[i][a] = nxt.phi[i][a] - prvphi[i][a];
-        }
-        // x face to the right of the last cell, with lane t+1's first cell
-        R Ur[NP], Wr[NP], Jr[NM];
-        {
-            R pR[NP], uR[NM], MR[NM], tau[1][NP];
-#pragma unroll
-            for (int a = 0; a < NP; ++a) pR[a] = lane_next(cur.phi[0][a]);
-#pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                uR[k] = lane_next(cur.mu[0][k]);
-                MR[k] = lane_next(cur.Mt[0][k]);
-            }
-            if constexpr (ANISO) {
-#pragma unroll
-                for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_next(cdy[0][a]);
-            }
-            face_core<R, NP, NM, ANISO, 1>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR,
-                                           c, Ur, Wr, Jr);
-        }
-        // the face on the left of the first cell is lane t-1's last face
-        R Wxl[NP], Jxl[NM];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Wxl[a] = lane_prev(Wr[a]);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) Jxl[k] = lane_prev(Jr[k]);
-
         R Cs[NP];
         psi_const<R, NP>((R)(tbase + tslope * (double)m), c, Cs);
         R phin[NP][V], mun[NM][V];
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            // x face (i, i+1) inside the lane, or the right face for the last cell
-            R Ux[NP], Wx[NP], Jx[NM];
-            if (i + 1 < V) {
-                R tau[1][NP];
-                if constexpr (ANISO) {
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) tau[0][a] = cdy[i][a] + cdy[i + 1][a];
-                }
-                face_core<R, NP, NM, ANISO, 1>(cur.phi[i], cur.phi[i + 1], tau, cur.Mt[i], cur.Mt[i + 1],
-                                               cur.mu[i], cur.mu[i + 1], c, Ux, Wx, Jx);
-            } else {
-#pragma unroll
-                for (int a = 0; a < NP; ++a) {
-                    Ux[a] = Ur[a];
-                    Wx[a] = Wr[a];
-                }
-#pragma unroll
-                for (int k = 0; k < NM; ++k) Jx[k] = Jr[k];
-            }
-            // y face (m, m+1) above cell i
-            R Uy[NP], Wy[NP], Jy[NM];
-            yface(cur, nxt, i, Uy, Wy, Jy);
-            R Gs[NP], Js[NM];
-#pragma unroll
-            for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - Wlo[i][a]);
-#pragma unroll
-            for (int k = 0; k < NM; ++k) Js[k] = (Jx[k] - Jxl[k]) + (Jy[k] - Jlo[i][k]);
-            R pn[NP], un[NM], h0[NP];
-            interp_h<R, NP>(cur.phi[i], h0);
-            cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un);
-#pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                phin[a][i] = pn[a];
-                Wlo[i][a] = Wy[a];
-                Wxl[a] = Wx[a];
-            }
-#pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                mun[k][i] = un[k];
-                Jlo[i][k] = Jy[k];
-                Jxl[k] = Jx[k];
-            }
-        }
+        row_update<R, NP, NM, ANISO, OBST, V>(cur, nxt, k, Cs, c, phin, mun);
         if (writes) {
             const int64_t o = (int64_t)m * nx + cs;
 #pragma unroll
             for (int a = 0; a < NP; ++a) vstore<R, V>(out + a * fs + o, phin[a]);
 #pragma unroll
-            for (int k = 0; k < NM; ++k) vstore<R, V>(out + (NP + k) * fs + o, mun[k]);
-        }
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int a = 0; a < NP; ++a) prvphi[i][a] = cur.phi[i][a];
+            for (int kk = 0; kk < NM; ++kk) vstore<R, V>(out + (NP + kk) * fs + o, mun[kk]);
         }
     };
 
@@ -284,17 +329,7 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         RowT prv;
         process(r0, prv);
         process(r1, cA);
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            R Ud[NP];
-            yface(prv, cA, i, Ud, Wlo[i], Jlo[i]);
-        }
-        if constexpr (ANISO) {
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-#pragma unroll
-                for (int a = 0; a < NP; ++a) prvphi[i][a] = prv.phi[i][a];
-        }
+        carry_init<R, NP, NM, ANISO, V>(prv, cA, k, c);
         process(r2, cB);
     }
 
@@ -304,7 +339,6 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     // DEPTH rows and issues the loads of the next DEPTH rows right after that
     // wait, giving every load DEPTH rows of arithmetic to land in; a raw row
     // is turned into a cell record just before the row that needs it.
-    constexpr unsigned kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt/lgkmcnt untouched
     int m = m0;
     if constexpr (DEPTH == 1) {
         RawT ld;
@@ -348,9 +382,161 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     }
 }
 
+// Index i mod n for any integer i (n >= 1).
+__device__ __forceinline__ int wrap(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Two steps in one pass.  A wave's lanes cover xs .. xs + 64 V - 1 with
+// xs = tx * 60 V - 2 V; lanes 2..61 are written.  Step 1 is computed on every
+// lane into registers (a row at a time, marching y as in strip2d) and step 2
+// from those rows, so the state is read and written once per two steps.
+// Step 1 must see exactly the ghosts a stored state would: a periodic ghost
+// row or column is computed from its wrapped neighbours (the same operands in
+// the same order as where it lives, so the same bits); a mirror ghost is an
+// exact copy of the cell it mirrors (made by a lane shuffle in x and by
+// reusing the row record in y), so a boundary face sees two identical cells
+// and carries nothing, as in the one-step kernel.  The output rows [m0, m1)
+// need step-1 rows m0-1 .. m1 and state rows m0-2 .. m1+1.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+__device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
+                                           const Coef<R>& c, double tbase0, double tbase1, double tslope,
+                                           int tx, int m0, int m1) {
+    constexpr int NF = NP + NM;
+    typedef Raw2d<R, NF, V> RawT;
+    typedef Row2d<R, NP, NM, V, ANISO> RowT;
+    const int lane = threadIdx.x & 63;
+    const bool perx = g.bcx == MP_BC_PERIODIC;
+    const bool pery = g.bcy == MP_BC_PERIODIC;
+    const int nx = g.nx, ny = g.ny;
+    const int64_t fs = g.fstride;
+    const int cs = (tx * W2X_LANES_OUT - 2 + lane) * V;  // first column of the lane
+    int col;
+    bool fixL = false, fixR = false;
+    if (perx) {
+        col = wrap(cs, nx);
+    } else if (cs >= 0 && cs < nx) {
+        col = cs;
+    } else if (cs == -V) {
+        col = 0;  // holds ghost column -1 = column 0 in its last slot
+        fixL = true;
+    } else if (cs == nx) {
+        col = nx - V;  // holds ghost column nx = column nx-1 in its first slot
+        fixR = true;
+    } else {
+        col = cs < 0 ? 0 : nx - V;  // farther out: never read by a written lane
+    }
+    const bool writes = lane >= 2 && lane <= W2X_LANES_OUT + 1 && cs < nx;
+    const bool top = !pery && m0 == 0;   // step-1 row -1 is a copy of row 0
+    const bool bot = !pery && m1 == ny;  // step-1 row ny is a copy of row ny-1
+    const int r_first = top ? 0 : m0 - 1;
+    const int r_last = bot ? ny - 1 : m1;  // step-1 rows computed: r_first .. r_last
+
+    auto rowmap = [&](int s) { return pery ? wrap(s, ny) : gmap(s, ny, false); };
+    auto load = [&](int s, RawT& r) {
+        const int64_t o = (int64_t)rowmap(s) * nx + col;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) vload<R, V>(in + f * fs + o, r.v[f]);
+    };
+    auto process = [&](RawT& r, RowT& P) {
+        mirror_fix<R, NF, V>(r.v, fixL, fixR);
+        make_row<R, NP, NM, ANISO, V>(r.v, P, c);
+    };
+
+    // step 0 -> 1: rows of the state in c0 (row r) and n0 (row r+1)
+    Carry2d<R, NP, NM, V, ANISO> k0, k1;
+    RowT c0, n0;
+    RawT ld;
+    {
+        RawT a, b, d;
+        load(r_first - 1, a);
+        load(r_first, b);
+        load(r_first + 1, d);
+        RowT prv;
+        process(a, prv);
+        process(b, c0);
+        carry_init<R, NP, NM, ANISO, V>(prv, c0, k0, c);
+        process(d, n0);
+    }
+    if (r_first + 2 <= r_last + 1) load(r_first + 2, ld);
+
+    // Step-1 row r into P, then the state window moves up one row.
+    auto step1 = [&](int r, RowT& P) {
+        R Cs[NP];
+        psi_const<R, NP>((R)(tbase0 + tslope * (double)rowmap(r)), c, Cs);
+        R phin[NP][V], mun[NM][V];
+        row_update<R, NP, NM, ANISO, OBST, V>(c0, n0, k0, Cs, c, phin, mun);
+        R v[NF][V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) v[a][i] = phin[a][i];
+#pragma unroll
+            for (int kk = 0; kk < NM; ++kk) v[NP + kk][i] = mun[kk][i];
+        }
+        // mirror ghost columns of step 1: copies of the cells they mirror
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const R nextFirst = lane_next(v[f][0]);
+            const R prevLast = lane_prev(v[f][V - 1]);
+            v[f][V - 1] = fixL ? nextFirst : v[f][V - 1];
+            v[f][0] = fixR ? prevLast : v[f][0];
+        }
+        make_row<R, NP, NM, ANISO, V>(v, P, c);
+        if (r + 1 <= r_last) {
+            c0 = n0;
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            process(ld, n0);
+            if (r + 3 <= r_last + 1) load(r + 3, ld);
+        }
+    };
+
+    // step 1 -> 2: step-1 rows in c1 (row q) and n1 (row q+1)
+    RowT c1, n1;
+    {
+        RowT lower;
+        step1(r_first, lower);
+        if (top) {
+            c1 = lower;
+        } else {
+            step1(r_first + 1, c1);
+        }
+        carry_init<R, NP, NM, ANISO, V>(lower, c1, k1, c);
+    }
+    for (int q = m0; q < m1; ++q) {
+        if (bot && q + 1 == ny)
+            n1 = c1;
+        else
+            step1(q + 1, n1);
+        R Cs[NP];
+        psi_const<R, NP>((R)(tbase1 + tslope * (double)q), c, Cs);
+        R phin[NP][V], mun[NM][V];
+        row_update<R, NP, NM, ANISO, OBST, V>(c1, n1, k1, Cs, c, phin, mun);
+        if (writes) {
+            const int64_t o = (int64_t)q * nx + cs;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) vstore<R, V>(out + a * fs + o, phin[a]);
+#pragma unroll
+            for (int kk = 0; kk < NM; ++kk) vstore<R, V>(out + (NP + kk) * fs + o, mun[kk]);
+        }
+        c1 = n1;
+    }
+}
+
 #ifndef MP_WAVES_PER_EU
 #define MP_WAVES_PER_EU 2
 #endif
+
+// XCD-aware block order: the hardware deals blocks round-robin to the 8 XCDs,
+// so block b works on (b mod 8) * (nb/8) + b/8 and each XCD gets a contiguous
+// band of strips.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x;
+    const int q8 = nb / 8;
+    const int b = blockIdx.x;
+    return (b < 8 * q8) ? (b % 8) * q8 + b / 8 : b;
+}
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
@@ -358,13 +544,9 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
          const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
          int seg, int ntx, int nseg) {
     const int wpb = blockDim.x >> 6;
-    const int nb = gridDim.x;
-    const int q8 = nb / 8;
-    const int b = blockIdx.x;
-    const int blk = (b < 8 * q8) ? (b % 8) * q8 + b / 8 : b;
     // wave-uniform by construction; readfirstlane tells the compiler so, which
     // keeps every row-loop branch scalar
-    const int wid = __builtin_amdgcn_readfirstlane(blk * wpb + (threadIdx.x >> 6));
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
     if (wid >= ntx * nseg) return;  // whole wave leaves; nothing below synchronises
     const int tx = wid % ntx;
     const int sg = wid / ntx;
@@ -374,14 +556,32 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
+k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+            const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+            int seg, int ntx, int nseg) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double n = (double)(*stepctr + kstep);
+    strip2d_x2<R, NP, NM, ANISO, OBST, V>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0), tslope,
+                                          tx, m0, min(m0 + seg, g.ny));
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
 int call_2d_v(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
-    const int ntx = (L.g.nx + W2D_LANES_OUT * V - 1) / (W2D_LANES_OUT * V);
+    const int wout = L.fuse == 2 ? W2X_LANES_OUT : W2D_LANES_OUT;
+    const int ntx = (L.g.nx + wout * V - 1) / (wout * V);
     const int nseg = (L.g.ny + L.seg - 1) / L.seg;
     const int wpb = L.bx / 64;
     const long long waves = (long long)ntx * nseg;
     const long long nblocks = (waves + wpb - 1) / wpb;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
-    k.func = (const void*)&k_step2d<R, NP, NM, ANISO, OBST, V>;
+    k.func = L.fuse == 2 ? (const void*)&k_step2d_x2<R, NP, NM, ANISO, OBST, V>
+                         : (const void*)&k_step2d<R, NP, NM, ANISO, OBST, V>;
     k.grid = dim3((unsigned)nblocks);
     k.block = dim3(L.bx);
     k.arg((const R*)L.in);

@@ -66,6 +66,10 @@ class Solver:
         """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
         abi.mp_set_graph(self.st, chunk)
 
+    def set_fusion(self, steps: int):
+        """Steps per kernel launch (1, or 2 for 2D grids: the state crosses HBM once per two steps)."""
+        abi.mp_set_fusion(self.st, steps)
+
     def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:
         """Pick the fastest tile for this workload (cached on disk); the state is unchanged."""
         from . import autotune

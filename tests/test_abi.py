@@ -35,11 +35,11 @@ def test_create_and_query_without_gpu():
         assert abi.mp_current(st) == (0, 0)
         abi.mp_set_step(st, 7, 1)
         assert abi.mp_current(st) == (1, 7)
-        assert abi.mp_get_tile(st) == (128, 8, 1)
-        abi.mp_set_tile(st, 256, 16)
-        assert abi.mp_get_tile(st) == (256, 16, 1)
+        assert abi.mp_get_tile(st) == (256, 32, 1)
+        abi.mp_set_tile(st, 128, 16)
+        assert abi.mp_get_tile(st) == (128, 16, 1)
         abi.mp_set_tile(st, 0, 0, -1)
-        assert abi.mp_get_tile(st) == (256, 16, -1)
+        assert abi.mp_get_tile(st) == (128, 16, -1)
     finally:
         abi.mp_destroy(st)
 
@@ -258,3 +258,29 @@ def test_autotune_signature_distinguishes_workloads():
     assert a != autotune.signature([q], "dev") and a != autotune.signature([p], "other")
     members = [m[0] for m in inputs.config_c4(ninst=3, side=(64, 80))]
     assert autotune.signature(members, "dev") != autotune.signature(members[:2], "dev")
+
+
+def test_fusion_setting_validation_without_gpu():
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        assert abi.mp_get_fusion(st) == 2  # the default for a single 2D grid
+        abi.mp_set_fusion(st, 1)
+        assert abi.mp_get_fusion(st) == 1
+        for bad in (0, 3, -1):
+            with pytest.raises(abi.MPError):
+                abi.mp_set_fusion(st, bad)
+    finally:
+        abi.mp_destroy(st)
+    st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
+    try:
+        with pytest.raises(abi.MPError, match="2D"):
+            abi.mp_set_fusion(st, 2)
+    finally:
+        abi.mp_destroy(st)
+    bst = abi.mp_create_batch([m[0] for m in inputs.config_c4(ninst=2, side=(64, 70))])
+    try:
+        abi.mp_set_fusion(bst, 2)  # batches of 2D grids take either
+        assert abi.mp_get_fusion(bst) == 2
+    finally:
+        abi.mp_destroy(bst)

@@ -14,11 +14,13 @@ from paper_2404_01035_amd import abi, inputs
 pytestmark = pytest.mark.gpu
 
 
-def run_gpu(p, phi, mu, nsteps, step0=0, tile=None):
+def run_gpu(p, phi, mu, nsteps, step0=0, tile=None, fuse=None):
     from paper_2404_01035_amd.solver import Solver
 
     s = Solver(p)
     try:
+        if fuse:
+            s.set_fusion(fuse)
         if tile:
             s.set_tile(*tile)
         s.load(phi, mu, step0)
@@ -66,11 +68,12 @@ def variant(dim, N, K, n, bc, potential="well", delta=0.0, undercooling=0.15, G=
     return p
 
 
-def test_c1_fp64_1000_steps_matches_oracle():
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_c1_fp64_1000_steps_matches_oracle(fuse):
     p, phi, mu = inputs.config_c1(seed=0)
-    f, m = run_gpu(p, phi, mu, 1000)
+    f, m = run_gpu(p, phi, mu, 1000, fuse=fuse)
     of, om = gp.run(phi, mu, 0, 1000, p)
-    print(f"C1 FP64 1000 steps: phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
+    print(f"C1 FP64 1000 steps, {fuse} per launch: phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
     assert errs(f, of) <= 1e-10
     assert errs(m, om) <= 1e-10
 
