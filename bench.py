@@ -3,15 +3,17 @@
 Headline workload: 2D 4096 x 4096 directional eutectic (3 phases, ternary: 2 mu
 fields), x periodic / y no-flux, seeded synthetic initial state (lamellae slab
 in melt).  A benchmark step is one forward-Euler time step of the whole field
-(one launch of the fused kernel).  The timed region runs exactly --steps steps
-in FP64 (``value``) and, separately, in FP32 (``fp32``), with the state
-resident in HBM, at the library's default tiles (the autotuner's picks for this
-workload; --tune re-tunes).
+(the fused phi + mu update); the 2D kernels perform two steps per launch, so
+the state crosses HBM once per two steps (bitwise the same result as single
+steps).  The timed region runs exactly --steps steps in FP64 (``value``) and,
+separately, in FP32 (``fp32``), with the state resident in HBM, at the
+library's default tiles (the autotuner's picks for this workload; --tune
+re-tunes).
 
 Further legs, each a block of the same JSON line:
   dendrite_3d  3D 512^3 binary dendrite with cubic anisotropy, FP32
-  batched      256 uneven 2D instances in one persistent launch per step,
-               replayed as HIP graphs, FP32
+  batched      256 uneven 2D instances in one persistent launch per two
+               steps, replayed as HIP graphs, FP32
   adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
                (every 100 steps) and the adjoint sweep; their cost ratio
 cpu_baseline   the FP64 oracle on two full 4096^2 steps, on the host.
@@ -38,20 +40,21 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # HBM bytes per launch of each leg's step kernel, from rocprofv3 counter runs:
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
 # counters read for a plain device copy of known size.  A figure holds only
-# for the tile it was taken at and for the kernel sources it was taken on
-# (sha256 over csrc/); otherwise the leg reports traffic null.
+# for the tile and steps per launch it was taken at and for the device sources
+# it was taken on (sha256 over csrc/*.hpp, *.hip); otherwise the leg reports
+# traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [128, 8, 1], "src": "16346d2207d3ad87",
-               "bytes": (2.0 * 345240.4 + 663579.7) * 1024},
-    "c2_f32": {"tile": [64, 8, 2], "src": "16346d2207d3ad87",
-               "bytes": (2.0 * 181914.7 + 329631.4) * 1024},
+    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "4e0b7195ae65200a",
+               "bytes": (2.0 * 374164.0 + 661948.5) * 1024},
+    "c2_f32": {"tile": [64, 16, 2], "fuse": 2, "src": "4e0b7195ae65200a",
+               "bytes": (2.0 * 207392.4 + 329343.6) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "src": "16346d2207d3ad87",
-           "bytes": (2.0 * 1094323.8 + 1572864.0) * 1024},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "4e0b7195ae65200a",
+           "bytes": (2.0 * 1075660.0 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 8, 1], "src": "16346d2207d3ad87",
-           "bytes": (2.0 * 711766.1 + 1265583.4) * 1024},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "4e0b7195ae65200a",
+           "bytes": (2.0 * 699494.1 + 1207230.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5")
@@ -66,7 +69,7 @@ def parse():
     ap.add_argument("--legs", type=str, default=",".join(ALL_LEGS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true",
-                    help="autotune the 2D legs instead of using the library's default tiles")
+                    help="autotune the legs instead of using the library's default tiles")
     ap.add_argument("--tile", type=str, default="", help="bx,seg,vec of the FP64 leg")
     ap.add_argument("--tile32", type=str, default="", help="bx,seg,vec of the FP32 leg")
     ap.add_argument("--tile3d", type=str, default="", help="bx,seg,vec of the 3D leg (no tuning)")
@@ -86,21 +89,26 @@ def log(msg):
 
 
 def source_hash():
+    """sha256 (16 hex digits) over the device sources in csrc/ (*.hpp, *.hip)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
+        if not name.endswith((".hpp", ".hip")):
+            continue
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_of(leg, tile):
+def traffic_of(leg, tile, fuse):
     t = TRAFFIC.get(leg)
-    if not t or list(t["tile"]) != list(tile) or t["src"] != source_hash():
+    if not t or list(t["tile"]) != list(tile) or t["fuse"] != fuse or t["src"] != source_hash():
         return None
     return t["bytes"]
 
 
 def roofline(bytes_per_step, ms_step, traffic=None):
+    """Algorithmic bytes per launch / launch time (= per step / step time, whatever the
+    steps per launch); traffic = counter HBM bytes per launch."""
     gbs = bytes_per_step / (ms_step * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -169,6 +177,7 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
     else:
         source = "default"
     used = list(abi.mp_get_tile(s.st))
+    fuse = abi.mp_get_fusion(s.st)
     s.step(warmup)
     with Timer() as t:
         s.step(steps)
@@ -180,15 +189,16 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
     return {
         "value": p.ncells * steps / (t.ms * 1e-3),
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of(f"c2_{precision}", used)),
+        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of(f"c2_{precision}", used, fuse)),
         "bytes_per_cell_update": bpc,
-        "algorithmic_bytes_per_launch": p.ncells * bpc,
+        "steps_per_launch": fuse,
+        "algorithmic_bytes_per_launch": fuse * p.ncells * bpc,
         "tile": {"bx": used[0], "seg": used[1], "vec": used[2], "source": source},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
 
-def leg_c3(n, steps, warmup, tile):
+def leg_c3(n, steps, warmup, tile, tune):
     from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import Solver
 
@@ -198,7 +208,7 @@ def leg_c3(n, steps, warmup, tile):
     del phi, mu
     if tile:
         s.set_tile(*tile)
-    else:
+    elif tune:
         s.autotune(reps=5, force=True)
     used = list(abi.mp_get_tile(s.st))
     s.step(warmup)
@@ -214,15 +224,16 @@ def leg_c3(n, steps, warmup, tile):
         "unit": "cell-updates/s",
         "steps": steps,
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of("c3", used)),
+        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of("c3", used, 1)),
         "bytes_per_cell_update": bpc,
+        "steps_per_launch": 1,
         "algorithmic_bytes_per_launch": p.ncells * bpc,
         "tile": {"bx": used[0], "seg": used[1], "vec": used[2]},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
 
-def leg_c4(steps, warmup, tile, graph_chunk=50):
+def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
     from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import BatchSolver
 
@@ -236,9 +247,10 @@ def leg_c4(steps, warmup, tile, graph_chunk=50):
     del members
     if tile:
         b.set_tile(*tile)
-    else:
+    elif tune:
         b.autotune(reps=5, force=True)
     used = list(abi.mp_get_tile(b.st))
+    fuse = abi.mp_get_fusion(b.st)
     b.set_graph(graph_chunk)
     b.step(warmup)
     with Timer() as t:
@@ -248,15 +260,16 @@ def leg_c4(steps, warmup, tile, graph_chunk=50):
     ms_step = t.ms / steps
     return {
         "workload": "256 independent 2D instances, sides U{64..1024}, N in {2,3}, 1-2 mu fields, "
-                    "periodic, FP32, one persistent launch per step, HIP graphs of "
+                    f"periodic, FP32, one persistent launch per {fuse} step(s), HIP graphs of "
                     f"{graph_chunk} steps",
         "value": cells * steps / (t.ms * 1e-3),
         "unit": "cell-updates/s",
         "steps": steps,
         "cells": cells,
         "ms_per_step": ms_step,
-        "roofline": roofline(bytes_step, ms_step, traffic_of("c4", used)),
-        "algorithmic_bytes_per_launch": bytes_step,
+        "roofline": roofline(bytes_step, ms_step, traffic_of("c4", used, fuse)),
+        "steps_per_launch": fuse,
+        "algorithmic_bytes_per_launch": fuse * bytes_step,
         "tile": {"seg": used[1], "vec": used[2]},
         "nonfinite_instances": sum(1 for d in diags if d["nonfinite"]),
     }
@@ -280,6 +293,7 @@ def leg_c5(nsteps, every=100, n=512):
 
     s = Solver(p)
     s.load(phi, mu)
+    tuned = s.autotune(reps=10, force=True)  # a small grid: the tiles differ from 4096^2's
     ckpt = s.checkpoint_buffer(nsteps, every)
     s.step_ckpt(2, 1, s.checkpoint_buffer(2, 1))  # warm the kernels
     s.load(phi, mu)
@@ -296,6 +310,7 @@ def leg_c5(nsteps, every=100, n=512):
     return {
         "workload": f"2D {n}x{n}, 3 phases, ternary, periodic, FP32 forward + FP32 adjoint, "
                     f"{nsteps} steps, checkpoints every {every}",
+        "tile": {k: tuned[k] for k in ("bx", "seg", "vec", "fuse")},
         "forward_ms": tf.ms,
         "adjoint_ms": ta.ms,
         "adjoint_over_forward": ta.ms / tf.ms,
@@ -365,6 +380,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r64["roofline"],
+        "steps_per_launch": r64["steps_per_launch"],
         "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_launch"],
         "tile": r64["tile"],
         "diag": r64["diag"],
@@ -377,10 +393,10 @@ def main():
         out["speedup_fp32_over_fp64"] = r32["value"] / r64["value"]
     if "c3" in legs:
         log(f"3D {a.n3d}^3 FP32")
-        out["dendrite_3d"] = leg_c3(a.n3d, a.steps3d, 5, parse_tile(a.tile3d))
+        out["dendrite_3d"] = leg_c3(a.n3d, a.steps3d, 5, parse_tile(a.tile3d), a.tune)
     if "c4" in legs:
         log("batched ensemble FP32")
-        out["batched"] = leg_c4(a.batch_steps, 50, parse_tile(a.tile_batch))
+        out["batched"] = leg_c4(a.batch_steps, 50, parse_tile(a.tile_batch), a.tune)
     if "c5" in legs:
         log("checkpointed forward + adjoint FP32")
         out["adjoint"] = leg_c5(a.adjoint_steps)

@@ -164,17 +164,18 @@ int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
 int mp_set_tile(mp_state* st, int bx, int seg, int vec);
 int mp_get_tile(const mp_state* st, int* bx, int* seg, int* vec);
 
-/* Autotuning support.  mp_tune_candidates writes up to ``cap`` (bx, seg, vec)
- * triples that are valid for this state into cand[3*i .. 3*i+2] and returns
- * how many there are (a negative MP_E_* on error); cand may be NULL to query
- * the count.  mp_tune times each of the ncand triples in ``cand``:
- * one untimed launch, then ``reps`` launches of one step from the current
- * buffer into the other one, bracketed by events on ``stream``, and stores
- * the mean milliseconds per launch in ms[i] (-1 for a triple the state
- * rejects).  The current buffer and the time level are untouched; the other
- * buffer is overwritten.  The fastest one is set (as by mp_set_tile) and its
- * index stored in *best.  Synchronises ``stream``.  Errors: MP_E_NULLPTR,
- * MP_E_UNBOUND, MP_E_PARAM (ncand < 1, reps < 1 or no valid triple), MP_E_HIP. */
+/* Autotuning support.  mp_tune_candidates writes up to ``cap`` candidates
+ * (bx, seg, vec, steps per launch) valid for this state into
+ * cand[4*i .. 4*i+3] and returns how many there are (a negative MP_E_* on
+ * error); cand may be NULL to query the count.  mp_tune times each of the
+ * ncand candidates in ``cand``: one untimed launch, then ``reps`` launches
+ * from the current buffer into the other one, bracketed by events on
+ * ``stream``, and stores the mean milliseconds per step in ms[i] (-1 for a
+ * candidate the state rejects).  The current buffer and the time level are
+ * untouched; the other buffer is overwritten.  The fastest candidate is set
+ * (as by mp_set_fusion and mp_set_tile) and its index stored in *best.
+ * Synchronises ``stream``.  Errors: MP_E_NULLPTR, MP_E_UNBOUND, MP_E_PARAM
+ * (ncand < 1, reps < 1 or no valid candidate), MP_E_HIP. */
 int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap);
 int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, int* best,
             void* stream);
@@ -230,8 +231,8 @@ int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream);
 int mp_step_ckpt(mp_state* st, int64_t nsteps, int64_t every, void* ckpt_buf, void* stream);
 
 /* Bytes of the caller-owned work buffer mp_adjoint needs for ``every``
- * (cotangent staging, two adjoint buffers, one segment of recomputed states,
- * per-block gradient partial sums); 0 for unsupported states. */
+ * (two cotangent buffers, the adjoint state, two segments of recomputed
+ * states, per-block gradient partial sums); 0 for unsupported states. */
 size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
 
 /* Discrete adjoint of nsteps steps recorded by mp_step_ckpt starting at time
@@ -241,7 +242,9 @@ size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
  * doubles) receives dL/dtheta with theta = (gamma_01, gamma_02, gamma_12,
  * D[0][0], D[0][1], D[1][0], D[1][1], D[2][0], D[2][1], tau) and dt held
  * fixed.  Each segment between checkpoints is recomputed from its checkpoint
- * into the work buffer and swept backwards; results do not depend on
+ * into the work buffer and swept backwards; the recomputation of the next
+ * segment runs on a second stream (created on first use, kept until
+ * mp_destroy) while the current one is swept.  Results do not depend on
  * ``every`` (bitwise).  Synchronises ``stream``.  Errors: MP_E_STATE (batched
  * state), MP_E_PARAM (3D, obstacle, anisotropy, bad sizes or alignment). */
 int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,

@@ -315,19 +315,19 @@ def mp_adjoint(st, ckpt_buf: int, nsteps: int, every: int, n0: int, lam_final: i
 
 
 def mp_tune_candidates(st):
-    """The (bx, seg, vec) tile triples the library accepts for this state."""
+    """The (bx, seg, vec, steps per launch) candidates the library accepts for this state."""
     L = lib()
     n = L.mp_tune_candidates(st, None, 0)
     _check(min(n, 0))
-    buf = (C.c_int32 * (3 * n))()
+    buf = (C.c_int32 * (4 * n))()
     _check(min(L.mp_tune_candidates(st, buf, n), 0))
-    return [tuple(buf[3 * i:3 * i + 3]) for i in range(n)]
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(n)]
 
 
 def mp_tune(st, cand, reps: int, stream: int = 0):
-    """Time each (bx, seg, vec) triple; returns (ms per launch list, index of the fastest, now set)."""
+    """Time each candidate; returns (ms per step list, index of the fastest, now set)."""
     n = len(cand)
-    buf = (C.c_int32 * (3 * n))(*[int(v) for tri in cand for v in tri])
+    buf = (C.c_int32 * (4 * n))(*[int(v) for tri in cand for v in tri])
     ms = (C.c_double * n)()
     best = C.c_int(-1)
     _check(lib().mp_tune(st, buf, n, int(reps), ms, C.byref(best), stream))

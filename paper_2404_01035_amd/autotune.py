@@ -1,8 +1,8 @@
 """Tile-shape autotuner for the step kernels, with an on-disk cache.
 
-The library times each candidate (bx, seg, vec) tile on the bound state itself
-(``mp_tune``: one step from the current buffer into the other, repeated, with
-events on the stream) and keeps the fastest.  The choice is cached per
+The library times each candidate -- tile (bx, seg, vec) and steps per launch --
+on the bound state itself (``mp_tune``: launches from the current buffer into
+the other, repeated, with events on the stream) and keeps the fastest per step.  The choice is cached per
 workload signature -- grid, phases, components, precision, potential,
 anisotropy, batch composition and device name -- in a JSON file, so later runs
 of the same workload set the tile without timing.  Results never depend on the
@@ -70,13 +70,15 @@ def tune(st, plist, stream: int, device: str, reps: int = 10, cache: str | None 
          force: bool = False) -> dict:
     """Pick and set the tile of bound state ``st`` (built from ``plist``).
 
-    Returns {"bx", "seg", "vec", "source": "cache" | "timed", "ms": {"bx,seg,vec": ms}}.
+    Returns {"bx", "seg", "vec", "fuse", "source": "cache" | "timed",
+    "ms": {"bx,seg,vec,fuse": ms per step}}.
     """
     path = cache or default_cache_path()
     key = signature(plist, device)
     data = _load(path)
     hit = data.get(key)
     if hit and not force:
+        abi.mp_set_fusion(st, hit["fuse"])
         abi.mp_set_tile(st, hit["bx"], hit["seg"], hit["vec"])
         return dict(hit, source="cache")
     cand = abi.mp_tune_candidates(st)
@@ -85,7 +87,8 @@ def tune(st, plist, stream: int, device: str, reps: int = 10, cache: str | None 
         "bx": cand[best][0],
         "seg": cand[best][1],
         "vec": cand[best][2],
-        "ms": {f"{b},{s},{v}": t for (b, s, v), t in zip(cand, ms)},
+        "fuse": cand[best][3],
+        "ms": {",".join(map(str, c)): t for c, t in zip(cand, ms)},
     }
     data[key] = rec
     _store(path, data)

@@ -2,9 +2,10 @@
 // derivation, buffer bookkeeping, kernel dispatch, graph replay and batching.
 // mp_dt_limit, mp_create, mp_create_batch, mp_state_bytes,
 // mp_workspace_bytes, mp_get_tile, mp_set_graph, mp_current,
-// mp_instance_count/offset, mp_destroy and mp_last_error make no HIP call, so
-// they work on a machine without a GPU; mp_set_step and mp_set_tile touch the
-// device only once the state is bound.
+// mp_instance_count/offset and mp_last_error make no HIP call, so they work
+// on a machine without a GPU, and neither does mp_destroy unless mp_adjoint
+// created its second stream; mp_set_step and mp_set_tile touch the device only
+// once the state is bound.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -53,6 +54,10 @@ struct mp_state {
     std::vector<int> item_inst;  // batch work list (host copy) for the current seg
     int nitems;
     int batch_blocks;
+    // adjoint: a second stream (default priority) that recomputes the next
+    // segment while the current one is swept, and the events ordering them
+    hipStream_t aux;
+    hipEvent_t ev[5];  // start, recomputed[2], swept[2]
 };
 
 namespace {
@@ -485,6 +490,8 @@ void init_state(mp_state* st) {
     st->gend[1] = 1;
     st->nitems = 0;
     st->batch_blocks = 0;
+    st->aux = nullptr;
+    for (hipEvent_t& e : st->ev) e = nullptr;
     st->aniso = false;
     for (const Inst& I : st->inst) st->aniso = st->aniso || I.aniso;
     st->precision = st->inst[0].prm.precision;
@@ -601,7 +608,7 @@ mp::AdjCoef<R> make_adj_coef(const Inst& I) {
 }
 
 struct AdjLayout {
-    size_t X, lamA, lamB, seg, acc, ctr, grad, total;
+    size_t X0, X1, lam, seg[2], acc, ctr, grad, total;
     size_t state;
     int nrows;
 };
@@ -615,13 +622,15 @@ AdjLayout adj_layout(const mp_state* st, int64_t every) {
     g.ny = (int)I.grid.n[1];
     L.nrows = mp::adj_blocks(g);
     size_t o = 0;
-    L.X = o;
+    L.X0 = o;
     o += L.state;
-    L.lamA = o;
+    L.X1 = o;
     o += L.state;
-    L.lamB = o;
+    L.lam = o;
     o += L.state;
-    L.seg = o;
+    L.seg[0] = o;
+    o += L.state * (size_t)every;
+    L.seg[1] = o;
     o += L.state * (size_t)every;
     L.acc = o;
     o += align_up(sizeof(double) * mp::ADJ_NPAR * (size_t)L.nrows);
@@ -865,19 +874,22 @@ int mp_tune_candidates(const mp_state* st, int32_t* cand, int cap) {
     if (d3) {
         for (int bx : {256, 512})
             if (bx == 256 || d3_tall_ok(st))
-                for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {bx, seg, 1});
+                for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {bx, seg, 1, 1});
     } else if (st->batch) {
-        for (int vec = 1; vec <= 2; vec *= 2)
-            for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg, vec});
+        for (int fuse = 1; fuse <= 2; ++fuse)
+            for (int vec = 1; vec <= 2; vec *= 2)
+                for (int seg : {4, 8, 16, 32, 64})
+                    v.insert(v.end(), {64 * mp::BATCH_WPB_HOST, seg, vec, fuse});
     } else {
-        for (int vec = 1; vec <= vmax; vec *= 2)
-            for (int bx : {64, 128, 256})
-                for (int seg : {8, 16, 32, 64, 128}) v.insert(v.end(), {bx, seg, vec});
+        for (int fuse = 1; fuse <= 2; ++fuse)
+            for (int vec = 1; vec <= vmax; vec *= 2)
+                for (int bx : {64, 128, 256})
+                    for (int seg : {4, 8, 16, 32, 64}) v.insert(v.end(), {bx, seg, vec, fuse});
     }
-    const int n = (int)(v.size() / 3);
+    const int n = (int)(v.size() / 4);
     if (cand)
         for (int i = 0; i < n && i < cap; ++i)
-            for (int j = 0; j < 3; ++j) cand[3 * i + j] = v[3 * i + j];
+            for (int j = 0; j < 4; ++j) cand[4 * i + j] = v[4 * i + j];
     ok();
     return n;
 }
@@ -888,14 +900,16 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_tune before mp_bind");
     if (ncand < 1 || reps < 1) return fail(MP_E_PARAM, "ncand and reps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
-    const int bx0 = st->bx, seg0 = st->seg, vec0 = st->vec;
+    const int bx0 = st->bx, seg0 = st->seg, vec0 = st->vec, fuse0 = st->fuse;
     hipEvent_t e[2] = {nullptr, nullptr};
     int rc = hip_check(hipEventCreate(&e[0]), "hipEventCreate");
     if (rc == MP_OK) rc = hip_check(hipEventCreate(&e[1]), "hipEventCreate");
     int bi = -1;
     for (int i = 0; i < ncand && rc == MP_OK; ++i) {
         ms[i] = -1.0;
-        if (mp_set_tile(st, cand[3 * i], cand[3 * i + 1], cand[3 * i + 2]) != MP_OK) continue;
+        const int32_t* c = cand + 4 * i;
+        if (mp_set_fusion(st, c[3]) != MP_OK) continue;
+        if (mp_set_tile(st, c[0], c[1], c[2]) != MP_OK) continue;
         mp::KernelCall k;
         if (make_step_call(st, 0, st->cur, k, st->fuse) != MP_OK) continue;
         rc = launch(k, s);
@@ -906,17 +920,20 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
         float t = 0.0f;
         if (rc == MP_OK) rc = hip_check(hipEventElapsedTime(&t, e[0], e[1]), "hipEventElapsedTime");
         if (rc != MP_OK) break;
-        ms[i] = (double)t / reps;
+        ms[i] = (double)t / reps / st->fuse;
         if (bi < 0 || ms[i] < ms[bi]) bi = i;
     }
     for (hipEvent_t x : e)
         if (x) (void)hipEventDestroy(x);
     if (rc != MP_OK || bi < 0) {
         const std::string why = rc != MP_OK ? g_err : std::string("no valid tile candidate");
+        (void)mp_set_fusion(st, fuse0);
         (void)mp_set_tile(st, bx0, seg0, vec0);
         return fail(rc != MP_OK ? rc : MP_E_PARAM, "mp_tune: %s", why.c_str());
     }
-    rc = mp_set_tile(st, cand[3 * bi], cand[3 * bi + 1], cand[3 * bi + 2]);
+    const int32_t* c = cand + 4 * bi;
+    rc = mp_set_fusion(st, c[3]);
+    if (rc == MP_OK) rc = mp_set_tile(st, c[0], c[1], c[2]);
     if (rc) return rc;
     *best = bi;
     return ok();
@@ -1002,11 +1019,12 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
     const AdjLayout L = adj_layout(st, every);
     char* w = (char*)work;
     const size_t sb = I.bytes;
-    void* lam[2] = {w + L.lamA, w + L.lamB};
+    void* X[2] = {w + L.X0, w + L.X1};
+    void* lam = w + L.lam;  // lambda, updated in place
     double* acc = (double*)(w + L.acc);
     int64_t* zctr = (int64_t*)(w + L.ctr);
     double* gdev = (double*)(w + L.grad);
-    rc = hip_check(hipMemcpyAsync(lam[0], lam_final, sb, hipMemcpyDeviceToDevice, s), "lambda copy");
+    rc = hip_check(hipMemcpyAsync(lam, lam_final, sb, hipMemcpyDeviceToDevice, s), "lambda copy");
     if (rc) return rc;
     mp::adj_fill(acc, (int64_t)L.nrows * mp::ADJ_NPAR, 0.0, s);
     mp::adj_fill((double*)zctr, 1, 0.0, s);  // all-zero bits: the int64 time-level base 0
@@ -1018,44 +1036,85 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
     A.g.fs = ncells_of(I.grid);
     A.nphases = I.N;
     A.nmu = I.K - 1;
-    A.X = w + L.X;
+    A.lam = lam;
     A.acc = acc;
     double tb0, tdn, tslope;
     temperature_law(I, tb0, tdn, tslope);
+    A.tt_slope = tslope;
     const mp::AdjCoef<double> cd = make_adj_coef<double>(I);
     const mp::AdjCoef<float> cf = make_adj_coef<float>(I);
-    int cur = 0;
+    auto run = [&](int which, const char* sB, const void* XB, const char* sA, void* XA, int64_t nA) {
+        A.which = which;
+        A.sB = sB;
+        A.XB = XB;
+        A.sA = sA;
+        A.XA = XA;
+        A.tt_row0 = tb0 + tdn * (double)nA;
+        int r = st->precision == MP_FP64 ? mp::adj_launch<double>(A, cd, s) : mp::adj_launch<float>(A, cf, s);
+        if (r) return fail(r, "no adjoint instance for this configuration");
+        return hip_check(hipGetLastError(), "adjoint launch");
+    };
     const int64_t nseg = (nsteps + every - 1) / every;
-    for (int64_t k = nseg - 1; k >= 0; --k) {
-        const int64_t base = n0 + k * every;
-        const int64_t len = (nsteps - k * every) < every ? (nsteps - k * every) : every;
-        char* seg = w + L.seg;
-        rc = hip_check(hipMemcpyAsync(seg, (const char*)ckpt_buf + (size_t)k * L.state, sb,
-                                      hipMemcpyDeviceToDevice, s),
-                       "checkpoint restore");
-        if (rc) return rc;
-        for (int64_t i = 0; i + 1 < len; ++i) {  // recompute the segment's states
+    auto len_of = [&](int64_t k) { return (nsteps - k * every) < every ? (nsteps - k * every) : every; };
+    // Segment k's states, restored from checkpoint k and recomputed into
+    // buffer k mod 2, on stream q.
+    auto recompute = [&](int64_t k, hipStream_t q) {
+        char* seg = w + L.seg[k & 1];
+        int r = hip_check(hipMemcpyAsync(seg, (const char*)ckpt_buf + (size_t)k * L.state, sb,
+                                         hipMemcpyDeviceToDevice, q),
+                          "checkpoint restore");
+        for (int64_t i = 0; r == MP_OK && i + 1 < len_of(k); ++i) {
             mp::KernelCall kc;
-            rc = make_single_call(st, seg + (size_t)i * L.state, seg + (size_t)(i + 1) * L.state, zctr,
-                                  (int)(base + i), kc);
-            if (rc) return fail(rc, "no kernel instance for this configuration");
-            rc = launch(kc, s);
-            if (rc) return rc;
+            r = make_single_call(st, seg + (size_t)i * L.state, seg + (size_t)(i + 1) * L.state, zctr,
+                                 (int)(n0 + k * every + i), kc);
+            if (r) return fail(r, "no kernel instance for this configuration");
+            r = launch(kc, q);
         }
-        for (int64_t i = len - 1; i >= 0; --i) {  // reverse sweep
-            A.s = seg + (size_t)i * L.state;
-            A.lam1 = lam[cur];
-            A.out = lam[1 - cur];
-            A.tt_row0 = tb0 + tdn * (double)(base + i);
-            A.tt_slope = tslope;
-            rc = st->precision == MP_FP64 ? mp::adj_launch<double>(A, cd, s) : mp::adj_launch<float>(A, cf, s);
-            if (rc) return fail(rc, "no adjoint instance for this configuration");
-            rc = hip_check(hipGetLastError(), "adjoint launch");
-            if (rc) return rc;
-            cur = 1 - cur;
+        return r;
+    };
+    // Reverse sweep of segment k on the caller's stream: pass A of its last
+    // step, then pass B of each step fused with pass A of the step before it,
+    // then pass B of its first step.
+    auto sweep = [&](int64_t k) {
+        char* seg = w + L.seg[k & 1];
+        const int64_t base = n0 + k * every, len = len_of(k);
+        auto at = [&](int64_t i) { return seg + (size_t)i * L.state; };
+        int p = 0;
+        int r = run(0, nullptr, nullptr, at(len - 1), X[p], base + len - 1);
+        for (int64_t i = len - 1; i >= 1 && r == MP_OK; --i) {
+            r = run(2, at(i), X[p], at(i - 1), X[1 - p], base + i - 1);
+            p = 1 - p;
         }
+        if (r == MP_OK) r = run(1, at(0), X[p], nullptr, nullptr, base);
+        return r;
+    };
+    // Segment k-1 is recomputed on the second stream while segment k is swept
+    // (it waits for the sweep of k+1, the last reader of its buffer).
+    if (!st->aux) {
+        rc = hip_check(hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking), "adjoint stream");
+        for (hipEvent_t& e : st->ev)
+            if (rc == MP_OK) rc = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "adjoint event");
+        if (rc) return rc;
     }
-    rc = hip_check(hipMemcpyAsync(lam_initial, lam[cur], sb, hipMemcpyDeviceToDevice, s), "lambda copy");
+    hipEvent_t* evrec = st->ev + 1;
+    hipEvent_t* evsw = st->ev + 3;
+    rc = hip_check(hipEventRecord(st->ev[0], s), "hipEventRecord");
+    if (rc == MP_OK) rc = hip_check(hipStreamWaitEvent(st->aux, st->ev[0], 0), "hipStreamWaitEvent");
+    if (rc == MP_OK && nseg > 0) rc = recompute(nseg - 1, st->aux);
+    if (rc == MP_OK && nseg > 0) rc = hip_check(hipEventRecord(evrec[(nseg - 1) & 1], st->aux), "hipEventRecord");
+    for (int64_t k = nseg - 1; k >= 0 && rc == MP_OK; --k) {
+        if (k >= 1) {
+            if (k + 1 <= nseg - 1)
+                rc = hip_check(hipStreamWaitEvent(st->aux, evsw[(k + 1) & 1], 0), "hipStreamWaitEvent");
+            if (rc == MP_OK) rc = recompute(k - 1, st->aux);
+            if (rc == MP_OK) rc = hip_check(hipEventRecord(evrec[(k - 1) & 1], st->aux), "hipEventRecord");
+        }
+        if (rc == MP_OK) rc = hip_check(hipStreamWaitEvent(s, evrec[k & 1], 0), "hipStreamWaitEvent");
+        if (rc == MP_OK) rc = sweep(k);
+        if (rc == MP_OK) rc = hip_check(hipEventRecord(evsw[k & 1], s), "hipEventRecord");
+    }
+    if (rc) return rc;
+    rc = hip_check(hipMemcpyAsync(lam_initial, lam, sb, hipMemcpyDeviceToDevice, s), "lambda copy");
     if (rc) return rc;
     mp::adj_reduce(acc, L.nrows, gdev, s);
     rc = hip_check(hipMemcpyAsync(grad_theta, gdev, sizeof(double) * mp::ADJ_NPAR, hipMemcpyDeviceToHost, s),
@@ -1067,6 +1126,9 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
 void mp_destroy(mp_state* st) {
     if (!st) return;
     drop_graphs(st);
+    for (hipEvent_t e : st->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st->aux) (void)hipStreamDestroy(st->aux);
     delete st;
 }
 

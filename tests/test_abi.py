@@ -229,12 +229,13 @@ def test_tune_candidates_and_errors_without_gpu():
     st = abi.mp_create(p)
     try:
         cand = abi.mp_tune_candidates(st)
-        assert len(cand) >= 4 and all(b in (64, 128, 256) and s >= 1 and v in (1, 2)
-                                      for b, s, v in cand)
-        for b, s, v in cand:  # every candidate is a tile the state accepts
+        assert len(cand) >= 4 and all(b in (64, 128, 256) and s >= 1 and v in (1, 2) and f in (1, 2)
+                                      for b, s, v, f in cand)
+        for b, s, v, f in cand:  # every candidate is one the state accepts
+            abi.mp_set_fusion(st, f)
             abi.mp_set_tile(st, b, s, v)
         L = abi.lib()
-        buf = (C.c_int32 * 3)(64, 16, 1)
+        buf = (C.c_int32 * 4)(64, 16, 1, 1)
         ms = (C.c_double * 1)()
         best = C.c_int()
         assert L.mp_tune(st, buf, 1, 3, ms, C.byref(best), None) == abi.MP_E_UNBOUND
@@ -243,7 +244,7 @@ def test_tune_candidates_and_errors_without_gpu():
         abi.mp_destroy(st)
     st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
     try:
-        assert {(b, v) for b, _, v in abi.mp_tune_candidates(st)} == {(256, 1), (512, 1)}
+        assert {(b, v, f) for b, _, v, f in abi.mp_tune_candidates(st)} == {(256, 1, 1), (512, 1, 1)}
         assert abi.lib().mp_set_tile(st, 0, 0, 2) == abi.MP_E_PARAM
     finally:
         abi.mp_destroy(st)

@@ -137,6 +137,7 @@ def test_autotuner_keeps_results_and_caches(tmp_path):
         r = s.autotune(reps=2, cache=cache)
         assert r["source"] == "timed" and all(t > 0 for t in r["ms"].values())
         assert abi_tile(s) == (r["bx"], r["seg"], r["vec"])
+        assert fusion(s) == r["fuse"]
         assert s.time_level == 0
         s.step(9)
         got = s.fields()
@@ -168,3 +169,9 @@ def abi_tile(s):
     from paper_2404_01035_amd import abi
 
     return abi.mp_get_tile(s.st)
+
+
+def fusion(s):
+    from paper_2404_01035_amd import abi
+
+    return abi.mp_get_fusion(s.st)
