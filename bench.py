@@ -41,19 +41,18 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
 # counters read for a plain device copy of known size.  A figure holds only
 # for the tile and steps per launch it was taken at and for the device sources
-# it was taken on (sha256 over csrc/*.hpp, *.hip); otherwise the leg reports
-# traffic null.
+# it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "4e0b7195ae65200a",
+    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "cf0dd6c69f18d09d",
                "bytes": (2.0 * 374164.0 + 661948.5) * 1024},
-    "c2_f32": {"tile": [64, 16, 2], "fuse": 2, "src": "4e0b7195ae65200a",
+    "c2_f32": {"tile": [64, 16, 2], "fuse": 2, "src": "780e054685d4f4d8",
                "bytes": (2.0 * 207392.4 + 329343.6) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "4e0b7195ae65200a",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "e68109c0892504ae",
            "bytes": (2.0 * 1075660.0 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "4e0b7195ae65200a",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "a96fa80e9e1a573c",
            "bytes": (2.0 * 699494.1 + 1207230.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
@@ -88,12 +87,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_hash():
-    """sha256 (16 hex digits) over the device sources in csrc/ (*.hpp, *.hip)."""
+# The device sources each leg's step kernel is built from.
+_COMMON = ["mp_internal.hpp", "gp_device.hpp"]
+LEG_SOURCES = {
+    "c2_f64": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
+    "c2_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
+    "c3": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
+    "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
+}
+
+
+def source_hash(leg):
+    """sha256 (16 hex digits) over the device sources of one leg's kernel."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if not name.endswith((".hpp", ".hip")):
-            continue
+    for name in LEG_SOURCES[leg]:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -101,7 +108,7 @@ def source_hash():
 
 def traffic_of(leg, tile, fuse):
     t = TRAFFIC.get(leg)
-    if not t or list(t["tile"]) != list(tile) or t["fuse"] != fuse or t["src"] != source_hash():
+    if not t or list(t["tile"]) != list(tile) or t["fuse"] != fuse or t["src"] != source_hash(leg):
         return None
     return t["bytes"]
 
