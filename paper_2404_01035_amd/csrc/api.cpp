@@ -196,19 +196,18 @@ mp::Coef<R> make_coef(const Inst& I) {
     mp::Coef<R> c;
     std::memset(&c, 0, sizeof c);
     c.cE = (R)(p.eps / (2.0 * dx));
-    c.inv_eps = (R)(1.0 / p.eps);
     c.kphi = (R)(p.dt / (p.tau * p.eps));
     c.qguard = (R)(4.0 * dx * dx * 1e-30);
     const double wfac = p.potential == MP_OBSTACLE ? 16.0 / (M_PI * M_PI) : 18.0;
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
     for (int q = 0; q < 3; ++q) {
         const double g = p.gamma[pa[q]][pb[q]];
-        c.g2d[q] = (R)(2.0 * g / dx);
+        c.g4d[q] = (R)(4.0 * g / dx);
         c.gd[q] = (R)(g / dx);
         c.del[q] = (R)p.delta[pa[q]][pb[q]];
-        c.wc[q] = (R)(wfac * g);
+        c.wce[q] = (R)(wfac * g / p.eps);
     }
-    c.gamma3 = (R)p.gamma3;
+    c.g3e = (R)(p.gamma3 / p.eps);
     const double dtf = p.dt / (2.0 * dx * dx);
     for (int a = 0; a < I.N; ++a) {
         c.C[a] = (R)p.C[a];
@@ -216,7 +215,6 @@ mp::Coef<R> make_coef(const Inst& I) {
         for (int k = 0; k < I.K - 1; ++k) {
             const double chi = 1.0 / (2.0 * p.A[a][k]);
             c.chi[a][k] = (R)chi;
-            c.halfchi[a][k] = (R)(0.5 * chi);
             c.B[a][k] = (R)p.B[a][k];
             c.Dt[a][k] = (R)(p.D[a][k] * chi * dtf);
         }

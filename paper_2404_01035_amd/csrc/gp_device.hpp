@@ -84,11 +84,10 @@ __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
                                           const R (&mL)[NM], const R (&mR)[NM],
                                           const R (&uL)[NM], const R (&uR)[NM], const Coef<R>& c,
                                           R (&U)[NP], R (&W)[NP], R (&J)[NM]) {
-    R sg[NP], dl[NP];
+    R sg[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        sg[a] = pL[a] + pR[a];
-        dl[a] = pR[a] - pL[a];
+        if constexpr (ANISO) sg[a] = pL[a] + pR[a];
         U[a] = R(0);
         W[a] = R(0);
     }
@@ -97,7 +96,8 @@ __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
 #pragma unroll
         for (int j = i + 1; j < NP; ++j) {
             const int pi = pair_index(i, j);
-            R q = sg[i] * dl[j] - sg[j] * dl[i];
+            // sigma_i delta_j - sigma_j delta_i = 2 (phi_L,i phi_R,j - phi_L,j phi_R,i)
+            const R qh = pL[i] * pR[j] - pL[j] * pR[i];
             R gh;
             if constexpr (ANISO) {
                 R d = c.del[pi];
@@ -106,12 +106,12 @@ __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
 #pragma unroll
                     for (int t = 0; t < NTG; ++t)
                         qt[t] = R(0.25) * (sg[i] * tau[t][j] - sg[j] * tau[t][i]);
-                    gh = c.gd[pi] * g_aniso<R, NTG>(q, qt, d, c.qguard);
+                    gh = c.gd[pi] * g_aniso<R, NTG>(R(2) * qh, qt, d, c.qguard);
                 } else {
-                    gh = c.g2d[pi] * q;
+                    gh = c.g4d[pi] * qh;
                 }
             } else {
-                gh = c.g2d[pi] * q;
+                gh = c.g4d[pi] * qh;
             }
             U[i] = U[i] - gh * pR[j];
             U[j] = U[j] + gh * pR[i];
@@ -123,17 +123,19 @@ __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
     for (int k = 0; k < NM; ++k) J[k] = (mL[k] + mR[k]) * (uR[k] - uL[k]);
 }
 
-// Interpolation functions h_a of Eq. hphi.
+// Interpolation functions h_a of Eq. hphi.  For N = 3 the coupling term
+// 2 phi_a phi_b phi_c is the same triple product for every phase.
 template <typename R, int NP>
 __device__ __forceinline__ void interp_h(const R (&phi)[NP], R (&h)[NP]) {
+    R e3x2 = R(0);
+    if constexpr (NP == 3) e3x2 = R(2) * (phi[0] * phi[1] * phi[2]);
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        R sq = phi[a] * phi[a];
-        h[a] = sq * (R(3) - R(2) * phi[a]);
-        if constexpr (NP == 3) {
-            const int b = a == 0 ? 1 : 0, g = a == 2 ? 1 : 2;
-            h[a] = h[a] + R(2) * phi[a] * (phi[b] * phi[g]);
-        }
+        const R sq = phi[a] * phi[a];
+        if constexpr (NP == 3)
+            h[a] = sq * (R(3) - R(2) * phi[a]) + e3x2;
+        else
+            h[a] = sq * (R(3) - R(2) * phi[a]);
     }
 }
 
@@ -163,31 +165,35 @@ __device__ __forceinline__ float fast_rcp(float x) {
     return fmaf(r, e, r);
 }
 
-// C^b + s^b (T - Te) for every phase: constant along a row of fixed y.
+// 2 (C^b + s^b (T - Te)) for every phase: constant along a row of fixed y.
 template <typename R, int NP>
 __device__ __forceinline__ void psi_const(R tt, const Coef<R>& c, R (&Cs)[NP]) {
 #pragma unroll
-    for (int b = 0; b < NP; ++b) Cs[b] = c.C[b] + c.s[b] * tt;
+    for (int b = 0; b < NP; ++b) Cs[b] = R(2) * (c.C[b] + c.s[b] * tt);
 }
 
 // Cell update from the face sums Gs_a = sum_axes (U_hi - W_lo) and
 // Js_k = sum_axes (J_hi - J_lo); h0 = h(phi^n) of the cell; Cs from psi_const.
+// The cell's psi is carried doubled, psi2 = 2 psi = Cs - sum_k chi (mu - B)^2,
+// so that chi (mu_k - B^b_k) serves psi and the mu source term alike.  h1
+// receives h(phi^{n+1}).
 template <typename R, int NP, int NM, bool OBST>
 __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM],
                                             const R (&h0)[NP], const R (&Gs)[NP],
                                             const R (&Js)[NM], const R (&Cs)[NP], const Coef<R>& c,
-                                            R (&phin)[NP], R (&mun)[NM]) {
-    R dmu[NP][NM];
-    R psi[NP];
+                                            R (&phin)[NP], R (&mun)[NM], R (&h1)[NP]) {
+    R dmu[NP][NM], cdm[NP][NM];
+    R psi2[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
         R v = Cs[b];
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
             dmu[b][k] = mu[k] - c.B[b][k];
-            v = v - c.halfchi[b][k] * dmu[b][k] * dmu[b][k];
+            cdm[b][k] = c.chi[b][k] * dmu[b][k];
+            v = v - cdm[b][k] * dmu[b][k];
         }
-        psi[b] = v;
+        psi2[b] = v;
     }
     R sq[NP];
 #pragma unroll
@@ -198,9 +204,12 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
         P[1] = phi[0] * phi[2];
         P[2] = phi[0] * phi[1];
     }
-    R psum = R(0);
-    if constexpr (NP == 3) psum = psi[0] + psi[1] + psi[2];
+    // the triple-junction well term and the psi sum share the factor P_a
+    R Z = R(0);
+    if constexpr (NP == 3) Z = c.g3e + ((psi2[0] + psi2[1]) + psi2[2]);
 
+    // Rr_a = cE Gs_a - (dw_a / eps + 3 psi2_a phi_a (1 - phi_a) + P_a Z); the
+    // well coefficients carry the 1/eps
     R Rr[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -208,19 +217,20 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
             if (b == a) continue;
-            const R wc = c.wc[pair_index(a < b ? a : b, a < b ? b : a)];
+            const R wc = c.wce[pair_index(a < b ? a : b, a < b ? b : a)];
             if constexpr (OBST)
                 dw = dw + wc * phi[b];
             else
                 dw = dw + wc * sq[b];
         }
-        if constexpr (!OBST) dw = dw * phi[a];
-        R dps = R(6) * psi[a] * (phi[a] * (R(1) - phi[a]));
-        if constexpr (NP == 3) {
-            dw = dw + c.gamma3 * P[a];
-            dps = dps + R(2) * P[a] * psum;
-        }
-        Rr[a] = c.cE * Gs[a] - (c.inv_eps * dw + dps);
+        const R t3 = R(3) - R(3) * phi[a];
+        R Y;
+        if constexpr (OBST)
+            Y = dw + phi[a] * (psi2[a] * t3);
+        else
+            Y = phi[a] * (dw + psi2[a] * t3);
+        if constexpr (NP == 3) Y = Y + P[a] * Z;
+        Rr[a] = c.cE * Gs[a] - Y;
     }
 
     double lam = 0.0;
@@ -241,7 +251,7 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
         for (int a = 0; a < NP; ++a) phin[a] = phin[a] * inv;
     }
 
-    R h1[NP], dh[NP];
+    R dh[NP];
     interp_h<R, NP>(phin, h1);
 #pragma unroll
     for (int a = 0; a < NP; ++a) dh[a] = h1[a] - h0[a];
@@ -250,7 +260,7 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
         R src = R(0), chik = R(0);
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
-            src = src + (dmu[a][k] * c.chi[a][k]) * dh[a];
+            src = src + cdm[a][k] * dh[a];
             chik = chik + h1[a] * c.chi[a][k];
         }
         mun[k] = mu[k] + (Js[k] - src) * fast_rcp(chik);
@@ -261,15 +271,18 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
 // lane 0's previous is lane 63).  FP32 goes through the LDS crossbar
 // (ds_bpermute), which leaves the vector ALU -- the FP32 step's limit -- to the
 // arithmetic; FP64 uses DPP wave rotates, two per value, which avoid the LDS
-// round trip.
+// round trip (for FP32 the rotates measured slower: each needs wait states
+// after the instruction that wrote its source).
 __device__ __forceinline__ float lane_next(float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)threadIdx.x + 1) & 63) << 2, __float_as_int(v)));
 }
 __device__ __forceinline__ float lane_prev(float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute((((int)threadIdx.x + 63) & 63) << 2, __float_as_int(v)));
 }
-__device__ __forceinline__ int rot_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false); }
-__device__ __forceinline__ int rot_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false); }
+// wave_rol:1 / wave_ror:1 have a source lane for every lane, so the DPP move
+// needs no "old" value (bound_ctrl set, no zeroing move before it)
+__device__ __forceinline__ int rot_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xF, 0xF, true); }
+__device__ __forceinline__ int rot_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, true); }
 __device__ __forceinline__ double lane_next(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = rot_next((int)(b & 0xffffffffLL));

@@ -23,16 +23,14 @@ struct Geom {
 template <typename R>
 struct Coef {
     R cE;          // eps / (2 dx)
-    R inv_eps;     // 1 / eps
     R kphi;        // dt / (tau eps)
     R qguard;      // (2 dx)^2 * 1e-30, the |q|^2 guard on the rescaled q
-    R g2d[3];      // 2 gamma_ab / dx (isotropic pair factor)
+    R g4d[3];      // 4 gamma_ab / dx (isotropic pair factor on phi_L,i phi_R,j - phi_L,j phi_R,i)
     R gd[3];       // gamma_ab / dx (anisotropic pair factor)
     R del[3];      // delta_ab
-    R wc[3];       // 18 gamma_ab (multi-well) or 16/pi^2 gamma_ab (obstacle)
-    R gamma3;      // gamma_abd
+    R wce[3];      // 18 gamma_ab / eps (multi-well) or 16/pi^2 gamma_ab / eps (obstacle)
+    R g3e;         // gamma_abd / eps
     R chi[3][2];   // 1 / (2 A)
-    R halfchi[3][2];  // 1 / (4 A)
     R B[3][2];
     R C[3];
     R s[3];

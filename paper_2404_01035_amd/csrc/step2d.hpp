@@ -98,9 +98,10 @@ struct Carry2d {
 };
 
 // Cell record from the V values of every field (field-major, as loaded).
-template <typename R, int NP, int NM, bool ANISO, int V>
+// HAVE_H: hv holds h(phi) of the cells already.
+template <typename R, int NP, int NM, bool ANISO, int V, bool HAVE_H = false>
 __device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, NM, V, ANISO>& P,
-                                         const Coef<R>& c) {
+                                         const Coef<R>& c, const R (*hv)[V] = nullptr) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
 #pragma unroll
@@ -108,7 +109,12 @@ __device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, 
 #pragma unroll
         for (int k = 0; k < NM; ++k) P.mu[i][k] = v[NP + k][i];
         R hh[NP];
-        interp_h<R, NP>(P.phi[i], hh);
+        if constexpr (HAVE_H) {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) hh[a] = hv[a][i];
+        } else {
+            interp_h<R, NP>(P.phi[i], hh);
+        }
         mobility<R, NP, NM>(hh, c, P.Mt[i]);
     }
     if constexpr (ANISO) {
@@ -155,12 +161,13 @@ __device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO>& prv
 }
 
 // New values of the row `cur` (nxt is the row above) and the carry moved up
-// one row.  Cs = psi_const of the row.
+// one row.  Cs = psi_const of the row; hn receives h of the new phi.
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
 __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur,
                                            const Row2d<R, NP, NM, V, ANISO>& nxt,
                                            Carry2d<R, NP, NM, V, ANISO>& k, const R (&Cs)[NP],
-                                           const Coef<R>& c, R (&phin)[NP][V], R (&mun)[NM][V]) {
+                                           const Coef<R>& c, R (&phin)[NP][V], R (&mun)[NM][V],
+                                           R (&hn)[NP][V]) {
     R cdy[ANISO ? V : 1][NP];
     if constexpr (ANISO) {
 #pragma unroll
@@ -222,12 +229,13 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur
         for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - k.Wlo[i][a]);
 #pragma unroll
         for (int kk = 0; kk < NM; ++kk) Js[kk] = (Jx[kk] - Jxl[kk]) + (Jy[kk] - k.Jlo[i][kk]);
-        R pn[NP], un[NM], h0[NP];
+        R pn[NP], un[NM], h0[NP], h1[NP];
         interp_h<R, NP>(cur.phi[i], h0);
-        cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un);
+        cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un, h1);
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
             phin[a][i] = pn[a];
+            hn[a][i] = h1[a];
             k.Wlo[i][a] = Wy[a];
             Wxl[a] = Wx[a];
         }
@@ -308,8 +316,8 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     auto row = [&](int m, const RowT& cur, const RowT& nxt) {
         R Cs[NP];
         psi_const<R, NP>((R)(tbase + tslope * (double)m), c, Cs);
-        R phin[NP][V], mun[NM][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(cur, nxt, k, Cs, c, phin, mun);
+        R phin[NP][V], mun[NM][V], hn[NP][V];
+        row_update<R, NP, NM, ANISO, OBST, V>(cur, nxt, k, Cs, c, phin, mun, hn);
         if (writes) {
             const int64_t o = (int64_t)m * nx + cs;
 #pragma unroll
@@ -399,7 +407,35 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // reusing the row record in y), so a boundary face sees two identical cells
 // and carries nothing, as in the one-step kernel.  The output rows [m0, m1)
 // need step-1 rows m0-1 .. m1 and state rows m0-2 .. m1+1.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+// Column loaded by a lane of a two-step strip wave whose first column is cs,
+// and whether the lane holds a mirror ghost column (fixL: ghost -1 in its
+// last slot, fixR: ghost nx in its first slot).
+template <int V>
+__device__ __forceinline__ int x2_column(const Geom& g, int cs, bool& fixL, bool& fixR) {
+    const int nx = g.nx;
+    fixL = fixR = false;
+    if (g.bcx == MP_BC_PERIODIC) return wrap(cs, nx);
+    if (cs >= 0 && cs < nx) return cs;
+    if (cs == -V) {
+        fixL = true;  // holds ghost column -1 = column 0 in its last slot
+        return 0;
+    }
+    if (cs == nx) {
+        fixR = true;  // holds ghost column nx = column nx-1 in its first slot
+        return nx - V;
+    }
+    return cs < 0 ? 0 : nx - V;  // farther out: never read by a written lane
+}
+
+// First column of a lane of two-step strip wave tx.
+template <int V>
+__device__ __forceinline__ int x2_first_col(int tx, int lane) {
+    return (tx * W2X_LANES_OUT - 2 + lane) * V;
+}
+
+// XEDGE: the wave holds a mirror ghost column (wave-uniform; only then are
+// the mirror copies of step 1 made).
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE>
 __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                            const Coef<R>& c, double tbase0, double tbase1, double tslope,
                                            int tx, int m0, int m1) {
@@ -407,26 +443,12 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     typedef Raw2d<R, NF, V> RawT;
     typedef Row2d<R, NP, NM, V, ANISO> RowT;
     const int lane = threadIdx.x & 63;
-    const bool perx = g.bcx == MP_BC_PERIODIC;
     const bool pery = g.bcy == MP_BC_PERIODIC;
     const int nx = g.nx, ny = g.ny;
     const int64_t fs = g.fstride;
-    const int cs = (tx * W2X_LANES_OUT - 2 + lane) * V;  // first column of the lane
-    int col;
-    bool fixL = false, fixR = false;
-    if (perx) {
-        col = wrap(cs, nx);
-    } else if (cs >= 0 && cs < nx) {
-        col = cs;
-    } else if (cs == -V) {
-        col = 0;  // holds ghost column -1 = column 0 in its last slot
-        fixL = true;
-    } else if (cs == nx) {
-        col = nx - V;  // holds ghost column nx = column nx-1 in its first slot
-        fixR = true;
-    } else {
-        col = cs < 0 ? 0 : nx - V;  // farther out: never read by a written lane
-    }
+    const int cs = x2_first_col<V>(tx, lane);
+    bool fixL, fixR;
+    const int col = x2_column<V>(g, cs, fixL, fixR);
     const bool writes = lane >= 2 && lane <= W2X_LANES_OUT + 1 && cs < nx;
     const bool top = !pery && m0 == 0;   // step-1 row -1 is a copy of row 0
     const bool bot = !pery && m1 == ny;  // step-1 row ny is a copy of row ny-1
@@ -440,7 +462,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         for (int f = 0; f < NF; ++f) vload<R, V>(in + f * fs + o, r.v[f]);
     };
     auto process = [&](RawT& r, RowT& P) {
-        mirror_fix<R, NF, V>(r.v, fixL, fixR);
+        if constexpr (XEDGE) mirror_fix<R, NF, V>(r.v, fixL, fixR);
         make_row<R, NP, NM, ANISO, V>(r.v, P, c);
     };
 
@@ -459,14 +481,17 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         carry_init<R, NP, NM, ANISO, V>(prv, c0, k0, c);
         process(d, n0);
     }
-    if (r_first + 2 <= r_last + 1) load(r_first + 2, ld);
+    load(r_first + 2, ld);
 
-    // Step-1 row r into P, then the state window moves up one row.
+    // Step-1 row r into P, then the state window moves up one row.  The
+    // window always moves (past the last row needed it reads clamped rows that
+    // go unused), so that the row loop below has a single path and the rows in
+    // flight stay in the registers they are loaded into.
     auto step1 = [&](int r, RowT& P) {
         R Cs[NP];
         psi_const<R, NP>((R)(tbase0 + tslope * (double)rowmap(r)), c, Cs);
-        R phin[NP][V], mun[NM][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(c0, n0, k0, Cs, c, phin, mun);
+        R phin[NP][V], mun[NM][V], hn[NP][V];
+        row_update<R, NP, NM, ANISO, OBST, V>(c0, n0, k0, Cs, c, phin, mun, hn);
         R v[NF][V];
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -476,20 +501,27 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
             for (int kk = 0; kk < NM; ++kk) v[NP + kk][i] = mun[kk][i];
         }
         // mirror ghost columns of step 1: copies of the cells they mirror
+        // (only the waves at a no-flux x edge hold such a column; elsewhere
+        // the record takes h of the new phi from the update)
+        if constexpr (XEDGE) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const R nextFirst = lane_next(v[f][0]);
-            const R prevLast = lane_prev(v[f][V - 1]);
-            v[f][V - 1] = fixL ? nextFirst : v[f][V - 1];
-            v[f][0] = fixR ? prevLast : v[f][0];
+            for (int f = 0; f < NF; ++f) {
+                const R nextFirst = lane_next(v[f][0]);
+                const R prevLast = lane_prev(v[f][V - 1]);
+                v[f][V - 1] = fixL ? nextFirst : v[f][V - 1];
+                v[f][0] = fixR ? prevLast : v[f][0];
+            }
+            make_row<R, NP, NM, ANISO, V>(v, P, c);
+        } else {
+            make_row<R, NP, NM, ANISO, V, true>(v, P, c, hn);
         }
-        make_row<R, NP, NM, ANISO, V>(v, P, c);
-        if (r + 1 <= r_last) {
-            c0 = n0;
-            __builtin_amdgcn_s_waitcnt(kWaitVm0);
-            process(ld, n0);
-            if (r + 3 <= r_last + 1) load(r + 3, ld);
-        }
+        c0 = n0;
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        process(ld, n0);
+#ifdef MP_X2_SCHEDB
+        __builtin_amdgcn_sched_barrier(0);
+#endif
+        load(r + 3, ld);
     };
 
     // step 1 -> 2: step-1 rows in c1 (row q) and n1 (row q+1)
@@ -504,15 +536,11 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         }
         carry_init<R, NP, NM, ANISO, V>(lower, c1, k1, c);
     }
-    for (int q = m0; q < m1; ++q) {
-        if (bot && q + 1 == ny)
-            n1 = c1;
-        else
-            step1(q + 1, n1);
+    auto step2 = [&](int q) {
         R Cs[NP];
         psi_const<R, NP>((R)(tbase1 + tslope * (double)q), c, Cs);
-        R phin[NP][V], mun[NM][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(c1, n1, k1, Cs, c, phin, mun);
+        R phin[NP][V], mun[NM][V], hn[NP][V];
+        row_update<R, NP, NM, ANISO, OBST, V>(c1, n1, k1, Cs, c, phin, mun, hn);
         if (writes) {
             const int64_t o = (int64_t)q * nx + cs;
 #pragma unroll
@@ -521,7 +549,17 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
             for (int kk = 0; kk < NM; ++kk) vstore<R, V>(out + (NP + kk) * fs + o, mun[kk]);
         }
         c1 = n1;
+    };
+    for (int q = m0; q < m1 - 1; ++q) {
+        step1(q + 1, n1);
+        step2(q);
     }
+    // last row: below a no-flux top edge step-1 row ny is a copy of row ny-1
+    if (bot)
+        n1 = c1;
+    else
+        step1(m1, n1);
+    step2(m1 - 1);
 }
 
 #ifndef MP_WAVES_PER_EU
@@ -567,8 +605,14 @@ k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     const int sg = wid / ntx;
     const int m0 = sg * seg;
     const double n = (double)(*stepctr + kstep);
-    strip2d_x2<R, NP, NM, ANISO, OBST, V>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0), tslope,
-                                          tx, m0, min(m0 + seg, g.ny));
+    bool fixL, fixR;
+    x2_column<V>(g, x2_first_col<V>(tx, threadIdx.x & 63), fixL, fixR);
+    if (__ballot(fixL || fixR) != 0)
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, true>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0),
+                                                    tslope, tx, m0, min(m0 + seg, g.ny));
+    else
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, false>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0),
+                                                     tslope, tx, m0, min(m0 + seg, g.ny));
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>

@@ -199,7 +199,8 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         for (int k = 0; k < NM; ++k) mu[k] = sv[s0][NP + k][pc];
         interp_h<R, NP>(phi, h0);
         R phin[NP], mun[NM];
-        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, c, phin, mun);
+        R h1[NP];
+        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, c, phin, mun, h1);
 
         if (valid) {
             const int64_t o = (int64_t)gx + (int64_t)gy * sy + (int64_t)m * sz;
