@@ -508,13 +508,12 @@ void init_state(mp_state* st) {
         st->vec = 1;
     } else {
         // two steps per launch (the state crosses HBM once per two steps);
-        // tiles measured best for it on 4096^2: one FP64 cell per lane keeps
-        // the kernel at 3 waves per SIMD without spills, two FP32 cells per
-        // lane give 8-byte accesses
+        // tiles measured best for it on 4096^2: one cell per lane (FP64 at 3
+        // waves per SIMD without spills, FP32 at 5), 32- / 16-row segments
         st->fuse = 2;
-        st->bx = st->precision == MP_FP64 ? 256 : 64;
+        st->bx = 256;
         st->seg = st->precision == MP_FP64 ? 32 : 16;
-        st->vec = st->precision == MP_FP64 ? 1 : 2;
+        st->vec = 1;
     }
 }
 
@@ -618,6 +617,7 @@ AdjLayout adj_layout(const mp_state* st, int64_t every) {
     mp::AdjGeom g;
     g.nx = (int)I.grid.n[0];
     g.ny = (int)I.grid.n[1];
+    g.seg = mp::adj_seg(g.nx, g.ny);
     L.nrows = mp::adj_blocks(g);
     size_t o = 0;
     L.X0 = o;
@@ -1032,6 +1032,7 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
     A.g.perx = I.grid.bc[0] == MP_BC_PERIODIC;
     A.g.pery = I.grid.bc[1] == MP_BC_PERIODIC;
     A.g.fs = ncells_of(I.grid);
+    A.g.seg = mp::adj_seg(A.g.nx, A.g.ny);
     A.nphases = I.N;
     A.nmu = I.K - 1;
     A.lam = lam;
@@ -1070,9 +1071,9 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
         }
         return r;
     };
-    // Reverse sweep of segment k on the caller's stream: pass A of its last
-    // step, then pass B of each step fused with pass A of the step before it,
-    // then pass B of its first step.
+    // Reverse sweep of segment k on the caller's stream: part A of its last
+    // step, then part B of each step fused with part A of the step before it,
+    // then part B of its first step.
     auto sweep = [&](int64_t k) {
         char* seg = w + L.seg[k & 1];
         const int64_t base = n0 + k * every, len = len_of(k);

@@ -36,6 +36,12 @@ __device__ __forceinline__ int gmap(int i, int n, bool periodic) {
     return i;
 }
 
+// Index i mod n for any integer i (n >= 1).
+__device__ __forceinline__ int wrap(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
 __device__ __forceinline__ int pair_index(int i, int j) { return i + j - 1; }  // (0,1)->0 (0,2)->1 (1,2)->2
 
 // 1/sqrt(x), x > 0 and normal: hardware estimate (about 1 ulp in FP32), two

@@ -390,12 +390,6 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     }
 }
 
-// Index i mod n for any integer i (n >= 1).
-__device__ __forceinline__ int wrap(int i, int n) {
-    const int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
 // Two steps in one pass.  A wave's lanes cover xs .. xs + 64 V - 1 with
 // xs = tx * 60 V - 2 V; lanes 2..61 are written.  Step 1 is computed on every
 // lane into registers (a row at a time, marching y as in strip2d) and step 2
