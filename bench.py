@@ -35,6 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# MI355X vector ALU peaks, TFLOP/s (an FMA counts 2): 256 CUs x 4 SIMDs x 2.4 GHz
+# x 16 FP64 lanes (78.6) or x 32 FP32 lanes (157.3), x 2
+ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 
 # HBM bytes per launch of each leg's step kernel, from rocprofv3 counter runs:
@@ -44,16 +47,16 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "cf0dd6c69f18d09d",
-               "bytes": (2.0 * 374164.0 + 661948.5) * 1024},
-    "c2_f32": {"tile": [64, 16, 2], "fuse": 2, "src": "780e054685d4f4d8",
-               "bytes": (2.0 * 207392.4 + 329343.6) * 1024},
+    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "517a6ba25bf6727b",
+               "bytes": (2.0 * 386869.4 + 666404.6) * 1024},
+    "c2_f32": {"tile": [256, 16, 1], "fuse": 2, "src": "7c2feaea3eab6117",
+               "bytes": (2.0 * 217035.7 + 333733.2) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "e68109c0892504ae",
-           "bytes": (2.0 * 1075660.0 + 1572864.0) * 1024},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "b786305b1f06790a",
+           "bytes": (2.0 * 1103156.8 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "a96fa80e9e1a573c",
-           "bytes": (2.0 * 699494.1 + 1207230.5) * 1024},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "cb28d1852047b0b5",
+           "bytes": (2.0 * 743739.5 + 1247130.9) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5")
@@ -120,6 +123,32 @@ def roofline(bytes_per_step, ms_step, traffic=None):
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic)}
+
+
+def flops_per_cell_update(nphases, ncomp, dim=2):
+    """Floating-point operations (an FMA counts 2) of one cell update of the
+    isotropic multi-well step as the kernels evaluate it, each face once:
+    the cell record (h, mobility), one face per axis, the face sums, h of the
+    old phi, and the cell update (doubled psi, driving force, Lagrange
+    multiplier, new phi and its h, mu with its reciprocal and two Newton steps)."""
+    n, m, d = nphases, ncomp - 1, dim
+    pairs = n * (n - 1) // 2
+    h = 5 * n + 3 if n == 3 else 4 * n
+    record = h + m * (2 * n - 1)
+    faces = d * (12 * pairs + 3 * m)
+    sums = (n + m) * (2 * d - 1)
+    cell = (4 * n * m + (6 if n == 3 else 0)
+            + n * (2 * n + 6 if n == 3 else 2 * n + 4)
+            + n + 3 * n + h + n + m * (4 * n + 10))
+    return record + faces + sums + h + cell
+
+
+def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
+    """Algorithmic flops per launch / launch time against the vector ALU peak."""
+    tf = flops_per_step / (ms_step * 1e-3) / 1e12
+    peak = ALU_PEAK_TFLOPS[precision]
+    return {"bound": "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(tf / peak, 4), "traffic": None if traffic is None else round(traffic)}
 
 
 def parse_tile(text):
@@ -192,11 +221,16 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
     s.close()
     elem = 8 if precision == "f64" else 4
     bpc = p.nfields * 2 * elem  # read + write of every field once
+    fpc = flops_per_cell_update(p.nphases, p.ncomp)
     ms_step = t.ms / steps
+    traffic = traffic_of(f"c2_{precision}", used, fuse)
     return {
         "value": p.ncells * steps / (t.ms * 1e-3),
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of(f"c2_{precision}", used, fuse)),
+        # two steps per launch from registers: the vector ALU, not HBM, bounds it
+        "roofline": alu_roofline(p.ncells * fpc, ms_step, precision, traffic),
+        "hbm_equivalent": roofline(p.ncells * bpc, ms_step, traffic),
+        "flops_per_cell_update": fpc,
         "bytes_per_cell_update": bpc,
         "steps_per_launch": fuse,
         "algorithmic_bytes_per_launch": fuse * p.ncells * bpc,
@@ -251,6 +285,7 @@ def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
     b.start(0)
     cells = sum(m[0].ncells for m in members)
     bytes_step = sum(m[0].ncells * m[0].nfields * 2 * 4 for m in members)
+    flops_step = sum(m[0].ncells * flops_per_cell_update(m[0].nphases, m[0].ncomp) for m in members)
     del members
     if tile:
         b.set_tile(*tile)
@@ -274,7 +309,8 @@ def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
         "steps": steps,
         "cells": cells,
         "ms_per_step": ms_step,
-        "roofline": roofline(bytes_step, ms_step, traffic_of("c4", used, fuse)),
+        "roofline": alu_roofline(flops_step, ms_step, "f32", traffic_of("c4", used, fuse)),
+        "hbm_equivalent": roofline(bytes_step, ms_step, traffic_of("c4", used, fuse)),
         "steps_per_launch": fuse,
         "algorithmic_bytes_per_launch": fuse * bytes_step,
         "tile": {"seg": used[1], "vec": used[2]},
@@ -387,6 +423,8 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r64["roofline"],
+        "hbm_equivalent": r64["hbm_equivalent"],
+        "flops_per_cell_update": r64["flops_per_cell_update"],
         "steps_per_launch": r64["steps_per_launch"],
         "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_launch"],
         "tile": r64["tile"],
