@@ -306,7 +306,7 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
     double lam = 0.0;
 #pragma unroll
     for (int a = 0; a < NP; ++a) lam = lam + (double)Rr[a];
-    lam = lam / NP;
+    lam = lam * (1.0 / NP);
     R dR[NP], phin[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -339,7 +339,7 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
         }
         const R Q = c.dt * divJ[k] - src;
         const R l1 = l1in[NP + k];
-        const R r = R(1) / chik;
+        const R r = fast_rcp(chik);
         const R lQ = l1 * r;
         const R lchi = -l1 * Q * r * r;
         ldiv[k] = c.dt * lQ;
@@ -366,7 +366,7 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
         lphin[a] = v;
         lmean = lmean + v;
     }
-    lmean = lmean / R(NP);
+    lmean = lmean * (R(1) / R(NP));
     R lR[NP];
     double gtau = 0.0;
 #pragma unroll
@@ -577,13 +577,12 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
         auto row = [&](int m, Cell& b0, Cell& b1, R (&x0)[NF], R (&x1)[NF], Cell& a0, Cell& a1) {
             const int64_t o = (int64_t)m * nx + cs;  // the owned cell (own lanes only)
             const bool ysame = rowmap(m) == rowmap(m + 1);
-            const bool more = m + 1 < m1;  // row m+2 is read
-            R lv[NF];  // lambda at the owned cell
+            R lv[NF];  // lambda at the cell (used at owned cells only)
+            {
+                const int64_t oc = at(m);  // = o at owned cells, in bounds elsewhere
 #pragma unroll
-            for (int f = 0; f < NF; ++f) lv[f] = R(0);
-            if (own)
-#pragma unroll
-                for (int f = 0; f < NF; ++f) lv[f] = lam[f * fs + o];
+                for (int f = 0; f < NF; ++f) lv[f] = lam[f * fs + oc];
+            }
             R lf[NF];
             if constexpr (DOB) {
                 // x face (lane, lane+1)
@@ -600,27 +599,41 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 R lpx[NP], lpxR[NP], lux[NM], luxR[NM], lMx[NM];
                 double gpx[3];
                 face_bwd<R, NP, NM>(b0.phi, pR, b0.mu, uR, b0.M, MR, x0, XR, c, lpx, lpxR, lux, luxR, lMx, gpx);
-                if (xsame) {
+                const R xm = xsame ? R(0) : R(1);  // mask: see the y face below
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) lpx[a] = lpxR[a] = R(0);
-#pragma unroll
-                    for (int k = 0; k < NM; ++k) lux[k] = luxR[k] = lMx[k] = R(0);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) gpx[q] = 0.0;
+                for (int a = 0; a < NP; ++a) {
+                    lpx[a] = lpx[a] * xm;
+                    lpxR[a] = lpxR[a] * xm;
                 }
+#pragma unroll
+                for (int k = 0; k < NM; ++k) {
+                    lux[k] = lux[k] * xm;
+                    luxR[k] = luxR[k] * xm;
+                    lMx[k] = lMx[k] * xm;
+                }
+#pragma unroll
+                for (int q = 0; q < 3; ++q) gpx[q] = gpx[q] * (double)xm;
                 // y face (m, m+1)
                 R lpy[NP], lpyU[NP], luy[NM], luyU[NM], lMy[NM];
                 double gpy[3];
                 face_bwd<R, NP, NM>(b0.phi, b1.phi, b0.mu, b1.mu, b0.M, b1.M, x0, x1, c, lpy, lpyU, luy, luyU, lMy,
                                     gpy);
-                if (ysame) {
+                // masks multiply (a select would let the compiler branch around the
+                // face, splitting the row body the scheduler interleaves)
+                const R ym = ysame ? R(0) : R(1);
 #pragma unroll
-                    for (int a = 0; a < NP; ++a) lpy[a] = lpyU[a] = R(0);
-#pragma unroll
-                    for (int k = 0; k < NM; ++k) luy[k] = luyU[k] = lMy[k] = R(0);
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) gpy[q] = 0.0;
+                for (int a = 0; a < NP; ++a) {
+                    lpy[a] = lpy[a] * ym;
+                    lpyU[a] = lpyU[a] * ym;
                 }
+#pragma unroll
+                for (int k = 0; k < NM; ++k) {
+                    luy[k] = luy[k] * ym;
+                    luyU[k] = luyU[k] * ym;
+                    lMy[k] = lMy[k] * ym;
+                }
+#pragma unroll
+                for (int q = 0; q < 3; ++q) gpy[q] = gpy[q] * (double)ym;
                 // the cell's four faces: x-hi (own), x-lo (from the previous
                 // lane), y-hi (own), y-lo (carried)
                 R lphi[NP], lmu[NM], lM[NM];
@@ -663,10 +676,9 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 }
                 // row m's slots are free: row m+2 is fetched into them while
                 // part A runs
-                if (more) {
-                    adj_fetch<R, NP, NM>(sB, fs, at(m + 2), b0);
-                    ldX(m + 2, x0);
-                }
+                // (past the segment's last row the clamped rows go unused)
+                adj_fetch<R, NP, NM>(sB, fs, at(m + 2), b0);
+                ldX(m + 2, x0);
             }
             if constexpr (DOA) {
                 // forward faces of sA: x-hi here, x-lo from the previous lane,
@@ -702,7 +714,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 for (int a = 0; a < NP; ++a) ph[a] = a0.phi[a];
 #pragma unroll
                 for (int k = 0; k < NM; ++k) mu[k] = a0.mu[k];
-                if (more) adj_fetch<R, NP, NM>(sA, fs, at(m + 2), a0);
+                adj_fetch<R, NP, NM>(sA, fs, at(m + 2), a0);
                 R l1[NF], Xo[NF], lo[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) l1[f] = lv[f];
@@ -729,10 +741,8 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     for (int f = 0; f < NF; ++f) lam[f * fs + o] = lv[f] + lf[f];
             }
             // the window moves up one row: row m+2's mobilities
-            if (more) {
-                if constexpr (DOB) adj_finish<R, NP, NM>(c, b0);
-                if constexpr (DOA) adj_finish<R, NP, NM>(c, a0);
-            }
+            if constexpr (DOB) adj_finish<R, NP, NM>(c, b0);
+            if constexpr (DOA) adj_finish<R, NP, NM>(c, a0);
         };
         int m = m0;
         for (; m + 1 < m1; m += 2) {

@@ -374,7 +374,7 @@ int sync_batch(mp_state* st) {
 }
 
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k, int fuse = 1);
+                     mp::KernelCall& k, int fuse = 1, void* out1 = nullptr);
 
 // One launch of `fuse` steps (1 or 2; a batch always 1); kstep is the
 // launch's offset from the device time level.
@@ -401,7 +401,7 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fus
 // Single-grid launch of `fuse` steps from ``in`` to ``out`` at time level
 // *ctr + kstep.
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k, int fuse) {
+                     mp::KernelCall& k, int fuse, void* out1) {
     const Inst& I = st->inst[0];
     mp::StepLaunch L;
     L.in = in;
@@ -416,6 +416,7 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.seg = st->seg;
     L.vec = st->vec;
     L.fuse = fuse;
+    L.out1 = out1;
     L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
@@ -1057,16 +1058,24 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
     auto len_of = [&](int64_t k) { return (nsteps - k * every) < every ? (nsteps - k * every) : every; };
     // Segment k's states, restored from checkpoint k and recomputed into
     // buffer k mod 2, on stream q.
+    // Two steps per launch where the kernel can also store the state between
+    // them (2D single grid at one cell per lane), else one.
     auto recompute = [&](int64_t k, hipStream_t q) {
         char* seg = w + L.seg[k & 1];
+        auto at = [&](int64_t i) { return seg + (size_t)i * L.state; };
         int r = hip_check(hipMemcpyAsync(seg, (const char*)ckpt_buf + (size_t)k * L.state, sb,
                                          hipMemcpyDeviceToDevice, q),
                           "checkpoint restore");
-        for (int64_t i = 0; r == MP_OK && i + 1 < len_of(k); ++i) {
+        for (int64_t i = 0; r == MP_OK && i + 1 < len_of(k);) {
+            const int kstep = (int)(n0 + k * every + i);
             mp::KernelCall kc;
-            r = make_single_call(st, seg + (size_t)i * L.state, seg + (size_t)(i + 1) * L.state, zctr,
-                                 (int)(n0 + k * every + i), kc);
-            if (r) return fail(r, "no kernel instance for this configuration");
+            if (i + 2 < len_of(k) && make_single_call(st, at(i), at(i + 2), zctr, kstep, kc, 2, at(i + 1)) == MP_OK) {
+                i += 2;
+            } else {
+                r = make_single_call(st, at(i), at(i + 1), zctr, kstep, kc);
+                if (r) return fail(r, "no kernel instance for this configuration");
+                i += 1;
+            }
             r = launch(kc, q);
         }
         return r;

@@ -25,7 +25,8 @@ template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int FUSE>
 __device__ __forceinline__ void run_strip(const R* src, R* dst, const InstDesc<R>& d, double tb0,
                                           double tb1, int tx, int m0, int m1) {
     if constexpr (FUSE == 2)
-        strip2d_x2<R, NP, NM, ANISO, OBST, V, true>(src, dst, d.g, d.c, tb0, tb1, d.tslope, tx, m0, m1);
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, true>(src, dst, nullptr, d.g, d.c, tb0, tb1, d.tslope, tx, m0,
+                                                    m1);
     else
         strip2d<R, NP, NM, ANISO, OBST, V, MP_STRIP_DEPTH, BATCH_W>(src, dst, d.g, d.c, tb0, d.tslope,
                                                                     tx, m0, m1);

@@ -51,6 +51,7 @@ struct DiagCoef {
 struct StepLaunch {
     const void* in;
     void* out;
+    void* out1 = nullptr;  // two steps per launch: also receives the state after the first
     Geom g;
     int nphases, nmu, dim, potential, aniso;
     int bx, seg, vec;

@@ -428,11 +428,12 @@ __device__ __forceinline__ int x2_first_col(int tx, int lane) {
 }
 
 // XEDGE: the wave holds a mirror ghost column (wave-uniform; only then are
-// the mirror copies of step 1 made).
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE>
-__device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
-                                           const Coef<R>& c, double tbase0, double tbase1, double tslope,
-                                           int tx, int m0, int m1) {
+// the mirror copies of step 1 made).  STORE1: the step-1 rows of the segment
+// are also written, to out1 (the state between the two steps).
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE, bool STORE1 = false>
+__device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
+                                           const Geom& g, const Coef<R>& c, double tbase0, double tbase1,
+                                           double tslope, int tx, int m0, int m1) {
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
     typedef Row2d<R, NP, NM, V, ANISO> RowT;
@@ -508,6 +509,13 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
             make_row<R, NP, NM, ANISO, V>(v, P, c);
         } else {
             make_row<R, NP, NM, ANISO, V, true>(v, P, c, hn);
+        }
+        if constexpr (STORE1) {
+            if (writes && r >= m0 && r < m1) {
+                const int64_t o = (int64_t)r * nx + cs;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) vstore<R, V>(out1 + f * fs + o, v[f]);
+            }
         }
         c0 = n0;
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -587,9 +595,9 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     strip2d<R, NP, NM, ANISO, OBST, V>(in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool STORE1 = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
-k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1, Geom g, Coef<R> c,
             const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
             int seg, int ntx, int nseg) {
     const int wpb = blockDim.x >> 6;
@@ -602,11 +610,13 @@ k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     bool fixL, fixR;
     x2_column<V>(g, x2_first_col<V>(tx, threadIdx.x & 63), fixL, fixR);
     if (__ballot(fixL || fixR) != 0)
-        strip2d_x2<R, NP, NM, ANISO, OBST, V, true>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0),
-                                                    tslope, tx, m0, min(m0 + seg, g.ny));
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, true, STORE1>(in, out, out1, g, c, tb0 + tdn * n,
+                                                            tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                            min(m0 + seg, g.ny));
     else
-        strip2d_x2<R, NP, NM, ANISO, OBST, V, false>(in, out, g, c, tb0 + tdn * n, tb0 + tdn * (n + 1.0),
-                                                     tslope, tx, m0, min(m0 + seg, g.ny));
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, false, STORE1>(in, out, out1, g, c, tb0 + tdn * n,
+                                                             tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                             min(m0 + seg, g.ny));
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
@@ -618,12 +628,24 @@ int call_2d_v(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     const long long waves = (long long)ntx * nseg;
     const long long nblocks = (waves + wpb - 1) / wpb;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
-    k.func = L.fuse == 2 ? (const void*)&k_step2d_x2<R, NP, NM, ANISO, OBST, V>
-                         : (const void*)&k_step2d<R, NP, NM, ANISO, OBST, V>;
+    if (L.out1) {
+        // the state between the two steps as well: built for the adjoint's
+        // recomputation (isotropic, multi-well, one cell per lane)
+        if constexpr (V == 1 && !ANISO && !OBST) {
+            if (L.fuse != 2) return MP_E_PARAM;
+            k.func = (const void*)&k_step2d_x2<R, NP, NM, ANISO, OBST, V, true>;
+        } else {
+            return MP_E_PARAM;
+        }
+    } else {
+        k.func = L.fuse == 2 ? (const void*)&k_step2d_x2<R, NP, NM, ANISO, OBST, V>
+                             : (const void*)&k_step2d<R, NP, NM, ANISO, OBST, V>;
+    }
     k.grid = dim3((unsigned)nblocks);
     k.block = dim3(L.bx);
     k.arg((const R*)L.in);
     k.arg((R*)L.out);
+    if (L.fuse == 2) k.arg((R*)L.out1);
     k.arg(L.g);
     k.arg(c);
     k.arg(L.stepctr);
