@@ -46,7 +46,10 @@ struct AdjCoef {
 
 constexpr int ADJ_NPAR = 10;  // gamma 01, 02, 12; D[a][k] (a < 3, k < 2); tau
 constexpr int ADJ_W = 62;     // columns owned by a strip wave (lanes 1..62)
-constexpr int ADJ_WPB = 4;    // waves per block
+#ifndef MP_ADJ_WPB
+#define MP_ADJ_WPB 4
+#endif
+constexpr int ADJ_WPB = MP_ADJ_WPB;  // waves per block
 
 template <typename R, int NP>
 __device__ __forceinline__ void h_of(const R (&p)[NP], R (&h)[NP]) {
