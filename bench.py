@@ -125,17 +125,29 @@ def roofline(bytes_per_step, ms_step, traffic=None):
             "traffic": None if traffic is None else round(traffic)}
 
 
-def flops_per_cell_update(nphases, ncomp, dim=2):
+def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False):
     """Floating-point operations (an FMA counts 2) of one cell update of the
-    isotropic multi-well step as the kernels evaluate it, each face once:
-    the cell record (h, mobility), one face per axis, the face sums, h of the
-    old phi, and the cell update (doubled psi, driving force, Lagrange
-    multiplier, new phi and its h, mu with its reciprocal and two Newton steps)."""
+    multi-well step as the kernels evaluate it, each face once: the cell
+    record (h, mobility), one face per axis, the face sums, h of the old phi,
+    and the cell update (doubled psi, driving force, Lagrange multiplier, new
+    phi and its h, mu with its reciprocal and two Newton steps).  An
+    anisotropic pair adds the tangential differences and q components and the
+    normal component of d(a_c^2 |q|^2)/dq (one reciprocal square root)."""
     n, m, d = nphases, ncomp - 1, dim
     pairs = n * (n - 1) // 2
     h = 5 * n + 3 if n == 3 else 4 * n
     record = h + m * (2 * n - 1)
-    faces = d * (12 * pairs + 3 * m)
+    if aniso:
+        t = d - 1  # tangential axes
+        # per face: sigma sums (n), tangential sums of the two cells' central
+        # differences (3 per phase and axis); per pair: q_n (4), q_t (4 per
+        # axis), |q|^2 (1 + 2t), rsqrt and the normalised components (5 + 4t),
+        # a_c (4), G_n (11), its small-|q| limit (5), the pair factor (1) and
+        # the U/W updates (8)
+        face = n + 3 * n * t + pairs * (4 + 4 * t + (1 + 2 * t) + (5 + 4 * t) + 4 + 11 + 5 + 1 + 8) + 3 * m
+        faces = d * face
+    else:
+        faces = d * (12 * pairs + 3 * m)
     sums = (n + m) * (2 * d - 1)
     cell = (4 * n * m + (6 if n == 3 else 0)
             + n * (2 * n + 6 if n == 3 else 2 * n + 4)
@@ -175,6 +187,25 @@ class Timer:
         self.e1.record(self.stream)
         self.torch.cuda.synchronize()
         self.ms = self.e0.elapsed_time(self.e1)
+
+
+def copy_bandwidth(n, reps=10):
+    """Read + write GB/s of a plain device copy of one FP64 C2-sized state buffer:
+    the practical HBM ceiling, a second denominator beside the 8 TB/s peak."""
+    import torch
+
+    nbytes = 5 * n * n * 8
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    with Timer() as t:
+        for _ in range(reps):
+            dst.copy_(src)
+    gbs = 2 * nbytes / (t.ms / reps * 1e-3) / 1e9
+    del src, dst
+    return {"achieved": round(gbs, 1), "unit": "GB/s", "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_each_way": nbytes}
 
 
 def copy_calibration(n, steps):
@@ -258,6 +289,7 @@ def leg_c3(n, steps, warmup, tile, tune):
     d = s.diagnostics()
     s.close()
     bpc = p.nfields * 2 * 4
+    fpc = flops_per_cell_update(p.nphases, p.ncomp, dim=3, aniso=True)
     ms_step = t.ms / steps
     return {
         "workload": f"3D {n}^3 binary dendrite, cubic anisotropy delta=0.02, no-flux, FP32",
@@ -266,6 +298,10 @@ def leg_c3(n, steps, warmup, tile, tune):
         "steps": steps,
         "ms_per_step": ms_step,
         "roofline": roofline(p.ncells * bpc, ms_step, traffic_of("c3", used, 1)),
+        # the flop side of the same kernel (neither side is saturated: LDS and
+        # latency bound)
+        "alu": alu_roofline(p.ncells * fpc, ms_step, "f32"),
+        "flops_per_cell_update": fpc,
         "bytes_per_cell_update": bpc,
         "steps_per_launch": 1,
         "algorithmic_bytes_per_launch": p.ncells * bpc,
@@ -445,6 +481,7 @@ def main():
     if "c5" in legs:
         log("checkpointed forward + adjoint FP32")
         out["adjoint"] = leg_c5(a.adjoint_steps)
+    out["copy_bandwidth"] = copy_bandwidth(a.n)
     if not a.no_cpu:
         log("CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(a.n)
