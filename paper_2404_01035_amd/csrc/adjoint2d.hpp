@@ -214,7 +214,7 @@ __device__ __forceinline__ void face_bwd(const R (&pA)[NP], const R (&pB)[NP], c
                                          const R (&uB)[NM], const R (&MA)[NM], const R (&MB)[NM],
                                          const R (&XA)[NP + NM], const R (&XB)[NP + NM], const AdjCoef<R>& c,
                                          R (&lpA)[NP], R (&lpB)[NP], R (&luA)[NM], R (&luB)[NM], R (&lM)[NM],
-                                         double (&gp)[3]) {
+                                         R (&gp)[3]) {
     R pb[NP], g[NP], lF[NP], lS[NP], lpb[NP], lg[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -226,7 +226,7 @@ __device__ __forceinline__ void face_bwd(const R (&pA)[NP], const R (&pB)[NP], c
         lg[a] = R(0);
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) gp[q] = 0.0;
+    for (int q = 0; q < 3; ++q) gp[q] = R(0);
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
@@ -240,7 +240,7 @@ __device__ __forceinline__ void face_bwd(const R (&pA)[NP], const R (&pB)[NP], c
             lpb[i] = lpb[i] + lF[j] * gG;
             lg[j] = lg[j] + lS[i] * gG;
             lg[i] = lg[i] - lS[j] * gG;
-            gp[pi] = (double)(lgG * Gn);
+            gp[pi] = lgG * Gn;
             const R lqn = R(2) * c.gam[pi] * lgG;
             lpb[i] = lpb[i] + lqn * g[j];
             lg[j] = lg[j] + lqn * pb[i];
@@ -262,13 +262,13 @@ __device__ __forceinline__ void face_bwd(const R (&pA)[NP], const R (&pB)[NP], c
     }
 }
 
-// Part A's backward at one cell from the forward step's gradient term grad
+// Part A's backward at one cell (phi, mu, h(phi)) from the forward step's gradient term grad
 // and flux divergence divJ there.  l1in = lambda^{n+1} at the cell; Xo
 // receives [lambda of grad_a (NP)][lambda of divJ_k (NM)], lo the cell-local
 // part of lambda^n; par collects the cell's gamma (potential) and tau terms.
 template <typename R, int NP, int NM>
-__device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[NM], const R (&grad)[NP],
-                                              const R (&divJ)[NM], const AdjCoef<R>& c, R ttc,
+__device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[NM], const R (&hphi)[NP],
+                                              const R (&grad)[NP], const R (&divJ)[NM], const AdjCoef<R>& c, R ttc,
                                               const R (&l1in)[NP + NM], R (&Xo)[NP + NM], R (&lo)[NP + NM],
                                               double (&par)[ADJ_NPAR]) {
     const R tt = ttc;
@@ -320,7 +320,8 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
     R phi0[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) phi0[a] = phi[a];
-    h_of<R, NP>(phi0, h0);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) h0[a] = hphi[a];
     h_of<R, NP>(phin, h1);
     dh_of<R, NP>(phi0, dh0);
     dh_of<R, NP>(phin, dh1);
@@ -438,10 +439,10 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
 }
 
 
-// A cell of one row of a state: phi, mu and the mobility.
+// A cell of one row of a state: phi, mu, the mobility and h(phi).
 template <typename R, int NP, int NM>
 struct ACell {
-    R phi[NP], mu[NM], M[NM];
+    R phi[NP], mu[NM], M[NM], h[NP];
 };
 
 template <typename R, int NP, int NM>
@@ -452,12 +453,11 @@ __device__ __forceinline__ void adj_fetch(const R* __restrict__ s, int64_t fs, i
     for (int k = 0; k < NM; ++k) q.mu[k] = s[(NP + k) * fs + o];
 }
 
-// The cell's mobility, once its phi is in.
+// The cell's h and mobility, once its phi is in.
 template <typename R, int NP, int NM>
 __device__ __forceinline__ void adj_finish(const AdjCoef<R>& c, ACell<R, NP, NM>& q) {
-    R h[NP];
-    h_of<R, NP>(q.phi, h);
-    mob_of<R, NP, NM>(h, c, q.M);
+    h_of<R, NP>(q.phi, q.h);
+    mob_of<R, NP, NM>(q.h, c, q.M);
 }
 
 template <typename R, int NP, int NM>
@@ -555,7 +555,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 adj_finish<R, NP, NM>(c, b0);
                 adj_finish<R, NP, NM>(c, b1);
                 R lpA[NP], luA[NM];
-                double gp[3];
+                R gp[3];
                 face_bwd<R, NP, NM>(bl.phi, b0.phi, bl.mu, b0.mu, bl.M, b0.M, xl, x0, c, lpA, cpB, luA, cuB, cMB,
                                     gp);
                 if (ysame) {
@@ -600,7 +600,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
 #pragma unroll
                 for (int f = 0; f < NF; ++f) XR[f] = lane_next(x0[f]);
                 R lpx[NP], lpxR[NP], lux[NM], luxR[NM], lMx[NM];
-                double gpx[3];
+                R gpx[3];
                 face_bwd<R, NP, NM>(b0.phi, pR, b0.mu, uR, b0.M, MR, x0, XR, c, lpx, lpxR, lux, luxR, lMx, gpx);
                 const R xm = xsame ? R(0) : R(1);  // mask: see the y face below
 #pragma unroll
@@ -615,10 +615,10 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     lMx[k] = lMx[k] * xm;
                 }
 #pragma unroll
-                for (int q = 0; q < 3; ++q) gpx[q] = gpx[q] * (double)xm;
+                for (int q = 0; q < 3; ++q) gpx[q] = gpx[q] * xm;
                 // y face (m, m+1)
                 R lpy[NP], lpyU[NP], luy[NM], luyU[NM], lMy[NM];
-                double gpy[3];
+                R gpy[3];
                 face_bwd<R, NP, NM>(b0.phi, b1.phi, b0.mu, b1.mu, b0.M, b1.M, x0, x1, c, lpy, lpyU, luy, luyU, lMy,
                                     gpy);
                 // masks multiply (a select would let the compiler branch around the
@@ -636,7 +636,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     lMy[k] = lMy[k] * ym;
                 }
 #pragma unroll
-                for (int q = 0; q < 3; ++q) gpy[q] = gpy[q] * (double)ym;
+                for (int q = 0; q < 3; ++q) gpy[q] = gpy[q] * ym;
                 // the cell's four faces: x-hi (own), x-lo (from the previous
                 // lane), y-hi (own), y-lo (carried)
                 R lphi[NP], lmu[NM], lM[NM];
@@ -648,12 +648,12 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     lM[k] = (lMx[k] + lane_prev(lMx[k])) + (lMy[k] + cMB[k]);
                 }
                 // mobility M_k = sum_b D_bk chi_bk h_b(phi)
-                R hi[NP], dhi[NP][NP];
-                h_of<R, NP>(b0.phi, hi);
+                const R(&hi)[NP] = b0.h;
+                R dhi[NP][NP];
                 dh_of<R, NP>(b0.phi, dhi);
                 if (own) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) parB[q] += gpx[q] + gpy[q];
+                    for (int q = 0; q < 3; ++q) parB[q] += (double)gpx[q] + (double)gpy[q];
 #pragma unroll
                     for (int k = 0; k < NM; ++k)
 #pragma unroll
@@ -712,9 +712,12 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     divJ[k] = (Jx[k] - Jl) * c.inv_dx + (Jy[k] - cJ[k]) * c.inv_dx;
                     cJ[k] = Jy[k];
                 }
-                R ph[NP], mu[NM];
+                R ph[NP], mu[NM], hA[NP];
 #pragma unroll
-                for (int a = 0; a < NP; ++a) ph[a] = a0.phi[a];
+                for (int a = 0; a < NP; ++a) {
+                    ph[a] = a0.phi[a];
+                    hA[a] = a0.h[a];
+                }
 #pragma unroll
                 for (int k = 0; k < NM; ++k) mu[k] = a0.mu[k];
                 adj_fetch<R, NP, NM>(sA, fs, at(m + 2), a0);
@@ -727,8 +730,8 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 double pc[ADJ_NPAR];
 #pragma unroll
                 for (int q = 0; q < ADJ_NPAR; ++q) pc[q] = 0.0;
-                adj_cell_back<R, NP, NM>(ph, mu, grad, divJ, c, (R)(tt_row0 + tt_slope * (double)m), l1, Xo, lo,
-                                         pc);
+                adj_cell_back<R, NP, NM>(ph, mu, hA, grad, divJ, c, (R)(tt_row0 + tt_slope * (double)m), l1, Xo,
+                                         lo, pc);
                 if (own) {
 #pragma unroll
                     for (int q = 0; q < ADJ_NPAR; ++q) parA[q] += pc[q];
