@@ -19,13 +19,15 @@ def _instance(nx, ny, N, K, seed, precision="f64", bc=(0, 0, 0), G=0.0):
     return p, phi, mu
 
 
-def _gpu_adjoint(p, phi, mu, lphi, lmu, nsteps, every):
+def _gpu_adjoint(p, phi, mu, lphi, lmu, nsteps, every, tile=None):
     import torch
 
     from paper_2404_01035_amd.solver import Solver
 
     s = Solver(p)
     try:
+        if tile is not None:
+            s.set_tile(*tile)
         s.load(phi, mu)
         ckpt = s.checkpoint_buffer(nsteps, every)
         s.step_ckpt(nsteps, every, ckpt)
@@ -84,6 +86,20 @@ def test_adjoint_checkpoint_spacing_is_bitwise_invariant():
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), every
             assert out[2] == ref[2], every
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_recomputation_two_step_store_matches_single_steps(precision):
+    """Segments are recomputed two steps per launch (the two-step kernel also storing the
+    state between its steps) at one cell per lane, one step per launch at two cells per
+    lane; the forward kernels agree bitwise across tiles, so the adjoints must too."""
+    p, phi, mu = _instance(64, 48, 3, 3, seed=8, precision=precision, bc=(0, 1, 0), G=2e-3)
+    rng = np.random.default_rng(4)
+    lphi, lmu = rng.normal(size=phi.shape), rng.normal(size=mu.shape)
+    one = _gpu_adjoint(p, phi, mu, lphi, lmu, 30, 11, tile=(64, 8, 1))
+    two = _gpu_adjoint(p, phi, mu, lphi, lmu, 30, 11, tile=(64, 8, 2))
+    assert np.array_equal(one[0], two[0]) and np.array_equal(one[1], two[1])
+    assert one[2] == two[2]
 
 
 def test_adjoint_zero_steps_is_identity():
