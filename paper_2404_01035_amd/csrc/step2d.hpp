@@ -520,9 +520,6 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         c0 = n0;
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         process(ld, n0);
-#ifdef MP_X2_SCHEDB
-        __builtin_amdgcn_sched_barrier(0);
-#endif
         load(r + 3, ld);
     };
 
