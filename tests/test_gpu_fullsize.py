@@ -68,6 +68,30 @@ def test_c2_full_grid_sampled_step(precision, tol):
     print(f"C2 {precision}: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}")
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 4e-6)])
+def test_c2_full_grid_sampled_two_step_launch(precision, tol):
+    """The launch bench.py times: one two-step launch of the default tile.  The oracle
+    takes the first step on the whole grid and the second on the windows."""
+    from paper_2404_01035_amd import abi
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu = inputs.config_c2(precision=precision)
+    s = Solver(p)
+    s.load(phi, mu)
+    del phi, mu
+    assert abi.mp_get_fusion(s.st) == 2
+    s.step(40)
+    phi0, mu0 = _state(s)
+    n0 = s.time_level
+    s.step(2)  # one launch of the two-step kernel
+    phi2, mu2 = _state(s)
+    s.close()
+    phi1, mu1 = gp.run(phi0.astype(np.float64), mu0.astype(np.float64), n0, 1, p)
+    w = _windows_2d(4096, 4096, np.random.default_rng(7), seg=32)
+    worst = _check_windows(p, phi1, mu1, phi2, mu2, n0 + 1, w, tol)
+    print(f"C2 {precision} two-step launch: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}")
+
+
 @pytest.mark.parametrize("precision,mass_tol", [("f64", 1e-12), ("f32", 1e-7)])
 def test_c2_full_grid_conservation(precision, mass_tol):
     from paper_2404_01035_amd.solver import Solver
