@@ -135,3 +135,45 @@ def test_c3_full_grid_sampled_step():
         w.append(((z, y, x), (z + 4, y + 4, x + 8)))
     worst = _check_windows(p, phi0, mu0, phi1, mu1, n0, w, 2e-6)
     print(f"C3 f32: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}")
+
+
+def test_c4_full_batch_sampled_instances():
+    """The full 256-instance ensemble in the benchmark's configuration (default tile, two
+    steps per launch, HIP graphs of 50 steps): sampled instances equal the single-grid
+    kernels bitwise, and the two smallest match the oracle."""
+    from paper_2404_01035_amd import abi
+    from paper_2404_01035_amd.solver import BatchSolver, Solver
+
+    members = inputs.config_c4()
+    nsteps = 4
+    b = BatchSolver([m[0] for m in members])
+    try:
+        assert abi.mp_get_fusion(b.st) == 2
+        b.set_graph(50)
+        for i, (_, phi, mu) in enumerate(members):
+            b.load(i, phi, mu)
+        b.start(0)
+        b.step(nsteps)
+        rng = np.random.default_rng(9)
+        cells = [m[0].ncells for m in members]
+        order = np.argsort(cells)
+        picks = sorted(set([int(order[0]), int(order[1]), int(order[-1])]
+                           + [int(i) for i in rng.choice(len(members), 5, replace=False)]))
+        got = {i: b.fields(i) for i in picks}
+    finally:
+        b.close()
+    for i in picks:
+        p, phi, mu = members[i]
+        s = Solver(p)
+        s.load(phi, mu)
+        s.step(nsteps)
+        ref = s.fields()
+        s.close()
+        assert np.array_equal(got[i][0], ref[0]) and np.array_equal(got[i][1], ref[1]), i
+    for i in (int(order[0]), int(order[1])):
+        p, phi, mu = members[i]
+        p64 = p.copy(precision="f64")
+        of, om = gp.run(phi.astype(np.float64), mu.astype(np.float64), 0, nsteps, p64)
+        # FP32 state against the FP64 oracle over four steps
+        assert np.max(np.abs(got[i][0] - of)) <= 1e-5, i
+        assert np.max(np.abs(got[i][1] - om)) <= 1e-4, i
