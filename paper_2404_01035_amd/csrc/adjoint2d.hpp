@@ -33,23 +33,36 @@
 
 namespace mp {
 
-// Plain (unfolded) coefficients of the adjoint.
+// Coefficients of the adjoint, with the grid and interface scalings folded in
+// (the same step as the plain form of Sec. 2.1, rearranged):
+//   on a face between cells L and R the gradient term of pair (i, j) reduces
+//   to K = phi_i^L phi_j^R - phi_i^R phi_j^L (q_n = K / dx), and the cell
+//   term eps [(F_hi - F_lo) / dx - (s_hi + s_lo) / 2] of that pair becomes
+//   w = c4e K times a neighbour's phi, c4e = 2 eps gamma_ij / dx^2;
+//   the mu flux of a face is J = (M_L + M_R)(mu_R - mu_L), its 1 / (2 dx^2)
+//   folded into ktj = dt / (2 dx^2).
 template <typename R>
 struct AdjCoef {
-    R inv_dx, eps, inv_eps, kphi, dt;
-    R ktau;        // dt / (tau^2 eps)
-    R gam[3];      // gamma_ab by pair
-    R w18[3];      // 18 gamma_ab by pair
-    R gamma3;
-    R chi[3][2], halfchi[3][2], B[3][2], C[3], s[3], Dchi[3][2];
+    R kphi;     // dt / (tau eps): the phi update
+    R ktj;      // dt / (2 dx^2): the mu update from the unscaled flux divergence
+    R c4e[3];   // 2 eps gamma_ab / dx^2 by pair
+    R w18e[3];  // 18 gamma_ab / eps by pair
+    R g3e;      // gamma3 / eps
+    R chi[3][2], B[3][2], C[3], s[3], Dchi[3][2];
+    // factors of the parameter sums, applied once at the end: part B (faces:
+    // gamma from K T, D from lM h) and part A (gamma from the potential, tau)
+    double scB[10], scA[10];
 };
 
 constexpr int ADJ_NPAR = 10;  // gamma 01, 02, 12; D[a][k] (a < 3, k < 2); tau
 constexpr int ADJ_W = 62;     // columns owned by a strip wave (lanes 1..62)
-#ifndef MP_ADJ_WPB
-#define MP_ADJ_WPB 4
-#endif
-constexpr int ADJ_WPB = MP_ADJ_WPB;  // waves per block
+
+// Waves per block: the FP32 kernels hold two waves per SIMD (a block of 8
+// fills one CU), the FP64 ones one (a block of 4).
+template <typename R>
+constexpr int adj_wpb() {
+    return sizeof(R) == 4 ? 8 : 4;
+}
 
 template <typename R, int NP>
 __device__ __forceinline__ void h_of(const R (&p)[NP], R (&h)[NP]) {
@@ -59,24 +72,34 @@ __device__ __forceinline__ void h_of(const R (&p)[NP], R (&h)[NP]) {
     for (int a = 0; a < NP; ++a) h[a] = p[a] * p[a] * (R(3) - R(2) * p[a]) + e3x2;
 }
 
-// dh[b][a] = dh_b / dphi_a
+// Derivatives of h: dh_b/dphi_a = [a == b] d_a + 2 P_a, with d_a = 6 phi_a
+// (1 - phi_a) and P_a the product of the other phases' phi (N = 3; for N = 2
+// the second term is absent).  So a sum over b of v_b dh_b/dphi_a is
+// v_a d_a + 2 P_a sum_b v_b.
 template <typename R, int NP>
-__device__ __forceinline__ void dh_of(const R (&p)[NP], R (&d)[NP][NP]) {
+__device__ __forceinline__ void dh_parts(const R (&p)[NP], R (&d)[NP], R (&P)[NP]) {
 #pragma unroll
-    for (int b = 0; b < NP; ++b)
+    for (int a = 0; a < NP; ++a) d[a] = R(6) * (p[a] - p[a] * p[a]);
+    if constexpr (NP == 3) {
+        P[0] = p[1] * p[2];
+        P[1] = p[0] * p[2];
+        P[2] = p[0] * p[1];
+    } else {
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            if (a == b) {
-                R v = R(6) * p[b] - R(6) * p[b] * p[b];
-                if constexpr (NP == 3) {
-                    const int u = b == 0 ? 1 : 0, w = b == 2 ? 1 : 2;
-                    v = v + R(2) * (p[u] * p[w]);
-                }
-                d[b][a] = v;
-            } else {
-                d[b][a] = NP == 3 ? R(2) * p[b] * p[3 - a - b] : R(0);
-            }
-        }
+        for (int a = 0; a < NP; ++a) P[a] = R(0);
+    }
+}
+
+// out_a = v_a d_a + 2 P_a sum_b v_b (the h chain rule above), added to out
+template <typename R, int NP>
+__device__ __forceinline__ void dh_apply(const R (&v)[NP], const R (&d)[NP], const R (&P)[NP], R (&out)[NP]) {
+    R s2 = R(0);
+    if constexpr (NP == 3) s2 = R(2) * (v[0] + v[1] + v[2]);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        out[a] = out[a] + v[a] * d[a];
+        if constexpr (NP == 3) out[a] = out[a] + s2 * P[a];
+    }
 }
 
 template <typename R, int NP, int NM>
@@ -90,32 +113,29 @@ __device__ __forceinline__ void mob_of(const R (&h)[NP], const AdjCoef<R>& c, R 
     }
 }
 
-// Forward face in plain form: F, S of the gradient term and J of the mu flux.
+// Forward face: its share Ehi of the gradient term (times eps) of the lower
+// cell L, Elo (subtracted) of the upper cell R, and the unscaled mu flux J.
 template <typename R, int NP, int NM>
 __device__ __forceinline__ void face_fwd(const R (&pL)[NP], const R (&pR)[NP], const R (&ML)[NM],
                                          const R (&MR)[NM], const R (&uL)[NM], const R (&uR)[NM],
-                                         const AdjCoef<R>& c, R (&F)[NP], R (&S)[NP], R (&J)[NM]) {
-    R pb[NP], g[NP];
+                                         const AdjCoef<R>& c, R (&Ehi)[NP], R (&Elo)[NP], R (&J)[NM]) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        pb[a] = R(0.5) * (pL[a] + pR[a]);
-        g[a] = (pR[a] - pL[a]) * c.inv_dx;
-        F[a] = R(0);
-        S[a] = R(0);
+        Ehi[a] = R(0);
+        Elo[a] = R(0);
     }
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
         for (int j = i + 1; j < NP; ++j) {
-            const R qn = pb[i] * g[j] - pb[j] * g[i];
-            const R gG = c.gam[pair_index(i, j)] * (R(2) * qn);
-            F[i] = F[i] - gG * pb[j];
-            F[j] = F[j] + gG * pb[i];
-            S[i] = S[i] + gG * g[j];
-            S[j] = S[j] - gG * g[i];
+            const R w = c.c4e[pair_index(i, j)] * (pL[i] * pR[j] - pR[i] * pL[j]);
+            Ehi[i] = Ehi[i] - w * pR[j];
+            Ehi[j] = Ehi[j] + w * pR[i];
+            Elo[i] = Elo[i] - w * pL[j];
+            Elo[j] = Elo[j] + w * pL[i];
         }
 #pragma unroll
-    for (int k = 0; k < NM; ++k) J[k] = R(0.5) * (ML[k] + MR[k]) * (uR[k] - uL[k]) * c.inv_dx;
+    for (int k = 0; k < NM; ++k) J[k] = (ML[k] + MR[k]) * (uR[k] - uL[k]);
 }
 
 // Sum over the 64 lanes of a wave, complete in lane 63: DPP steps in a fixed
@@ -144,18 +164,19 @@ __device__ __forceinline__ double wave_sum_last(double x) {
 // (0..8) first, then A's (0, 1, 2, 9).  rowq: slot q of the row, read by lane
 // q of the block's first wave at the kernel's start (no other block touches
 // the row).
-template <bool DOB, bool DOA>
+template <int WPB, bool DOB, bool DOA>
 __device__ __forceinline__ void adj_block_add(const double (&pb)[ADJ_NPAR], const double (&pa)[ADJ_NPAR],
+                                              const double (&scB)[ADJ_NPAR], const double (&scA)[ADJ_NPAR],
                                               double rowq, double* __restrict__ acc) {
     constexpr int NB = DOB ? 9 : 0, NA = DOA ? 4 : 0;
     constexpr int SA[4] = {0, 1, 2, 9};
-    __shared__ double red[ADJ_WPB][NB + NA];
+    __shared__ double red[WPB][NB + NA];
     const int t = threadIdx.x;
     double w[NB + NA > 0 ? NB + NA : 1];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) w[q] = wave_sum_last(pb[q]);
+    for (int q = 0; q < NB; ++q) w[q] = wave_sum_last(pb[q] * scB[q]);
 #pragma unroll
-    for (int q = 0; q < NA; ++q) w[NB + q] = wave_sum_last(pa[SA[q]]);
+    for (int q = 0; q < NA; ++q) w[NB + q] = wave_sum_last(pa[SA[q]] * scA[SA[q]]);
     if ((t & 63) == 63)
 #pragma unroll
         for (int q = 0; q < NB + NA; ++q) red[t >> 6][q] = w[q];
@@ -165,14 +186,14 @@ __device__ __forceinline__ void adj_block_add(const double (&pb)[ADJ_NPAR], cons
         if (DOB && t < 9) {
             double sum = red[0][t];
 #pragma unroll
-            for (int k = 1; k < ADJ_WPB; ++k) sum = sum + red[k][t];
+            for (int k = 1; k < WPB; ++k) sum = sum + red[k][t];
             r = r + sum;
         }
         if (DOA && (t < 3 || t == 9)) {
             const int j = NB + (t < 3 ? t : 3);
             double sum = red[0][j];
 #pragma unroll
-            for (int k = 1; k < ADJ_WPB; ++k) sum = sum + red[k][j];
+            for (int k = 1; k < WPB; ++k) sum = sum + red[k][j];
             r = r + sum;
         }
         if ((DOB && t < 9) || (DOA && (t < 3 || t == 9))) acc[(size_t)blockIdx.x * ADJ_NPAR + t] = r;
@@ -184,150 +205,164 @@ struct AdjGeom {
     int nx, ny;
     bool perx, pery;
     int64_t fs;
-    int seg;  // rows per strip segment
+    // wave plan: ntx strips of ADJ_W columns, each cut into pw segments of len
+    // or len + 1 rows (nlong of them long), one wave per segment
+    int ntx, pw, len, nlong;
 };
 
-// Rows per segment of the adjoint strips: long segments where the grid gives
-// enough waves to fill the chip (about two per SIMD), short ones otherwise.
-#ifndef MP_ADJ_WAVES
-#define MP_ADJ_WAVES 1536
-#endif
-inline int adj_seg(int nx, int ny) {
-    const long long ntx = (nx + ADJ_W - 1) / ADJ_W;
-    const long long s = ntx * ny / MP_ADJ_WAVES;
-    return s < 1 ? 1 : (s > 32 ? 32 : (int)s);
+// Plans the strips for `slots` waves resident at once (the chip's SIMDs times
+// the waves each holds): as many segments per strip as fill the slots once,
+// so that every wave starts together and the work per SIMD differs by at
+// most one row (the long segments go to different SIMDs, see adj_segment).
+inline void adj_plan(AdjGeom& g, int slots) {
+    g.ntx = (g.nx + ADJ_W - 1) / ADJ_W;
+    int pw = slots / g.ntx;
+    pw = pw < 1 ? 1 : (pw > g.ny ? g.ny : pw);
+    g.pw = pw;
+    g.len = g.ny / pw;
+    g.nlong = g.ny % pw;
 }
 
+template <int WPB>
 inline int adj_blocks(const AdjGeom& g) {
-    const long long ntx = (g.nx + ADJ_W - 1) / ADJ_W;
-    const long long nsg = (g.ny + g.seg - 1) / g.seg;
-    return (int)((ntx * nsg + ADJ_WPB - 1) / ADJ_WPB);
+    return (int)(((long long)g.ntx * g.pw + WPB - 1) / WPB);
 }
 
-// One face's backward.  A is the lower cell (smaller coordinate), B the
-// upper; X are the cells' cotangents of the gradient term (NP) and flux
-// divergence (NM).  lpA, luA / lpB, luB receive the face's share of lambda at
-// A / B, lM the share of the mobility cotangent (the same for both cells), gp
-// the face's gamma terms by pair.
+// Waves 0..7 of a block of 8 share SIMDs in pairs, either (w, w+4) or
+// (2i, 2i+1) depending on how the waves are dealt; the "a" waves {0, 2, 5, 7}
+// meet one "b" wave in both pairings.  a waves below x:
+__host__ __device__ inline int adj_count_a(int x) {
+    return 4 * (x >> 3) + ((0x33222110 >> (4 * (x & 7))) & 0xF);
+}
+
+// Rows [m0, m1) and strip tx of wave gw (tx >= ntx: idle).  The long segments
+// of a strip take its "a" waves first (with one wave per SIMD, WPB = 4, every
+// wave counts as "a"), so that no SIMD holds two of them while short ones
+// remain.
+template <int WPB>
+__host__ __device__ inline void adj_segment(const AdjGeom& g, int gw, int& tx, int& m0, int& m1) {
+    tx = gw / g.pw;
+    const int r = gw - tx * g.pw;
+    const int base = tx * g.pw;
+    int kA = r, nA = g.pw;
+    bool isA = true;
+    if constexpr (WPB == 8) {
+        const int cb = adj_count_a(base);
+        kA = adj_count_a(base + r) - cb;
+        nA = adj_count_a(base + g.pw) - cb;
+        isA = ((0xA5 >> (gw & 7)) & 1) != 0;
+    }
+    const int kB = r - kA;
+    const int eB = g.nlong > nA ? g.nlong - nA : 0;  // long segments left for "b" waves
+    const int before = (kA < g.nlong ? kA : g.nlong) + (kB < eB ? kB : eB);
+    const bool lng = isA ? kA < g.nlong : kB < eB;
+    m0 = g.len * r + before;
+    m1 = m0 + g.len + (lng ? 1 : 0);
+}
+
+// One face's backward, L the lower cell, R the upper.  XL, XR: the cells'
+// cotangents of the gradient term (times eps, NP) and of the unscaled flux
+// divergence (NM).  lpL / lpR receive the face's share of lambda_phi at L / R;
+// lu the share of lambda_mu at R (-lu at L); lM the share of the mobility
+// cotangent (both cells); gp the unscaled gamma terms K T by pair.
 template <typename R, int NP, int NM>
-__device__ __forceinline__ void face_bwd(const R (&pA)[NP], const R (&pB)[NP], const R (&uA)[NM],
-                                         const R (&uB)[NM], const R (&MA)[NM], const R (&MB)[NM],
-                                         const R (&XA)[NP + NM], const R (&XB)[NP + NM], const AdjCoef<R>& c,
-                                         R (&lpA)[NP], R (&lpB)[NP], R (&luA)[NM], R (&luB)[NM], R (&lM)[NM],
-                                         R (&gp)[3]) {
-    R pb[NP], g[NP], lF[NP], lS[NP], lpb[NP], lg[NP];
+__device__ __forceinline__ void face_bwd(const R (&pL)[NP], const R (&pR)[NP], const R (&uL)[NM],
+                                         const R (&uR)[NM], const R (&ML)[NM], const R (&MR)[NM],
+                                         const R (&XL)[NP + NM], const R (&XR)[NP + NM], const AdjCoef<R>& c,
+                                         R (&lpL)[NP], R (&lpR)[NP], R (&lu)[NM], R (&lM)[NM], R (&gp)[3]) {
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        pb[a] = R(0.5) * (pA[a] + pB[a]);
-        g[a] = (pB[a] - pA[a]) * c.inv_dx;
-        lF[a] = (XA[a] - XB[a]) * c.inv_dx;
-        lS[a] = -R(0.5) * (XA[a] + XB[a]);
-        lpb[a] = R(0);
-        lg[a] = R(0);
+        lpL[a] = R(0);
+        lpR[a] = R(0);
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) gp[q] = R(0);
+    // the pair's term is c4e K T with T = XL_j pR_i - XL_i pR_j + XR_i pL_j - XR_j pL_i
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
         for (int j = i + 1; j < NP; ++j) {
             const int pi = pair_index(i, j);
-            const R qn = pb[i] * g[j] - pb[j] * g[i];
-            const R Gn = R(2) * qn;
-            const R gG = c.gam[pi] * Gn;
-            const R lgG = -lF[i] * pb[j] + lF[j] * pb[i] + lS[i] * g[j] - lS[j] * g[i];
-            lpb[j] = lpb[j] - lF[i] * gG;
-            lpb[i] = lpb[i] + lF[j] * gG;
-            lg[j] = lg[j] + lS[i] * gG;
-            lg[i] = lg[i] - lS[j] * gG;
-            gp[pi] = lgG * Gn;
-            const R lqn = R(2) * c.gam[pi] * lgG;
-            lpb[i] = lpb[i] + lqn * g[j];
-            lg[j] = lg[j] + lqn * pb[i];
-            lpb[j] = lpb[j] - lqn * g[i];
-            lg[i] = lg[i] - lqn * pb[j];
+            const R K = pL[i] * pR[j] - pR[i] * pL[j];
+            const R T = (XL[j] * pR[i] - XL[i] * pR[j]) + (XR[i] * pL[j] - XR[j] * pL[i]);
+            gp[pi] = K * T;
+            const R t = c.c4e[pi] * T, kk = c.c4e[pi] * K;
+            lpL[i] = lpL[i] + (pR[j] * t - XR[j] * kk);
+            lpL[j] = lpL[j] + (XR[i] * kk - pR[i] * t);
+            lpR[i] = lpR[i] + (XL[j] * kk - pL[j] * t);
+            lpR[j] = lpR[j] + (pL[i] * t - XL[i] * kk);
         }
 #pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        lpA[a] = R(0.5) * lpb[a] - lg[a] * c.inv_dx;
-        lpB[a] = R(0.5) * lpb[a] + lg[a] * c.inv_dx;
-    }
-#pragma unroll
     for (int k = 0; k < NM; ++k) {
-        const R lJ = (XA[NP + k] - XB[NP + k]) * c.inv_dx;
-        lM[k] = lJ * R(0.5) * (uB[k] - uA[k]) * c.inv_dx;
-        const R lu = lJ * R(0.5) * (MA[k] + MB[k]) * c.inv_dx;
-        luA[k] = -lu;
-        luB[k] = lu;
+        const R xd = XL[NP + k] - XR[NP + k];
+        lu[k] = xd * (ML[k] + MR[k]);
+        lM[k] = xd * (uR[k] - uL[k]);
     }
 }
 
-// Part A's backward at one cell (phi, mu, h(phi)) from the forward step's gradient term grad
-// and flux divergence divJ there.  l1in = lambda^{n+1} at the cell; Xo
-// receives [lambda of grad_a (NP)][lambda of divJ_k (NM)], lo the cell-local
-// part of lambda^n; par collects the cell's gamma (potential) and tau terms.
+// Part A at one cell: the forward cell update of Sec. 2.1 from (phi, mu, h(phi))
+// and the cell's gradient term gradE (times eps) and unscaled flux divergence
+// divJ, then its backward.  l1in = lambda^{n+1} at the cell.  Xo receives the
+// cotangents of gradE (NP) and divJ (NM), lo the cell-local part of
+// lambda^n; parA collects the unscaled potential gamma terms and the tau term.
 template <typename R, int NP, int NM>
-__device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[NM], const R (&hphi)[NP],
-                                              const R (&grad)[NP], const R (&divJ)[NM], const AdjCoef<R>& c, R ttc,
+__device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[NM], const R (&h0)[NP],
+                                              const R (&gradE)[NP], const R (&divJ)[NM], const AdjCoef<R>& c, R tt,
                                               const R (&l1in)[NP + NM], R (&Xo)[NP + NM], R (&lo)[NP + NM],
-                                              double (&par)[ADJ_NPAR]) {
-    const R tt = ttc;
-    R dmu[NP][NM], psi[NP];
+                                              double (&parA)[ADJ_NPAR], bool own) {
+    // ---- forward --------------------------------------------------------
+    R dmu[NP][NM], cab[NP][NM], psi[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
         R v = c.C[b] + c.s[b] * tt;
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
             dmu[b][k] = mu[k] - c.B[b][k];
-            v = v - c.halfchi[b][k] * dmu[b][k] * dmu[b][k];
+            cab[b][k] = c.chi[b][k] * dmu[b][k];
+            v = v - R(0.5) * cab[b][k] * dmu[b][k];
         }
         psi[b] = v;
     }
-    R P[NP];
+    R d0[NP], P0[NP];
+    dh_parts<R, NP>(phi, d0, P0);
     R psum = R(0);
-    if constexpr (NP == 3) {
-        P[0] = phi[1] * phi[2];
-        P[1] = phi[0] * phi[2];
-        P[2] = phi[0] * phi[1];
-        psum = psi[0] + psi[1] + psi[2];
-    }
+    if constexpr (NP == 3) psum = psi[0] + psi[1] + psi[2];
+    R sq[NP];  // phi_b^2
+#pragma unroll
+    for (int a = 0; a < NP; ++a) sq[a] = phi[a] * phi[a];
+    double lam = 0.0;
     R Rr[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
         R dw = R(0);
 #pragma unroll
         for (int b = 0; b < NP; ++b)
-            if (b != a) dw = dw + c.w18[pair_index(a < b ? a : b, a < b ? b : a)] * phi[b] * phi[b];
+            if (b != a) dw = dw + c.w18e[pair_index(a < b ? a : b, a < b ? b : a)] * sq[b];
         dw = dw * phi[a];
-        R dps = R(6) * psi[a] * (phi[a] * (R(1) - phi[a]));
+        R dps = psi[a] * d0[a];
         if constexpr (NP == 3) {
-            dw = dw + c.gamma3 * P[a];
-            dps = dps + R(2) * P[a] * psum;
+            dw = dw + c.g3e * P0[a];
+            dps = dps + R(2) * P0[a] * psum;
         }
-        Rr[a] = c.eps * grad[a] - c.inv_eps * dw - dps;
+        Rr[a] = gradE[a] - dw - dps;
+        lam = lam + (double)Rr[a];
     }
-    double lam = 0.0;
-#pragma unroll
-    for (int a = 0; a < NP; ++a) lam = lam + (double)Rr[a];
-    lam = lam * (1.0 / NP);
+    lam = lam * (1.0 / NP);  // the Lagrange multiplier in FP64
     R dR[NP], phin[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
         dR[a] = (R)((double)Rr[a] - lam);
         phin[a] = phi[a] + c.kphi * dR[a];
     }
-    R h0[NP], h1[NP], dh0[NP][NP], dh1[NP][NP];
-    R phi0[NP];
-#pragma unroll
-    for (int a = 0; a < NP; ++a) phi0[a] = phi[a];
-#pragma unroll
-    for (int a = 0; a < NP; ++a) h0[a] = hphi[a];
+    R h1[NP], d1[NP], P1[NP];
     h_of<R, NP>(phin, h1);
-    dh_of<R, NP>(phi0, dh0);
-    dh_of<R, NP>(phin, dh1);
+    dh_parts<R, NP>(phin, d1, P1);
+    R dh[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) dh[b] = h1[b] - h0[b];
 
-    // ---- mu update -------------------------------------------------------
-    R lmu[NM], ldiv[NM], lh1[NP], lh0[NP];
+    // ---- mu update: mu + (ktj divJ - sum_b cab_b (h1_b - h0_b)) / sum_b chi_b h1_b
+    R lmu[NM], lh1[NP], lh0[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
         lh1[a] = R(0);
@@ -335,106 +370,91 @@ __device__ __forceinline__ void adj_cell_back(const R (&phi)[NP], const R (&mu)[
     }
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-        R src = R(0), chik = R(0);
+        R src = R(0), chik = R(0), cdh = R(0);
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
-            src = src + (dmu[b][k] * c.chi[b][k]) * (h1[b] - h0[b]);
-            chik = chik + h1[b] * c.chi[b][k];
+            src = src + cab[b][k] * dh[b];
+            chik = chik + c.chi[b][k] * h1[b];
+            cdh = cdh + c.chi[b][k] * dh[b];
         }
-        const R Q = c.dt * divJ[k] - src;
-        const R l1 = l1in[NP + k];
         const R r = fast_rcp(chik);
-        const R lQ = l1 * r;
-        const R lchi = -l1 * Q * r * r;
-        ldiv[k] = c.dt * lQ;
-        const R lsrc = -lQ;
-        R lm = l1;
+        const R dq = (c.ktj * divJ[k] - src) * r;  // the mu increment
+        const R lQ = l1in[NP + k] * r;
+        Xo[NP + k] = c.ktj * lQ;
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
-            const R cab = dmu[b][k] * c.chi[b][k];
-            lh1[b] = lh1[b] + lsrc * cab + lchi * c.chi[b][k];
-            lh0[b] = lh0[b] - lsrc * cab;
-            lm = lm + lsrc * (h1[b] - h0[b]) * c.chi[b][k];
+            const R a = lQ * c.chi[b][k];
+            lh0[b] = lh0[b] + a * dmu[b][k];
+            lh1[b] = lh1[b] - a * (dmu[b][k] + dq);
         }
-        lmu[k] = lm;
+        lmu[k] = l1in[NP + k] - lQ * cdh;
     }
 
     // ---- phi update ------------------------------------------------------
-    R lphin[NP], lphi[NP];
-    R lmean = R(0);
+    R lphin[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) lphin[a] = l1in[a];
+    dh_apply<R, NP>(lh1, d1, P1, lphin);
+    R lsum = R(0), tdot = R(0);
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        R v = l1in[a];
-#pragma unroll
-        for (int b = 0; b < NP; ++b) v = v + lh1[b] * dh1[b][a];
-        lphin[a] = v;
-        lmean = lmean + v;
+        lsum = lsum + lphin[a];
+        tdot = tdot + lphin[a] * dR[a];
     }
-    lmean = lmean * (R(1) / R(NP));
-    R lR[NP];
-    double gtau = 0.0;
+    const R lmean = lsum * (R(1) / R(NP));
+    R lR[NP], lphi[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        R v = lphin[a];
-#pragma unroll
-        for (int b = 0; b < NP; ++b) v = v + lh0[b] * dh0[b][a];
-        lphi[a] = v;
         lR[a] = c.kphi * (lphin[a] - lmean);
-        gtau -= (double)(c.ktau * lphin[a] * dR[a]);
+        lphi[a] = lphin[a];
+        Xo[a] = lR[a];
     }
-    par[9] += gtau;
-    // potential
+    dh_apply<R, NP>(lh0, d0, P0, lphi);
+    // potential: dw_a = phi_a sum_b w18e_ab phi_b^2 + g3e P_a, by pair (i, j)
+    R gpot[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int cc = 0; cc < NP; ++cc)
+    for (int i = 0; i < NP; ++i)
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            R d;
-            if (a == cc) {
-                d = R(0);
-#pragma unroll
-                for (int b = 0; b < NP; ++b)
-                    if (b != cc) d = d + c.w18[pair_index(cc < b ? cc : b, cc < b ? b : cc)] * phi[b] * phi[b];
-            } else {
-                d = R(2) * c.w18[pair_index(cc < a ? cc : a, cc < a ? a : cc)] * phi[cc] * phi[a];
-                if constexpr (NP == 3) d = d + c.gamma3 * phi[3 - a - cc];
-            }
-            lphi[a] = lphi[a] - lR[cc] * c.inv_eps * d;
+        for (int j = i + 1; j < NP; ++j) {
+            const int pi = pair_index(i, j);
+            const R u = lR[i] * phi[j], v = lR[j] * phi[i];
+            const R w = c.w18e[pi];
+            lphi[i] = lphi[i] - (w * phi[j]) * (u + R(2) * v);
+            lphi[j] = lphi[j] - (w * phi[i]) * (v + R(2) * u);
+            gpot[pi] = (phi[i] * phi[j]) * (u + v);
         }
+    if constexpr (NP == 3) {
+        // d(g3e P_a)/dphi_b (b != a) = g3e times the third phase's phi
+        lphi[0] = lphi[0] - c.g3e * (lR[1] * phi[2] + lR[2] * phi[1]);
+        lphi[1] = lphi[1] - c.g3e * (lR[0] * phi[2] + lR[2] * phi[0]);
+        lphi[2] = lphi[2] - c.g3e * (lR[0] * phi[1] + lR[1] * phi[0]);
+    }
+    // driving force dps_a = psi_a d_a + 2 P_a psum, differentiated in phi and psi
+    R sLP = R(0);  // 2 sum_a lR_a P_a
+    if constexpr (NP == 3) {
+        sLP = R(2) * (lR[0] * P0[0] + lR[1] * P0[1] + lR[2] * P0[2]);
+        const R p2 = R(2) * psum;
+        lphi[0] = lphi[0] - p2 * (lR[1] * phi[2] + lR[2] * phi[1]);
+        lphi[1] = lphi[1] - p2 * (lR[0] * phi[2] + lR[2] * phi[0]);
+        lphi[2] = lphi[2] - p2 * (lR[0] * phi[1] + lR[1] * phi[0]);
+    }
 #pragma unroll
-    for (int cc = 0; cc < NP; ++cc)
-#pragma unroll
-        for (int b = 0; b < NP; ++b)
-            if (b != cc)
-                par[pair_index(cc < b ? cc : b, cc < b ? b : cc)] -=
-                    (double)(lR[cc] * c.inv_eps * R(18) * phi[cc] * phi[b] * phi[b]);
-    // driving force sum_b psi_b dh_b/dphi_c, differentiated in phi and psi
-#pragma unroll
-    for (int cc = 0; cc < NP; ++cc)
-#pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            R d = a == cc ? R(6) * psi[cc] * (R(1) - R(2) * phi[cc]) : R(0);
-            if constexpr (NP == 3)
-                if (a != cc) d = R(2) * phi[3 - a - cc] * psum;
-            lphi[a] = lphi[a] - lR[cc] * d;
-        }
+    for (int a = 0; a < NP; ++a) lphi[a] = lphi[a] - lR[a] * psi[a] * (R(6) - R(12) * phi[a]);
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-        R lpsi = R(0);
+        const R lps = lR[b] * d0[b] + sLP;  // minus the cotangent of psi_b
 #pragma unroll
-        for (int cc = 0; cc < NP; ++cc) lpsi = lpsi - lR[cc] * dh0[b][cc];
-#pragma unroll
-        for (int k = 0; k < NM; ++k) lmu[k] = lmu[k] - lpsi * (dmu[b][k] * c.chi[b][k]);
-    }
-
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        Xo[a] = c.eps * lR[a];
-        lo[a] = lphi[a];
+        for (int k = 0; k < NM; ++k) lmu[k] = lmu[k] + lps * cab[b][k];
     }
 #pragma unroll
-    for (int k = 0; k < NM; ++k) {
-        Xo[NP + k] = ldiv[k];
-        lo[NP + k] = lmu[k];
+    for (int a = 0; a < NP; ++a) lo[a] = lphi[a];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) lo[NP + k] = lmu[k];
+    if (own) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < (NP == 3 ? 3 : 1)) parA[q] += (double)gpot[q];
+        parA[9] += (double)tdot;
     }
 }
 
@@ -474,11 +494,8 @@ __device__ __forceinline__ void adj_load(const R* __restrict__ s, int64_t fs, in
 // alone: that part in, lambda^n out; both: lambda^{n+1} in, step n-1's
 // cell-local part out).  The two parts' parameter sums are added B first, as
 // separate launches add them.
-#ifndef MP_ADJ_WAVES_PER_EU
-#define MP_ADJ_WAVES_PER_EU 2
-#endif
 template <typename R, int NP, int NM, bool DOA, bool DOB>
-__global__ void __launch_bounds__(64 * ADJ_WPB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? MP_ADJ_WAVES_PER_EU : 1)))
+__global__ void __launch_bounds__(64 * adj_wpb<R>()) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
 k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restrict__ sA, R* __restrict__ XA,
             R* __restrict__ lam, AdjGeom G, AdjCoef<R> c, double tt_row0, double tt_slope,
             double* __restrict__ acc) {
@@ -494,22 +511,19 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
     // accumulator row; its old values are read now, used at the end
     double rowq = 0.0;
     if (threadIdx.x < ADJ_NPAR) rowq = acc[(size_t)blockIdx.x * ADJ_NPAR + threadIdx.x];
+    constexpr int WPB = adj_wpb<R>();
     const int lane = threadIdx.x & 63;
-    const int ntx = (G.nx + ADJ_W - 1) / ADJ_W;
-    const int nsg = (G.ny + G.seg - 1) / G.seg;
     // wave-uniform by construction
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * ADJ_WPB + (int)(threadIdx.x >> 6));
-    if (wid < ntx * nsg) {
-        const int tx = wid % ntx;
-        const int m0 = (wid / ntx) * G.seg;
-        const int m1 = min(m0 + G.seg, G.ny);
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + (int)(threadIdx.x >> 6));
+    int tx, m0, m1;
+    adj_segment<WPB>(G, wid, tx, m0, m1);
+    if (tx < G.ntx) {
         const int nx = G.nx, ny = G.ny;
         const int64_t fs = G.fs;
         const int cs = tx * ADJ_W - 1 + lane;  // this lane's column
         // loaded column: wrapped, or (zero-flux) the ghost columns -1 and nx as
         // copies of 0 and nx-1; farther out clamped (never owned)
         const int col = G.perx ? wrap(cs, nx) : (cs < 0 ? 0 : (cs >= nx ? nx - 1 : cs));
-        const bool xsame = col == rot_next(col);  // face (lane, lane+1) joins a cell with itself
         const bool own = lane >= 1 && lane <= ADJ_W && cs < nx;
         // row index of rows m0-1 .. m1+1 (selects, no branches: periodic rows
         // lie within one period plus two rows of the grid)
@@ -530,11 +544,10 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
         // rows m and m+1: B's state and cotangents, A's state
         Cell b0, b1, a0, a1;
         R x0[NF], x1[NF];
-        // carries from the face (m-1, m): B's share for the upper cell, A's
-        // forward F, S, J
-        R cpB[NP], cuB[NM], cMB[NM], cF[NP], cS[NP], cJ[NM];
+        // carries from the face (m-1, m): B's shares for the upper cell (phi,
+        // mu, mobility), A's forward Elo and J
+        R cpB[NP], cuB[NM], cMB[NM], cE[NP], cJ[NM];
         {
-            const bool ysame = rowmap(m0 - 1) == rowmap(m0);
             Cell bl, al;
             R xl[NF];
             if constexpr (DOB) {
@@ -554,32 +567,25 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 adj_finish<R, NP, NM>(c, bl);
                 adj_finish<R, NP, NM>(c, b0);
                 adj_finish<R, NP, NM>(c, b1);
-                R lpA[NP], luA[NM];
-                R gp[3];
-                face_bwd<R, NP, NM>(bl.phi, b0.phi, bl.mu, b0.mu, bl.M, b0.M, xl, x0, c, lpA, cpB, luA, cuB, cMB,
-                                    gp);
-                if (ysame) {
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) cpB[a] = R(0);
-#pragma unroll
-                    for (int k = 0; k < NM; ++k) cuB[k] = cMB[k] = R(0);
-                }
+                R lpL[NP], gp[3];
+                face_bwd<R, NP, NM>(bl.phi, b0.phi, bl.mu, b0.mu, bl.M, b0.M, xl, x0, c, lpL, cpB, cuB, cMB, gp);
             }
             if constexpr (DOA) {
                 adj_finish<R, NP, NM>(c, al);
                 adj_finish<R, NP, NM>(c, a0);
                 adj_finish<R, NP, NM>(c, a1);
-                // a face between a cell and its copy has no flux: F, S, J vanish
-                face_fwd<R, NP, NM>(al.phi, a0.phi, al.M, a0.M, al.mu, a0.mu, c, cF, cS, cJ);
+                R Ehi[NP];
+                face_fwd<R, NP, NM>(al.phi, a0.phi, al.M, a0.M, al.mu, a0.mu, c, Ehi, cE, cJ);
             }
         }
 
         // Row m with rows m, m+1 in (b0, b1), (x0, x1), (a0, a1); row m+2 is
         // then loaded into the row-m slots, so that consecutive rows swap the
-        // roles of the two slots instead of copying records.
+        // roles of the two slots instead of copying records.  A face between a
+        // cell and its own copy (a zero-flux ghost) is evaluated like any
+        // other: its terms vanish up to rounding.
         auto row = [&](int m, Cell& b0, Cell& b1, R (&x0)[NF], R (&x1)[NF], Cell& a0, Cell& a1) {
             const int64_t o = (int64_t)m * nx + cs;  // the owned cell (own lanes only)
-            const bool ysame = rowmap(m) == rowmap(m + 1);
             R lv[NF];  // lambda at the cell (used at owned cells only)
             {
                 const int64_t oc = at(m);  // = o at owned cells, in bounds elsewhere
@@ -599,44 +605,11 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 }
 #pragma unroll
                 for (int f = 0; f < NF; ++f) XR[f] = lane_next(x0[f]);
-                R lpx[NP], lpxR[NP], lux[NM], luxR[NM], lMx[NM];
-                R gpx[3];
-                face_bwd<R, NP, NM>(b0.phi, pR, b0.mu, uR, b0.M, MR, x0, XR, c, lpx, lpxR, lux, luxR, lMx, gpx);
-                const R xm = xsame ? R(0) : R(1);  // mask: see the y face below
-#pragma unroll
-                for (int a = 0; a < NP; ++a) {
-                    lpx[a] = lpx[a] * xm;
-                    lpxR[a] = lpxR[a] * xm;
-                }
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    lux[k] = lux[k] * xm;
-                    luxR[k] = luxR[k] * xm;
-                    lMx[k] = lMx[k] * xm;
-                }
-#pragma unroll
-                for (int q = 0; q < 3; ++q) gpx[q] = gpx[q] * xm;
+                R lpx[NP], lpxR[NP], lux[NM], lMx[NM], gpx[3];
+                face_bwd<R, NP, NM>(b0.phi, pR, b0.mu, uR, b0.M, MR, x0, XR, c, lpx, lpxR, lux, lMx, gpx);
                 // y face (m, m+1)
-                R lpy[NP], lpyU[NP], luy[NM], luyU[NM], lMy[NM];
-                R gpy[3];
-                face_bwd<R, NP, NM>(b0.phi, b1.phi, b0.mu, b1.mu, b0.M, b1.M, x0, x1, c, lpy, lpyU, luy, luyU, lMy,
-                                    gpy);
-                // masks multiply (a select would let the compiler branch around the
-                // face, splitting the row body the scheduler interleaves)
-                const R ym = ysame ? R(0) : R(1);
-#pragma unroll
-                for (int a = 0; a < NP; ++a) {
-                    lpy[a] = lpy[a] * ym;
-                    lpyU[a] = lpyU[a] * ym;
-                }
-#pragma unroll
-                for (int k = 0; k < NM; ++k) {
-                    luy[k] = luy[k] * ym;
-                    luyU[k] = luyU[k] * ym;
-                    lMy[k] = lMy[k] * ym;
-                }
-#pragma unroll
-                for (int q = 0; q < 3; ++q) gpy[q] = gpy[q] * ym;
+                R lpy[NP], lpyU[NP], luy[NM], lMy[NM], gpy[3];
+                face_bwd<R, NP, NM>(b0.phi, b1.phi, b0.mu, b1.mu, b0.M, b1.M, x0, x1, c, lpy, lpyU, luy, lMy, gpy);
                 // the cell's four faces: x-hi (own), x-lo (from the previous
                 // lane), y-hi (own), y-lo (carried)
                 R lphi[NP], lmu[NM], lM[NM];
@@ -644,28 +617,28 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 for (int a = 0; a < NP; ++a) lphi[a] = (lpx[a] + lane_prev(lpxR[a])) + (lpy[a] + cpB[a]);
 #pragma unroll
                 for (int k = 0; k < NM; ++k) {
-                    lmu[k] = (lux[k] + lane_prev(luxR[k])) + (luy[k] + cuB[k]);
+                    lmu[k] = (lane_prev(lux[k]) - lux[k]) + (cuB[k] - luy[k]);
                     lM[k] = (lMx[k] + lane_prev(lMx[k])) + (lMy[k] + cMB[k]);
                 }
                 // mobility M_k = sum_b D_bk chi_bk h_b(phi)
-                const R(&hi)[NP] = b0.h;
-                R dhi[NP][NP];
-                dh_of<R, NP>(b0.phi, dhi);
+                R mb[NP], d[NP], P[NP];
+#pragma unroll
+                for (int b = 0; b < NP; ++b) {
+                    R v = R(0);
+#pragma unroll
+                    for (int k = 0; k < NM; ++k) v = v + lM[k] * c.Dchi[b][k];
+                    mb[b] = v;
+                }
+                dh_parts<R, NP>(b0.phi, d, P);
+                dh_apply<R, NP>(mb, d, P, lphi);
                 if (own) {
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) parB[q] += (double)gpx[q] + (double)gpy[q];
+                    for (int q = 0; q < (NP == 3 ? 3 : 1); ++q) parB[q] += (double)(gpx[q] + gpy[q]);
 #pragma unroll
                     for (int k = 0; k < NM; ++k)
 #pragma unroll
-                        for (int b = 0; b < NP; ++b)
-                            parB[3 + 2 * b + k] += (double)(lM[k] * c.chi[b][k] * hi[b]);
+                        for (int b = 0; b < NP; ++b) parB[3 + 2 * b + k] += (double)(lM[k] * b0.h[b]);
                 }
-#pragma unroll
-                for (int k = 0; k < NM; ++k)
-#pragma unroll
-                    for (int b = 0; b < NP; ++b)
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) lphi[a] = lphi[a] + lM[k] * c.Dchi[b][k] * dhi[b][a];
 #pragma unroll
                 for (int a = 0; a < NP; ++a) {
                     lf[a] = lphi[a];
@@ -674,7 +647,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
 #pragma unroll
                 for (int k = 0; k < NM; ++k) {
                     lf[NP + k] = lmu[k];
-                    cuB[k] = luyU[k];
+                    cuB[k] = luy[k];
                     cMB[k] = lMy[k];
                 }
                 // row m's slots are free: row m+2 is fetched into them while
@@ -694,22 +667,18 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                     uR[k] = lane_next(a0.mu[k]);
                     MR[k] = lane_next(a0.M[k]);
                 }
-                R Fx[NP], Sx[NP], Jx[NM], Fy[NP], Sy[NP], Jy[NM];
-                face_fwd<R, NP, NM>(a0.phi, pR, a0.M, MR, a0.mu, uR, c, Fx, Sx, Jx);
-                face_fwd<R, NP, NM>(a0.phi, a1.phi, a0.M, a1.M, a0.mu, a1.mu, c, Fy, Sy, Jy);
-                R grad[NP], divJ[NM];
+                R Ex[NP], Elx[NP], Jx[NM], Ey[NP], Ely[NP], Jy[NM];
+                face_fwd<R, NP, NM>(a0.phi, pR, a0.M, MR, a0.mu, uR, c, Ex, Elx, Jx);
+                face_fwd<R, NP, NM>(a0.phi, a1.phi, a0.M, a1.M, a0.mu, a1.mu, c, Ey, Ely, Jy);
+                R gradE[NP], divJ[NM];
 #pragma unroll
                 for (int a = 0; a < NP; ++a) {
-                    const R Fl = lane_prev(Fx[a]), Sl = lane_prev(Sx[a]);
-                    grad[a] = ((Fx[a] - Fl) * c.inv_dx - R(0.5) * (Sx[a] + Sl)) +
-                              ((Fy[a] - cF[a]) * c.inv_dx - R(0.5) * (Sy[a] + cS[a]));
-                    cF[a] = Fy[a];
-                    cS[a] = Sy[a];
+                    gradE[a] = (Ex[a] - lane_prev(Elx[a])) + (Ey[a] - cE[a]);
+                    cE[a] = Ely[a];
                 }
 #pragma unroll
                 for (int k = 0; k < NM; ++k) {
-                    const R Jl = lane_prev(Jx[k]);
-                    divJ[k] = (Jx[k] - Jl) * c.inv_dx + (Jy[k] - cJ[k]) * c.inv_dx;
+                    divJ[k] = (Jx[k] - lane_prev(Jx[k])) + (Jy[k] - cJ[k]);
                     cJ[k] = Jy[k];
                 }
                 R ph[NP], mu[NM], hA[NP];
@@ -727,14 +696,9 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
                 if constexpr (DOB)
 #pragma unroll
                     for (int f = 0; f < NF; ++f) l1[f] = l1[f] + lf[f];
-                double pc[ADJ_NPAR];
-#pragma unroll
-                for (int q = 0; q < ADJ_NPAR; ++q) pc[q] = 0.0;
-                adj_cell_back<R, NP, NM>(ph, mu, hA, grad, divJ, c, (R)(tt_row0 + tt_slope * (double)m), l1, Xo,
-                                         lo, pc);
+                adj_cell_back<R, NP, NM>(ph, mu, hA, gradE, divJ, c, (R)(tt_row0 + tt_slope * (double)m), l1, Xo,
+                                         lo, parA, own);
                 if (own) {
-#pragma unroll
-                    for (int q = 0; q < ADJ_NPAR; ++q) parA[q] += pc[q];
 #pragma unroll
                     for (int f = 0; f < NF; ++f) {
                         XA[f * fs + o] = Xo[f];
@@ -757,7 +721,7 @@ k_adj_strip(const R* __restrict__ sB, const R* __restrict__ XB, const R* __restr
         }
         if (m < m1) row(m, b0, b1, x0, x1, a0, a1);
     }
-    adj_block_add<DOB, DOA>(parB, parA, rowq, acc);
+    adj_block_add<WPB, DOB, DOA>(parB, parA, c.scB, c.scA, rowq, acc);
 }
 
 // One adjoint launch: part A of a step (which = 0), part B (which = 1) or
@@ -777,8 +741,8 @@ struct AdjLaunch {
 
 template <typename R, int NP, int NM>
 int adj_launch_t(const AdjLaunch& L, const AdjCoef<R>& c, hipStream_t st) {
-    const int nb = adj_blocks(L.g);
-    const dim3 grid(nb), block(64 * ADJ_WPB);
+    const int nb = adj_blocks<adj_wpb<R>()>(L.g);
+    const dim3 grid(nb), block(64 * adj_wpb<R>());
     if (L.which == 0)
         hipLaunchKernelGGL((k_adj_strip<R, NP, NM, true, false>), grid, block, 0, st, nullptr, nullptr,
                            (const R*)L.sA, (R*)L.XA, (R*)L.lam, L.g, c, L.tt_row0, L.tt_slope, L.acc);

@@ -579,27 +579,28 @@ mp::AdjCoef<R> make_adj_coef(const Inst& I) {
     const mp_params& p = I.prm;
     mp::AdjCoef<R> c;
     std::memset(&c, 0, sizeof c);
-    c.inv_dx = (R)(1.0 / I.grid.dx);
-    c.eps = (R)p.eps;
-    c.inv_eps = (R)(1.0 / p.eps);
+    const double dx2 = I.grid.dx * I.grid.dx;
     c.kphi = (R)(p.dt / (p.tau * p.eps));
-    c.dt = (R)p.dt;
-    c.ktau = (R)(p.dt / (p.tau * p.tau * p.eps));
+    c.ktj = (R)(p.dt / (2.0 * dx2));
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
     for (int q = 0; q < 3; ++q) {
-        c.gam[q] = (R)p.gamma[pa[q]][pb[q]];
-        c.w18[q] = (R)(18.0 * p.gamma[pa[q]][pb[q]]);
+        const double g = p.gamma[pa[q]][pb[q]];
+        c.c4e[q] = (R)(2.0 * p.eps * g / dx2);
+        c.w18e[q] = (R)(18.0 * g / p.eps);
+        c.scB[q] = 2.0 * p.eps / dx2;  // d(c4e K T)/d gamma
+        c.scA[q] = -18.0 / p.eps;      // d(-dw)/d gamma per phi_i phi_j (lR_i phi_j + lR_j phi_i)
     }
-    c.gamma3 = (R)p.gamma3;
+    c.g3e = (R)(p.gamma3 / p.eps);
+    c.scA[9] = -p.dt / (p.tau * p.tau * p.eps);  // d phi^{n+1}/d tau per (R - lambda)
     for (int a = 0; a < I.N; ++a) {
         c.C[a] = (R)p.C[a];
         c.s[a] = (R)p.s[a];
         for (int k = 0; k < I.K - 1; ++k) {
             const double chi = 1.0 / (2.0 * p.A[a][k]);
             c.chi[a][k] = (R)chi;
-            c.halfchi[a][k] = (R)(0.5 * chi);
             c.B[a][k] = (R)p.B[a][k];
             c.Dchi[a][k] = (R)(p.D[a][k] * chi);
+            c.scB[3 + 2 * a + k] = chi;  // dM_k/dD_ak per h_a
         }
     }
     return c;
@@ -611,15 +612,33 @@ struct AdjLayout {
     int nrows;
 };
 
+// The adjoint strips are planned for the wave slots of at most kAdjCUs
+// compute units (gfx950 has 256); the accumulator rows are sized for that
+// plan, which has at least as many blocks as the plan of a smaller device.
+constexpr int kAdjCUs = 256;
+
+mp::AdjGeom adj_geom(const Inst& I, int cus, bool fp64) {
+    mp::AdjGeom g;
+    g.nx = (int)I.grid.n[0];
+    g.ny = (int)I.grid.n[1];
+    g.perx = I.grid.bc[0] == MP_BC_PERIODIC;
+    g.pery = I.grid.bc[1] == MP_BC_PERIODIC;
+    g.fs = ncells_of(I.grid);
+    const int c = cus < 1 ? 1 : (cus > kAdjCUs ? kAdjCUs : cus);
+    mp::adj_plan(g, c * (fp64 ? mp::adj_wpb<double>() : mp::adj_wpb<float>()));
+    return g;
+}
+
+int adj_nblocks(const mp::AdjGeom& g, bool fp64) {
+    return fp64 ? mp::adj_blocks<mp::adj_wpb<double>()>(g) : mp::adj_blocks<mp::adj_wpb<float>()>(g);
+}
+
 AdjLayout adj_layout(const mp_state* st, int64_t every) {
     const Inst& I = st->inst[0];
     AdjLayout L;
     L.state = align_up(I.bytes);
-    mp::AdjGeom g;
-    g.nx = (int)I.grid.n[0];
-    g.ny = (int)I.grid.n[1];
-    g.seg = mp::adj_seg(g.nx, g.ny);
-    L.nrows = mp::adj_blocks(g);
+    const bool fp64 = st->precision == MP_FP64;
+    L.nrows = adj_nblocks(adj_geom(I, kAdjCUs, fp64), fp64);
     size_t o = 0;
     L.X0 = o;
     o += L.state;
@@ -1027,13 +1046,14 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
     if (rc) return rc;
     mp::adj_fill(acc, (int64_t)L.nrows * mp::ADJ_NPAR, 0.0, s);
     mp::adj_fill((double*)zctr, 1, 0.0, s);  // all-zero bits: the int64 time-level base 0
+    int dev = 0, cus = 0;
+    rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc == MP_OK) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    if (rc) return rc;
     mp::AdjLaunch A;
-    A.g.nx = (int)I.grid.n[0];
-    A.g.ny = (int)I.grid.n[1];
-    A.g.perx = I.grid.bc[0] == MP_BC_PERIODIC;
-    A.g.pery = I.grid.bc[1] == MP_BC_PERIODIC;
-    A.g.fs = ncells_of(I.grid);
-    A.g.seg = mp::adj_seg(A.g.nx, A.g.ny);
+    A.g = adj_geom(I, cus, st->precision == MP_FP64);
+    if (adj_nblocks(A.g, st->precision == MP_FP64) > L.nrows)
+        return fail(MP_E_STATE, "adjoint: wave plan exceeds the accumulator rows");
     A.nphases = I.N;
     A.nmu = I.K - 1;
     A.lam = lam;
