@@ -138,10 +138,9 @@ __device__ __forceinline__ void face_fwd(const R (&pL)[NP], const R (&pR)[NP], c
     for (int k = 0; k < NM; ++k) J[k] = (ML[k] + MR[k]) * (uR[k] - uL[k]);
 }
 
-// Sum over the 64 lanes of a wave, complete in lane 63: DPP steps in a fixed
-// pattern (pairs, quads, half rows, rows, then rows 0+1 into row 1 and rows
-// 2+3 into row 3, then row 1 into row 3), so the rounding does not depend on
-// timing.  Each step moves the two halves of the double and adds in FP64.
+// A DPP move of a double (both halves, the same pattern), for the quad sums
+// of the parameter terms; the fixed pattern keeps the rounding independent of
+// timing.
 template <unsigned CTRL, unsigned ROWS>
 __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
@@ -149,37 +148,44 @@ __device__ __forceinline__ double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ double wave_sum_last(double x) {
-    x = x + dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
-    x = x + dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
-    x = x + dpp_f64<0x141, 0xF>(x);  // row_half_mirror
-    x = x + dpp_f64<0x140, 0xF>(x);  // row_mirror
-    x = x + dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
-    x = x + dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
-    return x;
-}
 
-// Block-wide sums of the parameter terms, added to this block's accumulator
-// row: the wave sums above, then the wave sums in wave order; B's slots
-// (0..8) first, then A's (0, 1, 2, 9).  rowq: slot q of the row, read by lane
-// q of the block's first wave at the kernel's start (no other block touches
-// the row).
+// Block-wide sums of the parameter terms (each scaled by its factor), added
+// to this block's accumulator row: wave sums, then the wave sums in wave
+// order; B's slots (0..8) first, then A's (0, 1, 2, 9).  rowq: slot q of the
+// row, read by lane q of the block's first wave at the kernel's start (no
+// other block touches the row).
 template <int WPB, bool DOB, bool DOA>
 __device__ __forceinline__ void adj_block_add(const double (&pb)[ADJ_NPAR], const double (&pa)[ADJ_NPAR],
                                               const double (&scB)[ADJ_NPAR], const double (&scA)[ADJ_NPAR],
                                               double rowq, double* __restrict__ acc) {
     constexpr int NB = DOB ? 9 : 0, NA = DOA ? 4 : 0;
     constexpr int SA[4] = {0, 1, 2, 9};
-    __shared__ double red[WPB][NB + NA];
+    constexpr int NQ = NB + NA;
+    __shared__ double red[WPB][NQ];
     const int t = threadIdx.x;
-    double w[NB + NA > 0 ? NB + NA : 1];
+    // Wave sums through an LDS transpose: every lane stores its NQ terms, lane
+    // 4q + j adds terms j, j + 4, ..., j + 60 of value q in that order, and a
+    // quad sum completes value q in lane 4q.  Only the wave itself reads its
+    // slice (rows padded to 65 to spread the banks).
+    __shared__ double tr[WPB][NQ][65];
+    const int lane = t & 63, wv = t >> 6;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) w[q] = wave_sum_last(pb[q] * scB[q]);
+    for (int q = 0; q < NB; ++q) tr[wv][q][lane] = pb[q] * scB[q];
 #pragma unroll
-    for (int q = 0; q < NA; ++q) w[NB + q] = wave_sum_last(pa[SA[q]] * scA[SA[q]]);
-    if ((t & 63) == 63)
+    for (int q = 0; q < NA; ++q) tr[wv][NB + q][lane] = pa[SA[q]] * scA[SA[q]];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int qq = lane >> 2, j = lane & 3;
+    double sq = 0.0;
+    if (qq < NQ) {
+        sq = tr[wv][qq][j];
 #pragma unroll
-        for (int q = 0; q < NB + NA; ++q) red[t >> 6][q] = w[q];
+        for (int i = 1; i < 16; ++i) sq = sq + tr[wv][qq][j + 4 * i];
+    }
+    sq = sq + dpp_f64<0xB1, 0xF>(sq);  // quad_perm [1,0,3,2]
+    sq = sq + dpp_f64<0x4E, 0xF>(sq);  // quad_perm [2,3,0,1]
+    if (j == 0 && qq < NQ) red[wv][qq] = sq;
     __syncthreads();
     if (t < ADJ_NPAR) {
         double r = rowq;
@@ -190,10 +196,10 @@ __device__ __forceinline__ void adj_block_add(const double (&pb)[ADJ_NPAR], cons
             r = r + sum;
         }
         if (DOA && (t < 3 || t == 9)) {
-            const int j = NB + (t < 3 ? t : 3);
-            double sum = red[0][j];
+            const int ja = NB + (t < 3 ? t : 3);
+            double sum = red[0][ja];
 #pragma unroll
-            for (int k = 1; k < WPB; ++k) sum = sum + red[k][j];
+            for (int k = 1; k < WPB; ++k) sum = sum + red[k][ja];
             r = r + sum;
         }
         if ((DOB && t < 9) || (DOA && (t < 3 || t == 9))) acc[(size_t)blockIdx.x * ADJ_NPAR + t] = r;
