@@ -10,12 +10,16 @@
 //     potential and the driving force (with the second derivatives of h).  It
 //     leaves the cotangents X of the cell's gradient term and flux divergence
 //     (for the faces) and the cell-local part of lambda^n;
-//   part B (faces) backpropagates every face (q_n, G_n, the flux F and source
-//     s of the gradient term, the mu flux J) from the two cells' cotangents X
-//     into both cells, then the mobility M_k = sum_a D^a_k chi^a_k h_a of each
-//     cell.
-// A face whose two cells coincide (zero-flux ghost, or a periodic axis one
-// cell long) carries no flux and contributes nothing in either direction.
+//   part B (faces) backpropagates every face (the gradient-term flux and
+//     source, the mu flux J) from the two cells' cotangents X into both
+//     cells, then the mobility M_k = sum_a D^a_k chi^a_k h_a of each cell.
+// Both parts work on the step rearranged into closed forms (see AdjCoef and
+// dh_parts): on a face, pair (i, j) of the gradient term depends on the two
+// cells only through K = phi_i^L phi_j^R - phi_i^R phi_j^L, and for N = 3
+// every derivative of h_b is one diagonal term plus twice the product of the
+// other phases.  A face whose two cells coincide (zero-flux ghost, or a
+// periodic axis one cell long) carries no flux; it is evaluated like any
+// other and its terms vanish up to rounding.
 //
 // Layout of the work: as in the forward strip kernel, one wave per column
 // strip (lanes 1..62 own the strip's columns, lanes 0 and 63 hold the
@@ -24,9 +28,10 @@
 // to the next lane by a lane rotate; a y face by the row below it, which
 // carries the upper cell's share to the next row in registers.  B of step n
 // and A of step n-1 run in one pass (A needs lambda^n only at its own cell).
-// Parameter gradients are accumulated per lane in FP64 over the rows, summed
-// per block in a fixed order and added to that block's own accumulator row,
-// so the result is deterministic.
+// Segments are planned so that every wave of the chip starts at once (two per
+// SIMD in FP32, one in FP64).  Parameter gradients are accumulated per lane in
+// FP64 over the rows, summed per block in a fixed order and added to that
+// block's own accumulator row, so the result is deterministic.
 #pragma once
 
 #include "gp_device.hpp"
