@@ -53,6 +53,11 @@ CASES = {
     "n3k2_noflux_y_T": dict(nx=70, ny=45, N=3, K=2, bc=(0, 1, 0), G=3e-3),
     "n2k3_noflux": dict(nx=50, ny=66, N=2, K=3, bc=(1, 1, 0)),
     "n2k2_ragged": dict(nx=130, ny=20, N=2, K=2, bc=(0, 1, 0)),
+    # faces between a cell and itself: a periodic axis one cell long, a
+    # zero-flux axis one cell long, and zero-flux ghosts all round
+    "n3k3_one_column": dict(nx=1, ny=40, N=3, K=3, bc=(0, 0, 0)),
+    "n3k2_one_row_noflux": dict(nx=40, ny=1, N=3, K=2, bc=(0, 1, 0)),
+    "n2k2_3x2_noflux": dict(nx=3, ny=2, N=2, K=2, bc=(1, 1, 0)),
 }
 
 
