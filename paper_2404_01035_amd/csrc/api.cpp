@@ -8,6 +8,7 @@
 // once the state is bound.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,8 +52,9 @@ struct mp_state {
     hipGraphExec_t gexec[2];  // by starting buffer
     int gend[2];              // buffer current after a replay, by starting buffer
     std::vector<mp::KernelCall> gcalls[2];  // argument records of each graph's nodes, kept alive
-    std::vector<int> item_inst;  // batch work list (host copy) for the current seg
+    std::vector<int> items;  // batch work list (host copy): (instance, local item) pairs
     int nitems;
+    mp::BatchCuts cuts;      // first item of each XCD's slice of the list, and the end
     int batch_blocks;
     // adjoint: a second stream (default priority) that recomputes the next
     // segment while the current one is swept, and the events ordering them
@@ -295,20 +297,82 @@ void drop_graphs(mp_state* st) {
     }
 }
 
+// Work list of a batch: one item per (instance, column strip, row segment),
+// as (instance, local index) pairs, in instance order until arrange_items
+// deals it out.
 void build_items(mp_state* st) {
-    st->item_inst.clear();
+    st->items.clear();
     for (size_t i = 0; i < st->inst.size(); ++i) {
         const Inst& I = st->inst[i];
         const int nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
-        st->item_inst.insert(st->item_inst.end(), (size_t)strips_of(st, I) * nseg, (int)i);
+        const int n = strips_of(st, I) * nseg;
+        for (int l = 0; l < n; ++l) st->items.insert(st->items.end(), {(int)i, l});
     }
-    st->nitems = (int)st->item_inst.size();
+    st->nitems = (int)(st->items.size() / 2);
+    for (int x = 0; x <= 8; ++x) st->cuts.c[x] = (int)((long long)st->nitems * x / 8);
+}
+
+// Estimated cost of one item: its rows (plus the two-step halo rows) times
+// the strip's width in cells per lane times the work of a cell for (N, K).
+double item_cost(const mp_state* st, const Inst& I, int local) {
+    const int ntx = strips_of(st, I);
+    const int m0 = (local / ntx) * st->seg;
+    const int rows = (int)std::min<int64_t>(st->seg, I.grid.n[1] - m0);
+    const int N = I.N, nm = I.K - 1, pairs = N * (N - 1) / 2;
+    return (rows + 2.0) * vec_of(st, I) * (30.0 + 40.0 * N + 20.0 * nm + 14.0 * pairs + 6.0 * nm);
+}
+
+// Deal the work list to the persistent kernel, whose waves of XCD x take the
+// items cuts[x] .. cuts[x+1]-1 with stride wpx (its waves per XCD): whole
+// instances go to the XCD slices largest first, each to the slice with the
+// least work so far (an instance's strips then share one XCD's L2); inside a
+// slice the items are sorted by cost, largest first, and laid out in rounds
+// of wpx, every other round reversed, so that the waves' shares come out even.
+// Deterministic; the results do not depend on the order.
+void arrange_items(mp_state* st, int wpx) {
+    const int ninst = (int)st->inst.size();
+    std::vector<std::vector<int>> by_inst(ninst);
+    std::vector<double> icost(ninst, 0.0);
+    for (int it = 0; it < st->nitems; ++it) {
+        const int i = st->items[2 * it], l = st->items[2 * it + 1];
+        by_inst[i].push_back(l);
+        icost[i] += item_cost(st, st->inst[i], l);
+    }
+    std::vector<int> order(ninst);
+    for (int i = 0; i < ninst; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return icost[a] > icost[b]; });
+    std::vector<int> slice_of(ninst);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i : order) {
+        int x = 0;
+        for (int y = 1; y < 8; ++y)
+            if (load[y] < load[x]) x = y;
+        slice_of[i] = x;
+        load[x] += icost[i];
+    }
+    std::vector<int> out;
+    out.reserve(st->items.size());
+    for (int x = 0; x < 8; ++x) {
+        st->cuts.c[x] = (int)(out.size() / 2);
+        std::vector<std::pair<double, std::pair<int, int>>> v;
+        for (int i = 0; i < ninst; ++i)
+            if (slice_of[i] == x)
+                for (int l : by_inst[i]) v.push_back({item_cost(st, st->inst[i], l), {i, l}});
+        std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        const int w = wpx < 1 ? 1 : wpx;
+        for (size_t r0 = 0; r0 < v.size(); r0 += w) {
+            const size_t r1 = std::min(v.size(), r0 + (size_t)w);
+            if ((r0 / w) % 2 == 1) std::reverse(v.begin() + r0, v.begin() + r1);
+            for (size_t k = r0; k < r1; ++k) out.insert(out.end(), {v[k].second.first, v[k].second.second});
+        }
+    }
+    st->cuts.c[8] = (int)(out.size() / 2);
+    st->items.swap(out);
 }
 
 template <typename R>
 int upload_table(mp_state* st) {
     std::vector<mp::InstDesc<R>> tab(st->inst.size());
-    int item0 = 0;
     for (size_t i = 0; i < st->inst.size(); ++i) {
         const Inst& I = st->inst[i];
         mp::InstDesc<R>& d = tab[i];
@@ -320,8 +384,6 @@ int upload_table(mp_state* st) {
         d.vec = vec_of(st, I);
         d.seg = st->seg;
         d.nseg = (int)((I.grid.n[1] + st->seg - 1) / st->seg);
-        d.item0 = item0;
-        item0 += d.ntx * d.nseg;
         d.off = (int64_t)(I.off_bytes / sizeof(R));
         temperature_law(I, d.tb0, d.tdn, d.tslope);
         d.c = make_coef<R>(I);
@@ -330,9 +392,12 @@ int upload_table(mp_state* st) {
     int rc = hip_check(hipMemcpy(ws + ws_table_off(st), tab.data(),
                                  sizeof(mp::InstDesc<R>) * tab.size(), hipMemcpyHostToDevice),
                        "instance table upload");
-    if (rc) return rc;
-    return hip_check(hipMemcpy(ws + ws_items_off(st), st->item_inst.data(),
-                               sizeof(int) * st->item_inst.size(), hipMemcpyHostToDevice),
+    return rc;
+}
+
+int upload_items(mp_state* st) {
+    return hip_check(hipMemcpy((char*)st->ws + ws_items_off(st), st->items.data(), sizeof(int) * st->items.size(),
+                               hipMemcpyHostToDevice),
                      "work list upload");
 }
 
@@ -362,7 +427,9 @@ int choose_batch_blocks(mp_state* st) {
     nb = (nb + 7) / 8 * 8;
     if (nb < 8) nb = 8;
     st->batch_blocks = (int)nb;
-    return MP_OK;
+    build_items(st);
+    arrange_items(st, (int)(nb / 8) * mp::BATCH_WPB_HOST);
+    return upload_items(st);
 }
 
 int sync_batch(mp_state* st) {
@@ -384,8 +451,8 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fus
         L.in = st->buf[from];
         L.out = st->buf[1 - from];
         L.table = (const char*)st->ws + ws_table_off(st);
-        L.item_inst = (const int*)((const char*)st->ws + ws_items_off(st));
-        L.nitems = st->nitems;
+        L.items = (const int*)((const char*)st->ws + ws_items_off(st));
+        L.cuts = st->cuts;
         L.potential = st->potential;
         L.aniso = st->aniso ? 1 : 0;
         L.vmax = vec_cap(st);
@@ -746,7 +813,7 @@ size_t mp_state_bytes(const mp_state* st) {
 
 size_t mp_workspace_bytes(const mp_state* st) {
     if (!st) return 0;
-    return ws_items_off(st) + align_up(sizeof(int) * items_capacity(st));
+    return ws_items_off(st) + align_up(2 * sizeof(int) * items_capacity(st));
 }
 
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace) {

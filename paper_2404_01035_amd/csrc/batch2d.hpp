@@ -2,14 +2,15 @@
 //
 // The work list holds one item per (instance, column strip, row segment),
 // strips W2X_LANES_OUT lanes wide for both the one-step and the two-step
-// variant (so the list does not depend on the steps per launch),
-// instance by instance; item_inst[i] names the instance of item i and the
-// instance table (InstDesc) carries its grid, sizes, coefficients, state
-// offset and temperature law.  The grid is sized to what stays resident; each
-// wave walks items with a fixed stride (deterministic), inside the contiguous
-// slice of the list given to its XCD, so a strip's neighbours tend to share an
-// L2.  Each item runs the same strip function as the single-grid kernel, so a
-// batched instance is stepped bit for bit like a single one.
+// variant (so the list does not depend on the steps per launch), as
+// (instance, local index) pairs; the instance table (InstDesc) carries each
+// instance's grid, sizes, coefficients, state offset and temperature law.
+// The grid is sized to what stays resident; the waves of XCD x walk their
+// slice cuts[x] .. cuts[x+1]-1 of the list with a fixed stride.  The host
+// deals whole instances to the slices by cost (a strip's neighbours share an
+// L2) and orders each slice so that the waves' shares are even.  Each item
+// runs the same strip function as the single-grid kernel, so a batched
+// instance is stepped bit for bit like a single one, in any order.
 #pragma once
 
 #include "step2d.hpp"
@@ -66,20 +67,19 @@ __device__ __forceinline__ void run_item(const R* src, R* dst, const InstDesc<R>
 template <typename R, bool ANISO, bool OBST, int VMAX, int FUSE>
 __global__ void __launch_bounds__(64 * BATCH_WPB) __attribute__((amdgpu_waves_per_eu(2)))
 k_batch2d(const R* __restrict__ in, R* __restrict__ out, const InstDesc<R>* __restrict__ tab,
-          const int* __restrict__ item_inst, int nitems, const int64_t* __restrict__ stepctr,
-          int kstep) {
+          const int* __restrict__ items, BatchCuts cuts, const int64_t* __restrict__ stepctr, int kstep) {
     const int nb = gridDim.x;  // a multiple of 8
     const int b = blockIdx.x;
     const int xcd = b % 8;
     const int wpx = (nb / 8) * BATCH_WPB;  // waves per XCD
     const int rank = __builtin_amdgcn_readfirstlane((b / 8) * BATCH_WPB + (threadIdx.x >> 6));
-    const int lo = (int)((long long)nitems * xcd / 8);
-    const int hi = (int)((long long)nitems * (xcd + 1) / 8);
+    const int lo = cuts.c[xcd];
+    const int hi = cuts.c[xcd + 1];
     const int64_t n = *stepctr + kstep;
     for (int it = lo + rank; it < hi; it += wpx) {
-        const int inst = __builtin_amdgcn_readfirstlane(item_inst[it]);
+        const int inst = __builtin_amdgcn_readfirstlane(items[2 * it]);
+        const int local = __builtin_amdgcn_readfirstlane(items[2 * it + 1]);
         const InstDesc<R>& d = tab[inst];
-        const int local = it - d.item0;
         const int tx = local % d.ntx;
         const int m0 = (local / d.ntx) * d.seg;
         const int m1 = min(m0 + d.seg, d.g.ny);
@@ -112,8 +112,8 @@ int call_batch(const BatchLaunch& L, KernelCall& k) {
     k.arg((const R*)L.in);
     k.arg((R*)L.out);
     k.arg((const InstDesc<R>*)L.table);
-    k.arg(L.item_inst);
-    k.arg(L.nitems);
+    k.arg(L.items);
+    k.arg(L.cuts);
     k.arg(L.stepctr);
     k.arg(L.kstep);
     return MP_OK;

@@ -83,20 +83,25 @@ template <typename R>
 struct InstDesc {
     Geom g;
     int32_t np, nm;
-    int32_t ntx, nseg, seg, item0;  // work items item0 .. item0 + ntx*nseg - 1
+    int32_t ntx, nseg, seg;         // work items: ntx strips by nseg row segments of seg rows
     int32_t vec;                    // cells per lane of the strip kernel (vec2d_width)
     int64_t off;                    // element offset of the instance's state
     double tb0, tdn, tslope;        // T - Te = tb0 + tdn * n + tslope * j
     Coef<R> c;
 };
 
+// First work item of each XCD's slice of a batch's work list, and its end.
+struct BatchCuts {
+    int32_t c[9];
+};
+
 // One launch of the batched 2D kernel.
 struct BatchLaunch {
     const void* in;
     void* out;
-    const void* table;     // InstDesc<R>[ninst] in device memory
-    const int* item_inst;  // instance of each work item, in device memory
-    int nitems;
+    const void* table;  // InstDesc<R>[ninst] in device memory
+    const int* items;   // work list in device memory: (instance, local item) pairs
+    BatchCuts cuts;     // XCD x takes items cuts.c[x] .. cuts.c[x+1]-1
     int potential, aniso;
     int vmax;  // widest cells-per-lane among the items (1 or 2)
     int fuse;  // steps per launch (1 or 2)
