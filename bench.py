@@ -47,16 +47,16 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "7ec502b052f31cb7",
+    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "d4d559c2b9160bda",
                "bytes": (2.0 * 384880.5 + 664923.9) * 1024},
-    "c2_f32": {"tile": [256, 16, 1], "fuse": 2, "src": "d028610263df93c7",
+    "c2_f32": {"tile": [256, 16, 1], "fuse": 2, "src": "6ea397db48e1e19e",
                "bytes": (2.0 * 217042.8 + 334471.2) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "10d9e2e85f262709",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "78d914c69f777301",
            "bytes": (2.0 * 1094183.8 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "7e47a0a7c2447af7",
-           "bytes": (2.0 * 743790.9 + 1247184.4) * 1024},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "0beac1fdd800090e",
+           "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5")
