@@ -47,10 +47,10 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 32, 1], "fuse": 2, "src": "d4d559c2b9160bda",
-               "bytes": (2.0 * 384880.5 + 664923.9) * 1024},
-    "c2_f32": {"tile": [256, 16, 1], "fuse": 2, "src": "6ea397db48e1e19e",
-               "bytes": (2.0 * 217042.8 + 334471.2) * 1024},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "d4d559c2b9160bda",
+               "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "6ea397db48e1e19e",
+               "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "78d914c69f777301",
            "bytes": (2.0 * 1094183.8 + 1572864.0) * 1024},

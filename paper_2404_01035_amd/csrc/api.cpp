@@ -577,10 +577,12 @@ void init_state(mp_state* st) {
     } else {
         // two steps per launch (the state crosses HBM once per two steps);
         // tiles measured best for it on 4096^2: one cell per lane (FP64 at 3
-        // waves per SIMD without spills, FP32 at 5), 32- / 16-row segments
+        // waves per SIMD without spills, FP32 at 5), 31- / 14-row segments
+        // (their wave counts come out just under a whole number of the
+        // chip's resident wave slots, so the last wave round is nearly full)
         st->fuse = 2;
         st->bx = 256;
-        st->seg = st->precision == MP_FP64 ? 32 : 16;
+        st->seg = st->precision == MP_FP64 ? 31 : 14;
         st->vec = 1;
     }
 }

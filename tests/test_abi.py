@@ -35,7 +35,7 @@ def test_create_and_query_without_gpu():
         assert abi.mp_current(st) == (0, 0)
         abi.mp_set_step(st, 7, 1)
         assert abi.mp_current(st) == (1, 7)
-        assert abi.mp_get_tile(st) == (256, 32, 1)
+        assert abi.mp_get_tile(st) == (256, 31, 1)
         abi.mp_set_tile(st, 128, 16)
         assert abi.mp_get_tile(st) == (128, 16, 1)
         abi.mp_set_tile(st, 0, 0, -1)

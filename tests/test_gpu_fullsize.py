@@ -15,11 +15,11 @@ from paper_2404_01035_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _windows_2d(ny, nx, rng, tile_x=64, seg=16):
+def _windows_2d(ny, nx, rng, tile_x=62, seg=16):
     w = [((0, 0), (8, 70)), ((ny - 8, nx - 70), (ny, nx)), ((56, 1000), (72, 1100)),
          ((0, nx - 40), (6, nx)), ((ny - 5, 0), (ny, 40))]
-    for k in (1, 2, 31):  # wave-tile borders (62-wide strips) and segment borders
-        x = 62 * k
+    for k in (1, 2, 31):  # strip borders (tile_x columns) and segment borders (seg rows)
+        x = tile_x * k
         y = seg * k
         w.append(((y - 3, x - 4), (y + 3, x + 4)))
     for _ in range(4):
@@ -63,7 +63,8 @@ def test_c2_full_grid_sampled_step(precision, tol):
     s.step(1)
     phi1, mu1 = _state(s)
     s.close()
-    w = _windows_2d(4096, 4096, np.random.default_rng(3))
+    # one step per launch: 62-column strips, the default 31 (FP64) / 14 (FP32) row segments
+    w = _windows_2d(4096, 4096, np.random.default_rng(3), seg=31 if precision == "f64" else 14)
     worst = _check_windows(p, phi0, mu0, phi1, mu1, n0, w, tol)
     print(f"C2 {precision}: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}")
 
@@ -87,7 +88,8 @@ def test_c2_full_grid_sampled_two_step_launch(precision, tol):
     phi2, mu2 = _state(s)
     s.close()
     phi1, mu1 = gp.run(phi0.astype(np.float64), mu0.astype(np.float64), n0, 1, p)
-    w = _windows_2d(4096, 4096, np.random.default_rng(7), seg=32)
+    # the default two-step tiles: 60-column strips, 31 (FP64) / 14 (FP32) row segments
+    w = _windows_2d(4096, 4096, np.random.default_rng(7), tile_x=60, seg=31 if precision == "f64" else 14)
     worst = _check_windows(p, phi1, mu1, phi2, mu2, n0 + 1, w, tol)
     print(f"C2 {precision} two-step launch: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}")
 
