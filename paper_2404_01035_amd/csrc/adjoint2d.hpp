@@ -491,13 +491,6 @@ __device__ __forceinline__ void adj_finish(const AdjCoef<R>& c, ACell<R, NP, NM>
     mob_of<R, NP, NM>(q.h, c, q.M);
 }
 
-template <typename R, int NP, int NM>
-__device__ __forceinline__ void adj_load(const R* __restrict__ s, int64_t fs, int64_t o, const AdjCoef<R>& c,
-                                         ACell<R, NP, NM>& q) {
-    adj_fetch<R, NP, NM>(s, fs, o, q);
-    adj_finish<R, NP, NM>(c, q);
-}
-
 // Adjoint strip kernel.  DOB: part B of step n (sB = s^n, XB = part A's
 // cotangents of step n); DOA: part A at sA (step n-1 when fused, else the
 // step itself), writing its cotangents to XA.  lam: lambda, updated in place

@@ -447,8 +447,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     const bool writes = lane >= 2 && lane <= W2X_LANES_OUT + 1 && cs < nx;
     const bool top = !pery && m0 == 0;   // step-1 row -1 is a copy of row 0
     const bool bot = !pery && m1 == ny;  // step-1 row ny is a copy of row ny-1
-    const int r_first = top ? 0 : m0 - 1;
-    const int r_last = bot ? ny - 1 : m1;  // step-1 rows computed: r_first .. r_last
+    const int r_first = top ? 0 : m0 - 1;  // step-1 rows computed: r_first .. (bot ? ny - 1 : m1)
 
     auto rowmap = [&](int s) { return pery ? wrap(s, ny) : gmap(s, ny, false); };
     auto load = [&](int s, RawT& r) {
