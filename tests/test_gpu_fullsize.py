@@ -179,3 +179,76 @@ def test_c4_full_batch_sampled_instances():
         # FP32 state against the FP64 oracle over four steps
         assert np.max(np.abs(got[i][0] - of)) <= 1e-5, i
         assert np.max(np.abs(got[i][1] - om)) <= 1e-4, i
+
+
+def _c5_adjoint(precision, target64, nsteps=2000, every=100):
+    """The benchmark's C5 configuration: loss 1/2 |phi^N - phi*|^2 at nominal theta,
+    checkpoints every 100 steps; returns (lambda^0, gradients, loss)."""
+    import torch
+
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu, _ = inputs.config_c5(precision=precision)
+    s = Solver(p)
+    try:
+        s.load(phi, mu)
+        ckpt = s.checkpoint_buffer(nsteps, every)
+        s.step_ckpt(nsteps, every, ckpt)
+        cur = s.current().double()
+        lam = torch.zeros_like(cur)
+        lam[: p.nphases] = cur[: p.nphases] - torch.from_numpy(target64).to(cur.device)
+        loss = 0.5 * float((lam[: p.nphases] ** 2).sum())
+        lam0, g = s.adjoint(lam, ckpt, nsteps, every, 0)
+        return lam0.double().cpu().numpy(), g, loss
+    finally:
+        s.close()
+
+
+def _c5_loss64(theta, target64, nsteps=2000):
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu, _ = inputs.config_c5(precision="f64")
+    s = Solver(inputs.theta_into(p, theta))
+    try:
+        s.load(phi, mu)
+        s.step(nsteps)
+        f, _ = s.fields()
+        return 0.5 * float(np.sum((f - target64) ** 2))
+    finally:
+        s.close()
+
+
+def test_c5_full_size_adjoint():
+    """C5 at full size in the benchmark's configuration (512^2, 2000 steps,
+    checkpoints every 100), where the oracle cannot go: the FP64 adjoint's tau and
+    gamma_01 gradients against central differences of the FP64 loss, and the
+    FP32 adjoint (the benchmarked one) against the FP64 adjoint."""
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu, theta_star = inputs.config_c5(precision="f64")
+    s = Solver(inputs.theta_into(p, theta_star))
+    s.load(phi, mu)
+    s.step(2000)
+    target64, _ = s.fields()
+    s.close()
+    lam64, g64, loss64 = _c5_adjoint("f64", target64)
+    lam32, g32, loss32 = _c5_adjoint("f32", target64)
+    nominal = [1.0] * 6
+    for idx, key in ((5, "tau"), (0, "gamma01")):
+        h = 1e-4
+        up = list(nominal)
+        dn = list(nominal)
+        up[idx] += h
+        dn[idx] -= h
+        fd = (_c5_loss64(up, target64) - _c5_loss64(dn, target64)) / (2 * h)
+        rel = abs(g64[key] - fd) / abs(fd)
+        print(f"C5 FP64 adjoint {key}: {g64[key]:.10g} vs central difference {fd:.10g} (rel {rel:.2e})")
+        assert rel <= 1e-6, (key, g64[key], fd)  # measured 2e-8 (tau), 8e-9 (gamma01)
+    worst = 0.0
+    for key in ("gamma01", "gamma02", "gamma12", "D20", "D21", "tau"):
+        rel = abs(g32[key] - g64[key]) / max(abs(g64[key]), 1e-3 * abs(g64["tau"]))
+        worst = max(worst, rel)
+    lam_rel = float(np.max(np.abs(lam32 - lam64)) / np.max(np.abs(lam64)))
+    print(f"C5 FP32 vs FP64 adjoint: worst gradient rel {worst:.2e}, lambda^0 rel {lam_rel:.2e}, "
+          f"loss {loss32:.6g} vs {loss64:.6g}")
+    assert worst <= 1e-4 and lam_rel <= 1e-3  # measured 2.6e-6 and 7.1e-5
