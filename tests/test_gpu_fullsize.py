@@ -252,3 +252,24 @@ def test_c5_full_size_adjoint():
     print(f"C5 FP32 vs FP64 adjoint: worst gradient rel {worst:.2e}, lambda^0 rel {lam_rel:.2e}, "
           f"loss {loss32:.6g} vs {loss64:.6g}")
     assert worst <= 1e-4 and lam_rel <= 1e-3  # measured 2.6e-6 and 7.1e-5
+
+
+def test_c2_full_grid_fp32_against_fp64():
+    """The FP32 path's error per field on the full C2 grid after 2000 steps, against
+    the FP64 path (pinned to the oracle): phi within 1e-4."""
+    from paper_2404_01035_amd.solver import Solver
+
+    out = {}
+    for precision in ("f64", "f32"):
+        p, phi, mu = inputs.config_c2(precision=precision)
+        s = Solver(p)
+        s.load(phi, mu)
+        del phi, mu
+        s.step(2000)
+        out[precision] = s.fields()
+        s.close()
+    ephi = float(np.max(np.abs(out["f32"][0] - out["f64"][0])))
+    emu = float(np.max(np.abs(out["f32"][1] - out["f64"][1])))
+    print(f"C2 4096^2, 2000 steps: FP32 - FP64 max |dphi| {ephi:.2e}, max |dmu| {emu:.2e}")
+    assert ephi <= 1e-4  # measured 3.5e-5
+    assert emu <= 1e-4   # measured 1.2e-5
