@@ -30,6 +30,10 @@ Diffusion potentials, Eq. Mu_explicit_temperature with j_at = 0:
     value the mean of the two cells; chi_k = sum_a h_a(phi^{n+1}) chi^a_k.
   * B^a is temperature independent, so the dT/dt term vanishes.
 
+With the anti-trapping current of Eq. jatr (``step_antitrapping``, kept apart
+from ``step``), the mu update divides dt div(M grad mu - j_at) - sum_a c^a dh_a
+instead; ``antitrapping_faces`` states how the current is placed on faces.
+
 Boundaries: periodic (wrap) or zero-flux (ghost = mirror of the edge cell),
 per axis; corners by composition.  Temperature T(y, t) = T0 + G (y - y0 - V t)
 with t = n dt and y = j dx.
@@ -652,3 +656,103 @@ def adjoint_run(phi0, mu0, n0, nsteps, p, lphiN, lmuN):
         tot["D"] += g["D"]
         tot["tau"] += g["tau"]
     return lphi, lmu, tot
+
+
+# ----------------------------------------------------------------------------
+# Anti-trapping current (Eq. jatr).  Not part of ``step``: ``step_antitrapping``
+# is the step with it.
+# ----------------------------------------------------------------------------
+
+AT_TINY = 1e-30  # |grad phi|^2 at or below this: the unit normal is taken as zero
+
+
+def at_prefactor(phi0, p):
+    """The scalar in front of (c^a - c^liq) dphi_a/dt n_a in Eq. jatr.
+
+    Multi-well potential: eps / (2 sqrt 2).  Double obstacle:
+    pi eps phi0 (1 - h(phi0)) / (4 sqrt(phi0 (1 - phi0))) with the two-phase
+    h(phi0) = phi0^2 (3 - 2 phi0); it tends to 0 at phi0 = 0 and 1 and is taken
+    as 0 outside (0, 1).
+    """
+    if p.potential != "obstacle":
+        return p.eps / (2.0 * np.sqrt(2.0)) + 0.0 * phi0
+    inside = (phi0 > 0.0) & (phi0 < 1.0)
+    f = np.where(inside, phi0, 0.5)
+    val = np.pi * p.eps * f * (1.0 - f * f * (3.0 - 2.0 * f)) / (4.0 * np.sqrt(f * (1.0 - f)))
+    return np.where(inside, val, 0.0)
+
+
+def _face_gradient(Pf, p, a):
+    """Gradient of padded fields on the faces normal to axis a, one array per
+    spatial axis in ``spatial_axes`` order: the normal component is the
+    difference of the two cells, a tangential one the mean of the two cells'
+    central differences (the same stencil as the anisotropic face term)."""
+    nd = p.dim
+    comps = []
+    for b, _ in spatial_axes(p):
+        if b == a:
+            comps.append((_sub(Pf, nd, {a: slice(1, None)}) - _sub(Pf, nd, {a: slice(0, -1)})) / p.dx)
+        else:
+            tl = (_sub(Pf, nd, {a: slice(0, -1), b: slice(2, None)})
+                  - _sub(Pf, nd, {a: slice(0, -1), b: slice(0, -2)})) / (2.0 * p.dx)
+            tr = (_sub(Pf, nd, {a: slice(1, None), b: slice(2, None)})
+                  - _sub(Pf, nd, {a: slice(1, None), b: slice(0, -2)})) / (2.0 * p.dx)
+            comps.append(0.5 * (tl + tr))
+    return comps
+
+
+def antitrapping_faces(phi, phin, mu, p):
+    """Per axis a: (a, j) with j the normal component of j_at on the faces normal
+    to a, shape (K-1, ..., n_a + 1, ...).
+
+    Eq. jatr summed over the solid phases (the liquid is the last phase):
+        j_k = sum_{a < N-1} P(phi_a) (c^a_k - c^liq_k) dphi_a/dt n_a . e_axis (-n_a . n_liq),
+    n = grad phi / |grad phi| from phi^n.  On a face, dphi_a/dt = (phi^{n+1} - phi^n)/dt,
+    c^a(mu^n) and the prefactor's phi are means of the two cells; the gradient
+    is ``_face_gradient``.
+    """
+    nd = p.dim
+    N = p.nphases
+    liq = N - 1
+    Pphi, Pphin, Pmu = pad(phi, p), pad(phin, p), pad(mu, p)
+    Pc = c_phase(Pmu, p)
+    out = []
+    for a, _ in spatial_axes(p):
+        def mean(F):
+            return 0.5 * (_sub(F, nd, {a: slice(0, -1)}) + _sub(F, nd, {a: slice(1, None)}))
+
+        grads = _face_gradient(Pphi, p, a)
+        norm2 = sum(g * g for g in grads)
+        ok = norm2 > AT_TINY
+        inv = np.where(ok, 1.0 / np.sqrt(np.where(ok, norm2, 1.0)), 0.0)
+        units = [g * inv for g in grads]
+        normal = [i for i, (b, _) in enumerate(spatial_axes(p)) if b == a][0]
+        rate = (mean(Pphin) - mean(Pphi)) / p.dt
+        pbar = mean(Pphi)
+        cbar = mean(Pc)
+        j = [0.0 * pbar[0] for _ in range(p.nmu)]
+        for al in range(N - 1):
+            weight = -sum(u[al] * u[liq] for u in units)
+            common = at_prefactor(pbar[al], p) * rate[al] * units[normal][al] * weight
+            for k in range(p.nmu):
+                j[k] = j[k] + common * (cbar[al][k] - cbar[liq][k])
+        out.append((a, np.stack(j)))
+    return out
+
+
+def step_antitrapping(phi, mu, n, p):
+    """One step with the anti-trapping current in Eq. Mu_explicit_temperature:
+        mu^{n+1} = mu^n + (dt div(M grad mu - j_at) - sum_a c^a(mu^n) [h_a(phi^{n+1}) - h_a(phi^n)]) / chi.
+    phi^{n+1} is that of ``step``; j_at is ``antitrapping_faces`` of (phi^n, phi^{n+1}, mu^n)."""
+    phin, mun = step(phi, mu, n, p)
+    chi = chi_phase(p)
+    h1 = h(phin)
+    out = []
+    div = [0.0 * mu[k] for k in range(p.nmu)]
+    for a, j in antitrapping_faces(phi, phin, mu, p):
+        for k in range(p.nmu):
+            div[k] = div[k] + (_along(j[k], a, slice(1, None)) - _along(j[k], a, slice(0, -1))) / p.dx
+    for k in range(p.nmu):
+        chik = sum(h1[b] * chi[b][k] for b in range(p.nphases))
+        out.append(mun[k] - p.dt * div[k] / chik)
+    return phin, np.stack(out)
