@@ -47,15 +47,15 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "1ec4f7169dcb528b",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "6e2eeb30c1003a7d",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a6871722a0e2921f",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "54c91d5dca69cf03",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "bb53016f8f2e6021",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "81371fb33d083eef",
            "bytes": (2.0 * 1094183.8 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "23d8d25ae3a694bc",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "112d348f54601712",
            "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"

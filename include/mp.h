@@ -190,6 +190,24 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
 int mp_set_fusion(mp_state* st, int steps);
 int mp_get_fusion(const mp_state* st, int* steps);
 
+/* Anti-trapping current of Eq. jatr (Sec. 2.1) in the mu update of Eq.
+ * Mu_explicit_temperature: on = 1 switches it on, 0 off (the default).  With
+ * it, mu^{n+1} = mu^n + (dt div(M grad mu - j_at) - sum_a c^a dh_a) / chi, where
+ * j_at = sum over the solid phases a (the liquid is the last phase) of
+ * P (c^a - c^liq) dphi_a/dt n_a (-n_a . n_liq), n = grad phi / |grad phi| of
+ * phi^n, P = eps / (2 sqrt 2) for the multi-well potential and
+ * pi eps phi (1 - h(phi)) / (4 sqrt(phi (1 - phi))) for the obstacle one.  On a
+ * face: the normal gradient is the difference of its two cells, a tangential
+ * one the mean of their central differences; dphi/dt = (phi^{n+1} - phi^n)/dt,
+ * c^a(mu^n) and the prefactor's phi are means of the two cells; a unit normal
+ * with |grad phi|^2 <= 1e-30 is zero.  mp_step then runs one step per launch
+ * (each step is followed by a correction kernel that reads states n and n+1),
+ * ignores mp_set_fusion and mp_set_graph, and mp_adjoint returns MP_E_STATE.
+ * Host only.  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0 or 1, a 3D grid),
+ * MP_E_STATE (a batched state). */
+int mp_set_antitrapping(mp_state* st, int on);
+int mp_get_antitrapping(const mp_state* st, int* on);
+
 /* Replay steps as a HIP graph: chunk = steps per graph (even, >= 2), or 0 to
  * launch kernel by kernel (the default).  The graph is built explicitly (no
  * stream capture), so any stream works, the null stream included; it is

@@ -33,6 +33,7 @@ EXPORTS = [
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
     "mp_tune_candidates", "mp_tune", "mp_set_fusion", "mp_get_fusion",
+    "mp_set_antitrapping", "mp_get_antitrapping",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -129,6 +130,10 @@ def lib():
         L.mp_set_fusion.argtypes = [vp, C.c_int]
         L.mp_get_fusion.restype = C.c_int
         L.mp_get_fusion.argtypes = [vp, C.POINTER(C.c_int)]
+        L.mp_set_antitrapping.restype = C.c_int
+        L.mp_set_antitrapping.argtypes = [vp, C.c_int]
+        L.mp_get_antitrapping.restype = C.c_int
+        L.mp_get_antitrapping.argtypes = [vp, C.POINTER(C.c_int)]
         L.mp_tune_candidates.restype = C.c_int
         L.mp_tune_candidates.argtypes = [vp, C.POINTER(C.c_int32), C.c_int]
         L.mp_tune.restype = C.c_int
@@ -276,6 +281,16 @@ def mp_get_fusion(st) -> int:
     v = C.c_int()
     _check(lib().mp_get_fusion(st, C.byref(v)))
     return v.value
+
+
+def mp_set_antitrapping(st, on: bool):
+    _check(lib().mp_set_antitrapping(st, 1 if on else 0))
+
+
+def mp_get_antitrapping(st) -> bool:
+    v = C.c_int()
+    _check(lib().mp_get_antitrapping(st, C.byref(v)))
+    return bool(v.value)
 
 
 def mp_set_graph(st, chunk: int):

@@ -48,6 +48,7 @@ struct mp_state {
     int64_t step;
     int bx, seg, vec;  // vec: cap on cells per lane of the 2D strips (-1: none)
     int fuse;  // steps per launch of the step kernel: 1, or 2 (2D single grid)
+    bool antitrap;  // anti-trapping current on (2D single grid; one step per launch, no graphs)
     int graph_chunk;
     hipGraphExec_t gexec[2];  // by starting buffer
     int gend[2];              // buffer current after a replay, by starting buffer
@@ -221,6 +222,25 @@ mp::Coef<R> make_coef(const Inst& I) {
             c.Dt[a][k] = (R)(p.D[a][k] * chi * dtf);
         }
     }
+    return c;
+}
+
+template <typename R>
+mp::AtCoef<R> make_at_coef(const Inst& I) {
+    const mp_params& p = I.prm;
+    mp::AtCoef<R> c;
+    std::memset(&c, 0, sizeof c);
+    c.prefw = (R)(p.eps / (2.0 * std::sqrt(2.0)));
+    c.prefo = (R)(M_PI * p.eps / 4.0);
+    c.obstacle = p.potential == MP_OBSTACLE ? 1 : 0;
+    c.rdx = (R)(1.0 / I.grid.dx);
+    c.rdt = (R)(1.0 / p.dt);
+    c.dt = (R)p.dt;
+    for (int a = 0; a < I.N; ++a)
+        for (int k = 0; k < I.K - 1; ++k) {
+            c.chi[a][k] = (R)(1.0 / (2.0 * p.A[a][k]));
+            c.B[a][k] = (R)p.B[a][k];
+        }
     return c;
 }
 
@@ -551,6 +571,7 @@ void init_state(mp_state* st) {
     st->step = 0;
     st->graph_chunk = 0;
     st->fuse = 1;
+    st->antitrap = false;
     st->gexec[0] = st->gexec[1] = nullptr;
     st->gend[0] = 0;
     st->gend[1] = 1;
@@ -731,6 +752,7 @@ AdjLayout adj_layout(const mp_state* st, int64_t every) {
 
 int adj_supported(const mp_state* st) {
     if (st->batch) return fail(MP_E_STATE, "adjoint: batched states are not supported");
+    if (st->antitrap) return fail(MP_E_STATE, "adjoint: the anti-trapping current is not supported");
     const Inst& I = st->inst[0];
     if (I.grid.dim != 2) return fail(MP_E_PARAM, "adjoint: 2D grids only");
     if (I.prm.potential != MP_WELL) return fail(MP_E_PARAM, "adjoint: the obstacle projection is not differentiable");
@@ -748,6 +770,41 @@ int call_step_f32(const StepLaunch& L, const Coef<float>& c, KernelCall& k) {
     return L.dim == 3 ? call_step_dim<float, true>(L, c, k) : call_step_dim<float, false>(L, c, k);
 }
 }  // namespace mp
+
+namespace {
+
+// Steps with the anti-trapping current: each step is a one-step launch of the
+// step kernel followed by the correction of its mu^{n+1} from states n and n+1.
+int step_antitrapping(mp_state* st, int64_t nsteps, hipStream_t s) {
+    const Inst& I = st->inst[0];
+    mp::AtLaunch A;
+    A.g = make_geom(I.grid);
+    A.nphases = I.N;
+    A.nmu = I.K - 1;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        mp::KernelCall k;
+        int rc = make_step_call(st, (int)i, st->cur, k, 1);
+        if (rc) return fail(rc, "no kernel instance for this configuration");
+        rc = launch(k, s);
+        if (rc) return rc;
+        A.prev = st->buf[st->cur];
+        A.next = st->buf[1 - st->cur];
+        rc = st->precision == MP_FP64 ? mp::at_launch<double>(A, make_at_coef<double>(I), s)
+                                      : mp::at_launch<float>(A, make_at_coef<float>(I), s);
+        if (rc) return fail(rc, "anti-trapping kernel launch failed");
+        st->cur = 1 - st->cur;
+    }
+    if (nsteps > 0) {
+        mp::KernelCall k;
+        mp::call_advance(dev_ctr(st), nsteps, k);
+        const int rc = launch(k, s);
+        if (rc) return rc;
+        st->step += nsteps;
+    }
+    return ok();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -847,6 +904,7 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_step before mp_bind");
     if (nsteps < 0) return fail(MP_E_PARAM, "nsteps must be >= 0");
     hipStream_t s = (hipStream_t)stream;
+    if (st->antitrap) return step_antitrapping(st, nsteps, s);
     int64_t left = nsteps;
     const int C = st->graph_chunk;
     if (C > 0) {
@@ -1043,6 +1101,22 @@ int mp_get_fusion(const mp_state* st, int* steps) {
     return ok();
 }
 
+int mp_set_antitrapping(mp_state* st, int on) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (on != 0 && on != 1) return fail(MP_E_PARAM, "on must be 0 or 1 (got %d)", on);
+    if (on && st->batch) return fail(MP_E_STATE, "anti-trapping current: batched states are not supported");
+    if (on && st->inst[0].grid.dim != 2) return fail(MP_E_PARAM, "anti-trapping current: 2D grids only");
+    drop_graphs(st);
+    st->antitrap = on == 1;
+    return ok();
+}
+
+int mp_get_antitrapping(const mp_state* st, int* on) {
+    if (!st || !on) return fail(MP_E_NULLPTR, "state or on is NULL");
+    *on = st->antitrap ? 1 : 0;
+    return ok();
+}
+
 int mp_set_graph(mp_state* st, int chunk) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (chunk < 0 || (chunk > 0 && (chunk < 2 || chunk % 2)))
@@ -1093,10 +1167,11 @@ int mp_step_ckpt(mp_state* st, int64_t nsteps, int64_t every, void* ckpt_buf, vo
 
 int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,
                const void* lam_final, void* lam_initial, double* grad_theta, void* work, void* stream) {
-    if (!st || !ckpt_buf || !lam_final || !lam_initial || !grad_theta || !work)
-        return fail(MP_E_NULLPTR, "mp_adjoint: NULL argument");
+    if (!st) return fail(MP_E_NULLPTR, "mp_adjoint: state is NULL");
     int rc = adj_supported(st);
     if (rc) return rc;
+    if (!ckpt_buf || !lam_final || !lam_initial || !grad_theta || !work)
+        return fail(MP_E_NULLPTR, "mp_adjoint: NULL argument");
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_adjoint before mp_bind");
     if (nsteps < 0 || every < 1 || n0 < 0) return fail(MP_E_PARAM, "nsteps, n0 must be >= 0 and every >= 1");
     if (((uintptr_t)work | (uintptr_t)ckpt_buf) & (kAlign - 1))

@@ -151,6 +151,28 @@ constexpr int W2X_LANES_OUT_HOST = 60;  // the two-step strip keeps two halo lan
 constexpr int BATCH_WPB_HOST = 4;
 inline int batch_waves_per_block_host() { return BATCH_WPB_HOST; }
 
+// Anti-trapping current of Eq. jatr, applied to the mu^{n+1} of a finished 2D
+// single-grid step (antitrap2d.hpp).
+template <typename R>
+struct AtCoef {
+    R prefw;       // multi-well prefactor eps / (2 sqrt 2)
+    R prefo;       // obstacle prefactor scale pi eps / 4
+    int obstacle;  // 1: obstacle prefactor, 0: multi-well
+    R rdx, rdt, dt;
+    R chi[3][2];   // 1 / (2 A^a_k)
+    R B[3][2];
+};
+
+struct AtLaunch {
+    const void* prev;  // state n: phi^n, mu^n
+    void* next;        // state n+1: phi^{n+1} read, mu^{n+1} corrected in place
+    Geom g;
+    int nphases, nmu;
+};
+
+template <typename R>
+int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s);
+
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
                 const DiagCoef& dc, double* partials, double* result, hipStream_t s);
 int diag_blocks(int64_t ncells);

@@ -70,6 +70,10 @@ class Solver:
         """Steps per kernel launch (1, or 2 for 2D grids: the state crosses HBM once per two steps)."""
         abi.mp_set_fusion(self.st, steps)
 
+    def set_antitrapping(self, on: bool = True):
+        """Anti-trapping current of Eq. jatr in the mu update (2D; one step per launch, no graphs)."""
+        abi.mp_set_antitrapping(self.st, on)
+
     def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:
         """Pick the fastest tile for this workload (cached on disk); the state is unchanged."""
         from . import autotune

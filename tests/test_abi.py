@@ -285,3 +285,41 @@ def test_fusion_setting_validation_without_gpu():
         assert abi.mp_get_fusion(bst) == 2
     finally:
         abi.mp_destroy(bst)
+
+
+def test_antitrapping_switch_validation_without_gpu():
+    import ctypes as C
+    L = abi.lib()
+    p, _, _ = inputs.config_c1()
+    st = abi.mp_create(p)
+    try:
+        assert abi.mp_get_antitrapping(st) is False  # off by default
+        abi.mp_set_antitrapping(st, True)
+        assert abi.mp_get_antitrapping(st) is True
+        for bad in (-1, 2):
+            assert L.mp_set_antitrapping(st, bad) == abi.MP_E_PARAM
+        assert abi.mp_get_antitrapping(st) is True
+        # the adjoint refuses it before looking at its buffers
+        g = (C.c_double * 10)()
+        rc = L.mp_adjoint(st, None, 10, 5, 0, None, None, g, None, None)
+        assert rc == abi.MP_E_STATE and "anti-trapping" in abi.mp_last_error()
+        abi.mp_set_antitrapping(st, False)
+        assert abi.mp_get_antitrapping(st) is False
+    finally:
+        abi.mp_destroy(st)
+    assert L.mp_set_antitrapping(None, 1) == abi.MP_E_NULLPTR
+    assert L.mp_get_antitrapping(None, None) == abi.MP_E_NULLPTR
+    st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
+    try:
+        with pytest.raises(abi.MPError, match="2D"):
+            abi.mp_set_antitrapping(st, True)
+        abi.mp_set_antitrapping(st, False)  # off is always accepted
+    finally:
+        abi.mp_destroy(st)
+    bst = abi.mp_create_batch([m[0] for m in inputs.config_c4(ninst=2, side=(64, 70))])
+    try:
+        with pytest.raises(abi.MPError) as ei:
+            abi.mp_set_antitrapping(bst, True)
+        assert ei.value.code == abi.MP_E_STATE
+    finally:
+        abi.mp_destroy(bst)

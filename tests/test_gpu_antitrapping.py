@@ -1,0 +1,130 @@
+"""GPU parity of the step with the anti-trapping current (Eq. jatr) against the
+oracle's ``step_antitrapping``, on the same seeded inputs, through the C ABI.
+
+Sizes span several 64 x 4 correction tiles with ragged tails; the cases mix
+both potentials, N = 2 and 3, K = 2 and 3, periodic and zero-flux axes and a
+temperature gradient.  FP64 is held to 1e-10 (the bar of the plain step),
+FP32 to 1e-4.  The switch's interplay with the launch options (two steps per
+launch, graphs) and the adjoint's refusal are checked too.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle import gp
+from paper_2404_01035_amd import inputs
+from test_gpu_parity import errs, nuclei_case, variant
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_run_at(phi, mu, n0, nsteps, p):
+    for i in range(nsteps):
+        phi, mu = gp.step_antitrapping(phi, mu, n0 + i, p)
+    return phi, mu
+
+
+def run_gpu_at(p, phi, mu, nsteps, step0=0, on=True, fuse=None, graph=None):
+    from paper_2404_01035_amd.solver import Solver
+
+    s = Solver(p)
+    try:
+        if fuse:
+            s.set_fusion(fuse)
+        if graph:
+            s.set_graph(graph)
+        s.set_antitrapping(on)
+        s.load(phi, mu, step0)
+        s.step(nsteps)
+        return s.fields()
+    finally:
+        s.close()
+
+
+CASES = {
+    # name: (params kwargs, steps)
+    "n2k2_periodic": (dict(dim=2, N=2, K=2, n=(130, 50, 1), bc=(0, 0, 0)), 120),
+    "n3k3_ragged_noflux_y_gradient": (dict(dim=2, N=3, K=3, n=(197, 70, 1), bc=(0, 1, 0), G=2e-3), 120),
+    "n3k2_noflux": (dict(dim=2, N=3, K=2, n=(77, 66, 1), bc=(1, 1, 0)), 120),
+    "n2k3_noflux_x": (dict(dim=2, N=2, K=3, n=(65, 37, 1), bc=(1, 0, 0)), 120),
+    "n3k3_obstacle": (dict(dim=2, N=3, K=3, n=(90, 61, 1), bc=(0, 1, 0), potential="obstacle"), 100),
+    "n2k2_obstacle_aniso": (dict(dim=2, N=2, K=2, n=(64, 64, 1), bc=(0, 0, 0), potential="obstacle",
+                                 delta=0.02), 100),
+    "n3k3_aniso": (dict(dim=2, N=3, K=3, n=(150, 40, 1), bc=(0, 0, 0), delta=0.03), 100),
+}
+
+
+def _case(name, precision="f64"):
+    kw, steps = CASES[name]
+    p = variant(seed=zlib.crc32(name.encode()) % 1000, precision=precision, **kw)
+    phi, mu = nuclei_case(p, seed=9, count=6, radius=min(p.n[:p.dim]) / 4 + 2)
+    return p, phi, mu, steps
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp64_with_antitrapping_matches_oracle(name):
+    p, phi, mu, steps = _case(name)
+    print(f"case {name}: grid {p.n[:2]}, {steps} steps", flush=True)
+    f, m = run_gpu_at(p, phi, mu, steps, step0=5)
+    of, om = oracle_run_at(phi, mu, 5, steps, p)
+    _, pm = gp.run(phi, mu, 5, steps, p)
+    print(f"{name}: phi {errs(f, of):.3e} mu {errs(m, om):.3e}; the current moves mu by {errs(om, pm):.3e}")
+    assert errs(f, of) <= 1e-10
+    assert errs(m, om) <= 1e-10
+    assert errs(om, pm) > 1e-6  # the case exercises the current
+
+
+def test_c1_fp64_with_antitrapping_500_steps():
+    p, phi, mu = inputs.config_c1(seed=0)
+    f, m = run_gpu_at(p, phi, mu, 500)
+    of, om = oracle_run_at(phi, mu, 0, 500, p)
+    print(f"C1 FP64 500 steps with the current: phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
+    assert errs(f, of) <= 1e-10
+    assert errs(m, om) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["n2k2_periodic", "n3k3_ragged_noflux_y_gradient"])
+def test_fp32_with_antitrapping_matches_oracle(name):
+    p, phi, mu, steps = _case(name, precision="f32")
+    f, m = run_gpu_at(p, phi, mu, steps, step0=5)
+    of, om = oracle_run_at(phi, mu, 5, steps, p)
+    print(f"{name} FP32: phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
+    assert errs(f, of) <= 1e-4
+    assert errs(m, om) <= 1e-4
+
+
+def test_switch_overrides_fusion_and_graphs_and_switches_back():
+    p, phi, mu, _ = _case("n3k2_noflux")
+    steps = 37
+    ref = run_gpu_at(p, phi, mu, steps)
+    for fuse, graph in ((2, None), (1, 8), (2, 4)):
+        f, m = run_gpu_at(p, phi, mu, steps, fuse=fuse, graph=graph)
+        assert np.array_equal(f, ref[0]) and np.array_equal(m, ref[1]), (fuse, graph)
+    # off again: the plain step, bitwise
+    from test_gpu_parity import run_gpu
+
+    plain = run_gpu(p, phi, mu, steps, fuse=2)
+    f, m = run_gpu_at(p, phi, mu, steps, on=False, fuse=2)
+    assert np.array_equal(f, plain[0]) and np.array_equal(m, plain[1])
+
+
+def test_adjoint_refuses_the_antitrapping_current():
+    import torch
+
+    from paper_2404_01035_amd import abi
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu = inputs.config_c1(seed=0)
+    s = Solver(p)
+    try:
+        s.set_antitrapping(True)
+        assert abi.mp_get_antitrapping(s.st)
+        s.load(phi, mu)
+        ckpt = s.checkpoint_buffer(4, 2)
+        s.step_ckpt(4, 2, ckpt)
+        lam = torch.zeros(p.nfields * p.ncells, dtype=s.dtype).cuda()
+        with pytest.raises(Exception, match="anti-trapping"):
+            s.adjoint(lam, ckpt, 4, 2, 0)
+    finally:
+        s.close()
