@@ -57,9 +57,14 @@ TRAFFIC = {
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "112d348f54601712",
            "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
+    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
+    "at_f64": {"tile": [62, 32, 1], "fuse": 1, "src": "1193675644a0c2bb",
+               "bytes": (2.0 * 781748.9 + 270959.5) * 1024},
+    "at_f32": {"tile": [62, 32, 1], "fuse": 1, "src": "1193675644a0c2bb",
+               "bytes": (2.0 * 414506.9 + 139716.8) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
-ALL_LEGS = ("c2", "c3", "c4", "c5")
+ALL_LEGS = ("c2", "c3", "c4", "c5", "at")
 
 
 def parse():
@@ -97,7 +102,11 @@ LEG_SOURCES = {
     "c2_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
     "c3": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
     "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
+    "at_f64": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
+    "at_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
 }
+# The correction kernel's fixed strip shape (columns written per wave, rows per wave, cells per lane).
+AT_TILE = [62, 32, 1]
 
 
 def source_hash(leg):
@@ -266,6 +275,47 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
         "steps_per_launch": fuse,
         "algorithmic_bytes_per_launch": fuse * p.ncells * bpc,
         "tile": {"bx": used[0], "seg": used[1], "vec": used[2], "source": source},
+        "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
+    }
+
+
+def leg_at(precision, n, steps, warmup):
+    """The C2 step with the anti-trapping current: one step per launch followed by the
+    correction kernel.  The same run without the current (one step per launch) is
+    timed first; the difference is the correction kernel's time per step."""
+    from paper_2404_01035_amd.solver import Solver
+    from paper_2404_01035_amd import inputs
+
+    p, phi, mu = inputs.config_c2(precision=precision, n=(n, n, 1))
+    s = Solver(p)
+    s.load(phi, mu)
+    del phi, mu
+    s.set_fusion(1)
+    s.step(warmup)
+    with Timer() as t0:
+        s.step(steps)
+    s.set_antitrapping(True)
+    s.step(warmup)
+    with Timer() as t1:
+        s.step(steps)
+    d = s.diagnostics()
+    s.close()
+    elem = 8 if precision == "f64" else 4
+    nm = p.ncomp - 1
+    # phi^n, phi^{n+1}, mu^n and mu^{n+1} read, mu^{n+1} written, once per cell
+    bpc = (2 * p.nphases + 3 * nm) * elem
+    ms_plain, ms_at = t0.ms / steps, t1.ms / steps
+    ms_corr = ms_at - ms_plain
+    return {
+        "value": p.ncells * steps / (t1.ms * 1e-3),
+        "unit": "cell-updates/s",
+        "ms_per_step": ms_at,
+        "ms_per_step_without_current": ms_plain,
+        "correction_ms_per_step": ms_corr,
+        "correction_bytes_per_cell": bpc,
+        # the correction kernel: time = step with the current - step without
+        "roofline": roofline(p.ncells * bpc, ms_corr, traffic_of(f"at_{precision}", AT_TILE, 1))
+        if ms_corr > 0 else None,
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
@@ -481,6 +531,13 @@ def main():
     if "c5" in legs:
         log("checkpointed forward + adjoint FP32")
         out["adjoint"] = leg_c5(a.adjoint_steps)
+    if "at" in legs:
+        at_steps = min(a.steps, 200)
+        log(f"anti-trapping current {a.n}x{a.n}, FP64 and FP32, {at_steps} steps")
+        out["antitrapping"] = {"workload": f"2D {a.n}x{a.n} directional eutectic with the anti-trapping "
+                                           "current, one step per launch + correction",
+                               "f64": leg_at("f64", a.n, at_steps, 5),
+                               "f32": leg_at("f32", a.n, at_steps, 5)}
     out["copy_bandwidth"] = copy_bandwidth(a.n)
     if not a.no_cpu:
         log("CPU oracle sample")

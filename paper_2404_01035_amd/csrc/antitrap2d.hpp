@@ -15,7 +15,8 @@
 //   j_k = sum over solids a of P(phi_a) (c^a_k - c^liq_k) dphi_a/dt
 //         n_a . e_n (-n_a . n_liq), the liquid being the last phase.
 // Ghost cells (periodic wrap or zero-flux mirror) come from index arithmetic.
-// One thread per cell; the 3 x 3 neighbourhood is read through the caches.
+// One wave per strip of 62 columns by 32 rows: each field is read once per cell
+// (plus the halo) and each face is evaluated once.
 #pragma once
 
 #include "mp_internal.hpp"
@@ -70,88 +71,143 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
     }
 }
 
+constexpr int AT_LANES_OUT = 62;  // written lanes per wave (lanes 0 and 63 hold the x halo)
+constexpr int AT_SEG = 32;        // rows per wave
+constexpr int AT_WAVES = 4;       // waves per block
+
+// One row of one wave: every field of the row's cell at this lane.
 template <typename R, int NP, int NM>
-__global__ void __launch_bounds__(256) k_antitrap2d(const R* __restrict__ prev, R* __restrict__ next, Geom g,
-                                                     AtCoef<R> c) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int jrow = (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    if (i >= g.nx || jrow >= g.ny) return;
+struct AtRow {
+    R p[NP];   // phi^n
+    R q[NP];   // phi^{n+1}
+    R u[NM];   // mu^n
+    R m[NM];   // mu^{n+1} of the step without the current
+    R tx[NP];  // central difference of phi^n along x, / (2 dx)
+};
+
+// Loads of one row (issued early: the march keeps one row in flight ahead of the one it uses).
+template <typename R, int NP, int NM>
+__device__ inline void at_fetch(const R* __restrict__ prev, const R* __restrict__ next, const Geom& g, int col,
+                                int row, AtRow<R, NP, NM>& r) {
+    const int64_t o = (int64_t)row * g.nx + col;
     const int64_t fs = g.fstride;
-    const int xs[3] = {at_wrap(i - 1, g.nx, g.bcx), i, at_wrap(i + 1, g.nx, g.bcx)};
-    const int ys[3] = {at_wrap(jrow - 1, g.ny, g.bcy), jrow, at_wrap(jrow + 1, g.ny, g.bcy)};
-    // phi^n on the 3 x 3 neighbourhood, phi^{n+1} and mu^n on the cell and its 4 neighbours
-    R P[3][3][NP];
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-            for (int a = 0; a < NP; ++a) P[dy][dx][a] = prev[a * fs + (int64_t)ys[dy] * g.nx + xs[dx]];
-    // (a corner ghost is the per-axis maps composed, as on the ghost-padded grid)
-    R Q[5][NP], U[5][NM];  // centre, x-, x+, y-, y+
-    const int qx[5] = {xs[1], xs[0], xs[2], xs[1], xs[1]};
-    const int qy[5] = {ys[1], ys[1], ys[1], ys[0], ys[2]};
-#pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        const int64_t o = (int64_t)qy[s] * g.nx + qx[s];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Q[s][a] = next[a * fs + o];
-#pragma unroll
-        for (int k = 0; k < NM; ++k) U[s][k] = prev[(NP + k) * fs + o];
-    }
-    // central differences / (2 dx): along y for the cells of row jrow (x faces),
-    // along x for the cells of column i (y faces)
-    const R h2 = R(0.5) * c.rdx;
-    R ty[3][NP], tx[3][NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            ty[d][a] = (P[2][d][a] - P[0][d][a]) * h2;  // cell (xs[d], jrow)
-            tx[d][a] = (P[d][2][a] - P[d][0][a]) * h2;  // cell (i, ys[d])
-        }
+        r.p[a] = prev[a * fs + o];
+        r.q[a] = next[a * fs + o];
     }
-    R jxl[NM] = {}, jxh[NM] = {}, jyl[NM] = {}, jyh[NM] = {};
-    at_face<R, NP, NM>(P[1][0], P[1][1], ty[0], ty[1], Q[1], Q[0], U[1], U[0], c, jxl);
-    at_face<R, NP, NM>(P[1][1], P[1][2], ty[1], ty[2], Q[0], Q[2], U[0], U[2], c, jxh);
-    at_face<R, NP, NM>(P[0][1], P[1][1], tx[0], tx[1], Q[3], Q[0], U[3], U[0], c, jyl);
-    at_face<R, NP, NM>(P[1][1], P[2][1], tx[1], tx[2], Q[0], Q[4], U[0], U[4], c, jyh);
-    // chi_k(phi^{n+1}) = sum_b h_b chi^b_k, h of Eq. hphi
-    R hb[NP];
-#pragma unroll
-    for (int b = 0; b < NP; ++b) {
-        const R f = Q[0][b];
-        R cross = R(0);
-        if constexpr (NP == 3) cross = Q[0][(b + 1) % 3] * Q[0][(b + 2) % 3];
-        hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
-    }
-    const int64_t oc = (int64_t)jrow * g.nx + i;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-        R chik = R(0);
+        r.u[k] = prev[(NP + k) * fs + o];
+        r.m[k] = next[(NP + k) * fs + o];
+    }
+}
+
+// The row's central differences along x, from the neighbouring lanes.
+template <typename R, int NP, int NM>
+__device__ inline void at_finish(AtRow<R, NP, NM>& r, R h2) {
 #pragma unroll
-        for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
-        const R div = (jxh[k] - jxl[k]) * c.rdx + (jyh[k] - jyl[k]) * c.rdx;
-        R* m = next + (NP + k) * fs + oc;
-        *m = *m - c.dt * div / chik;
+    for (int a = 0; a < NP; ++a) r.tx[a] = (__shfl_down(r.p[a], 1) - __shfl_up(r.p[a], 1)) * h2;
+}
+
+// A wave owns columns x0 .. x0 + 61 (lanes 1..62; lane 0 and 63 are the x
+// neighbours) over rows y0 .. y0 + AT_SEG - 1, and walks them top-down with
+// rows y - 1, y, y + 1 in registers.  The x face below a lane (between its
+// cell and the one to its left) is evaluated by that lane, the one above is
+// its right neighbour's; the y face below a row is the one above the row
+// before it.  Each face is evaluated once, with the operands and operations
+// of the per-face definition, whichever cell it serves.
+template <typename R, int NP, int NM>
+__global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restrict__ prev, R* __restrict__ next,
+                                                              Geom g, AtCoef<R> c, int nstrips, int nitems) {
+    const int item = (int)blockIdx.x * AT_WAVES + (int)(threadIdx.x >> 6);
+    if (item >= nitems) return;  // whole waves only
+    const int lane = (int)(threadIdx.x & 63);
+    const int strip = item % nstrips;
+    const int y0 = (item / nstrips) * AT_SEG;
+    const int y1 = y0 + AT_SEG < g.ny ? y0 + AT_SEG : g.ny;
+    const int craw = strip * AT_LANES_OUT - 1 + lane;  // -1 .. nx + 62
+    const bool own = lane >= 1 && lane <= AT_LANES_OUT && craw < g.nx;
+    const int col = at_wrap(craw < g.nx ? craw : g.nx, g.nx, g.bcx);  // lanes past the right ghost repeat it
+    const R h2 = R(0.5) * c.rdx;
+    AtRow<R, NP, NM> lo, mid, hi, ahead;
+    at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(y0 - 1, g.ny, g.bcy), lo);
+    at_fetch<R, NP, NM>(prev, next, g, col, y0, mid);
+    at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(y0 + 1, g.ny, g.bcy), hi);
+    at_finish<R, NP, NM>(lo, h2);
+    at_finish<R, NP, NM>(mid, h2);
+    at_finish<R, NP, NM>(hi, h2);
+    // y face between rows y0 - 1 and y0
+    R jylo[NM] = {};
+    at_face<R, NP, NM>(lo.p, mid.p, lo.tx, mid.tx, lo.q, mid.q, lo.u, mid.u, c, jylo);
+    for (int y = y0; y < y1; ++y) {
+        // row y + 2, needed by the next pass (past the grid's ghost row it is
+        // a clamped or wrapped row that goes unused)
+        const int ya = y + 2 < g.ny + 1 ? y + 2 : g.ny;
+        at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(ya, g.ny, g.bcy), ahead);
+        // x face between this lane's cell and the left neighbour, on row y
+        R ty[NP], tyl[NP], pl[NP], ql[NP], ul[NM];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            ty[a] = (hi.p[a] - lo.p[a]) * h2;
+            tyl[a] = __shfl_up(ty[a], 1);
+            pl[a] = __shfl_up(mid.p[a], 1);
+            ql[a] = __shfl_up(mid.q[a], 1);
+        }
+#pragma unroll
+        for (int k = 0; k < NM; ++k) ul[k] = __shfl_up(mid.u[k], 1);
+        R jxl[NM] = {};
+        at_face<R, NP, NM>(pl, mid.p, tyl, ty, ql, mid.q, ul, mid.u, c, jxl);
+        R jyhi[NM] = {};
+        at_face<R, NP, NM>(mid.p, hi.p, mid.tx, hi.tx, mid.q, hi.q, mid.u, hi.u, c, jyhi);
+        // chi_k(phi^{n+1}) = sum_b h_b chi^b_k, h of Eq. hphi
+        R hb[NP];
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            const R f = mid.q[b];
+            R cross = R(0);
+            if constexpr (NP == 3) cross = mid.q[(b + 1) % 3] * mid.q[(b + 2) % 3];
+            hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
+        }
+        const int64_t oc = (int64_t)y * g.nx + col;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            const R jxh = __shfl_down(jxl[k], 1);
+            if (own) {
+                R chik = R(0);
+#pragma unroll
+                for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
+                const R div = (jxh - jxl[k]) * c.rdx + (jyhi[k] - jylo[k]) * c.rdx;
+                next[(NP + k) * g.fstride + oc] = mid.m[k] - c.dt * div / chik;
+            }
+            jylo[k] = jyhi[k];
+        }
+        at_finish<R, NP, NM>(ahead, h2);
+        lo = mid;
+        mid = hi;
+        hi = ahead;
     }
 }
 
 template <typename R>
 int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
-    if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1 || (L.g.ny + 3) / 4 > 65535) return MP_E_PARAM;
-    dim3 block(64, 4);
-    dim3 grid((unsigned)((L.g.nx + 63) / 64), (unsigned)((L.g.ny + 3) / 4));
+    if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1) return MP_E_PARAM;
+    const int nstrips = (L.g.nx + AT_LANES_OUT - 1) / AT_LANES_OUT;
+    const int64_t items = (int64_t)nstrips * ((L.g.ny + AT_SEG - 1) / AT_SEG);
+    if (items > INT32_MAX - AT_WAVES) return MP_E_PARAM;
+    const int nitems = (int)items;
+    dim3 block(64 * AT_WAVES);
+    dim3 grid((unsigned)((nitems + AT_WAVES - 1) / AT_WAVES));
     const R* prev = (const R*)L.prev;
     R* next = (R*)L.next;
     if (L.nphases == 2 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap2d<R, 2, 1>), grid, block, 0, s, prev, next, L.g, c);
+        hipLaunchKernelGGL((k_antitrap2d<R, 2, 1>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
     else if (L.nphases == 2 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap2d<R, 2, 2>), grid, block, 0, s, prev, next, L.g, c);
+        hipLaunchKernelGGL((k_antitrap2d<R, 2, 2>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
     else if (L.nphases == 3 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap2d<R, 3, 1>), grid, block, 0, s, prev, next, L.g, c);
+        hipLaunchKernelGGL((k_antitrap2d<R, 3, 1>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
     else if (L.nphases == 3 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap2d<R, 3, 2>), grid, block, 0, s, prev, next, L.g, c);
+        hipLaunchKernelGGL((k_antitrap2d<R, 3, 2>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
     else
         return MP_E_PARAM;
     return hipGetLastError() == hipSuccess ? MP_OK : MP_E_HIP;

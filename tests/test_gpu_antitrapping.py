@@ -1,7 +1,8 @@
 """GPU parity of the step with the anti-trapping current (Eq. jatr) against the
 oracle's ``step_antitrapping``, on the same seeded inputs, through the C ABI.
 
-Sizes span several 64 x 4 correction tiles with ragged tails; the cases mix
+Sizes span several 62-column x 32-row correction strips with ragged tails, one
+strip exactly, one row and a grid smaller than a strip; the cases mix
 both potentials, N = 2 and 3, K = 2 and 3, periodic and zero-flux axes and a
 temperature gradient.  FP64 is held to 1e-10 (the bar of the plain step),
 FP32 to 1e-4.  The switch's interplay with the launch options (two steps per
@@ -52,6 +53,10 @@ CASES = {
     "n2k2_obstacle_aniso": (dict(dim=2, N=2, K=2, n=(64, 64, 1), bc=(0, 0, 0), potential="obstacle",
                                  delta=0.02), 100),
     "n3k3_aniso": (dict(dim=2, N=3, K=3, n=(150, 40, 1), bc=(0, 0, 0), delta=0.03), 100),
+    # one 62-column strip exactly; one row over two strips; a grid smaller than one strip
+    "n3k2_one_strip_periodic": (dict(dim=2, N=3, K=2, n=(62, 33, 1), bc=(0, 0, 0)), 60),
+    "n2k2_one_row_63": (dict(dim=2, N=2, K=2, n=(63, 1, 1), bc=(1, 0, 0)), 60),
+    "n2k3_tiny_3x2_noflux": (dict(dim=2, N=2, K=3, n=(3, 2, 1), bc=(1, 1, 0)), 60),
 }
 
 
@@ -128,3 +133,27 @@ def test_adjoint_refuses_the_antitrapping_current():
             s.adjoint(lam, ckpt, 4, 2, 0)
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("precision,mass_tol", [("f64", 1e-12), ("f32", 1e-7)])
+def test_c2_full_grid_with_current_conserves_solute(precision, mass_tol):
+    # At 4096^2 (the benchmark's grid) the current is a divergence, so the solute
+    # sum c = sum_a h_a c^a(mu) stays fixed up to rounding, as without it.
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu = inputs.config_c2(precision=precision)
+    s = Solver(p)
+    try:
+        s.set_antitrapping(True)
+        s.load(phi, mu)
+        del phi, mu
+        d0 = s.diagnostics()
+        s.step(200)
+        d1 = s.diagnostics()
+    finally:
+        s.close()
+    drift = [abs(d1["mass"][k] - d0["mass"][k]) / abs(d0["mass"][k]) for k in range(2)]
+    print(f"C2 {precision} with the current, 200 steps: mass drift {drift[0]:.2e} {drift[1]:.2e}")
+    assert max(drift) <= mass_tol
+    assert d1["nonfinite"] == 0
+    assert d1["max_sum_dev"] <= (1e-12 if precision == "f64" else 1e-4)
