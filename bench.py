@@ -58,10 +58,10 @@ TRAFFIC = {
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "112d348f54601712",
            "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 32, 1], "fuse": 1, "src": "1193675644a0c2bb",
-               "bytes": (2.0 * 781748.9 + 270959.5) * 1024},
-    "at_f32": {"tile": [62, 32, 1], "fuse": 1, "src": "1193675644a0c2bb",
-               "bytes": (2.0 * 414506.9 + 139716.8) * 1024},
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "d747f51f1e273590",
+               "bytes": (2.0 * 867775.7 + 269022.1) * 1024},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "d747f51f1e273590",
+               "bytes": (2.0 * 459730.5 + 137750.1) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5", "at")
@@ -106,7 +106,7 @@ LEG_SOURCES = {
     "at_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
 }
 # The correction kernel's fixed strip shape (columns written per wave, rows per wave, cells per lane).
-AT_TILE = [62, 32, 1]
+AT_TILE = [62, 12, 1]
 
 
 def source_hash(leg):

@@ -15,7 +15,7 @@
 //   j_k = sum over solids a of P(phi_a) (c^a_k - c^liq_k) dphi_a/dt
 //         n_a . e_n (-n_a . n_liq), the liquid being the last phase.
 // Ghost cells (periodic wrap or zero-flux mirror) come from index arithmetic.
-// One wave per strip of 62 columns by 32 rows: each field is read once per cell
+// One wave per strip of 62 columns by 12 rows: each field is read once per cell
 // (plus the halo) and each face is evaluated once.
 #pragma once
 
@@ -72,7 +72,10 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
 }
 
 constexpr int AT_LANES_OUT = 62;  // written lanes per wave (lanes 0 and 63 hold the x halo)
-constexpr int AT_SEG = 32;        // rows per wave
+#ifndef MP_AT_SEG
+#define MP_AT_SEG 12
+#endif
+constexpr int AT_SEG = MP_AT_SEG;  // rows per wave
 constexpr int AT_WAVES = 4;       // waves per block
 
 // One row of one wave: every field of the row's cell at this lane.
