@@ -756,3 +756,61 @@ def step_antitrapping(phi, mu, n, p):
         chik = sum(h1[b] * chi[b][k] for b in range(p.nphases))
         out.append(mun[k] - p.dt * div[k] / chik)
     return phin, np.stack(out)
+
+
+def _runs(idx):
+    """Maximal stretches of consecutive source indices: (position, first, last + 1)."""
+    out = []
+    start = 0
+    for k in range(1, len(idx) + 1):
+        if k == len(idx) or idx[k] != idx[k - 1] + 1:
+            out.append((start, int(idx[start]), int(idx[k - 1]) + 1))
+            start = k
+    return out
+
+
+def step_antitrapping_window(phi, mu, n, p, lo, hi):
+    """``step_antitrapping`` evaluated only on the box lo <= index < hi (array order).
+
+    The current of a box cell needs phi^{n+1} of its face neighbours: the box
+    and a one-cell rim, each rim cell being, by the ghost rule of ``pad``, the
+    grid cell it stands for.  Their phi^{n+1} and plain mu^{n+1} come from
+    ``step_window`` over the stretches of consecutive grid cells the rim maps
+    to; the current is then evaluated on that patch, whose own outer ghosts
+    reach only faces the box does not use.
+    """
+    import itertools
+
+    nd = p.dim
+    bcs = [bc for _, bc in spatial_axes(p)][::-1]  # array order
+    shape = phi.shape[1:]
+    ix = [_ghost_index(lo[i], hi[i], shape[i], bcs[i]) for i in range(nd)]
+    grid = np.ix_(*ix)
+    dt_ = np.result_type(phi, np.float64)
+    Pphi = np.asarray(phi[(slice(None),) + grid], dtype=dt_)
+    Pmu = np.asarray(mu[(slice(None),) + grid], dtype=np.result_type(mu, np.float64))
+    Pphin = np.empty_like(Pphi)
+    Pmun = np.empty_like(Pmu)
+    for pieces in itertools.product(*[_runs(i) for i in ix]):
+        wlo = tuple(r[1] for r in pieces)
+        whi = tuple(r[2] for r in pieces)
+        f, m = step_window(phi, mu, n, p, wlo, whi)
+        dst = (slice(None),) + tuple(slice(r[0], r[0] + r[2] - r[1]) for r in pieces)
+        Pphin[dst] = f
+        Pmun[dst] = m
+    box = (slice(None),) + (slice(1, -1),) * nd
+    div = 0.0
+    for a, j in antitrapping_faces(Pphi, Pphin, Pmu, p):
+        L = j.shape[a]  # faces along a: the patch's cells + 1; box cells sit at 1 .. L - 3
+        hi_f = _sub(_along(j, a, slice(2, L - 1)), nd, {a: slice(None)})
+        lo_f = _sub(_along(j, a, slice(1, L - 2)), nd, {a: slice(None)})
+        div = div + (hi_f - lo_f) / p.dx
+    phin = Pphin[box]
+    mun = Pmun[box]
+    chi = chi_phase(p)
+    h1 = h(phin)
+    out = []
+    for k in range(p.nmu):
+        chik = sum(h1[b] * chi[b][k] for b in range(p.nphases))
+        out.append(mun[k] - p.dt * div[k] / chik)
+    return phin, np.stack(out)

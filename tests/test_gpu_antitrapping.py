@@ -157,3 +157,37 @@ def test_c2_full_grid_with_current_conserves_solute(precision, mass_tol):
     assert max(drift) <= mass_tol
     assert d1["nonfinite"] == 0
     assert d1["max_sum_dev"] <= (1e-12 if precision == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_c2_full_grid_sampled_step_with_current(precision, tol):
+    # The benchmark's grid and launch: one step with the current from the seeded
+    # input as loaded, checked window by window against the oracle's windowed step
+    # (windows on the correction strips' column and 12-row borders, the grid's
+    # edges and across the slab's interface).
+    from paper_2404_01035_amd.solver import Solver
+    from test_gpu_fullsize import _as_loaded, _slab_windows, _windows_2d
+
+    p, phi, mu = inputs.config_c2(precision=precision)
+    s = Solver(p)
+    try:
+        s.set_antitrapping(True)
+        s.load(phi, mu)
+        s.step(1)
+        gphi, gmu = s.fields()
+    finally:
+        s.close()
+    phi0, mu0 = _as_loaded(phi, mu, precision)
+    del phi, mu
+    w = _windows_2d(4096, 4096, np.random.default_rng(11), tile_x=62, seg=12) + _slab_windows(4096)
+    worst = [0.0, 0.0, 0.0]
+    for lo, hi in w:
+        of, om = gp.step_antitrapping_window(phi0, mu0, 0, p, lo, hi)
+        _, pm = gp.step_window(phi0, mu0, 0, p, lo, hi)
+        sl = (slice(None),) + tuple(slice(a, b) for a, b in zip(lo, hi))
+        ef, em = errs(gphi[sl], of), errs(gmu[sl], om)
+        worst = [max(worst[0], ef), max(worst[1], em), max(worst[2], errs(om, pm))]
+        assert ef <= tol and em <= tol, (lo, hi, ef, em)
+    print(f"C2 {precision} with the current, one step: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}; "
+          f"the current moves mu by up to {worst[2]:.2e} there")
+    assert worst[2] > 1e-8  # the windows see the current

@@ -221,3 +221,27 @@ def test_divergence_enters_the_mu_update_with_its_sign(r1):
     h1 = gp.h(phin)
     chik = h1[0] * chi[0][0] + h1[1] * chi[1][0]
     np.testing.assert_allclose(mu_at[0] - mu_plain[0], -p.dt * div_step / chik, rtol=1e-9, atol=1e-16)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 0)])
+def test_windowed_step_matches_the_full_step(bc):
+    p = small_params(N=3, n=(9, 7, 1), bc=bc, seed=21, G=0.02)
+    phi, mu = random_state(p, seed=22, simplex=True)
+    fphi, fmu = gp.step_antitrapping(phi, mu, 3, p)
+    for lo, hi in [((0, 0), (7, 9)), ((0, 0), (2, 3)), ((5, 6), (7, 9)), ((2, 3), (5, 7)), ((0, 8), (7, 9)),
+                   ((6, 0), (7, 9))]:
+        wphi, wmu = gp.step_antitrapping_window(phi, mu, 3, p, lo, hi)
+        sl = (slice(None), slice(lo[0], hi[0]), slice(lo[1], hi[1]))
+        np.testing.assert_allclose(wphi, fphi[sl], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(wmu, fmu[sl], rtol=0, atol=1e-14)
+
+
+def test_windowed_step_matches_the_full_step_3d():
+    p = small_params(N=2, dim=3, n=(6, 5, 4), bc=(0, 1, 0), seed=23)
+    phi, mu = random_state(p, seed=24, simplex=True)
+    fphi, fmu = gp.step_antitrapping(phi, mu, 0, p)
+    for lo, hi in [((0, 0, 0), (4, 5, 6)), ((1, 2, 3), (3, 5, 6)), ((3, 0, 0), (4, 2, 2))]:
+        wphi, wmu = gp.step_antitrapping_window(phi, mu, 0, p, lo, hi)
+        sl = (slice(None),) + tuple(slice(a, b) for a, b in zip(lo, hi))
+        np.testing.assert_allclose(wphi, fphi[sl], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(wmu, fmu[sl], rtol=0, atol=1e-14)
