@@ -203,8 +203,8 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * with |grad phi|^2 <= 1e-30 is zero.  mp_step then runs one step per launch
  * (each step is followed by a correction kernel that reads states n and n+1),
  * ignores mp_set_fusion and mp_set_graph, and mp_adjoint returns MP_E_STATE.
- * Host only.  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0 or 1, a 3D grid),
- * MP_E_STATE (a batched state). */
+ * 2D and 3D single grids.  Host only.  Errors: MP_E_NULLPTR, MP_E_PARAM (on
+ * not 0 or 1), MP_E_STATE (a batched state). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 

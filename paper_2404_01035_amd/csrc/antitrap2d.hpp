@@ -192,8 +192,147 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
     }
 }
 
+// 3D: one thread per cell, the six faces evaluated one after the other from the
+// caches.  A face normal to axis a between cells L and R = L + e_a takes, per
+// phase, the normal difference and, along each of the other two axes t, the mean
+// of the two cells' central differences; the components enter |grad phi|^2 and
+// -n_a . n_liq in the order x, y, z.
+template <typename R, int NP, int NM>
+__device__ inline void at_face3(const R* __restrict__ prev, const R* __restrict__ next, const Geom& g,
+                                const AtCoef<R>& c, int axis, const int* cl, const int* cr, R* j) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int bc[3] = {g.bcx, g.bcy, g.bcz};
+    auto at = [&](const int* q, int t, int d) -> int64_t {  // cell q shifted by d along axis t
+        int v[3] = {q[0], q[1], q[2]};
+        v[t] = at_wrap(v[t] + d, n[t], bc[t]);
+        return ((int64_t)v[2] * g.ny + v[1]) * g.nx + v[0];
+    };
+    const int64_t fs = g.fstride;
+    const int64_t oL = ((int64_t)cl[2] * g.ny + cl[1]) * g.nx + cl[0];
+    const int64_t oR = ((int64_t)cr[2] * g.ny + cr[1]) * g.nx + cr[0];
+    constexpr int LIQ = NP - 1;
+    R pL[NP], pR[NP], u[3][NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        pL[a] = prev[a * fs + oL];
+        pR[a] = prev[a * fs + oR];
+    }
+    R n2[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) n2[a] = R(0);
+    const R h2 = R(0.5) * c.rdx;
+    for (int t = 0; t < 3; ++t) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            R gc;
+            if (t == axis) {
+                gc = (pR[a] - pL[a]) * c.rdx;
+            } else {
+                const R tl = (prev[a * fs + at(cl, t, 1)] - prev[a * fs + at(cl, t, -1)]) * h2;
+                const R tr = (prev[a * fs + at(cr, t, 1)] - prev[a * fs + at(cr, t, -1)]) * h2;
+                gc = R(0.5) * (tl + tr);
+            }
+            u[t][a] = gc;
+            n2[a] += gc * gc;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        const R inv = n2[a] > R(1e-30) ? R(1) / sqrt(n2[a]) : R(0);
+        u[0][a] *= inv;
+        u[1][a] *= inv;
+        u[2][a] *= inv;
+    }
+    R uL[NM], uR[NM], cl_[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        uL[k] = prev[(NP + k) * fs + oL];
+        uR[k] = prev[(NP + k) * fs + oR];
+        cl_[k] = R(0.5) * (c.chi[LIQ][k] * (uL[k] - c.B[LIQ][k]) + c.chi[LIQ][k] * (uR[k] - c.B[LIQ][k]));
+    }
+#pragma unroll
+    for (int a = 0; a < NP - 1; ++a) {
+        const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
+        const R rate = (R(0.5) * (next[a * fs + oL] + next[a * fs + oR]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+        const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[axis][a] * weight;
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            const R ca = R(0.5) * (c.chi[a][k] * (uL[k] - c.B[a][k]) + c.chi[a][k] * (uR[k] - c.B[a][k]));
+            j[k] += common * (ca - cl_[k]);
+        }
+    }
+}
+
+template <typename R, int NP, int NM>
+__global__ void __launch_bounds__(256) k_antitrap3d(const R* __restrict__ prev, R* __restrict__ next, Geom g,
+                                                     AtCoef<R> c) {
+    const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
+    const int jy = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
+    const int kz = (int)blockIdx.z;
+    if (i >= g.nx || jy >= g.ny || kz >= g.nz) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int bc[3] = {g.bcx, g.bcy, g.bcz};
+    const int me[3] = {i, jy, kz};
+    R div[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) div[k] = R(0);
+    for (int axis = 0; axis < 3; ++axis) {
+        int lo[3] = {i, jy, kz}, hi[3] = {i, jy, kz};
+        lo[axis] = at_wrap(me[axis] - 1, n[axis], bc[axis]);
+        hi[axis] = at_wrap(me[axis] + 1, n[axis], bc[axis]);
+        R jl[NM], jh[NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) jl[k] = jh[k] = R(0);
+        at_face3<R, NP, NM>(prev, next, g, c, axis, lo, me, jl);
+        at_face3<R, NP, NM>(prev, next, g, c, axis, me, hi, jh);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) div[k] += (jh[k] - jl[k]) * c.rdx;
+    }
+    const int64_t fs = g.fstride;
+    const int64_t oc = ((int64_t)kz * g.ny + jy) * g.nx + i;
+    R q[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) q[b] = next[b * fs + oc];
+    R hb[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+        const R f = q[b];
+        R cross = R(0);
+        if constexpr (NP == 3) cross = q[(b + 1) % 3] * q[(b + 2) % 3];
+        hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
+    }
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        R chik = R(0);
+#pragma unroll
+        for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
+        next[(NP + k) * fs + oc] = next[(NP + k) * fs + oc] - c.dt * div[k] / chik;
+    }
+}
+
+template <typename R>
+int at_launch3d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
+    if (L.g.nx < 1 || L.g.ny < 1 || L.g.nz < 1 || (L.g.ny + 3) / 4 > 65535 || L.g.nz > 65535) return MP_E_PARAM;
+    dim3 block(256);
+    dim3 grid((unsigned)((L.g.nx + 63) / 64), (unsigned)((L.g.ny + 3) / 4), (unsigned)L.g.nz);
+    const R* prev = (const R*)L.prev;
+    R* next = (R*)L.next;
+    if (L.nphases == 2 && L.nmu == 1)
+        hipLaunchKernelGGL((k_antitrap3d<R, 2, 1>), grid, block, 0, s, prev, next, L.g, c);
+    else if (L.nphases == 2 && L.nmu == 2)
+        hipLaunchKernelGGL((k_antitrap3d<R, 2, 2>), grid, block, 0, s, prev, next, L.g, c);
+    else if (L.nphases == 3 && L.nmu == 1)
+        hipLaunchKernelGGL((k_antitrap3d<R, 3, 1>), grid, block, 0, s, prev, next, L.g, c);
+    else if (L.nphases == 3 && L.nmu == 2)
+        hipLaunchKernelGGL((k_antitrap3d<R, 3, 2>), grid, block, 0, s, prev, next, L.g, c);
+    else
+        return MP_E_PARAM;
+    return hipGetLastError() == hipSuccess ? MP_OK : MP_E_HIP;
+}
+
 template <typename R>
 int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
+    if (L.g.nz > 1) return at_launch3d<R>(L, c, s);
     if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1) return MP_E_PARAM;
     const int nstrips = (L.g.nx + AT_LANES_OUT - 1) / AT_LANES_OUT;
     const int64_t items = (int64_t)nstrips * ((L.g.ny + AT_SEG - 1) / AT_SEG);

@@ -1105,7 +1105,6 @@ int mp_set_antitrapping(mp_state* st, int on) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (on != 0 && on != 1) return fail(MP_E_PARAM, "on must be 0 or 1 (got %d)", on);
     if (on && st->batch) return fail(MP_E_STATE, "anti-trapping current: batched states are not supported");
-    if (on && st->inst[0].grid.dim != 2) return fail(MP_E_PARAM, "anti-trapping current: 2D grids only");
     drop_graphs(st);
     st->antitrap = on == 1;
     return ok();

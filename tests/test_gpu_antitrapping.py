@@ -57,6 +57,11 @@ CASES = {
     "n3k2_one_strip_periodic": (dict(dim=2, N=3, K=2, n=(62, 33, 1), bc=(0, 0, 0)), 60),
     "n2k2_one_row_63": (dict(dim=2, N=2, K=2, n=(63, 1, 1), bc=(1, 0, 0)), 60),
     "n2k3_tiny_3x2_noflux": (dict(dim=2, N=2, K=3, n=(3, 2, 1), bc=(1, 1, 0)), 60),
+    # 3D (the one-thread-per-cell correction kernel)
+    "3d_n2k2_noflux": (dict(dim=3, N=2, K=2, n=(37, 9, 21), bc=(1, 1, 1)), 40),
+    "3d_n3k3_mixed_bc_gradient": (dict(dim=3, N=3, K=3, n=(20, 13, 17), bc=(0, 1, 0), G=1e-3), 40),
+    "3d_n2k3_periodic_obstacle_aniso": (dict(dim=3, N=2, K=3, n=(17, 11, 9), bc=(0, 0, 0), potential="obstacle",
+                                             delta=0.02), 40),
 }
 
 
