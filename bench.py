@@ -279,6 +279,40 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
     }
 
 
+def leg_at3d(n, steps, warmup):
+    """The 3D dendrite (FP32) with the anti-trapping current: one 3D step launch and
+    the 3D correction kernel per step, against the same run without the current."""
+    from paper_2404_01035_amd.solver import Solver
+    from paper_2404_01035_amd import inputs
+
+    p, phi, mu = inputs.config_c3(n=(n, n, n))
+    s = Solver(p)
+    s.load(phi, mu)
+    del phi, mu
+    s.step(warmup)
+    with Timer() as t0:
+        s.step(steps)
+    s.set_antitrapping(True)
+    s.step(warmup)
+    with Timer() as t1:
+        s.step(steps)
+    d = s.diagnostics()
+    s.close()
+    bpc = (2 * p.nphases + 3 * (p.ncomp - 1)) * 4
+    ms_plain, ms_at = t0.ms / steps, t1.ms / steps
+    ms_corr = ms_at - ms_plain
+    return {
+        "value": p.ncells * steps / (t1.ms * 1e-3),
+        "unit": "cell-updates/s",
+        "ms_per_step": ms_at,
+        "ms_per_step_without_current": ms_plain,
+        "correction_ms_per_step": ms_corr,
+        "correction_bytes_per_cell": bpc,
+        "roofline": roofline(p.ncells * bpc, ms_corr) if ms_corr > 0 else None,
+        "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
+    }
+
+
 def leg_at(precision, n, steps, warmup):
     """The C2 step with the anti-trapping current: one step per launch followed by the
     correction kernel.  The same run without the current (one step per launch) is
@@ -537,7 +571,9 @@ def main():
         out["antitrapping"] = {"workload": f"2D {a.n}x{a.n} directional eutectic with the anti-trapping "
                                            "current, one step per launch + correction",
                                "f64": leg_at("f64", a.n, at_steps, 5),
-                               "f32": leg_at("f32", a.n, at_steps, 5)}
+                               "f32": leg_at("f32", a.n, at_steps, 5),
+                               "dendrite_3d_f32": dict(leg_at3d(a.n3d, min(a.steps3d, 50), 3),
+                                                       workload=f"3D {a.n3d}^3 binary dendrite with the current")}
     out["copy_bandwidth"] = copy_bandwidth(a.n)
     if not a.no_cpu:
         log("CPU oracle sample")

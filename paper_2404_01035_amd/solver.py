@@ -71,7 +71,7 @@ class Solver:
         abi.mp_set_fusion(self.st, steps)
 
     def set_antitrapping(self, on: bool = True):
-        """Anti-trapping current of Eq. jatr in the mu update (2D; one step per launch, no graphs)."""
+        """Anti-trapping current of Eq. jatr in the mu update (2D and 3D; one step per launch, no graphs)."""
         abi.mp_set_antitrapping(self.st, on)
 
     def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:
