@@ -58,9 +58,9 @@ TRAFFIC = {
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "112d348f54601712",
            "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "77df44982e6373c0",
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "7f724703195dd7d3",
                "bytes": (2.0 * 867775.7 + 269022.1) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "77df44982e6373c0",
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "7f724703195dd7d3",
                "bytes": (2.0 * 459730.5 + 137750.1) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"

@@ -192,35 +192,39 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
     }
 }
 
-// 3D: one thread per cell, the six faces evaluated one after the other from the
-// caches.  A face normal to axis a between cells L and R = L + e_a takes, per
-// phase, the normal difference and, along each of the other two axes t, the mean
-// of the two cells' central differences; the components enter |grad phi|^2 and
-// -n_a . n_liq in the order x, y, z.
+// 3D: one thread per cell.  The cell's 19-point neighbourhood of phi^n (the
+// 3 x 3 x 3 cube without its corners: every point a face of the cell needs) is
+// read once into registers, then the six faces are evaluated from it.  A face
+// normal to axis a between cells L and R = L + e_a takes, per phase, the normal
+// difference and, along each other axis t, the mean of the two cells' central
+// differences; the components enter |grad phi|^2 and -n_a . n_liq in the order
+// x, y, z.
+template <typename R, int NP>
+struct AtCube {
+    R p[3][3][3][NP];  // [z][y][x], centre at [1][1][1]
+};
+
+template <typename R, int NP>
+__device__ inline R at_cube(const AtCube<R, NP>& C, const int* q, int a) {
+    return C.p[q[2]][q[1]][q[0]][a];
+}
+
 template <typename R, int NP, int NM>
-__device__ inline void at_face3(const R* __restrict__ prev, const R* __restrict__ next, const Geom& g,
-                                const AtCoef<R>& c, int axis, const int* cl, const int* cr, R* j) {
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int bc[3] = {g.bcx, g.bcy, g.bcz};
-    auto at = [&](const int* q, int t, int d) -> int64_t {  // cell q shifted by d along axis t
-        int v[3] = {q[0], q[1], q[2]};
-        v[t] = at_wrap(v[t] + d, n[t], bc[t]);
-        return ((int64_t)v[2] * g.ny + v[1]) * g.nx + v[0];
-    };
-    const int64_t fs = g.fstride;
-    const int64_t oL = ((int64_t)cl[2] * g.ny + cl[1]) * g.nx + cl[0];
-    const int64_t oR = ((int64_t)cr[2] * g.ny + cr[1]) * g.nx + cr[0];
+__device__ inline void at_face_cube(const AtCube<R, NP>& C, int axis, int side, const R* qL, const R* qR,
+                                    const R* uL, const R* uR, const AtCoef<R>& c, R* j) {
     constexpr int LIQ = NP - 1;
-    R pL[NP], pR[NP], u[3][NP];
+    int L[3] = {1, 1, 1}, Rr[3] = {1, 1, 1};
+    L[axis] = side;
+    Rr[axis] = side + 1;
+    const R h2 = R(0.5) * c.rdx;
+    R u[3][NP], n2[NP], pL[NP], pR[NP];
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
-        pL[a] = prev[a * fs + oL];
-        pR[a] = prev[a * fs + oR];
+        pL[a] = at_cube(C, L, a);
+        pR[a] = at_cube(C, Rr, a);
+        n2[a] = R(0);
     }
-    R n2[NP];
 #pragma unroll
-    for (int a = 0; a < NP; ++a) n2[a] = R(0);
-    const R h2 = R(0.5) * c.rdx;
     for (int t = 0; t < 3; ++t) {
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
@@ -228,8 +232,14 @@ __device__ inline void at_face3(const R* __restrict__ prev, const R* __restrict_
             if (t == axis) {
                 gc = (pR[a] - pL[a]) * c.rdx;
             } else {
-                const R tl = (prev[a * fs + at(cl, t, 1)] - prev[a * fs + at(cl, t, -1)]) * h2;
-                const R tr = (prev[a * fs + at(cr, t, 1)] - prev[a * fs + at(cr, t, -1)]) * h2;
+                int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]};
+                int rp[3] = {Rr[0], Rr[1], Rr[2]}, rm[3] = {Rr[0], Rr[1], Rr[2]};
+                lp[t] += 1;
+                lm[t] -= 1;
+                rp[t] += 1;
+                rm[t] -= 1;
+                const R tl = (at_cube(C, lp, a) - at_cube(C, lm, a)) * h2;
+                const R tr = (at_cube(C, rp, a) - at_cube(C, rm, a)) * h2;
                 gc = R(0.5) * (tl + tr);
             }
             u[t][a] = gc;
@@ -243,17 +253,14 @@ __device__ inline void at_face3(const R* __restrict__ prev, const R* __restrict_
         u[1][a] *= inv;
         u[2][a] *= inv;
     }
-    R uL[NM], uR[NM], cl_[NM];
+    R cl_[NM];
 #pragma unroll
-    for (int k = 0; k < NM; ++k) {
-        uL[k] = prev[(NP + k) * fs + oL];
-        uR[k] = prev[(NP + k) * fs + oR];
+    for (int k = 0; k < NM; ++k)
         cl_[k] = R(0.5) * (c.chi[LIQ][k] * (uL[k] - c.B[LIQ][k]) + c.chi[LIQ][k] * (uR[k] - c.B[LIQ][k]));
-    }
 #pragma unroll
     for (int a = 0; a < NP - 1; ++a) {
         const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
-        const R rate = (R(0.5) * (next[a * fs + oL] + next[a * fs + oR]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+        const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
         const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[axis][a] * weight;
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
@@ -270,35 +277,56 @@ __global__ void __launch_bounds__(256) k_antitrap3d(const R* __restrict__ prev, 
     const int jy = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
     const int kz = (int)blockIdx.z;
     if (i >= g.nx || jy >= g.ny || kz >= g.nz) return;
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const int bc[3] = {g.bcx, g.bcy, g.bcz};
-    const int me[3] = {i, jy, kz};
+    const int64_t fs = g.fstride;
+    const int xs[3] = {at_wrap(i - 1, g.nx, g.bcx), i, at_wrap(i + 1, g.nx, g.bcx)};
+    const int ys[3] = {at_wrap(jy - 1, g.ny, g.bcy), jy, at_wrap(jy + 1, g.ny, g.bcy)};
+    const int zs[3] = {at_wrap(kz - 1, g.nz, g.bcz), kz, at_wrap(kz + 1, g.nz, g.bcz)};
+    AtCube<R, NP> C;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int far = (dz != 1) + (dy != 1) + (dx != 1);
+#pragma unroll
+                for (int a = 0; a < NP; ++a)
+                    C.p[dz][dy][dx][a] =
+                        far == 3 ? R(0) : prev[a * fs + ((int64_t)zs[dz] * g.ny + ys[dy]) * g.nx + xs[dx]];
+            }
+    // phi^{n+1} and mu^n of the cell and its six face neighbours: centre, then (axis, side)
+    R Q[7][NP], U[7][NM];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+        int d[3] = {1, 1, 1};
+        if (s > 0) d[(s - 1) / 2] = ((s - 1) % 2 == 0) ? 0 : 2;
+        const int64_t o = ((int64_t)zs[d[2]] * g.ny + ys[d[1]]) * g.nx + xs[d[0]];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) Q[s][a] = next[a * fs + o];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) U[s][k] = prev[(NP + k) * fs + o];
+    }
     R div[NM];
 #pragma unroll
     for (int k = 0; k < NM; ++k) div[k] = R(0);
+#pragma unroll
     for (int axis = 0; axis < 3; ++axis) {
-        int lo[3] = {i, jy, kz}, hi[3] = {i, jy, kz};
-        lo[axis] = at_wrap(me[axis] - 1, n[axis], bc[axis]);
-        hi[axis] = at_wrap(me[axis] + 1, n[axis], bc[axis]);
         R jl[NM], jh[NM];
 #pragma unroll
         for (int k = 0; k < NM; ++k) jl[k] = jh[k] = R(0);
-        at_face3<R, NP, NM>(prev, next, g, c, axis, lo, me, jl);
-        at_face3<R, NP, NM>(prev, next, g, c, axis, me, hi, jh);
+        const int lo = 1 + 2 * axis, hi = 2 + 2 * axis;
+        at_face_cube<R, NP, NM>(C, axis, 0, Q[lo], Q[0], U[lo], U[0], c, jl);
+        at_face_cube<R, NP, NM>(C, axis, 1, Q[0], Q[hi], U[0], U[hi], c, jh);
 #pragma unroll
         for (int k = 0; k < NM; ++k) div[k] += (jh[k] - jl[k]) * c.rdx;
     }
-    const int64_t fs = g.fstride;
     const int64_t oc = ((int64_t)kz * g.ny + jy) * g.nx + i;
-    R q[NP];
-#pragma unroll
-    for (int b = 0; b < NP; ++b) q[b] = next[b * fs + oc];
     R hb[NP];
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
-        const R f = q[b];
+        const R f = Q[0][b];
         R cross = R(0);
-        if constexpr (NP == 3) cross = q[(b + 1) % 3] * q[(b + 2) % 3];
+        if constexpr (NP == 3) cross = Q[0][(b + 1) % 3] * Q[0][(b + 2) % 3];
         hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
     }
 #pragma unroll
