@@ -94,7 +94,8 @@ def test_c1_fp64_with_antitrapping_500_steps():
     assert errs(m, om) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["n2k2_periodic", "n3k3_ragged_noflux_y_gradient"])
+@pytest.mark.parametrize("name", ["n2k2_periodic", "n3k3_ragged_noflux_y_gradient", "3d_n2k2_noflux",
+                                  "3d_n3k3_mixed_bc_gradient"])
 def test_fp32_with_antitrapping_matches_oracle(name):
     p, phi, mu, steps = _case(name, precision="f32")
     f, m = run_gpu_at(p, phi, mu, steps, step0=5)
