@@ -62,6 +62,9 @@ TRAFFIC = {
                "bytes": (2.0 * 867775.7 + 269022.1) * 1024},
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "7f724703195dd7d3",
                "bytes": (2.0 * 459730.5 + 137750.1) * 1024},
+    # profiles/k_antitrap3d_dendrite_512_f32.md
+    "at3d_f32": {"tile": [64, 4, 1], "fuse": 1, "src": "7f724703195dd7d3",
+                 "bytes": (2.0 * 2646601.9 + 524288.0) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5", "at")
@@ -104,7 +107,10 @@ LEG_SOURCES = {
     "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
     "at_f64": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
     "at_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
+    "at3d_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
 }
+# The 3D correction kernel's fixed block shape (x cells, y rows, cells per lane).
+AT3D_TILE = [64, 4, 1]
 # The correction kernel's fixed strip shape (columns written per wave, rows per wave, cells per lane).
 AT_TILE = [62, 12, 1]
 
@@ -308,7 +314,8 @@ def leg_at3d(n, steps, warmup):
         "ms_per_step_without_current": ms_plain,
         "correction_ms_per_step": ms_corr,
         "correction_bytes_per_cell": bpc,
-        "roofline": roofline(p.ncells * bpc, ms_corr) if ms_corr > 0 else None,
+        "roofline": roofline(p.ncells * bpc, ms_corr, traffic_of("at3d_f32", AT3D_TILE, 1))
+        if ms_corr > 0 else None,
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
