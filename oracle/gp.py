@@ -241,6 +241,15 @@ def G_normal(qn, qt, delta):
 # The step
 # ----------------------------------------------------------------------------
 
+def obstacle_clip(phin):
+    """Projection of the obstacle step: Eq. Obstacle makes w infinite outside
+    [0, 1], read here as clipping every phi_a of the forward-Euler update to
+    [0, 1] and then dividing by the sum over the phases, so sum_a phi_a = 1
+    again.  phin has the phase index first."""
+    out = np.clip(phin, 0.0, 1.0)
+    return out / out.sum(axis=0, keepdims=True)
+
+
 def _faces(Pphi, p):
     """Per axis: (F, s) face arrays of the gradient term, shape (N, ..., n_a + 1, ...)."""
     nd = p.dim
@@ -310,8 +319,7 @@ def _step_padded(Pphi, Pmu, n, p, y_origin=0):
     lam = sum(R[a] for a in range(N)) / N
     phin = phi + p.dt * (R - lam) / (p.tau * p.eps)
     if p.potential == "obstacle":
-        phin = np.clip(phin, 0.0, 1.0)
-        phin = phin / phin.sum(axis=0, keepdims=True)
+        phin = obstacle_clip(phin)
     # diffusion potentials
     chi = chi_phase(p)
     D = np.asarray(p.D)[:N, : p.nmu]

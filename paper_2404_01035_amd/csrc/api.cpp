@@ -48,7 +48,7 @@ struct mp_state {
     int64_t step;
     int bx, seg, vec;  // vec: cap on cells per lane of the 2D strips (-1: none)
     int fuse;  // steps per launch of the step kernel: 1, or 2 (2D single grid)
-    bool antitrap;  // anti-trapping current on (2D single grid; one step per launch, no graphs)
+    bool antitrap;  // anti-trapping current on (2D and 3D single grids; one step per launch, no graphs)
     int graph_chunk;
     hipGraphExec_t gexec[2];  // by starting buffer
     int gend[2];              // buffer current after a replay, by starting buffer

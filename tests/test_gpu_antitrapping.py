@@ -1,7 +1,7 @@
 """GPU parity of the step with the anti-trapping current (Eq. jatr) against the
 oracle's ``step_antitrapping``, on the same seeded inputs, through the C ABI.
 
-Sizes span several 62-column x 32-row correction strips with ragged tails, one
+Sizes span several 62-column x 12-row correction strips with ragged tails, one
 strip exactly, one row and a grid smaller than a strip; the cases mix
 both potentials, N = 2 and 3, K = 2 and 3, periodic and zero-flux axes and a
 temperature gradient.  FP64 is held to 1e-10 (the bar of the plain step),

@@ -523,12 +523,77 @@ def test_step_window_matches_full_step_3d():
         assert np.array_equal(mw, m[sl])
 
 
-def test_obstacle_keeps_bounds_and_sum():
-    p = small_params(N=3, n=(16, 12, 1), potential="obstacle", gamma3=0.3)
+@pytest.mark.parametrize("raw,want", [
+    ((-0.1, 0.6, 0.5), (0.0, 6.0 / 11.0, 5.0 / 11.0)),   # clip, then divide by 1.1
+    ((1.2, -0.1, -0.1), (1.0, 0.0, 0.0)),
+    ((0.7, 0.7, -0.4), (0.5, 0.5, 0.0)),
+    ((0.2, 0.3, 0.5), (0.2, 0.3, 0.5)),                    # inside: unchanged
+    ((1.05, -0.05), (1.0, 0.0)),
+    ((-0.02, 1.02), (0.0, 1.0)),
+])
+def test_obstacle_clip_hand_values(raw, want):
+    """Clip to [0, 1] then renormalise (the obstacle projection), values worked by hand."""
+    got = gp.obstacle_clip(np.array(raw, dtype=np.float64).reshape(-1, 1, 1))
+    assert np.allclose(got[:, 0, 0], want, rtol=0, atol=1e-15)
+
+
+def _band_state(p):
+    """Random simplex state whose left half is a pure 0-1 mixture: there the
+    obstacle pushes phase 2 below zero (gamma_02 + gamma_12 > gamma_01), so the
+    projection acts in every step."""
     phi, mu = random_state(p, seed=12, simplex=True)
-    f, m = gp.run(phi, mu, 0, 50, p)
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0.3, 0.7, size=p.spatial[:-1] + (8,))
+    phi[0, :, :8] = a
+    phi[1, :, :8] = 1.0 - a
+    phi[2, :, :8] = 0.0
+    return phi, mu
+
+
+def test_obstacle_step_projects_the_euler_update_and_keeps_bounds():
+    p = small_params(N=3, n=(16, 12, 1), potential="obstacle", gamma3=0.3)
+    assert p.gamma[0, 2] + p.gamma[1, 2] > p.gamma[0, 1]
+    phi, mu = _band_state(p)
+    clipped = 0
+    f, m = phi, mu
+    for n in range(50):
+        # the unconstrained forward-Euler update, from the pinned right-hand side
+        R = gp.rhs_phi(f, m, n, p)
+        raw = f + p.dt * (R - R.mean(axis=0)) / (p.tau * p.eps)
+        clipped += int(np.count_nonzero((raw < 0.0) | (raw > 1.0)))
+        f1, m = gp.step(f, m, n, p)
+        # cell by cell: clip each phase to [0, 1], divide by the clipped sum
+        want = np.empty_like(raw)
+        for j in range(raw.shape[1]):
+            for i in range(raw.shape[2]):
+                v = [min(max(float(x), 0.0), 1.0) for x in raw[:, j, i]]
+                tot = sum(v)
+                want[:, j, i] = [x / tot for x in v]
+        assert np.allclose(f1, want, rtol=0, atol=1e-15)
+        f = f1
+    assert clipped > 100
     assert f.min() >= 0.0 and f.max() <= 1.0
     assert np.max(np.abs(f.sum(axis=0) - 1)) < 1e-14
+
+
+def test_diagnostics_hand_values():
+    """min chi and solute mass of a mixture field, by hand: h(0.3) = 0.216,
+    h(0.5) = 0.5, h(0.9) = 0.972; chi^0 = 1/2, chi^1 = 1/4, so
+    chi = 0.25 + 0.25 h_0 is smallest (0.304) where phi_0 = 0.3; with B = 0 and
+    mu = 0.4, c^0 = 0.2, c^1 = 0.1 and c = 0.1 + 0.1 h_0."""
+    p = inputs.Params(dim=2, n=(3, 2, 1), nphases=2, ncomp=2, dx=0.5)
+    p.A[:2, 0] = (1.0, 2.0)
+    p.B[:2, 0] = 0.0
+    phi0 = np.array([[0.3, 0.5, 0.9], [0.9, 0.5, 0.3]])
+    phi = np.stack([phi0, 1.0 - phi0])
+    mu = np.full((1, 2, 3), 0.4)
+    d = gp.diagnostics(phi, mu, p)
+    assert abs(d["min_chi"][0] - 0.304) < 1e-15
+    h0 = [0.216, 0.5, 0.972]
+    mass = 2 * sum(0.1 + 0.1 * x for x in h0) * 0.25
+    assert abs(d["mass"][0] - mass) < 1e-15
+    assert abs(d["volume"][0] - 2 * (0.3 + 0.5 + 0.9) * 0.25) < 1e-15
+    assert d["max_sum_dev"] == 0.0 and d["nonfinite"] == 0
 
 
 @pytest.mark.parametrize("n", [(1, 5, 1), (2, 3, 1), (3, 1, 1)])
