@@ -5,10 +5,14 @@ fields), x periodic / y no-flux, seeded synthetic initial state (lamellae slab
 in melt).  A benchmark step is one forward-Euler time step of the whole field
 (the fused phi + mu update); the 2D kernels perform two steps per launch, so
 the state crosses HBM once per two steps (bitwise the same result as single
-steps).  The timed region runs exactly --steps steps in FP64 (``value``) and,
-separately, in FP32 (``fp32``), with the state resident in HBM, at the
+steps).  Each leg is timed as the median of five regions of exactly --steps
+steps, after --warmup steps and untimed steps until 150 ms have passed, with
+the state resident in HBM: FP64 (``value``) and FP32 (``fp32``), at the
 library's default tiles (the autotuner's picks for this workload; --tune
-re-tunes).
+re-tunes).  ``roofline`` takes the bound by the max(bytes / bandwidth,
+flops / peak) rule over the algorithmic bytes (one read and one write of the
+state per step) and flops, and carries the HBM fraction of the real (counter)
+traffic and the vector-ALU issue fraction beside it.
 
 Further legs, each a block of the same JSON line:
   dendrite_3d  3D 512^3 binary dendrite with cubic anisotropy, FP32
@@ -16,7 +20,9 @@ Further legs, each a block of the same JSON line:
                steps, replayed as HIP graphs, FP32
   adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
                (every 100 steps) and the adjoint sweep; their cost ratio
-cpu_baseline   the FP64 oracle on two full 4096^2 steps, on the host.
+cpu_baseline   the FP64 oracle on the full 4096^2 grid, on the host's cores: two
+               steps split into row bands over the usable CPUs (at most 16),
+               and one step in a single process; lscpu's model and counts.
 
 Prints one JSON line.  Options: --gpus (only 1 is supported), --steps,
 --warmup, --legs, --no-cpu, --n (2D grid side), --tune, --tile / --tile32 /
@@ -89,6 +95,8 @@ def parse():
     ap.add_argument("--n3d", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=400)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only the host-CPU oracle timing (prints its record; no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of one FP64 state buffer instead")
     return ap.parse_args()
@@ -178,6 +186,50 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
             "frac": round(tf / peak, 4), "traffic": None if traffic is None else round(traffic)}
 
 
+# Vector-ALU issue of each leg's step kernel, from rocprofv3 SQ counter runs:
+# VALU instructions per launch (SQ_INSTS_VALU summed over the launch's waves),
+# keyed like TRAFFIC (tile, steps per launch, source hash).  A wave64 FP64
+# instruction occupies its SIMD for 4 cycles, an FP32 one for 2 (the vector
+# peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
+VALU = {}
+VALU_CYCLES = {"f64": 4, "f32": 2}
+SIMDS = 1024         # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9     # MI355X peak engine clock
+
+
+def valu_of(leg, tile, fuse):
+    t = VALU.get(leg)
+    if not t or list(t["tile"]) != list(tile) or t["fuse"] != fuse or t["src"] != source_hash(leg):
+        return None
+    return t["insts"]
+
+
+def bound_record(bytes_per_step, flops_per_step, ms_step, precision, traffic=None, valu_insts=None,
+                 steps_per_launch=1):
+    """Roofline of a step kernel by the max(bytes / bandwidth, flops / peak) rule:
+    the side whose ideal time is the larger bounds it, and ``roofline``/
+    ``alu_roofline`` of that side is returned.  Beside it: ``ideal_ms`` of both
+    sides; ``counter_frac``, the HBM rate of the real (counter) traffic against
+    the peak, and ``valu_issue_frac``, the share of the launch time the VALU
+    instructions occupy their SIMDs -- both null without a counter figure for
+    this exact kernel and tile.  Two-step kernels read and write the state once
+    per two steps, so their algorithmic-bytes rate (one read and one write per
+    step) can exceed the HBM peak; the counter and issue fractions are then
+    the limits that bind."""
+    t_hbm = bytes_per_step / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_alu = flops_per_step / (ALU_PEAK_TFLOPS[precision] * 1e12) * 1e3
+    if t_hbm >= t_alu:
+        rec = roofline(bytes_per_step, ms_step, traffic)
+    else:
+        rec = alu_roofline(flops_per_step, ms_step, precision, traffic)
+    ms_launch = ms_step * steps_per_launch
+    rec["ideal_ms_per_step"] = {"hbm": round(t_hbm, 6), "alu": round(t_alu, 6)}
+    rec["counter_frac"] = None if traffic is None else round(traffic / (ms_launch * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+    rec["valu_issue_frac"] = None if valu_insts is None else round(
+        valu_insts * VALU_CYCLES[precision] / SIMDS / CLOCK_HZ / (ms_launch * 1e-3), 4)
+    return rec
+
+
 def parse_tile(text):
     return [int(v) for v in text.split(",")] if text else None
 
@@ -202,6 +254,36 @@ class Timer:
         self.e1.record(self.stream)
         self.torch.cuda.synchronize()
         self.ms = self.e0.elapsed_time(self.e1)
+
+
+REGIONS = 5          # timed regions per leg; the median is reported
+SETTLE_MS = 150.0    # untimed steps after the warm-up until this much wall time has passed
+
+
+def measure(step, steps, warmup, regions=REGIONS, settle_ms=SETTLE_MS):
+    """Time ``step(steps)``: ``warmup`` untimed steps, then untimed steps in
+    chunks of ``steps`` until ``settle_ms`` of wall time has passed (clocks and
+    caches settle; short runs such as 20 steps otherwise time a cold GPU), then
+    ``regions`` regions of exactly ``steps`` steps, each bracketed by a device
+    synchronisation and HIP events on the stream the kernels run on.  Returns
+    the median region's milliseconds, every region's, and the settle steps."""
+    import torch
+
+    if warmup > 0:
+        step(warmup)
+    torch.cuda.synchronize()
+    settle = 0
+    t0 = time.perf_counter()
+    while steps > 0 and (time.perf_counter() - t0) * 1e3 < settle_ms and settle < 50 * max(steps, 1):
+        step(steps)
+        torch.cuda.synchronize()
+        settle += steps
+    ms = []
+    for _ in range(regions):
+        with Timer() as t:
+            step(steps)
+        ms.append(t.ms)
+    return sorted(ms)[len(ms) // 2], ms, settle
 
 
 def copy_bandwidth(n, reps=10):
@@ -260,22 +342,23 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
         source = "default"
     used = list(abi.mp_get_tile(s.st))
     fuse = abi.mp_get_fusion(s.st)
-    s.step(warmup)
-    with Timer() as t:
-        s.step(steps)
+    ms, regions, settle = measure(s.step, steps, warmup)
     d = s.diagnostics()
     s.close()
     elem = 8 if precision == "f64" else 4
     bpc = p.nfields * 2 * elem  # read + write of every field once
     fpc = flops_per_cell_update(p.nphases, p.ncomp)
-    ms_step = t.ms / steps
-    traffic = traffic_of(f"c2_{precision}", used, fuse)
+    ms_step = ms / steps
+    leg = f"c2_{precision}"
+    traffic = traffic_of(leg, used, fuse)
     return {
-        "value": p.ncells * steps / (t.ms * 1e-3),
+        "value": p.ncells * steps / (ms * 1e-3),
         "ms_per_step": ms_step,
-        # two steps per launch from registers: the vector ALU, not HBM, bounds it
-        "roofline": alu_roofline(p.ncells * fpc, ms_step, precision, traffic),
-        "hbm_equivalent": roofline(p.ncells * bpc, ms_step, traffic),
+        "region_ms": [round(x, 4) for x in regions],
+        "settle_steps": settle,
+        "roofline": bound_record(p.ncells * bpc, p.ncells * fpc, ms_step, precision, traffic,
+                                 valu_of(leg, used, fuse), fuse),
+        "alu": alu_roofline(p.ncells * fpc, ms_step, precision),
         "flops_per_cell_update": fpc,
         "bytes_per_cell_update": bpc,
         "steps_per_launch": fuse,
@@ -287,7 +370,8 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
 
 def leg_at3d(n, steps, warmup):
     """The 3D dendrite (FP32) with the anti-trapping current: one 3D step launch and
-    the 3D correction kernel per step, against the same run without the current."""
+    the 3D correction kernel per step, against the same run without the current
+    (median regions of each; their difference is the correction kernel's time)."""
     from paper_2404_01035_amd.solver import Solver
     from paper_2404_01035_amd import inputs
 
@@ -295,22 +379,19 @@ def leg_at3d(n, steps, warmup):
     s = Solver(p)
     s.load(phi, mu)
     del phi, mu
-    s.step(warmup)
-    with Timer() as t0:
-        s.step(steps)
+    ms0, _, _ = measure(s.step, steps, warmup)
     s.set_antitrapping(True)
-    s.step(warmup)
-    with Timer() as t1:
-        s.step(steps)
+    ms1, regions, _ = measure(s.step, steps, warmup)
     d = s.diagnostics()
     s.close()
     bpc = (2 * p.nphases + 3 * (p.ncomp - 1)) * 4
-    ms_plain, ms_at = t0.ms / steps, t1.ms / steps
+    ms_plain, ms_at = ms0 / steps, ms1 / steps
     ms_corr = ms_at - ms_plain
     return {
-        "value": p.ncells * steps / (t1.ms * 1e-3),
+        "value": p.ncells * steps / (ms1 * 1e-3),
         "unit": "cell-updates/s",
         "ms_per_step": ms_at,
+        "region_ms": [round(x, 4) for x in regions],
         "ms_per_step_without_current": ms_plain,
         "correction_ms_per_step": ms_corr,
         "correction_bytes_per_cell": bpc,
@@ -323,7 +404,8 @@ def leg_at3d(n, steps, warmup):
 def leg_at(precision, n, steps, warmup):
     """The C2 step with the anti-trapping current: one step per launch followed by the
     correction kernel.  The same run without the current (one step per launch) is
-    timed first; the difference is the correction kernel's time per step."""
+    timed first; the difference of the two median regions is the correction
+    kernel's time per step."""
     from paper_2404_01035_amd.solver import Solver
     from paper_2404_01035_amd import inputs
 
@@ -332,25 +414,22 @@ def leg_at(precision, n, steps, warmup):
     s.load(phi, mu)
     del phi, mu
     s.set_fusion(1)
-    s.step(warmup)
-    with Timer() as t0:
-        s.step(steps)
+    ms0, _, _ = measure(s.step, steps, warmup)
     s.set_antitrapping(True)
-    s.step(warmup)
-    with Timer() as t1:
-        s.step(steps)
+    ms1, regions, _ = measure(s.step, steps, warmup)
     d = s.diagnostics()
     s.close()
     elem = 8 if precision == "f64" else 4
     nm = p.ncomp - 1
     # phi^n, phi^{n+1}, mu^n and mu^{n+1} read, mu^{n+1} written, once per cell
     bpc = (2 * p.nphases + 3 * nm) * elem
-    ms_plain, ms_at = t0.ms / steps, t1.ms / steps
+    ms_plain, ms_at = ms0 / steps, ms1 / steps
     ms_corr = ms_at - ms_plain
     return {
-        "value": p.ncells * steps / (t1.ms * 1e-3),
+        "value": p.ncells * steps / (ms1 * 1e-3),
         "unit": "cell-updates/s",
         "ms_per_step": ms_at,
+        "region_ms": [round(x, 4) for x in regions],
         "ms_per_step_without_current": ms_plain,
         "correction_ms_per_step": ms_corr,
         "correction_bytes_per_cell": bpc,
@@ -374,23 +453,22 @@ def leg_c3(n, steps, warmup, tile, tune):
     elif tune:
         s.autotune(reps=5, force=True)
     used = list(abi.mp_get_tile(s.st))
-    s.step(warmup)
-    with Timer() as t:
-        s.step(steps)
+    ms, regions, settle = measure(s.step, steps, warmup)
     d = s.diagnostics()
     s.close()
     bpc = p.nfields * 2 * 4
     fpc = flops_per_cell_update(p.nphases, p.ncomp, dim=3, aniso=True)
-    ms_step = t.ms / steps
+    ms_step = ms / steps
     return {
         "workload": f"3D {n}^3 binary dendrite, cubic anisotropy delta=0.02, no-flux, FP32",
-        "value": p.ncells * steps / (t.ms * 1e-3),
+        "value": p.ncells * steps / (ms * 1e-3),
         "unit": "cell-updates/s",
         "steps": steps,
         "ms_per_step": ms_step,
-        "roofline": roofline(p.ncells * bpc, ms_step, traffic_of("c3", used, 1)),
-        # the flop side of the same kernel (neither side is saturated: LDS and
-        # latency bound)
+        "region_ms": [round(x, 4) for x in regions],
+        "roofline": bound_record(p.ncells * bpc, p.ncells * fpc, ms_step, "f32", traffic_of("c3", used, 1),
+                                 valu_of("c3", used, 1), 1),
+        # the flop side of the same kernel
         "alu": alu_roofline(p.ncells * fpc, ms_step, "f32"),
         "flops_per_cell_update": fpc,
         "bytes_per_cell_update": bpc,
@@ -421,23 +499,23 @@ def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
     used = list(abi.mp_get_tile(b.st))
     fuse = abi.mp_get_fusion(b.st)
     b.set_graph(graph_chunk)
-    b.step(warmup)
-    with Timer() as t:
-        b.step(steps)
+    ms, regions, _ = measure(b.step, steps, warmup)
     diags = b.diagnostics()
     b.close()
-    ms_step = t.ms / steps
+    ms_step = ms / steps
     return {
         "workload": "256 independent 2D instances, sides U{64..1024}, N in {2,3}, 1-2 mu fields, "
                     f"periodic, FP32, one persistent launch per {fuse} step(s), HIP graphs of "
                     f"{graph_chunk} steps",
-        "value": cells * steps / (t.ms * 1e-3),
+        "value": cells * steps / (ms * 1e-3),
         "unit": "cell-updates/s",
         "steps": steps,
         "cells": cells,
         "ms_per_step": ms_step,
-        "roofline": alu_roofline(flops_step, ms_step, "f32", traffic_of("c4", used, fuse)),
-        "hbm_equivalent": roofline(bytes_step, ms_step, traffic_of("c4", used, fuse)),
+        "region_ms": [round(x, 4) for x in regions],
+        "roofline": bound_record(bytes_step, flops_step, ms_step, "f32", traffic_of("c4", used, fuse),
+                                 valu_of("c4", used, fuse), fuse),
+        "alu": alu_roofline(flops_step, ms_step, "f32"),
         "steps_per_launch": fuse,
         "algorithmic_bytes_per_launch": fuse * bytes_step,
         "tile": {"seg": used[1], "vec": used[2]},
@@ -466,25 +544,35 @@ def leg_c5(nsteps, every=100, n=512):
     tuned = s.autotune(reps=10, force=True)  # a small grid: the tiles differ from 4096^2's
     ckpt = s.checkpoint_buffer(nsteps, every)
     s.step_ckpt(2, 1, s.checkpoint_buffer(2, 1))  # warm the kernels
-    s.load(phi, mu)
-    with Timer() as tf:
-        s.step_ckpt(nsteps, every, ckpt)
+    fwd = []
+    for _ in range(REGIONS):  # each region: the whole checkpointed run from the initial state
+        s.load(phi, mu)
+        with Timer() as tf:
+            s.step_ckpt(nsteps, every, ckpt)
+        fwd.append(tf.ms)
     lam = torch.zeros_like(s.current())
     lam[: p.nphases] = s.current()[: p.nphases] - target
     loss = 0.5 * float((lam[: p.nphases].double() ** 2).sum())
     s.adjoint(lam, ckpt, 2 * every, every, 0)  # warm
-    with Timer() as ta:
-        _, g = s.adjoint(lam, ckpt, nsteps, every, 0)
+    adj = []
+    for _ in range(REGIONS):
+        with Timer() as ta:
+            _, g = s.adjoint(lam, ckpt, nsteps, every, 0)
+        adj.append(ta.ms)
     s.close()
+    ms_f = sorted(fwd)[len(fwd) // 2]
+    ms_a = sorted(adj)[len(adj) // 2]
     grads = [g["gamma01"], g["gamma02"], g["gamma12"], g["D20"], g["D21"], g["tau"]]
     return {
         "workload": f"2D {n}x{n}, 3 phases, ternary, periodic, FP32 forward + FP32 adjoint, "
                     f"{nsteps} steps, checkpoints every {every}",
         "tile": {k: tuned[k] for k in ("bx", "seg", "vec", "fuse")},
-        "forward_ms": tf.ms,
-        "adjoint_ms": ta.ms,
-        "adjoint_over_forward": ta.ms / tf.ms,
-        "forward_cell_updates_per_s": p.ncells * nsteps / (tf.ms * 1e-3),
+        "forward_ms": ms_f,
+        "adjoint_ms": ms_a,
+        "forward_region_ms": [round(x, 3) for x in fwd],
+        "adjoint_region_ms": [round(x, 3) for x in adj],
+        "adjoint_over_forward": ms_a / ms_f,
+        "forward_cell_updates_per_s": p.ncells * nsteps / (ms_f * 1e-3),
         "loss": loss,
         "grad_theta": dict(zip(["gamma01", "gamma02", "gamma12", "Dliq1", "Dliq2", "tau"],
                                [float(v) for v in grads])),
@@ -492,27 +580,107 @@ def leg_c5(nsteps, every=100, n=512):
     }
 
 
-def cpu_baseline(n, nsteps=2):
-    """The FP64 oracle (numpy: elementwise array passes, one thread) on ``nsteps``
-    full-grid steps of the headline workload."""
+def host_cpu():
+    """The host CPU as lscpu reports it, and the CPUs this process may run on."""
+    import subprocess
+
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    info["usable_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
+_BAND = {}
+
+
+def _band_step(args):
+    """Worker: the oracle's windowed step over rows [lo, hi) of the state in _BAND."""
+    from oracle import gp
+
+    lo, hi, n = args
+    p = _BAND["p"]
+    return lo, gp.step_window(_BAND["phi"], _BAND["mu"], n, p, (lo, 0), (hi, p.n[0]))
+
+
+def oracle_band_steps(phi, mu, n0, nsteps, p, workers):
+    """``nsteps`` oracle steps of a 2D state, each split into ``workers`` row bands
+    stepped in parallel processes by the oracle's windowed step (equal to the
+    full step: it gathers the same ghosts).  Forks, so it runs only in a process
+    that has not touched the GPU."""
+    import multiprocessing
+
+    import numpy as np
+
+    ny = phi.shape[1]
+    bands = [(ny * i // workers, ny * (i + 1) // workers) for i in range(workers)]
+    ctx = multiprocessing.get_context("fork")
+    for k in range(nsteps):
+        _BAND.update(phi=phi, mu=mu, p=p)
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_band_step, [(lo, hi, n0 + k) for lo, hi in bands])
+        nphi, nmu = np.empty_like(phi), np.empty_like(mu)
+        for lo, (f, m) in res:
+            nphi[:, lo:lo + f.shape[1]] = f
+            nmu[:, lo:lo + m.shape[1]] = m
+        phi, mu = nphi, nmu
+    return phi, mu
+
+
+def cpu_baseline_run(n, steps_one=1, steps_all=2, max_workers=16):
+    """The FP64 oracle on the headline workload, on the host's cores: one process
+    (numpy's elementwise passes run on one thread) for ``steps_one`` full-grid
+    steps, and ``workers`` processes (the usable CPUs, at most ``max_workers``)
+    stepping row bands for ``steps_all`` steps."""
     from oracle import gp
     from paper_2404_01035_amd import inputs
 
     p, phi, mu = inputs.config_c2(precision="f64", n=(n, n, 1))
+    host = host_cpu()
     t0 = time.perf_counter()
-    gp.run(phi, mu, 0, nsteps, p)
-    dt = time.perf_counter() - t0
+    gp.run(phi, mu, 0, steps_one, p)
+    t_one = time.perf_counter() - t0
+    workers = max(1, min(max_workers, host["usable_cpus"]))
+    t0 = time.perf_counter()
+    oracle_band_steps(phi, mu, 0, steps_all, p, workers)
+    t_all = time.perf_counter() - t0
     return {
-        "value": p.ncells * nsteps / dt,
+        "value": p.ncells * steps_all / t_all,
         "unit": "cell-updates/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": f"{nsteps} steps of the full {n}x{n} grid, FP64 numpy oracle ({dt:.1f} s)",
+        "sample": f"{steps_all} steps of the full {n}x{n} FP64 grid, each split into {workers} row bands "
+                  f"stepped by the oracle's windowed step in {workers} processes ({t_all:.1f} s)",
+        "single_thread": {"value": p.ncells * steps_one / t_one, "cores": 1,
+                          "sample": f"{steps_one} full-grid step(s) in one process ({t_one:.1f} s)"},
+        "host": host,
     }
+
+
+def cpu_baseline(n):
+    """cpu_baseline_run in a child process that never touches the GPU (it forks
+    workers, which a process holding a GPU context must not do)."""
+    import subprocess
+
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--n", str(n)],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log(f"CPU baseline failed: {r.stderr[-500:]}")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
     a = parse()
+    if a.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_run(a.n)), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)
@@ -550,7 +718,11 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r64["roofline"],
-        "hbm_equivalent": r64["hbm_equivalent"],
+        "alu": r64["alu"],
+        "region_ms": r64["region_ms"],
+        "settle_steps": r64["settle_steps"],
+        "timing": f"median of {REGIONS} timed regions of exactly --steps steps each, after --warmup "
+                  f"steps and untimed steps until {SETTLE_MS:.0f} ms had passed",
         "flops_per_cell_update": r64["flops_per_cell_update"],
         "steps_per_launch": r64["steps_per_launch"],
         "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_launch"],

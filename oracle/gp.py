@@ -170,37 +170,148 @@ def dw(phi, p):
     return np.stack(out)
 
 
+def is_obstacle(p):
+    """Both obstacle variants use the potential of Eq. Obstacle."""
+    return p.potential in ("obstacle", "obstacle_active")
+
+
+def extended(p):
+    """True when the parameters use temperature-dependent B or C, off-diagonal
+    A or D, per-pair relaxation constants or the active-set obstacle."""
+    N, K1 = p.nphases, p.nmu
+    return bool(np.any(np.asarray(p.Bt)[:N, :K1] != 0.0) or np.any(np.asarray(p.Ct)[:N] != 0.0)
+                or np.any(np.asarray(p.A01)[:N] != 0.0) or np.any(np.asarray(p.D01)[:N] != 0.0)
+                or np.any(np.asarray(p.tau_ab)[:N, :N] != 0.0) or p.potential == "obstacle_active")
+
+
+def hessian(p):
+    """H^a_kj = d^2 f^a / (dc_k dc_j) of Eq. free_energy_density, read with i <= j:
+    2 A^a_k on the diagonal and A^a_01 off it; shape (N, K-1, K-1)."""
+    N, K1 = p.nphases, p.nmu
+    H = np.zeros((N, K1, K1), dtype=np.result_type(np.asarray(p.A), np.asarray(p.A01)))
+    for a in range(N):
+        for k in range(K1):
+            H[a, k, k] = 2.0 * p.A[a][k]
+        if K1 == 2:
+            H[a, 0, 1] = H[a, 1, 0] = p.A01[a]
+    return H
+
+
+def chi_matrix(p):
+    """Susceptibilities dc^a/dmu = (H^a)^-1, shape (N, K-1, K-1) (a library inverse)."""
+    return np.linalg.inv(hessian(p))
+
+
 def chi_phase(p):
-    """Susceptibility dc^a_k/dmu_k = 1/(2 A^a_k) of the diagonal parabolic free energy."""
+    """Diagonal susceptibility dc^a_k/dmu_k = 1/(2 A^a_k) (no off-diagonal A)."""
+    if p.nmu == 2 and np.any(np.asarray(p.A01)[: p.nphases] != 0.0):
+        raise ValueError("chi_phase: off-diagonal A; use chi_matrix")
     return 1.0 / (2.0 * np.asarray(p.A)[: p.nphases, : p.nmu])
 
 
-def c_phase(mu, p):
-    """Phase compositions c^a_k(mu) = (mu_k - B^a_k) / (2 A^a_k); shape (N, K-1, ...)."""
-    A = np.asarray(p.A)
-    B = np.asarray(p.B)
-    return np.stack([np.stack([(mu[k] - B[a][k]) / (2.0 * A[a][k]) for k in range(p.nmu)])
+def _t_dependent(p):
+    return bool(np.any(np.asarray(p.Bt)[: p.nphases, : p.nmu] != 0.0))
+
+
+def B_of_T(p, T):
+    """B^a_k(T) = B^a_k + Bt^a_k (T - Te); shape (N, K-1) + shape of T."""
+    T = np.asarray(T)
+    return np.stack([np.stack([p.B[a][k] + p.Bt[a][k] * (T - p.Te) for k in range(p.nmu)])
                      for a in range(p.nphases)])
 
 
-def free_energy(c, a, p):
-    """f^a(c) = sum_k A^a_k c_k^2 + B^a_k c_k + C^a (Eq. free_energy_density, V_m = 1)."""
-    out = p.C[a]
+def C_of_T(p, T):
+    """C^a(T) = C^a + s^a (T - Te) + Ct^a (T - Te)^2; shape (N,) + shape of T."""
+    T = np.asarray(T)
+    return np.stack([p.C[a] + p.s[a] * (T - p.Te) + p.Ct[a] * (T - p.Te) ** 2 for a in range(p.nphases)])
+
+
+def c_phase(mu, p, T=None):
+    """Phase compositions c^a(mu, T) = chi^a (mu - B^a(T)), the stationary point of
+    f^a(c) - mu . c; shape (N, K-1, ...).  T may be omitted when B does not
+    depend on temperature."""
+    if T is None:
+        if _t_dependent(p):
+            raise ValueError("c_phase: B depends on T; pass T")
+        T = p.Te
+    chi = chi_matrix(p)
+    Bm = B_of_T(p, T)
+    out = []
+    for a in range(p.nphases):
+        comp = []
+        for k in range(p.nmu):
+            acc = 0.0
+            for j in range(p.nmu):
+                acc = acc + chi[a, k, j] * (mu[j] - Bm[a][j])
+            comp.append(acc)
+        out.append(np.stack(comp))
+    return np.stack(out)
+
+
+def free_energy(c, a, p, T=None):
+    """f^a(c) = sum_k A^a_k c_k^2 + A^a_01 c_0 c_1 + sum_k B^a_k(T) c_k + C^a(T)
+    (Eq. free_energy_density with V_m = 1, read with i <= j)."""
+    if T is None:
+        if _t_dependent(p) or np.any(np.asarray(p.Ct) != 0.0):
+            raise ValueError("free_energy: coefficients depend on T; pass T")
+        T = p.Te
+    Bm = B_of_T(p, T)
+    out = C_of_T(p, T)[a]
     for k in range(p.nmu):
-        out = out + p.A[a][k] * c[k] ** 2 + p.B[a][k] * c[k]
+        out = out + p.A[a][k] * c[k] ** 2 + Bm[a][k] * c[k]
+    if p.nmu == 2:
+        out = out + p.A01[a] * c[0] * c[1]
     return out
 
 
 def psi_phase(mu, T, p):
-    """Grand potentials psi^a(mu, T) = f^a(c^a) - mu . c^a plus s^a (T - Te); shape (N, ...)."""
-    ca = c_phase(mu, p)
+    """Grand potentials psi^a(mu, T) = f^a(c^a(mu, T); T) - mu . c^a; shape (N, ...)."""
+    ca = c_phase(mu, p, T)
     out = []
     for a in range(p.nphases):
-        val = free_energy(ca[a], a, p)
+        val = free_energy(ca[a], a, p, T)
         for k in range(p.nmu):
             val = val - mu[k] * ca[a][k]
-        out.append(val + p.s[a] * (T - p.Te))
+        out.append(val)
     return np.stack(out)
+
+
+def dc_dT(p):
+    """(dc^a_k/dT) at fixed mu = -(chi^a Bt^a)_k; shape (N, K-1)."""
+    chi = chi_matrix(p)
+    return np.stack([-(chi[a] @ np.asarray(p.Bt[a][: p.nmu], dtype=np.float64)) for a in range(p.nphases)])
+
+
+def diffusivity(p):
+    """D^a as (K-1) x (K-1) matrices: D^a_kk on the diagonal, D^a_01 off it."""
+    N, K1 = p.nphases, p.nmu
+    D = np.zeros((N, K1, K1), dtype=np.result_type(np.asarray(p.D), np.asarray(p.D01)))
+    for a in range(N):
+        for k in range(K1):
+            D[a, k, k] = p.D[a][k]
+        if K1 == 2:
+            D[a, 0, 1] = D[a, 1, 0] = p.D01[a]
+    return D
+
+
+def relaxation(phi, p):
+    """tau of Eq. phi_eqn at every cell.  With per-pair constants tau_ab (the Tau
+    key of Sec. 5) it is their weighted mean
+        tau(phi) = sum_{a<b} tau_ab phi_a phi_b / sum_{a<b} phi_a phi_b,
+    falling back to the single tau where the pair sum is <= 1e-30 (bulk);
+    otherwise the single tau."""
+    N = p.nphases
+    pairs = [(a, b) for a in range(N) for b in range(a + 1, N)]
+    if not any(p.tau_ab[a][b] != 0.0 for a, b in pairs):
+        return p.tau + 0.0 * phi[0]
+    num = 0.0 * phi[0]
+    den = 0.0 * phi[0]
+    for a, b in pairs:
+        w = phi[a] * phi[b]
+        num = num + p.tau_ab[a][b] * w
+        den = den + w
+    ok = np.real(den) > 1e-30
+    return np.where(ok, num / np.where(ok, den, 1.0), p.tau)
 
 
 def temperature(p, n, shape, y_origin=0):
@@ -248,6 +359,29 @@ def obstacle_clip(phin):
     again.  phin has the phase index first."""
     out = np.clip(phin, 0.0, 1.0)
     return out / out.sum(axis=0, keepdims=True)
+
+
+def simplex_projection(y):
+    """Projection of the active-set obstacle step: every cell's (y_a) goes to the
+    nearest point (Euclidean) of the simplex {phi_a >= 0, sum_a phi_a = 1}.  The
+    active set starts as all phases; the multiplier shift theta = (sum over the
+    active set of y - 1) / (its size) is subtracted from the active phases, and
+    phases that come out negative leave the set (set to 0) until none does.
+    In the terms of Eq. phi_eqn: lambda is the mean of the right-hand sides over
+    the phases that stay present, plus the share of the mass of the phases that
+    left.  y has the phase index first."""
+    N = y.shape[0]
+    active = np.ones(np.shape(y), dtype=bool)
+    x = y
+    for _ in range(N):
+        cnt = active.sum(axis=0)
+        theta = (np.where(active, y, 0.0).sum(axis=0) - 1.0) / cnt
+        x = np.where(active, y - theta, 0.0)
+        neg = active & (np.real(x) < 0.0)
+        if not neg.any():
+            break
+        active = active & ~neg
+    return x
 
 
 def _faces(Pphi, p):
@@ -311,38 +445,57 @@ def _rhs_padded(Pphi, Pmu, n, p, y_origin=0):
 def _step_padded(Pphi, Pmu, n, p, y_origin=0):
     """One forward-Euler step of (phi, mu) on the interior of padded fields."""
     nd = p.dim
-    N = p.nphases
+    N, K1 = p.nphases, p.nmu
     phi = _sub(Pphi, nd, {})
     mu = _sub(Pmu, nd, {})
     # phase fields
     R = _rhs_padded(Pphi, Pmu, n, p, y_origin)
     lam = sum(R[a] for a in range(N)) / N
-    phin = phi + p.dt * (R - lam) / (p.tau * p.eps)
+    phin = phi + p.dt * (R - lam) / (relaxation(phi, p) * p.eps)
     if p.potential == "obstacle":
         phin = obstacle_clip(phin)
-    # diffusion potentials
-    chi = chi_phase(p)
-    D = np.asarray(p.D)[:N, : p.nmu]
+    elif p.potential == "obstacle_active":
+        phin = simplex_projection(phin)
+    # diffusion potentials: M = sum_b h_b(phi^n) D^b chi^b per cell, face value
+    # the mean of the two cells, J = M_face grad mu
+    chi = chi_matrix(p)
+    Dm = diffusivity(p)
     hP = h(Pphi)
-    div = [0.0 * mu[k] for k in range(p.nmu)]
-    for k in range(p.nmu):
-        M = sum(D[b][k] * chi[b][k] * hP[b] for b in range(N))[None]
+    DC = np.stack([Dm[b] @ chi[b] for b in range(N)])
+    div = [0.0 * mu[k] for k in range(K1)]
+    for k in range(K1):
         for a, _ in spatial_axes(p):
-            ML = _sub(M, nd, {a: slice(0, -1)})[0]
-            MR = _sub(M, nd, {a: slice(1, None)})[0]
-            muL = _sub(Pmu[k:k + 1], nd, {a: slice(0, -1)})[0]
-            muR = _sub(Pmu[k:k + 1], nd, {a: slice(1, None)})[0]
-            J = 0.5 * (ML + MR) * (muR - muL) / p.dx
-            div[k] = div[k] + (_along(J, a, slice(1, None)) - _along(J, a, slice(0, -1))) / p.dx
+            for jj in range(K1):
+                M = sum(DC[b, k, jj] * hP[b] for b in range(N))[None]
+                ML = _sub(M, nd, {a: slice(0, -1)})[0]
+                MR = _sub(M, nd, {a: slice(1, None)})[0]
+                muL = _sub(Pmu[jj:jj + 1], nd, {a: slice(0, -1)})[0]
+                muR = _sub(Pmu[jj:jj + 1], nd, {a: slice(1, None)})[0]
+                J = 0.5 * (ML + MR) * (muR - muL) / p.dx
+                div[k] = div[k] + (_along(J, a, slice(1, None)) - _along(J, a, slice(0, -1))) / p.dx
+    T0 = temperature(p, n, phi.shape[1:], y_origin)
+    T1 = temperature(p, n + 1, phi.shape[1:], y_origin)
     h0 = h(phi)
     h1 = h(phin)
-    ca = c_phase(mu, p)
-    mun = []
-    for k in range(p.nmu):
+    ca = c_phase(mu, p, T0)
+    dcdT = dc_dT(p)
+    rhs = []
+    for k in range(K1):
         src = sum(ca[b][k] * (h1[b] - h0[b]) for b in range(N))
-        chik = sum(h1[b] * chi[b][k] for b in range(N))
-        mun.append(mu[k] + (p.dt * div[k] - src) / chik)
-    return phin, np.stack(mun)
+        # the dT/dt term of Eq. Mu_explicit_temperature, at h(phi^{n+1})
+        theta = sum(h1[b] * dcdT[b][k] for b in range(N)) * (T1 - T0)
+        rhs.append(p.dt * div[k] - src - theta)
+    # [sum_b h_b(phi^{n+1}) chi^b] dmu = rhs
+    if K1 == 1:
+        chik = sum(h1[b] * chi[b, 0, 0] for b in range(N))
+        return phin, np.stack([mu[0] + rhs[0] / chik])
+    chit = np.empty(phi.shape[1:] + (2, 2), dtype=np.result_type(h1, chi))
+    for k in range(2):
+        for jj in range(2):
+            chit[..., k, jj] = sum(h1[b] * chi[b, k, jj] for b in range(N))
+    rv = np.stack(rhs, axis=-1)[..., None]
+    dmu = np.linalg.solve(chit, rv)[..., 0]
+    return phin, np.stack([mu[k] + dmu[..., k] for k in range(2)])
 
 
 def rhs_phi(phi, mu, n, p):
@@ -350,15 +503,16 @@ def rhs_phi(phi, mu, n, p):
     return _rhs_padded(pad(phi, p), pad(mu, p), n, p)
 
 
-def step(phi, mu, n, p):
-    """One step from time level n: returns (phi^{n+1}, mu^{n+1})."""
-    return _step_padded(pad(phi, p), pad(mu, p), n, p)
+def step(phi, mu, n, p, y_origin=0):
+    """One step from time level n: returns (phi^{n+1}, mu^{n+1}).  y_origin: the
+    frame's offset in rows (cell j sits at y = (j + y_origin) dx; see ``shift``)."""
+    return _step_padded(pad(phi, p), pad(mu, p), n, p, y_origin)
 
 
-def run(phi, mu, n0, nsteps, p):
+def run(phi, mu, n0, nsteps, p, y_origin=0):
     """nsteps steps starting at time level n0."""
     for i in range(nsteps):
-        phi, mu = step(phi, mu, n0 + i, p)
+        phi, mu = step(phi, mu, n0 + i, p, y_origin)
     return phi, mu
 
 
@@ -370,7 +524,7 @@ def _ghost_index(lo, hi, n, bc):
     return np.clip(idx, 0, n - 1)
 
 
-def step_window(phi, mu, n, p, lo, hi):
+def step_window(phi, mu, n, p, lo, hi, y_origin=0):
     """One step evaluated only on the box lo <= index < hi (array order, spatial axes).
 
     Gathers the box plus a one-cell rim with the same ghost rule as ``pad`` and
@@ -386,7 +540,7 @@ def step_window(phi, mu, n, p, lo, hi):
     # promote (e.g. an FP32 state) so the window is stepped in FP64 or complex
     Pphi = np.asarray(phi[(slice(None),) + grid], dtype=np.result_type(phi, np.float64))
     Pmu = np.asarray(mu[(slice(None),) + grid], dtype=np.result_type(mu, np.float64))
-    return _step_padded(Pphi, Pmu, n, p, y_origin=lo[-2])
+    return _step_padded(Pphi, Pmu, n, p, y_origin=y_origin + lo[-2])
 
 
 # ----------------------------------------------------------------------------
@@ -419,20 +573,23 @@ def energy(phi, mu, n, p):
     return p.dx ** nd * (p.eps * Eg + np.sum(bulk))
 
 
-def composition(phi, mu, p):
-    """Mixture composition c_k = sum_a h_a(phi) c^a_k(mu) (the composition constraint of Sec. 2.1)."""
+def composition(phi, mu, p, n=0, y_origin=0):
+    """Mixture composition c_k = sum_a h_a(phi) c^a_k(mu, T) (the composition
+    constraint of Sec. 2.1), T that of time level n."""
     hh = h(phi)
-    ca = c_phase(mu, p)
+    ca = c_phase(mu, p, temperature(p, n, phi.shape[1:], y_origin))
     return np.stack([sum(hh[a] * ca[a][k] for a in range(p.nphases)) for k in range(p.nmu)])
 
 
-def diagnostics(phi, mu, p):
-    """Reference values of the diagnostics reductions (plain FP64 sums)."""
+def diagnostics(phi, mu, p, n=0, y_origin=0):
+    """Reference values of the diagnostics reductions (plain FP64 sums) of the
+    state at time level n; min_chi is the smallest diagonal entry
+    sum_a h_a (chi^a)_kk."""
     vol = p.dx ** p.dim
-    c = composition(phi, mu, p)
+    c = composition(phi, mu, p, n, y_origin)
     hh = h(phi)
-    chi = chi_phase(p)
-    chik = np.stack([sum(hh[a] * chi[a][k] for a in range(p.nphases)) for k in range(p.nmu)])
+    chi = chi_matrix(p)
+    chik = np.stack([sum(hh[a] * chi[a, k, k] for a in range(p.nphases)) for k in range(p.nmu)])
     finite = np.isfinite(phi).all(axis=0) & np.isfinite(mu).all(axis=0)
     return {
         "max_sum_dev": float(np.max(np.abs(phi.sum(axis=0) - 1.0))),
@@ -488,6 +645,9 @@ def adjoint_step(phi, mu, n, p, lphi1, lmu1):
     """
     if p.potential != "well":
         raise ValueError("adjoint: the obstacle projection is not differentiable")
+    if extended(p):
+        raise ValueError("adjoint: temperature-dependent B/C, off-diagonal A/D and per-pair tau "
+                         "are not supported")
     N, K1, nd = p.nphases, p.nmu, p.dim
     if any(p.delta[i][j] != 0.0 for i in range(N) for j in range(i + 1, N)):
         raise ValueError("adjoint: anisotropic gradient energy not supported")
@@ -682,7 +842,7 @@ def at_prefactor(phi0, p):
     h(phi0) = phi0^2 (3 - 2 phi0); it tends to 0 at phi0 = 0 and 1 and is taken
     as 0 outside (0, 1).
     """
-    if p.potential != "obstacle":
+    if not is_obstacle(p):
         return p.eps / (2.0 * np.sqrt(2.0)) + 0.0 * phi0
     inside = (phi0 > 0.0) & (phi0 < 1.0)
     f = np.where(inside, phi0, 0.5)
@@ -709,21 +869,25 @@ def _face_gradient(Pf, p, a):
     return comps
 
 
-def antitrapping_faces(phi, phin, mu, p):
+def antitrapping_faces(phi, phin, mu, p, n=0, y_origin=0, T=None):
     """Per axis a: (a, j) with j the normal component of j_at on the faces normal
     to a, shape (K-1, ..., n_a + 1, ...).
 
     Eq. jatr summed over the solid phases (the liquid is the last phase):
         j_k = sum_{a < N-1} P(phi_a) (c^a_k - c^liq_k) dphi_a/dt n_a . e_axis (-n_a . n_liq),
     n = grad phi / |grad phi| from phi^n.  On a face, dphi_a/dt = (phi^{n+1} - phi^n)/dt,
-    c^a(mu^n) and the prefactor's phi are means of the two cells; the gradient
-    is ``_face_gradient``.
+    c^a(mu^n, T^n) and the prefactor's phi are means of the two cells (a ghost
+    cell takes the c^a of the cell it stands for); the gradient is
+    ``_face_gradient``.  T: temperature of phi's cells (default: that of time
+    level n in the frame y_origin).
     """
     nd = p.dim
     N = p.nphases
     liq = N - 1
-    Pphi, Pphin, Pmu = pad(phi, p), pad(phin, p), pad(mu, p)
-    Pc = c_phase(Pmu, p)
+    Pphi, Pphin = pad(phi, p), pad(phin, p)
+    if T is None:
+        T = temperature(p, n, phi.shape[1:], y_origin)
+    Pc = pad(c_phase(mu, p, T), p)
     out = []
     for a, _ in spatial_axes(p):
         def mean(F):
@@ -748,22 +912,33 @@ def antitrapping_faces(phi, phin, mu, p):
     return out
 
 
-def step_antitrapping(phi, mu, n, p):
-    """One step with the anti-trapping current in Eq. Mu_explicit_temperature:
-        mu^{n+1} = mu^n + (dt div(M grad mu - j_at) - sum_a c^a(mu^n) [h_a(phi^{n+1}) - h_a(phi^n)]) / chi.
-    phi^{n+1} is that of ``step``; j_at is ``antitrapping_faces`` of (phi^n, phi^{n+1}, mu^n)."""
-    phin, mun = step(phi, mu, n, p)
-    chi = chi_phase(p)
+def _correct_mu(mun, phin, div, p):
+    """mu^{n+1} - dt chi(phi^{n+1})^-1 div j_at, chi = sum_b h_b chi^b."""
+    chi = chi_matrix(p)
     h1 = h(phin)
-    out = []
+    N, K1 = p.nphases, p.nmu
+    if K1 == 1:
+        chik = sum(h1[b] * chi[b, 0, 0] for b in range(N))
+        return np.stack([mun[0] - p.dt * div[0] / chik])
+    chit = np.empty(phin.shape[1:] + (2, 2), dtype=np.result_type(h1, chi))
+    for k in range(2):
+        for jj in range(2):
+            chit[..., k, jj] = sum(h1[b] * chi[b, k, jj] for b in range(N))
+    d = np.linalg.solve(chit, np.stack([p.dt * div[0], p.dt * div[1]], axis=-1)[..., None])[..., 0]
+    return np.stack([mun[k] - d[..., k] for k in range(2)])
+
+
+def step_antitrapping(phi, mu, n, p, y_origin=0):
+    """One step with the anti-trapping current in Eq. Mu_explicit_temperature:
+        mu^{n+1} = mu^n + chi^-1 (dt div(M grad mu - j_at) - sum_a c^a(mu^n) [h_a(phi^{n+1}) - h_a(phi^n)] - Theta).
+    phi^{n+1} and the rest of mu^{n+1} are those of ``step``; j_at is
+    ``antitrapping_faces`` of (phi^n, phi^{n+1}, mu^n)."""
+    phin, mun = step(phi, mu, n, p, y_origin)
     div = [0.0 * mu[k] for k in range(p.nmu)]
-    for a, j in antitrapping_faces(phi, phin, mu, p):
+    for a, j in antitrapping_faces(phi, phin, mu, p, n, y_origin):
         for k in range(p.nmu):
             div[k] = div[k] + (_along(j[k], a, slice(1, None)) - _along(j[k], a, slice(0, -1))) / p.dx
-    for k in range(p.nmu):
-        chik = sum(h1[b] * chi[b][k] for b in range(p.nphases))
-        out.append(mun[k] - p.dt * div[k] / chik)
-    return phin, np.stack(out)
+    return phin, _correct_mu(mun, phin, div, p)
 
 
 def _runs(idx):
@@ -777,7 +952,7 @@ def _runs(idx):
     return out
 
 
-def step_antitrapping_window(phi, mu, n, p, lo, hi):
+def step_antitrapping_window(phi, mu, n, p, lo, hi, y_origin=0):
     """``step_antitrapping`` evaluated only on the box lo <= index < hi (array order).
 
     The current of a box cell needs phi^{n+1} of its face neighbours: the box
@@ -802,23 +977,63 @@ def step_antitrapping_window(phi, mu, n, p, lo, hi):
     for pieces in itertools.product(*[_runs(i) for i in ix]):
         wlo = tuple(r[1] for r in pieces)
         whi = tuple(r[2] for r in pieces)
-        f, m = step_window(phi, mu, n, p, wlo, whi)
+        f, m = step_window(phi, mu, n, p, wlo, whi, y_origin)
         dst = (slice(None),) + tuple(slice(r[0], r[0] + r[2] - r[1]) for r in pieces)
         Pphin[dst] = f
         Pmun[dst] = m
     box = (slice(None),) + (slice(1, -1),) * nd
+    # temperature of each patch cell: that of the grid row it stands for
+    yrows = ix[-2].reshape((-1, 1) if nd == 2 else (1, -1, 1))
+    Tp = np.broadcast_to(p.T0 + p.G * ((yrows + y_origin) * p.dx - p.y0 - p.V * (n * p.dt)), Pphi.shape[1:])
     div = 0.0
-    for a, j in antitrapping_faces(Pphi, Pphin, Pmu, p):
+    for a, j in antitrapping_faces(Pphi, Pphin, Pmu, p, T=Tp):
         L = j.shape[a]  # faces along a: the patch's cells + 1; box cells sit at 1 .. L - 3
         hi_f = _sub(_along(j, a, slice(2, L - 1)), nd, {a: slice(None)})
         lo_f = _sub(_along(j, a, slice(1, L - 2)), nd, {a: slice(None)})
         div = div + (hi_f - lo_f) / p.dx
     phin = Pphin[box]
     mun = Pmun[box]
-    chi = chi_phase(p)
-    h1 = h(phin)
-    out = []
-    for k in range(p.nmu):
-        chik = sum(h1[b] * chi[b][k] for b in range(p.nphases))
-        out.append(mun[k] - p.dt * div[k] / chik)
-    return phin, np.stack(out)
+    return phin, _correct_mu(mun, phin, [div[k] for k in range(p.nmu)], p)
+
+
+# ----------------------------------------------------------------------------
+# Moving frame (the SHIFT / Shiftj keys of Sec. 5; the moving box of the
+# directional-solidification examples): solid rows leave the domain at the
+# bottom and melt of the original alloy composition enters at the top.
+# ----------------------------------------------------------------------------
+
+def front_row(phi):
+    """Highest row index (y, the second-slowest array axis in 3D, the slowest in
+    2D) holding a cell whose liquid fraction (the last phase) is below 1/2; -1
+    if there is none."""
+    liq = phi[-1]
+    yax = liq.ndim - 2  # y is axis 0 of (ny, nx) and axis 1 of (nz, ny, nx)
+    other = tuple(i for i in range(liq.ndim) if i != yax)
+    rows = np.nonzero(np.any(np.real(liq) < 0.5, axis=other))[0]
+    return int(rows[-1]) if rows.size else -1
+
+
+def shift(phi, mu, s, mu_melt):
+    """Shift the frame up by s >= 0 rows along y: row j takes row j + s, the top
+    s rows become melt (liquid fraction 1, mu = mu_melt per component).  After
+    it the grid's row j stands at y = (j + y_origin + s) dx, so the caller adds
+    s to the frame offset it passes to ``step``."""
+    nd = phi.ndim - 1
+    yax = 1 if nd == 2 else 2
+    ny = phi.shape[yax]
+    s = int(s)
+    if s < 0 or s > ny:
+        raise ValueError("shift: s must lie in [0, ny]")
+    keep = [slice(None)] * phi.ndim
+    keep[yax] = slice(s, ny)
+    melt_shape = list(phi.shape)
+    melt_shape[yax] = s
+    mphi = np.zeros(melt_shape, dtype=phi.dtype)
+    mphi[-1] = 1.0
+    mu_shape = list(mu.shape)
+    mu_shape[yax] = s
+    mmu = np.empty(mu_shape, dtype=mu.dtype)
+    for k in range(mu.shape[0]):
+        mmu[k] = mu_melt[k]
+    return (np.concatenate([phi[tuple(keep)], mphi], axis=yax),
+            np.concatenate([mu[tuple(keep)], mmu], axis=yax))

@@ -14,8 +14,19 @@ Parameter meaning follows the grand-potential model of MICROSIM
 * ``A, B, C``      diagonal parabolic free-energy coefficients per phase and
                    independent component, f^a(c) = sum_k A_k c_k^2 + B_k c_k + C
                    (Eq. free_energy_density with V_m = 1)
-* ``s``            slope of C^a with temperature, C^a(T) = C^a + s^a (T - Te)
-* ``D``            diagonal diffusivity per phase and component (Eq. Mass_conservation)
+* ``s``            slope of C^a with temperature, C^a(T) = C^a + s^a (T - Te) + Ct^a (T - Te)^2
+* ``Bt``, ``Ct``   temperature dependence of the parabolic coefficients (Sec. 3: B and C
+                   as functions of T from the slopes of the coexistence lines):
+                   B^a_k(T) = B^a_k + Bt^a_k (T - Te); zero by default
+* ``A01``          off-diagonal curvature A^a_01 of Eq. free_energy_density (i < j term,
+                   K = 3 only): f^a gains A01 c_0 c_1; zero by default
+* ``D``            diffusivity per phase and component (Eq. Mass_conservation); ``D01``
+                   its symmetric off-diagonal entry D^a_01 = D^a_10 (K = 3), zero by default
+* ``tau_ab``       relaxation constant per phase pair (the Tau key of Sec. 5); all zero
+                   (the default) means the single ``tau`` everywhere
+* ``potential``    "well" (Eq. Well), "obstacle" (Eq. Obstacle; clip-and-renormalise
+                   projection) or "obstacle_active" (Eq. Obstacle with the Lagrange
+                   multiplier over the active phases: projection onto the simplex)
 * ``Te``           temperature at which C^a is given (Equilibrium_temperature, Sec. 5)
 * ``T0, G, V, y0`` frozen, translating temperature field
                    T(y, t) = T0 + G (y - y0 - V t) (the Tempgrady input of Sec. 5:
@@ -54,7 +65,7 @@ class Params:
     nphases: int = 2                # N, the liquid is the last phase
     ncomp: int = 2                  # K, components; K - 1 independent mu fields
     precision: str = "f64"          # "f64" | "f32"
-    potential: str = "well"         # "well" | "obstacle"
+    potential: str = "well"         # "well" | "obstacle" | "obstacle_active"
     eps: float = 4.0
     tau: float = 1.0
     dt: float = 0.05
@@ -66,6 +77,11 @@ class Params:
     C: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
     s: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
     D: np.ndarray = field(default_factory=lambda: np.zeros((MAX_PHASES, MAX_MU)))
+    Bt: np.ndarray = field(default_factory=lambda: np.zeros((MAX_PHASES, MAX_MU)))
+    Ct: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    A01: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    D01: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    tau_ab: np.ndarray = field(default_factory=_z33)
     Te: float = 1.0
     T0: float = 1.0
     G: float = 0.0
@@ -91,7 +107,7 @@ class Params:
 
     def copy(self, **kw) -> "Params":
         p = replace(self, **kw)
-        for name in ("gamma", "delta", "A", "B", "C", "s", "D"):
+        for name in ("gamma", "delta", "A", "B", "C", "s", "D", "Bt", "Ct", "A01", "D01", "tau_ab"):
             if name not in kw:
                 setattr(p, name, np.array(getattr(self, name), dtype=np.float64))
         return p
@@ -127,6 +143,72 @@ def parabolic_coefficients(A, ceq, liquid):
     return B, C
 
 
+def hessians(A, A01=None):
+    """Curvature matrices H^a = d^2 f^a / dc dc of Eq. free_energy_density read with
+    i <= j: 2 A^a_k on the diagonal and A^a_01 off it; shape (N, K-1, K-1)."""
+    A = np.asarray(A, dtype=np.float64)
+    npha, K1 = A.shape
+    H = np.zeros((npha, K1, K1))
+    for a in range(npha):
+        for k in range(K1):
+            H[a, k, k] = 2.0 * A[a, k]
+        if K1 == 2 and A01 is not None:
+            H[a, 0, 1] = H[a, 1, 0] = float(A01[a])
+    return H
+
+
+def parabolic_coefficients_T(A, ceq, slopes, liquid, A01=None):
+    """B(T), C(T) of the parabolic free energies from curvatures, equilibrium
+    compositions at Te and the slopes of the coexistence lines (Sec. 3).
+
+    The equilibrium compositions move linearly with temperature,
+    c^a_eq(T) = ceq^a + (T - Te) / slopes^a (slopes = dT/dc per phase and
+    component), and every solid a is put in equilibrium with the liquid at each T
+    by Eq. Coeff_B and Eq. Coeff_C with the liquid as reference (B^l = C^l = 0):
+    B^a = H^l c^l_eq - H^a c^a_eq (H of ``hessians``; the cross-term sign as the
+    equal-mu condition gives it) and C^a = (c^a_eq H^a c^a_eq - c^l_eq H^l c^l_eq) / 2.
+    B is then linear in T and C quadratic.  The common linear term -mu_e . c,
+    mu_e = H^l ceq^l, is subtracted from every phase (a gauge: it shifts mu
+    only), so all phases coexist at mu = 0 at Te.  Returns (B, Bt, C, s, Ct)
+    with B^a(T) = B^a + Bt^a (T - Te) and C^a(T) = C^a + s^a (T - Te) + Ct^a (T - Te)^2.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    ceq = np.asarray(ceq, dtype=np.float64)
+    u = 1.0 / np.asarray(slopes, dtype=np.float64)
+    npha, K1 = A.shape
+    H = hessians(A, A01)
+    B = np.zeros((npha, K1))
+    Bt = np.zeros((npha, K1))
+    C = np.zeros(npha)
+    s = np.zeros(npha)
+    Ct = np.zeros(npha)
+    l = liquid
+    for a in range(npha):
+        if a == l:
+            continue
+        B[a] = H[l] @ ceq[l] - H[a] @ ceq[a]
+        Bt[a] = H[l] @ u[l] - H[a] @ u[a]
+        C[a] = 0.5 * (ceq[a] @ H[a] @ ceq[a] - ceq[l] @ H[l] @ ceq[l])
+        s[a] = u[a] @ H[a] @ ceq[a] - u[l] @ H[l] @ ceq[l]
+        Ct[a] = 0.5 * (u[a] @ H[a] @ u[a] - u[l] @ H[l] @ u[l])
+    mu_e = H[l] @ ceq[l]
+    B = B - mu_e[None, :]
+    return B, Bt, C, s, Ct
+
+
+def _sym2_min_eig(a, b, c):
+    """Smaller eigenvalue of the symmetric 2 x 2 matrix [[a, b], [b, c]]."""
+    return 0.5 * (a + c) - math.sqrt(0.25 * (a - c) ** 2 + b * b)
+
+
+def _norm2_2x2(m):
+    """Spectral norm of a 2 x 2 matrix: the square root of the larger eigenvalue of m^T m."""
+    a = m[0][0] * m[0][0] + m[1][0] * m[1][0]
+    b = m[0][0] * m[0][1] + m[1][0] * m[1][1]
+    c = m[0][1] * m[0][1] + m[1][1] * m[1][1]
+    return math.sqrt(0.5 * (a + c) + math.sqrt(0.25 * (a - c) ** 2 + b * b))
+
+
 def dt_limit(p: Params) -> float:
     """Explicit (forward Euler) stability limit used to size dt.
 
@@ -134,7 +216,11 @@ def dt_limit(p: Params) -> float:
     coefficient at most 2 gamma_max (N-1)/N / tau, raised by a margin of
     (1 + 20 delta_max) for the anisotropic stiffness.  Diffusion potentials: the
     mu equation is a diffusion with coefficient M/chi <= max_a(D^a chi^a) / min_a chi^a.
-    The FTCS bound dx^2 / (2 d coefficient) applies to both.
+    The FTCS bound dx^2 / (2 d coefficient) applies to both.  With per-pair
+    relaxation constants the smallest of them (and tau) counts.  With
+    off-diagonal A or D (K = 3) the mu coefficient is the matrix chi^-1 M, whose
+    eigenvalues are at most max_a |D^a chi^a|_2 / min_a lambda_min(chi^a)
+    (sum_a h_a = 1, h_a >= 0 on the simplex).
     """
     N, K1, d = p.nphases, p.nmu, p.dim
     g = np.asarray(p.gamma)[:N, :N]
@@ -143,10 +229,24 @@ def dt_limit(p: Params) -> float:
     dmax = float(np.max(np.abs(dl[np.triu_indices(N, 1)])))
     base = p.dx * p.dx / (2.0 * d)
     lim = math.inf
+    tau = float(p.tau)
+    tab = np.asarray(p.tau_ab)[:N, :N][np.triu_indices(N, 1)]
+    if np.any(tab != 0.0):
+        tau = min(tau, float(np.min(tab)))
     if gmax > 0:
-        lim = base * p.tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax))
-    chi = 1.0 / (2.0 * np.asarray(p.A)[:N, :K1])
+        lim = base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax))
     Dm = np.asarray(p.D)[:N, :K1]
+    if K1 == 2 and (np.any(np.asarray(p.A01)[:N] != 0.0) or np.any(np.asarray(p.D01)[:N] != 0.0)):
+        chi = np.linalg.inv(hessians(np.asarray(p.A)[:N, :K1], np.asarray(p.A01)[:N]))
+        lmin = min(_sym2_min_eig(chi[a, 0, 0], chi[a, 0, 1], chi[a, 1, 1]) for a in range(N))
+        top = 0.0
+        for a in range(N):
+            Da = np.array([[Dm[a, 0], p.D01[a]], [p.D01[a], Dm[a, 1]]])
+            top = max(top, _norm2_2x2(Da @ chi[a]))
+        if top > 0:
+            lim = min(lim, base * lmin / top)
+        return lim
+    chi = 1.0 / (2.0 * np.asarray(p.A)[:N, :K1])
     for k in range(K1):
         top = float(np.max(Dm[:, k] * chi[:, k]))
         if top > 0:

@@ -54,3 +54,30 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stdout + r.stderr
+
+
+def test_bound_follows_the_max_rule():
+    # 1 GB and 10 GFLOP per step in 0.2 ms: HBM ideal 0.125 ms > ALU ideal 0.127 ms? no:
+    # FP64 peak 78.6 TFLOP/s -> 10e9 / 78.6e12 = 0.127 ms > 0.125 ms: the ALU bounds it
+    r = bench.bound_record(1.0e9, 10.0e9, 0.2, "f64")
+    assert r["bound"] == "alu"
+    r = bench.bound_record(1.1e9, 10.0e9, 0.2, "f64", traffic=0.5e9, valu_insts=1.0e8, steps_per_launch=2)
+    assert r["bound"] == "hbm"
+    assert r["frac"] == pytest.approx(1.1e9 / 0.2e-3 / 8e12, rel=1e-3)
+    # counter traffic per two-step launch of 0.4 ms; VALU issue 1e8 x 4 cycles / 1024 SIMDs / 2.4 GHz
+    assert r["counter_frac"] == pytest.approx(0.5e9 / 0.4e-3 / 8e12, rel=1e-3)
+    assert r["valu_issue_frac"] == pytest.approx(1.0e8 * 4 / 1024 / 2.4e9 / 0.4e-3, rel=1e-3)
+    assert bench.bound_record(1.0e9, 1.0, 0.2, "f32")["counter_frac"] is None
+
+
+def test_band_split_oracle_equals_the_full_step():
+    """The CPU baseline's parallel row bands reproduce the oracle's full-grid steps bitwise."""
+    import numpy as np
+
+    from oracle import gp
+    from paper_2404_01035_amd import inputs
+
+    p, phi, mu = inputs.config_c2(precision="f64", n=(40, 37, 1))
+    f, m = bench.oracle_band_steps(phi, mu, 3, 2, p, workers=3)
+    rf, rm = gp.run(phi, mu, 3, 2, p)
+    assert np.array_equal(f, rf) and np.array_equal(m, rm)
