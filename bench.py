@@ -20,6 +20,10 @@ Further legs, each a block of the same JSON line:
                steps, replayed as HIP graphs, FP32
   adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
                (every 100 steps) and the adjoint sweep; their cost ratio
+  antitrapping the 4096^2 eutectic and the 512^3 dendrite with the
+               anti-trapping current (step + correction kernel per step)
+  extended     the 4096^2 eutectic with temperature-dependent coefficients
+               (the general kernels), FP64 and FP32
 cpu_baseline   the FP64 oracle on the full 4096^2 grid, on the host's cores: two
                steps split into row bands over the usable CPUs (at most 16),
                and one step in a single process; lscpu's model and counts.
@@ -53,27 +57,27 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "6e2eeb30c1003a7d",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "a9b2f6cb87949665",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "54c91d5dca69cf03",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "0ea3e9c72697aab3",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "81371fb33d083eef",
-           "bytes": (2.0 * 1094183.8 + 1572864.0) * 1024},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "8f12064e5c47603d",
+           "bytes": (2.0 * 1150852.3 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "112d348f54601712",
-           "bytes": (2.0 * 705130.6 + 1235434.8) * 1024},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
+           "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "7f724703195dd7d3",
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "e225c3bd64067218",
                "bytes": (2.0 * 867775.7 + 269022.1) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "7f724703195dd7d3",
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "e225c3bd64067218",
                "bytes": (2.0 * 459730.5 + 137750.1) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [64, 4, 1], "fuse": 1, "src": "7f724703195dd7d3",
+    "at3d_f32": {"tile": [64, 4, 1], "fuse": 1, "src": "e225c3bd64067218",
                  "bytes": (2.0 * 2646601.9 + 524288.0) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
-ALL_LEGS = ("c2", "c3", "c4", "c5", "at")
+ALL_LEGS = ("c2", "c3", "c4", "c5", "at", "ext")
 
 
 def parse():
@@ -95,6 +99,8 @@ def parse():
     ap.add_argument("--n3d", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=400)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--settle-ms", type=float, default=None,
+                    help="untimed settle time before the timed regions (default 150 ms; 0 for counter runs)")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="only the host-CPU oracle timing (prints its record; no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -111,6 +117,8 @@ _COMMON = ["mp_internal.hpp", "gp_device.hpp"]
 LEG_SOURCES = {
     "c2_f64": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
     "c2_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
+    "c2ext_f64": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_gen_f64_2d.hip"],
+    "c2ext_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_gen_f32_2d.hip"],
     "c3": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
     "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
     "at_f64": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
@@ -148,14 +156,17 @@ def roofline(bytes_per_step, ms_step, traffic=None):
             "traffic": None if traffic is None else round(traffic)}
 
 
-def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False):
+def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False, ext=False):
     """Floating-point operations (an FMA counts 2) of one cell update of the
     multi-well step as the kernels evaluate it, each face once: the cell
     record (h, mobility), one face per axis, the face sums, h of the old phi,
     and the cell update (doubled psi, driving force, Lagrange multiplier, new
     phi and its h, mu with its reciprocal and two Newton steps).  An
     anisotropic pair adds the tangential differences and q components and the
-    normal component of d(a_c^2 |q|^2)/dq (one reciprocal square root)."""
+    normal component of d(a_c^2 |q|^2)/dq (one reciprocal square root).  The
+    extended model's general cell (ext) adds B(T) and the quadratic C(T), the
+    dT/dt term, for two mu fields the off-diagonal susceptibility terms, the
+    mobility matrix with its face products and the 2 x 2 solve, and tau(phi)."""
     n, m, d = nphases, ncomp - 1, dim
     pairs = n * (n - 1) // 2
     h = 5 * n + 3 if n == 3 else 4 * n
@@ -175,7 +186,12 @@ def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False):
     cell = (4 * n * m + (6 if n == 3 else 0)
             + n * (2 * n + 6 if n == 3 else 2 * n + 4)
             + n + 3 * n + h + n + m * (4 * n + 10))
-    return record + faces + sums + h + cell
+    extra = 0
+    if ext:
+        extra = 3 * n * m + 2 * n + 2 * n * m + 14  # B(T), C(T)^2 term, Theta, tau(phi)
+        if m == 2:
+            extra += 4 * n + 6 * d + 2 * (2 * n - 1) + 4  # cross chi, face J products, M matrix, solve
+    return record + faces + sums + h + cell + extra
 
 
 def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
@@ -191,7 +207,14 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # keyed like TRAFFIC (tile, steps per launch, source hash).  A wave64 FP64
 # instruction occupies its SIMD for 4 cycles, an FP32 one for 2 (the vector
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
-VALU = {}
+VALU = {
+    # profiles/k_step2d_eutectic_4096_f64_f32.md
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "a9b2f6cb87949665", "insts": 153857451.0},
+    # profiles/k_step3d_dendrite_512_f32.md
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "8f12064e5c47603d", "insts": 543752776.3},
+    # profiles/k_batch2d_ensemble_256_f32.md
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
+}
 VALU_CYCLES = {"f64": 4, "f32": 2}
 SIMDS = 1024         # 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9     # MI355X peak engine clock
@@ -260,7 +283,7 @@ REGIONS = 5          # timed regions per leg; the median is reported
 SETTLE_MS = 150.0    # untimed steps after the warm-up until this much wall time has passed
 
 
-def measure(step, steps, warmup, regions=REGIONS, settle_ms=SETTLE_MS):
+def measure(step, steps, warmup, regions=REGIONS, settle_ms=None):
     """Time ``step(steps)``: ``warmup`` untimed steps, then untimed steps in
     chunks of ``steps`` until ``settle_ms`` of wall time has passed (clocks and
     caches settle; short runs such as 20 steps otherwise time a cold GPU), then
@@ -269,6 +292,8 @@ def measure(step, steps, warmup, regions=REGIONS, settle_ms=SETTLE_MS):
     the median region's milliseconds, every region's, and the settle steps."""
     import torch
 
+    if settle_ms is None:
+        settle_ms = SETTLE_MS
     if warmup > 0:
         step(warmup)
     torch.cuda.synchronize()
@@ -324,11 +349,14 @@ def copy_calibration(n, steps):
                       "frac_of_8TBs": gbs / HBM_PEAK_GBS}), flush=True)
 
 
-def leg_c2(precision, n, steps, warmup, tile, tune):
+def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
+    """The 4096^2 eutectic; slopes: with temperature-dependent coefficients
+    (the general kernels of the extended model)."""
     from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import Solver
 
-    p, phi, mu = inputs.config_c2(precision=precision, n=(n, n, 1))
+    cfg = inputs.config_c2_slopes if slopes else inputs.config_c2
+    p, phi, mu = cfg(precision=precision, n=(n, n, 1))
     s = Solver(p)
     s.load(phi, mu)
     del phi, mu
@@ -347,9 +375,9 @@ def leg_c2(precision, n, steps, warmup, tile, tune):
     s.close()
     elem = 8 if precision == "f64" else 4
     bpc = p.nfields * 2 * elem  # read + write of every field once
-    fpc = flops_per_cell_update(p.nphases, p.ncomp)
+    fpc = flops_per_cell_update(p.nphases, p.ncomp, ext=slopes)
     ms_step = ms / steps
-    leg = f"c2_{precision}"
+    leg = f"c2{'ext' if slopes else ''}_{precision}"
     traffic = traffic_of(leg, used, fuse)
     return {
         "value": p.ncells * steps / (ms * 1e-3),
@@ -678,6 +706,9 @@ def cpu_baseline(n):
 
 def main():
     a = parse()
+    global SETTLE_MS
+    if a.settle_ms is not None:
+        SETTLE_MS = a.settle_ms
     if a.cpu_baseline_only:
         print(json.dumps(cpu_baseline_run(a.n)), flush=True)
         return
@@ -753,6 +784,15 @@ def main():
                                "f32": leg_at("f32", a.n, at_steps, 5),
                                "dendrite_3d_f32": dict(leg_at3d(a.n3d, min(a.steps3d, 50), 3),
                                                        workload=f"3D {a.n3d}^3 binary dendrite with the current")}
+    if "ext" in legs:
+        log(f"extended model: {a.n}x{a.n} eutectic with temperature-dependent coefficients")
+        out["extended"] = {
+            "workload": f"2D {a.n}x{a.n} directional eutectic with B(T), C(T) from coexistence-line slopes "
+                        "and the dT/dt term (general kernels, two steps per launch)",
+            "f64": leg_c2("f64", a.n, a.steps, a.warmup, None, False, slopes=True),
+            "f32": dict(leg_c2("f32", a.n, a.steps, a.warmup, None, False, slopes=True),
+                        dtype="f32 (FP64 Lagrange multiplier and reductions)"),
+        }
     out["copy_bandwidth"] = copy_bandwidth(a.n)
     if not a.no_cpu:
         log("CPU oracle sample")

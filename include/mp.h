@@ -58,7 +58,12 @@ enum {
 
 enum { MP_BC_PERIODIC = 0, MP_BC_NOFLUX = 1 };   /* BOUNDARY codes 3 and 1 of Sec. 5 */
 enum { MP_FP64 = 0, MP_FP32 = 1 };
-enum { MP_WELL = 0, MP_OBSTACLE = 1 };           /* Function_W of Sec. 5: Eq. Well / Eq. Obstacle */
+/* Function_W of Sec. 5: Eq. Well, Eq. Obstacle.  The obstacle's "infinite outside
+ * [0, 1]" is imposed either by clipping the forward-Euler update to [0, 1] and
+ * renormalising (MP_OBSTACLE) or with the Lagrange multiplier over the active
+ * phases, i.e. the update's nearest point of the simplex {phi >= 0, sum phi = 1}
+ * (MP_OBSTACLE_ACTIVE). */
+enum { MP_WELL = 0, MP_OBSTACLE = 1, MP_OBSTACLE_ACTIVE = 2 };
 
 typedef struct mp_state mp_state; /* opaque */
 
@@ -83,10 +88,26 @@ typedef struct {
  *   s            C^a(T) = C[a] + s[a] (T - Te)
  *   D            diffusivity per phase and component, >= 0 (Eq. Mass_conservation)
  *   Te, T0, G, V, y0  temperature T(y,t) = T0 + G (y - y0 - V t), t = step * dt
- *                (the Tempgrady key of Sec. 5) */
+ *                (the Tempgrady key of Sec. 5)
+ * Extended model (all zero: the terms are absent; a state that uses any of them
+ * runs the general kernels, see mp_create):
+ *   Bt, Ct       temperature dependence of the parabolic coefficients from the
+ *                slopes of the coexistence lines (Sec. 3):
+ *                B^a_k(T) = B[a][k] + Bt[a][k] (T - Te),
+ *                C^a(T) = C[a] + s[a] (T - Te) + Ct[a] (T - Te)^2; the mu update
+ *                then carries the dT/dt term of Eq. Mu_explicit_temperature
+ *   A01          off-diagonal curvature: f^a gains A01[a] c_0 c_1 (Eq.
+ *                free_energy_density with its i < j term; K = 3); every
+ *                [[2 A[a][0], A01[a]], [A01[a], 2 A[a][1]]] must be positive definite
+ *   D01          symmetric off-diagonal diffusivity D^a_01 = D^a_10 (Eq.
+ *                Mass_conservation with a full D^a; K = 3), D^a positive semidefinite
+ *   tau_ab       relaxation constant per phase pair (the Tau key of Sec. 5;
+ *                symmetric, all > 0 or all 0): tau of Eq. phi_eqn becomes
+ *                sum_{a<b} tau_ab phi_a phi_b / sum_{a<b} phi_a phi_b, and tau
+ *                where that pair sum is <= 1e-30 */
 typedef struct {
     int32_t precision; /* MP_FP64 | MP_FP32 */
-    int32_t potential; /* MP_WELL | MP_OBSTACLE */
+    int32_t potential; /* MP_WELL | MP_OBSTACLE | MP_OBSTACLE_ACTIVE */
     double eps, tau, dt;
     double gamma[3][3];
     double gamma3;
@@ -95,6 +116,9 @@ typedef struct {
     double s[3];
     double D[3][2];
     double Te, T0, G, V, y0;
+    double Bt[3][2], Ct[3];
+    double A01[3], D01[3];
+    double tau_ab[3][3];
 } mp_params;
 
 /* Global diagnostics of the current state, reduced in FP64 with Neumaier
@@ -110,14 +134,24 @@ typedef struct {
 
 /* Explicit stability limit used by mp_create (host only, no GPU needed):
  * dx^2/(2d) * min( tau / (2 gamma_max (N-1)/N (1 + 20 delta_max)),
- *                  min_k min_a chi^a_k / max_a (D^a_k chi^a_k) ), chi = 1/(2A).
+ *                  min_k min_a chi^a_k / max_a (D^a_k chi^a_k) ), chi = 1/(2A);
+ * with per-pair tau_ab the smallest of them and tau counts, and with A01 or D01
+ * the mu part is min_a lambda_min(chi^a) / max_a |D^a chi^a|_2 (chi^a the
+ * inverse curvature matrix), a bound on the eigenvalues of chi^-1 M.
  * Returns a negative value for invalid input. */
 double mp_dt_limit(const mp_grid* grid, int nphases, int ncomp, const mp_params* params);
 
-/* Validate the problem and build a solver state (host only, no GPU needed).
- * nphases N in {2, 3}; ncomp K in {2, 3} (K - 1 diffusion potentials).
+/* Validate the problem and build a solver state (host only, no GPU needed):
+ * the grand-potential step of Sec. 2.1 (Eq. phi_eqn for the phase fields, Eq.
+ * Mu_explicit_temperature for the diffusion potentials) on this grid.
+ * nphases N in {2, 3}; ncomp K in {2, 3} (K - 1 diffusion potentials).  A
+ * problem that uses the extended model (non-zero Bt, Ct, A01, D01 or tau_ab, or
+ * MP_OBSTACLE_ACTIVE) runs the general kernels: one cell per lane in 2D and
+ * 64 x 4 tiles in 3D whatever mp_set_tile says; batched states, the adjoint
+ * and the anti-trapping current do not take it.
  * Errors: MP_E_NULLPTR, MP_E_PARAM (dim, n, bc, dx, N, K, precision,
- * potential, eps, tau, A, D, gamma, delta out of range), MP_E_UNSTABLE. */
+ * potential, eps, tau, A, D, gamma, delta or an extended coefficient out of
+ * range), MP_E_UNSTABLE. */
 int mp_create(const mp_grid* grid, int nphases, int ncomp, const mp_params* params,
               mp_state** out);
 
@@ -133,7 +167,8 @@ size_t mp_workspace_bytes(const mp_state* st);
  * workspace with a synchronous copy. */
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
 
-/* Advance nsteps >= 0 forward-Euler steps on ``stream`` (asynchronous).
+/* Advance nsteps >= 0 forward-Euler steps (Sec. 2.1: the explicit scheme of
+ * Eq. phi_eqn and Eq. Mu_explicit_temperature) on ``stream`` (asynchronous).
  * Each kernel launch reads the current buffer and writes the other one, and
  * performs one step, or two (mp_set_fusion; an odd remainder is a single
  * step), so the current buffer flips once per launch: mp_current
@@ -255,7 +290,8 @@ int mp_step_ckpt(mp_state* st, int64_t nsteps, int64_t every, void* ckpt_buf, vo
 size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
 
 /* Discrete adjoint of nsteps steps recorded by mp_step_ckpt starting at time
- * level n0 (2D, isotropic, multi-well only; the obstacle projection is not
+ * level n0: the exact transpose of the explicit step of Sec. 2.1 (2D,
+ * isotropic, multi-well, base model only; the obstacle projection is not
  * differentiable).  lam_final holds dL/ds at the final state (state layout);
  * lam_initial receives dL/ds at the initial state.  grad_theta (host, 10
  * doubles) receives dL/dtheta with theta = (gamma_01, gamma_02, gamma_12,
@@ -269,6 +305,22 @@ size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
 int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,
                const void* lam_final, void* lam_initial, double* grad_theta, void* work,
                void* stream);
+
+/* Moving frame (the SHIFT / Shiftj keys of Sec. 5, the moving box of the
+ * directional-solidification runs): mp_front_row reduces the current state to
+ * the highest row (y index) holding a cell whose liquid fraction (the last
+ * phase) is below 1/2, or -1 (synchronises ``stream``).  mp_shift moves the
+ * frame up by ``rows`` (0 <= rows <= ny): row j of the new current buffer is
+ * row j + rows of the old one, the top ``rows`` rows are melt (liquid fraction
+ * 1, mu_k = mu_melt[k] for k < K-1, host memory), and from then on row j stands
+ * at y = (j + offset) dx in the temperature law, offset being the sum of all
+ * shifts (returned in *offset when offset is not NULL).  One copy kernel on
+ * ``stream``; the current buffer flips, the time level is unchanged.  In 3D the
+ * shift is along y as well.  Checkpoints taken before a shift do not replay
+ * across it.  Single grids only.  Errors: MP_E_NULLPTR, MP_E_UNBOUND,
+ * MP_E_STATE (batched state), MP_E_PARAM (rows out of range), MP_E_HIP. */
+int mp_front_row(mp_state* st, int64_t* row, void* stream);
+int mp_shift(mp_state* st, int64_t rows, const double* mu_melt, int64_t* offset, void* stream);
 
 /* Free host-side state (device buffers stay with the caller). NULL is a no-op. */
 void mp_destroy(mp_state* st);

@@ -18,7 +18,8 @@ MP_E_PARAM, MP_E_UNSTABLE, MP_E_NULLPTR, MP_E_UNBOUND, MP_E_HIP, MP_E_NONFINITE,
     -1, -2, -3, -4, -5, -6, -7)
 MP_BC_PERIODIC, MP_BC_NOFLUX = 0, 1
 MP_FP64, MP_FP32 = 0, 1
-MP_WELL, MP_OBSTACLE = 0, 1
+MP_WELL, MP_OBSTACLE, MP_OBSTACLE_ACTIVE = 0, 1, 2
+POTENTIALS = {"well": MP_WELL, "obstacle": MP_OBSTACLE, "obstacle_active": MP_OBSTACLE_ACTIVE}
 
 ERROR_NAMES = {
     MP_E_PARAM: "MP_E_PARAM", MP_E_UNSTABLE: "MP_E_UNSTABLE", MP_E_NULLPTR: "MP_E_NULLPTR",
@@ -33,7 +34,7 @@ EXPORTS = [
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
     "mp_tune_candidates", "mp_tune", "mp_set_fusion", "mp_get_fusion",
-    "mp_set_antitrapping", "mp_get_antitrapping",
+    "mp_set_antitrapping", "mp_get_antitrapping", "mp_front_row", "mp_shift",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -53,6 +54,8 @@ class mp_params(C.Structure):
         ("s", C.c_double * 3), ("D", (C.c_double * 2) * 3),
         ("Te", C.c_double), ("T0", C.c_double), ("G", C.c_double), ("V", C.c_double),
         ("y0", C.c_double),
+        ("Bt", (C.c_double * 2) * 3), ("Ct", C.c_double * 3), ("A01", C.c_double * 3), ("D01", C.c_double * 3),
+        ("tau_ab", (C.c_double * 3) * 3),
     ]
 
 
@@ -100,6 +103,10 @@ def lib():
         L.mp_set_step.argtypes = [vp, C.c_int64, C.c_int]
         L.mp_diagnostics.restype = C.c_int
         L.mp_diagnostics.argtypes = [vp, C.POINTER(mp_diag), vp]
+        L.mp_front_row.restype = C.c_int
+        L.mp_front_row.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        L.mp_shift.restype = C.c_int
+        L.mp_shift.argtypes = [vp, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
         L.mp_set_tile.restype = C.c_int
         L.mp_set_tile.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.mp_get_tile.restype = C.c_int
@@ -166,7 +173,7 @@ def to_grid(p) -> mp_grid:
 def to_params(p) -> mp_params:
     c = mp_params()
     c.precision = MP_FP64 if p.precision == "f64" else MP_FP32
-    c.potential = MP_WELL if p.potential == "well" else MP_OBSTACLE
+    c.potential = POTENTIALS[p.potential]
     c.eps, c.tau, c.dt = float(p.eps), float(p.tau), float(p.dt)
     c.gamma3 = float(p.gamma3)
     g = np.asarray(p.gamma, dtype=np.float64)
@@ -183,6 +190,15 @@ def to_params(p) -> mp_params:
             c.B[a][k] = float(B[a, k])
             c.D[a][k] = float(Dm[a, k])
     c.Te, c.T0, c.G, c.V, c.y0 = (float(x) for x in (p.Te, p.T0, p.G, p.V, p.y0))
+    Bt, tab = np.asarray(p.Bt, dtype=np.float64), np.asarray(p.tau_ab, dtype=np.float64)
+    for a in range(3):
+        c.Ct[a] = float(p.Ct[a])
+        c.A01[a] = float(p.A01[a])
+        c.D01[a] = float(p.D01[a])
+        for k in range(2):
+            c.Bt[a][k] = float(Bt[a, k])
+        for b in range(3):
+            c.tau_ab[a][b] = float(tab[a, b])
     return c
 
 
@@ -247,6 +263,21 @@ def mp_diagnostics_batch(st, stream: int = 0, allow_nonfinite: bool = False) -> 
     if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
         _check(rc)
     return [_diag_dict(arr[i]) for i in range(n)]
+
+
+def mp_front_row(st, stream: int = 0) -> int:
+    """Highest row holding a cell with liquid fraction below 1/2 (-1 if none)."""
+    r = C.c_int64()
+    _check(lib().mp_front_row(st, C.byref(r), stream))
+    return r.value
+
+
+def mp_shift(st, rows: int, mu_melt, stream: int = 0) -> int:
+    """Shift the frame up by ``rows`` with melt at ``mu_melt``; returns the total offset."""
+    m = (C.c_double * 2)(*([float(v) for v in mu_melt] + [0.0, 0.0])[:2])
+    off = C.c_int64()
+    _check(lib().mp_shift(st, int(rows), m, C.byref(off), stream))
+    return off.value
 
 
 def mp_create_batch(plist) -> int:

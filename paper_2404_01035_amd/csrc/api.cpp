@@ -31,6 +31,8 @@ struct Inst {
     int N, K;
     mp_params prm;
     bool aniso;
+    bool ext;                 // uses the extended model: the general kernels
+    int64_t yshift;           // frame offset in rows (mp_shift)
     size_t off_bytes, bytes;  // within each state buffer
 };
 
@@ -108,8 +110,8 @@ int check_params(int N, int K, const mp_params* p) {
     if (K != 2 && K != 3) return fail(MP_E_PARAM, "ncomp must be 2 or 3 (got %d)", K);
     if (p->precision != MP_FP64 && p->precision != MP_FP32)
         return fail(MP_E_PARAM, "precision must be MP_FP64 or MP_FP32");
-    if (p->potential != MP_WELL && p->potential != MP_OBSTACLE)
-        return fail(MP_E_PARAM, "potential must be MP_WELL or MP_OBSTACLE");
+    if (p->potential != MP_WELL && p->potential != MP_OBSTACLE && p->potential != MP_OBSTACLE_ACTIVE)
+        return fail(MP_E_PARAM, "potential must be MP_WELL, MP_OBSTACLE or MP_OBSTACLE_ACTIVE");
     if (!(p->eps > 0) || !finite(p->eps)) return fail(MP_E_PARAM, "eps must be positive and finite");
     if (!(p->tau > 0)) return fail(MP_E_PARAM, "tau must be positive");
     if (!(p->dt > 0) || !finite(p->dt)) return fail(MP_E_PARAM, "dt must be positive and finite");
@@ -138,19 +140,99 @@ int check_params(int N, int K, const mp_params* p) {
     }
     if (!finite(p->Te) || !finite(p->T0) || !finite(p->G) || !finite(p->V) || !finite(p->y0))
         return fail(MP_E_PARAM, "temperature parameters must be finite");
+    // extended model
+    bool anypair = false, allpair = true;
+    for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; ++b) {
+            const double t = p->tau_ab[a][b];
+            if (!finite(t) || t < 0.0) return fail(MP_E_PARAM, "tau_ab[%d][%d] must be >= 0 and finite", a, b);
+            if (t != p->tau_ab[b][a]) return fail(MP_E_PARAM, "tau_ab must be symmetric (tau_ab[%d][%d])", a, b);
+            anypair = anypair || t > 0.0;
+            allpair = allpair && t > 0.0;
+        }
+    if (anypair && !allpair) return fail(MP_E_PARAM, "tau_ab: every pair > 0, or all 0");
+    for (int a = 0; a < N; ++a) {
+        if (!finite(p->Ct[a])) return fail(MP_E_PARAM, "Ct[%d] must be finite", a);
+        for (int k = 0; k < K - 1; ++k)
+            if (!finite(p->Bt[a][k])) return fail(MP_E_PARAM, "Bt[%d][%d] must be finite", a, k);
+        if (K == 3) {
+            if (!finite(p->A01[a]) || !finite(p->D01[a])) return fail(MP_E_PARAM, "A01/D01[%d] must be finite", a);
+            if (!(4.0 * p->A[a][0] * p->A[a][1] - p->A01[a] * p->A01[a] > 0.0))
+                return fail(MP_E_PARAM, "phase %d: the curvature matrix [[2A0, A01], [A01, 2A1]] must be positive definite", a);
+            if (!(p->D[a][0] * p->D[a][1] - p->D01[a] * p->D01[a] >= 0.0))
+                return fail(MP_E_PARAM, "phase %d: the diffusivity matrix [[D0, D01], [D01, D1]] must be positive semidefinite", a);
+        }
+    }
     return MP_OK;
 }
 
+// Susceptibility chi^a = (H^a)^-1 of phase a, H^a = [[2 A0, A01], [A01, 2 A1]]
+// (K = 3) or 2 A0 (K = 2); the plain 1 / (2 A) where there is no cross term.
+void chi_of(const mp_params& p, int a, int K, double chi[2][2]) {
+    chi[0][0] = chi[0][1] = chi[1][0] = chi[1][1] = 0.0;
+    if (K == 3 && p.A01[a] != 0.0) {
+        const double det = 4.0 * p.A[a][0] * p.A[a][1] - p.A01[a] * p.A01[a];
+        chi[0][0] = 2.0 * p.A[a][1] / det;
+        chi[1][1] = 2.0 * p.A[a][0] / det;
+        chi[0][1] = chi[1][0] = -p.A01[a] / det;
+        return;
+    }
+    for (int k = 0; k < K - 1; ++k) chi[k][k] = 1.0 / (2.0 * p.A[a][k]);
+}
+
+// Diffusivity matrix D^a (the off-diagonal entry for K = 3).
+void diff_of(const mp_params& p, int a, int K, double D[2][2]) {
+    D[0][0] = p.D[a][0];
+    D[1][1] = K == 3 ? p.D[a][1] : 0.0;
+    D[0][1] = D[1][0] = K == 3 ? p.D01[a] : 0.0;
+}
+
+bool uses_extended(int N, int K, const mp_params& p) {
+    if (p.potential == MP_OBSTACLE_ACTIVE) return true;
+    for (int a = 0; a < N; ++a) {
+        if (p.Ct[a] != 0.0) return true;
+        for (int k = 0; k < K - 1; ++k)
+            if (p.Bt[a][k] != 0.0) return true;
+        if (K == 3 && (p.A01[a] != 0.0 || p.D01[a] != 0.0)) return true;
+        for (int b = a + 1; b < N; ++b)
+            if (p.tau_ab[a][b] != 0.0) return true;
+    }
+    return false;
+}
+
 double dt_limit_of(const mp_grid* g, int N, int K, const mp_params* p) {
-    double gmax = 0.0, dmax = 0.0;
+    double gmax = 0.0, dmax = 0.0, tau = p->tau;
     for (int a = 0; a < N; ++a)
         for (int b = a + 1; b < N; ++b) {
             gmax = std::fmax(gmax, p->gamma[a][b]);
             dmax = std::fmax(dmax, std::fabs(p->delta[a][b]));
+            if (p->tau_ab[a][b] > 0.0) tau = std::fmin(tau, p->tau_ab[a][b]);
         }
     const double base = g->dx * g->dx / (2.0 * g->dim);
     double lim = INFINITY;
-    if (gmax > 0) lim = base * p->tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax));
+    if (gmax > 0) lim = base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax));
+    bool cross = false;
+    for (int a = 0; a < N && K == 3; ++a) cross = cross || p->A01[a] != 0.0 || p->D01[a] != 0.0;
+    if (cross) {
+        // eigenvalues of chi^-1 M are at most max_a |D^a chi^a|_2 / min_a lambda_min(chi^a)
+        double lmin = INFINITY, top = 0.0;
+        for (int a = 0; a < N; ++a) {
+            double c[2][2], D[2][2];
+            chi_of(*p, a, K, c);
+            diff_of(*p, a, K, D);
+            lmin = std::fmin(lmin, 0.5 * (c[0][0] + c[1][1]) -
+                                       std::sqrt(0.25 * (c[0][0] - c[1][1]) * (c[0][0] - c[1][1]) + c[0][1] * c[0][1]));
+            double m[2][2];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) m[i][j] = D[i][0] * c[0][j] + D[i][1] * c[1][j];
+            const double sa = m[0][0] * m[0][0] + m[1][0] * m[1][0];
+            const double sb = m[0][0] * m[0][1] + m[1][0] * m[1][1];
+            const double sc = m[0][1] * m[0][1] + m[1][1] * m[1][1];
+            top = std::fmax(top, std::sqrt(0.5 * (sa + sc) + std::sqrt(0.25 * (sa - sc) * (sa - sc) + sb * sb)));
+        }
+        if (top > 0) lim = std::fmin(lim, base * lmin / top);
+        return lim;
+    }
     for (int k = 0; k < K - 1; ++k) {
         double top = 0.0, cmin = INFINITY;
         for (int a = 0; a < N; ++a) {
@@ -187,6 +269,8 @@ Inst make_inst(const mp_grid* g, int N, int K, const mp_params* p) {
     for (int a = 0; a < N; ++a)
         for (int b = a + 1; b < N; ++b)
             if (p->delta[a][b] != 0.0) I.aniso = true;
+    I.ext = uses_extended(N, K, *p);
+    I.yshift = 0;
     I.bytes = (size_t)ncells_of(*g) * (size_t)(N + K - 1) * elem_of(p->precision);
     I.off_bytes = 0;
     return I;
@@ -201,7 +285,7 @@ mp::Coef<R> make_coef(const Inst& I) {
     c.cE = (R)(p.eps / (2.0 * dx));
     c.kphi = (R)(p.dt / (p.tau * p.eps));
     c.qguard = (R)(4.0 * dx * dx * 1e-30);
-    const double wfac = p.potential == MP_OBSTACLE ? 16.0 / (M_PI * M_PI) : 18.0;
+    const double wfac = p.potential != MP_WELL ? 16.0 / (M_PI * M_PI) : 18.0;  // both obstacle projections
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
     for (int q = 0; q < 3; ++q) {
         const double g = p.gamma[pa[q]][pb[q]];
@@ -215,14 +299,55 @@ mp::Coef<R> make_coef(const Inst& I) {
     for (int a = 0; a < I.N; ++a) {
         c.C[a] = (R)p.C[a];
         c.s[a] = (R)p.s[a];
+        double chi[2][2];
+        chi_of(p, a, I.K, chi);
         for (int k = 0; k < I.K - 1; ++k) {
-            const double chi = 1.0 / (2.0 * p.A[a][k]);
-            c.chi[a][k] = (R)chi;
+            c.chi[a][k] = (R)chi[k][k];
             c.B[a][k] = (R)p.B[a][k];
-            c.Dt[a][k] = (R)(p.D[a][k] * chi * dtf);
+            c.Dt[a][k] = (R)(p.D[a][k] * chi[k][k] * dtf);
         }
     }
     return c;
+}
+
+// T - Te per step of the temperature law (T0 + G (y - y0 - V t), t = n dt).
+double temperature_step(const Inst& I) { return -I.prm.G * I.prm.V * I.prm.dt; }
+
+// The extended model's coefficients for the general kernels.
+template <typename R>
+mp::CoefX<R> make_coefx(const Inst& I) {
+    const mp_params& p = I.prm;
+    mp::CoefX<R> x;
+    std::memset(&x, 0, sizeof x);
+    const double dtf = p.dt / (2.0 * I.grid.dx * I.grid.dx);
+    const double dT = temperature_step(I);
+    const int K1 = I.K - 1;
+    for (int a = 0; a < I.N; ++a) {
+        double chi[2][2], D[2][2];
+        chi_of(p, a, I.K, chi);
+        diff_of(p, a, I.K, D);
+        x.Ct[a] = (R)p.Ct[a];
+        x.chx[a] = (R)(K1 == 2 ? chi[0][1] : 0.0);
+        for (int k = 0; k < K1; ++k) {
+            x.Bt[a][k] = (R)p.Bt[a][k];
+            double cb = 0.0;
+            for (int j = 0; j < K1; ++j) {
+                cb += chi[k][j] * p.Bt[a][j];
+                double dc = 0.0;
+                for (int l = 0; l < K1; ++l) dc += D[k][l] * chi[l][j];
+                x.Dx[a][k][j] = (R)(dc * dtf);
+            }
+            x.th[a][k] = (R)(-cb * dT);
+        }
+    }
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+    for (int q = 0; q < 3; ++q) {
+        x.tab[q] = (R)p.tau_ab[pa[q]][pb[q]];
+        if (pb[q] < I.N && p.tau_ab[pa[q]][pb[q]] > 0.0) x.tpair = 1;
+    }
+    x.ktau = (R)(p.dt / p.eps);
+    x.proj = p.potential == MP_OBSTACLE_ACTIVE ? 1 : 0;
+    return x;
 }
 
 template <typename R>
@@ -232,7 +357,7 @@ mp::AtCoef<R> make_at_coef(const Inst& I) {
     std::memset(&c, 0, sizeof c);
     c.prefw = (R)(p.eps / (2.0 * std::sqrt(2.0)));
     c.prefo = (R)(M_PI * p.eps / 4.0);
-    c.obstacle = p.potential == MP_OBSTACLE ? 1 : 0;
+    c.obstacle = p.potential != MP_WELL ? 1 : 0;
     c.rdx = (R)(1.0 / I.grid.dx);
     c.rdt = (R)(1.0 / p.dt);
     c.dt = (R)p.dt;
@@ -256,11 +381,12 @@ mp::Geom make_geom(const mp_grid& gr) {
     return g;
 }
 
-// T - Te at row j and step n: T0 + G (j dx - y0 - V n dt) - Te = tb0 + tdn n + tslope j
+// T - Te at row j and step n: T0 + G ((j + yshift) dx - y0 - V n dt) - Te
+// = tb0 + tdn n + tslope j
 void temperature_law(const Inst& I, double& tb0, double& tdn, double& tslope) {
     const mp_params& p = I.prm;
-    tb0 = p.T0 - p.Te - p.G * p.y0;
-    tdn = -p.G * p.V * p.dt;
+    tb0 = p.T0 - p.Te - p.G * p.y0 + p.G * I.grid.dx * (double)I.yshift;
+    tdn = temperature_step(I);
     tslope = p.G * I.grid.dx;
 }
 
@@ -507,6 +633,13 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
+    if (I.ext) {
+        if (st->precision == MP_FP64)
+            return I.grid.dim == 3 ? mp::call_step_gen<double, true>(L, make_coef<double>(I), make_coefx<double>(I), k)
+                                   : mp::call_step_gen<double, false>(L, make_coef<double>(I), make_coefx<double>(I), k);
+        return I.grid.dim == 3 ? mp::call_step_gen<float, true>(L, make_coef<float>(I), make_coefx<float>(I), k)
+                               : mp::call_step_gen<float, false>(L, make_coef<float>(I), make_coefx<float>(I), k);
+    }
     if (st->precision == MP_FP64) return mp::call_step_f64(L, make_coef<double>(I), k);
     return mp::call_step_f32(L, make_coef<float>(I), k);
 }
@@ -608,28 +741,46 @@ void init_state(mp_state* st) {
     }
 }
 
-int diag_instance(mp_state* st, int i, hipStream_t s) {
+// Diagnostics of instance i of the state held in ``base`` (one state buffer),
+// with per-block partials in ``partials`` and the result record in ``result``.
+int diag_instance_at(const mp_state* st, int i, const void* base, int64_t step, double* partials, double* result,
+                     hipStream_t s) {
     const Inst& I = st->inst[i];
     mp::DiagCoef dc;
     std::memset(&dc, 0, sizeof dc);
-    for (int a = 0; a < I.N; ++a)
+    for (int a = 0; a < I.N; ++a) {
+        double chi[2][2];
+        chi_of(I.prm, a, I.K, chi);
+        dc.chx[a] = I.K == 3 ? chi[0][1] : 0.0;
         for (int k = 0; k < I.K - 1; ++k) {
-            dc.chi[a][k] = 1.0 / (2.0 * I.prm.A[a][k]);
+            dc.chi[a][k] = chi[k][k];
             dc.B[a][k] = I.prm.B[a][k];
+            dc.Bt[a][k] = I.prm.Bt[a][k];
         }
+    }
     dc.vol = std::pow(I.grid.dx, I.grid.dim);
-    double* ws = (double*)st->ws;
-    const void* state = (const char*)st->buf[st->cur] + I.off_bytes;
-    int rc = mp::launch_diag(state, st->precision, make_geom(I.grid), I.N, I.K - 1, dc, ws,
-                             ws + (size_t)(mp::DIAG_BLOCKS_MAX + i) * mp::DIAG_VALS, s);
+    double tb0, tdn, tslope;
+    temperature_law(I, tb0, tdn, tslope);
+    dc.tt0 = tb0 + tdn * (double)step;
+    dc.tslope = tslope;
+    dc.nx = (int32_t)I.grid.n[0];
+    dc.ny = (int32_t)I.grid.n[1];
+    const void* state = (const char*)base + I.off_bytes;
+    int rc = mp::launch_diag(state, st->precision, make_geom(I.grid), I.N, I.K - 1, dc, partials, result, s);
     if (rc) return fail(rc, "no diagnostics instance");
     return hip_check(hipGetLastError(), "diagnostics launch");
 }
 
-void unpack_diag(const mp_state* st, int i, const double* r, mp_diag* out) {
+int diag_instance(mp_state* st, int i, hipStream_t s) {
+    double* ws = (double*)st->ws;
+    return diag_instance_at(st, i, st->buf[st->cur], st->step, ws,
+                            ws + (size_t)(mp::DIAG_BLOCKS_MAX + i) * mp::DIAG_VALS, s);
+}
+
+void unpack_diag(const mp_state* st, int i, const double* r, int64_t step, mp_diag* out) {
     const Inst& I = st->inst[i];
     std::memset(out, 0, sizeof *out);
-    out->step = st->step;
+    out->step = step;
     for (int k = 0; k < I.K - 1; ++k) {
         out->mass[k] = r[mp::DV_MASS + 2 * k] + r[mp::DV_MASS + 2 * k + 1];
         out->min_chi[k] = r[mp::DV_MINCHI + k];
@@ -656,7 +807,7 @@ int diag_many(mp_state* st, mp_diag* out, void* stream) {
     if (rc) return rc;
     int64_t bad = 0;
     for (int i = 0; i < n; ++i) {
-        unpack_diag(st, i, &r[(size_t)i * mp::DIAG_VALS], &out[i]);
+        unpack_diag(st, i, &r[(size_t)i * mp::DIAG_VALS], st->step, &out[i]);
         bad += out[i].nonfinite;
     }
     if (bad > 0) return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)bad);
@@ -754,6 +905,8 @@ int adj_supported(const mp_state* st) {
     if (st->batch) return fail(MP_E_STATE, "adjoint: batched states are not supported");
     if (st->antitrap) return fail(MP_E_STATE, "adjoint: the anti-trapping current is not supported");
     const Inst& I = st->inst[0];
+    if (I.ext)
+        return fail(MP_E_PARAM, "adjoint: the extended model (Bt, Ct, A01, D01, tau_ab, MP_OBSTACLE_ACTIVE) is not supported");
     if (I.grid.dim != 2) return fail(MP_E_PARAM, "adjoint: 2D grids only");
     if (I.prm.potential != MP_WELL) return fail(MP_E_PARAM, "adjoint: the obstacle projection is not differentiable");
     if (I.aniso) return fail(MP_E_PARAM, "adjoint: anisotropic gradient energy not supported");
@@ -848,6 +1001,9 @@ int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const i
             rc = fail(MP_E_PARAM, "%sall instances must share one precision", who);
         if (rc == MP_OK && i > 0 && params[i].potential != params[0].potential)
             rc = fail(MP_E_PARAM, "%sall instances must share one potential", who);
+        if (rc == MP_OK && uses_extended(nphases[i], ncomp[i], params[i]))
+            rc = fail(MP_E_PARAM, "%sbatched states take the base model only (no Bt, Ct, A01, D01, tau_ab, "
+                      "MP_OBSTACLE_ACTIVE)", who);
         if (rc) {
             delete st;
             return rc;
@@ -1105,6 +1261,8 @@ int mp_set_antitrapping(mp_state* st, int on) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (on != 0 && on != 1) return fail(MP_E_PARAM, "on must be 0 or 1 (got %d)", on);
     if (on && st->batch) return fail(MP_E_STATE, "anti-trapping current: batched states are not supported");
+    if (on && st->inst[0].ext)
+        return fail(MP_E_STATE, "anti-trapping current: the extended model is not supported");
     drop_graphs(st);
     st->antitrap = on == 1;
     return ok();
@@ -1292,6 +1450,49 @@ int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every
                    "gradient copy");
     if (rc) return rc;
     return hip_check(hipStreamSynchronize(s), "adjoint sync");
+}
+
+int mp_front_row(mp_state* st, int64_t* row, void* stream) {
+    if (!st || !row) return fail(MP_E_NULLPTR, "state or row is NULL");
+    if (st->batch) return fail(MP_E_STATE, "mp_front_row: batched states are not supported");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_front_row before mp_bind");
+    hipStream_t s = (hipStream_t)stream;
+    const Inst& I = st->inst[0];
+    // scratch: the diagnostics partials and the first result record of the workspace
+    double* ws = (double*)st->ws;
+    int64_t* res = (int64_t*)(ws + (size_t)mp::DIAG_BLOCKS_MAX * mp::DIAG_VALS);
+    int rc = mp::launch_front(st->buf[st->cur], st->precision, make_geom(I.grid), I.N, (int*)ws, res, s);
+    if (rc) return fail(rc, "no front kernel");
+    rc = hip_check(hipGetLastError(), "front launch");
+    int64_t r = -1;
+    if (rc == MP_OK) rc = hip_check(hipMemcpyAsync(&r, res, sizeof r, hipMemcpyDeviceToHost, s), "front copy");
+    if (rc == MP_OK) rc = hip_check(hipStreamSynchronize(s), "front sync");
+    if (rc) return rc;
+    *row = r;
+    return ok();
+}
+
+int mp_shift(mp_state* st, int64_t rows, const double* mu_melt, int64_t* offset, void* stream) {
+    if (!st) return fail(MP_E_NULLPTR, "state is NULL");
+    if (st->batch) return fail(MP_E_STATE, "mp_shift: batched states are not supported");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_shift before mp_bind");
+    Inst& I = st->inst[0];
+    if (rows < 0 || rows > I.grid.n[1]) return fail(MP_E_PARAM, "rows must lie in [0, ny]");
+    if (!mu_melt && I.K > 1) return fail(MP_E_NULLPTR, "mu_melt is NULL");
+    for (int k = 0; k < I.K - 1; ++k)
+        if (!std::isfinite(mu_melt[k])) return fail(MP_E_PARAM, "mu_melt[%d] must be finite", k);
+    if (rows > 0) {
+        int rc = mp::launch_shift(st->buf[st->cur], st->buf[1 - st->cur], st->precision, make_geom(I.grid), I.N,
+                                  I.K - 1, (int)rows, mu_melt, (hipStream_t)stream);
+        if (rc) return fail(rc, "no shift kernel");
+        rc = hip_check(hipGetLastError(), "shift launch");
+        if (rc) return rc;
+        st->cur = 1 - st->cur;
+        I.yshift += rows;
+        drop_graphs(st);  // the temperature law's origin is a kernel argument
+    }
+    if (offset) *offset = I.yshift;
+    return ok();
 }
 
 void mp_destroy(mp_state* st) {

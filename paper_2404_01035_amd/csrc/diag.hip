@@ -7,6 +7,7 @@
 #include "mp_internal.hpp"
 
 namespace mp {
+
 namespace {
 
 constexpr int DT = 256;  // threads per diagnostics block
@@ -132,10 +133,17 @@ __global__ void __launch_bounds__(DT) k_diag(const R* __restrict__ st, int64_t n
         h_fp64<NP>(p, h);
         A.maxdev = fmax(A.maxdev, fabs(sum - 1.0));
         for (int a = 0; a < NP; ++a) neu_add(A.vol[a], p[a] * dc.vol);
+        // T - Te of the cell's row (the composition depends on T through B(T))
+        const double tt = dc.tt0 + dc.tslope * (double)((i / dc.nx) % dc.ny);
+        double dm[NP][NM];
+        for (int a = 0; a < NP; ++a)
+            for (int k = 0; k < NM; ++k) dm[a][k] = mu[k] - dc.B[a][k] - dc.Bt[a][k] * tt;
         for (int k = 0; k < NM; ++k) {
             double cc = 0.0, chi = 0.0;
             for (int a = 0; a < NP; ++a) {
-                cc += h[a] * (mu[k] - dc.B[a][k]) * dc.chi[a][k];
+                double ca = dm[a][k] * dc.chi[a][k];
+                if (NM == 2) ca += dm[a][1 - k] * dc.chx[a];  // c^a = chi^a (mu - B^a(T))
+                cc += h[a] * ca;
                 chi += h[a] * dc.chi[a][k];
             }
             neu_add(A.mass[k], cc * dc.vol);

@@ -81,13 +81,21 @@ __device__ __forceinline__ R g_aniso(R qn, const R (&qt)[NTG], R d, R guard) {
     return small ? R(2) * a0 * a0 * qn : gen;
 }
 
+// Entries of a cell's scaled mobility record: NM (diagonal M) or, in the
+// general kernels, the NM x NM matrix row by row.
+template <int NM, bool GEN>
+constexpr int mob_n() {
+    return GEN ? NM * NM : NM;
+}
+
 // One face: U, W (gradient term) and J (mu flux).  tau[t][a] is the unscaled
 // sum of the two cells' central differences along tangential axis t
-// (= 4 dx times the face's tangential gradient); unused when !ANISO.
-template <typename R, int NP, int NM, bool ANISO, int NTG>
+// (= 4 dx times the face's tangential gradient); unused when !ANISO.  GEN:
+// mL, mR are mobility matrices and J = (M~_L + M~_R) (mu_R - mu_L).
+template <typename R, int NP, int NM, bool ANISO, int NTG, bool GEN = false>
 __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
                                           const R (&tau)[NTG > 0 ? NTG : 1][NP],
-                                          const R (&mL)[NM], const R (&mR)[NM],
+                                          const R (&mL)[mob_n<NM, GEN>()], const R (&mR)[mob_n<NM, GEN>()],
                                           const R (&uL)[NM], const R (&uR)[NM], const Coef<R>& c,
                                           R (&U)[NP], R (&W)[NP], R (&J)[NM]) {
     R sg[NP];
@@ -125,8 +133,14 @@ __device__ __forceinline__ void face_core(const R (&pL)[NP], const R (&pR)[NP],
             W[j] = W[j] + gh * pL[i];
         }
     }
+    if constexpr (GEN && NM == 2) {
+        const R d0 = uR[0] - uL[0], d1 = uR[1] - uL[1];
+        J[0] = (mL[0] + mR[0]) * d0 + (mL[1] + mR[1]) * d1;
+        J[1] = (mL[2] + mR[2]) * d0 + (mL[3] + mR[3]) * d1;
+    } else {
 #pragma unroll
-    for (int k = 0; k < NM; ++k) J[k] = (mL[k] + mR[k]) * (uR[k] - uL[k]);
+        for (int k = 0; k < NM; ++k) J[k] = (mL[k] + mR[k]) * (uR[k] - uL[k]);
+    }
 }
 
 // Interpolation functions h_a of Eq. hphi.  For N = 3 the coupling term
@@ -157,6 +171,31 @@ __device__ __forceinline__ void mobility(const R (&h)[NP], const Coef<R>& c, R (
     }
 }
 
+// The general kernels' mobility matrix M~_kj = sum_a (D^a chi^a)_kj dt / (2 dx^2) h_a,
+// row by row.
+template <typename R, int NP, int NM>
+__device__ __forceinline__ void mobility_gen(const R (&h)[NP], const CoefX<R>& x, R (&Mt)[NM * NM]) {
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            R m = R(0);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) m = m + x.Dx[a][k][j] * h[a];
+            Mt[k * NM + j] = m;
+        }
+}
+
+// Either mobility record, by the kernel's model.
+template <typename R, int NP, int NM, bool GEN>
+__device__ __forceinline__ void mobility_any(const R (&h)[NP], const Coef<R>& c, const CoefX<R>* x,
+                                             R (&Mt)[mob_n<NM, GEN>()]) {
+    if constexpr (GEN)
+        mobility_gen<R, NP, NM>(h, *x, Mt);
+    else
+        mobility<R, NP, NM>(h, c, Mt);
+}
+
 // Reciprocal to within a few ulp: hardware estimate plus Newton steps.
 __device__ __forceinline__ double fast_rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -176,6 +215,17 @@ template <typename R, int NP>
 __device__ __forceinline__ void psi_const(R tt, const Coef<R>& c, R (&Cs)[NP]) {
 #pragma unroll
     for (int b = 0; b < NP; ++b) Cs[b] = R(2) * (c.C[b] + c.s[b] * tt);
+}
+
+// The same with the quadratic term of C^b(T) (general kernels).
+template <typename R, int NP, bool GEN>
+__device__ __forceinline__ void psi_const_any(R tt, const Coef<R>& c, const CoefX<R>* x, R (&Cs)[NP]) {
+    if constexpr (GEN) {
+#pragma unroll
+        for (int b = 0; b < NP; ++b) Cs[b] = R(2) * (c.C[b] + (c.s[b] + x->Ct[b] * tt) * tt);
+    } else {
+        psi_const<R, NP>(tt, c, Cs);
+    }
 }
 
 // Cell update from the face sums Gs_a = sum_axes (U_hi - W_lo) and
@@ -271,6 +321,181 @@ __device__ __forceinline__ void cell_update(const R (&phi)[NP], const R (&mu)[NM
         }
         mun[k] = mu[k] + (Js[k] - src) * fast_rcp(chik);
     }
+}
+
+// Nearest point (Euclidean) of the simplex {phi >= 0, sum phi = 1} to y: the
+// obstacle step with the Lagrange multiplier over the active phases.  The
+// active set starts as all phases; theta = (sum of the active y - 1) / (their
+// count) is subtracted from the active phases and a phase that comes out
+// negative leaves the set.  NP passes always suffice (a pass that removes
+// nothing repeats the previous one), so every lane runs the same NP passes.
+template <typename R, int NP>
+__device__ __forceinline__ void simplex_project(R (&y)[NP]) {
+    bool act[NP];
+    R x[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) act[a] = true;
+#pragma unroll
+    for (int it = 0; it < NP; ++it) {
+        R s = R(0);
+        int n = 0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            s = s + (act[a] ? y[a] : R(0));
+            n += act[a] ? 1 : 0;
+        }
+        const R inv = n == 1 ? R(1) : (n == 2 ? R(0.5) : R(1) / R(3));
+        const R th = (s - R(1)) * inv;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            x[a] = act[a] ? y[a] - th : R(0);
+            act[a] = act[a] && !(x[a] < R(0));
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) y[a] = act[a] ? x[a] : R(0);
+}
+
+// Cell update of the extended model (general kernels): as cell_update, with
+// B^b(T) = B^b + Bt^b tt and C^b(T) (in Cs) at this cell's T - Te = tt, the
+// susceptibility and mobility as NM x NM matrices (psi^b = C^b - (mu - B^b)
+// chi^b (mu - B^b) / 2, c^b = chi^b (mu - B^b)), the dT/dt term
+// Theta_k = sum_a h_a(phi^{n+1}) (dc^a_k/dT) (T^{n+1} - T^n), the update
+// mu^{n+1} = mu + [sum_a h_a(phi^{n+1}) chi^a]^-1 (Js - source - Theta) by a
+// 2 x 2 solve, tau(phi) = sum tau_ab phi_a phi_b / sum phi_a phi_b from the
+// per-pair constants (the single tau in bulk, where the pair sum is <= 1e-30),
+// and for the obstacle either projection.
+template <typename R, int NP, int NM, bool OBST>
+__device__ __forceinline__ void cell_update_gen(const R (&phi)[NP], const R (&mu)[NM], const R (&h0)[NP],
+                                                const R (&Gs)[NP], const R (&Js)[NM], const R (&Cs)[NP], R tt,
+                                                const Coef<R>& c, const CoefX<R>& x, R (&phin)[NP],
+                                                R (&mun)[NM], R (&h1)[NP]) {
+    R dmu[NP][NM], cdm[NP][NM];
+    R psi2[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+#pragma unroll
+        for (int k = 0; k < NM; ++k) dmu[b][k] = mu[k] - (c.B[b][k] + x.Bt[b][k] * tt);
+        if constexpr (NM == 2) {
+            cdm[b][0] = c.chi[b][0] * dmu[b][0] + x.chx[b] * dmu[b][1];
+            cdm[b][1] = x.chx[b] * dmu[b][0] + c.chi[b][1] * dmu[b][1];
+        } else {
+            cdm[b][0] = c.chi[b][0] * dmu[b][0];
+        }
+        R v = Cs[b];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) v = v - cdm[b][k] * dmu[b][k];
+        psi2[b] = v;
+    }
+    R sq[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) sq[a] = phi[a] * phi[a];
+    R P[NP];
+    if constexpr (NP == 3) {
+        P[0] = phi[1] * phi[2];
+        P[1] = phi[0] * phi[2];
+        P[2] = phi[0] * phi[1];
+    }
+    R Z = R(0);
+    if constexpr (NP == 3) Z = c.g3e + ((psi2[0] + psi2[1]) + psi2[2]);
+    R Rr[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        R dw = R(0);
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            if (b == a) continue;
+            const R wc = c.wce[pair_index(a < b ? a : b, a < b ? b : a)];
+            if constexpr (OBST)
+                dw = dw + wc * phi[b];
+            else
+                dw = dw + wc * sq[b];
+        }
+        const R t3 = R(3) - R(3) * phi[a];
+        R Y;
+        if constexpr (OBST)
+            Y = dw + phi[a] * (psi2[a] * t3);
+        else
+            Y = phi[a] * (dw + psi2[a] * t3);
+        if constexpr (NP == 3) Y = Y + P[a] * Z;
+        Rr[a] = c.cE * Gs[a] - Y;
+    }
+    double lam = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP; ++a) lam = lam + (double)Rr[a];
+    lam = lam * (1.0 / NP);
+    R kp = c.kphi;
+    if (x.tpair) {
+        R num, den;
+        if constexpr (NP == 3) {
+            num = (x.tab[0] * P[2] + x.tab[1] * P[1]) + x.tab[2] * P[0];
+            den = (P[2] + P[1]) + P[0];
+        } else {
+            den = phi[0] * phi[1];
+            num = x.tab[0] * den;
+        }
+        kp = den > R(1e-30) ? x.ktau * (den * fast_rcp(num)) : c.kphi;
+    }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) phin[a] = phi[a] + kp * (R)((double)Rr[a] - lam);
+    if constexpr (OBST) {
+        if (x.proj) {
+            simplex_project<R, NP>(phin);
+        } else {
+            R sum = R(0);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                phin[a] = fmin(fmax(phin[a], R(0)), R(1));
+                sum = sum + phin[a];
+            }
+            const R inv = R(1) / sum;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) phin[a] = phin[a] * inv;
+        }
+    }
+    R dh[NP];
+    interp_h<R, NP>(phin, h1);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) dh[a] = h1[a] - h0[a];
+    R rhs[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        R src = R(0), th = R(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            src = src + cdm[a][k] * dh[a];
+            th = th + h1[a] * x.th[a][k];
+        }
+        rhs[k] = (Js[k] - src) - th;
+    }
+    R c00 = R(0);
+#pragma unroll
+    for (int a = 0; a < NP; ++a) c00 = c00 + h1[a] * c.chi[a][0];
+    if constexpr (NM == 2) {
+        R c11 = R(0), c01 = R(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            c11 = c11 + h1[a] * c.chi[a][1];
+            c01 = c01 + h1[a] * x.chx[a];
+        }
+        const R inv = fast_rcp(c00 * c11 - c01 * c01);
+        mun[0] = mu[0] + (c11 * rhs[0] - c01 * rhs[1]) * inv;
+        mun[1] = mu[1] + (c00 * rhs[1] - c01 * rhs[0]) * inv;
+    } else {
+        mun[0] = mu[0] + rhs[0] * fast_rcp(c00);
+    }
+}
+
+// Either cell update, by the kernel's model.
+template <typename R, int NP, int NM, bool OBST, bool GEN>
+__device__ __forceinline__ void cell_update_any(const R (&phi)[NP], const R (&mu)[NM], const R (&h0)[NP],
+                                                const R (&Gs)[NP], const R (&Js)[NM], const R (&Cs)[NP], R tt,
+                                                const Coef<R>& c, const CoefX<R>* x, R (&phin)[NP],
+                                                R (&mun)[NM], R (&h1)[NP]) {
+    if constexpr (GEN)
+        cell_update_gen<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, tt, c, *x, phin, mun, h1);
+    else
+        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, c, phin, mun, h1);
 }
 
 // Value of the next / previous lane of the wave (lane 63's next is lane 0 and

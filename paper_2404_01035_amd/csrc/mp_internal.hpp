@@ -37,11 +37,34 @@ struct Coef {
     R Dt[3][2];    // D chi dt / (2 dx^2)
 };
 
+// Terms of the extended model, read only by the general (GEN) kernels:
+// temperature-dependent B and C (Sec. 3), the dT/dt term of Eq.
+// Mu_explicit_temperature, off-diagonal susceptibility and mobility (Eq.
+// free_energy_density with the i < j term, Eq. Mass_conservation with a full
+// D), per-pair relaxation constants and the active-set obstacle projection.
+template <typename R>
+struct CoefX {
+    R Bt[3][2];     // B^a_k(T) = B^a_k + Bt^a_k (T - Te)
+    R Ct[3];        // C^a(T) = C^a + s^a (T - Te) + Ct^a (T - Te)^2
+    R chx[3];       // off-diagonal susceptibility (chi^a)_01 (K = 3); the diagonal is Coef::chi
+    R Dx[3][2][2];  // scaled mobility (D^a chi^a)_kj dt / (2 dx^2)
+    R th[3][2];     // Theta coefficient (dc^a_k/dT) (T^{n+1} - T^n) = -(chi^a Bt^a)_k (T^{n+1} - T^n)
+    R tab[3];       // per-pair relaxation constants tau_ab (pair index)
+    R ktau;         // dt / eps
+    int32_t tpair;  // 1: tau(phi) from tab; 0: the single tau (Coef::kphi)
+    int32_t proj;   // obstacle projection: 0 clip and renormalise, 1 onto the simplex (active set)
+};
+
 // Coefficients the FP64 diagnostics reduction needs.
 struct DiagCoef {
     double chi[3][2];
     double B[3][2];
     double vol;      // dx^d
+    double Bt[3][2]; // B^a_k(T) = B + Bt (T - Te)
+    double chx[3];   // off-diagonal susceptibility (K = 3)
+    double tt0;      // T - Te at row 0 of the reduced state's time level
+    double tslope;   // T - Te per row
+    int32_t nx, ny;  // rows: cell i lies in row (i / nx) mod ny
 };
 
 // One launch of the fused step kernel.  The time level of the launch is
@@ -119,6 +142,10 @@ int call_step_f64(const StepLaunch& L, const Coef<double>& c, KernelCall& k);
 int call_step_f32(const StepLaunch& L, const Coef<float>& c, KernelCall& k);
 template <typename R, bool D3>
 int call_step_dim(const StepLaunch& L, const Coef<R>& c, KernelCall& k);
+// The general kernels of the extended model (one cell per lane in 2D, 64 x 4
+// tiles in 3D).
+template <typename R, bool D3>
+int call_step_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k);
 template <typename R>
 int call_batch(const BatchLaunch& L, KernelCall& k);
 void call_advance(int64_t* ctr, int64_t by, KernelCall& k);
@@ -176,5 +203,13 @@ int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s);
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
                 const DiagCoef& dc, double* partials, double* result, hipStream_t s);
 int diag_blocks(int64_t ncells);
+
+// Moving frame (frame.hip): the front row (partials: front_blocks ints) and
+// the shift of a state by whole rows along y with melt appended.
+int front_blocks(int64_t ncells);
+int launch_front(const void* state, int precision, const Geom& g, int nphases, int* partials, int64_t* result,
+                 hipStream_t s);
+int launch_shift(const void* in, void* out, int precision, const Geom& g, int nphases, int nmu, int rows,
+                 const double* mu_melt, hipStream_t s);
 
 }  // namespace mp

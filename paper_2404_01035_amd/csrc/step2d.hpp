@@ -79,12 +79,12 @@ struct Raw2d {
 };
 
 // Cell record of one row (cell-major); for anisotropy also the x central
-// differences phi(x+1) - phi(x-1).
-template <typename R, int NP, int NM, int V, bool ANISO>
+// differences phi(x+1) - phi(x-1).  GEN: the mobility is a matrix.
+template <typename R, int NP, int NM, int V, bool ANISO, bool GEN = false>
 struct Row2d {
     R phi[V][NP];
     R mu[V][NM];
-    R Mt[V][NM];
+    R Mt[V][mob_n<NM, GEN>()];
     R cdx[ANISO ? V : 1][NP];
 };
 
@@ -99,9 +99,10 @@ struct Carry2d {
 
 // Cell record from the V values of every field (field-major, as loaded).
 // HAVE_H: hv holds h(phi) of the cells already.
-template <typename R, int NP, int NM, bool ANISO, int V, bool HAVE_H = false>
-__device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, NM, V, ANISO>& P,
-                                         const Coef<R>& c, const R (*hv)[V] = nullptr) {
+template <typename R, int NP, int NM, bool ANISO, int V, bool HAVE_H = false, bool GEN = false>
+__device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, NM, V, ANISO, GEN>& P,
+                                         const Coef<R>& c, const R (*hv)[V] = nullptr,
+                                         const CoefX<R>* x = nullptr) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
 #pragma unroll
@@ -115,7 +116,7 @@ __device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, 
         } else {
             interp_h<R, NP>(P.phi[i], hh);
         }
-        mobility<R, NP, NM>(hh, c, P.Mt[i]);
+        mobility_any<R, NP, NM, GEN>(hh, c, x, P.Mt[i]);
     }
     if constexpr (ANISO) {
 #pragma unroll
@@ -130,27 +131,28 @@ __device__ __forceinline__ void make_row(const R (&v)[NP + NM][V], Row2d<R, NP, 
 }
 
 // y face between rows A (below) and B (above) at slot i.
-template <typename R, int NP, int NM, bool ANISO, int V>
-__device__ __forceinline__ void yface(const Row2d<R, NP, NM, V, ANISO>& A, const Row2d<R, NP, NM, V, ANISO>& B,
-                                      int i, const Coef<R>& c, R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
+template <typename R, int NP, int NM, bool ANISO, int V, bool GEN = false>
+__device__ __forceinline__ void yface(const Row2d<R, NP, NM, V, ANISO, GEN>& A,
+                                      const Row2d<R, NP, NM, V, ANISO, GEN>& B, int i, const Coef<R>& c,
+                                      R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
     R tau[1][NP];
     if constexpr (ANISO) {
 #pragma unroll
         for (int a = 0; a < NP; ++a) tau[0][a] = A.cdx[i][a] + B.cdx[i][a];
     }
-    face_core<R, NP, NM, ANISO, 1>(A.phi[i], B.phi[i], tau, A.Mt[i], B.Mt[i], A.mu[i], B.mu[i], c, U, Wf,
-                                   J);
+    face_core<R, NP, NM, ANISO, 1, GEN>(A.phi[i], B.phi[i], tau, A.Mt[i], B.Mt[i], A.mu[i], B.mu[i], c, U, Wf,
+                                        J);
 }
 
 // Carry of the first row of a pass, from the row below it.
-template <typename R, int NP, int NM, bool ANISO, int V>
-__device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO>& prv,
-                                           const Row2d<R, NP, NM, V, ANISO>& cur,
+template <typename R, int NP, int NM, bool ANISO, int V, bool GEN = false>
+__device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO, GEN>& prv,
+                                           const Row2d<R, NP, NM, V, ANISO, GEN>& cur,
                                            Carry2d<R, NP, NM, V, ANISO>& k, const Coef<R>& c) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         R Ud[NP];
-        yface<R, NP, NM, ANISO, V>(prv, cur, i, c, Ud, k.Wlo[i], k.Jlo[i]);
+        yface<R, NP, NM, ANISO, V, GEN>(prv, cur, i, c, Ud, k.Wlo[i], k.Jlo[i]);
     }
     if constexpr (ANISO) {
 #pragma unroll
@@ -161,13 +163,15 @@ __device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO>& prv
 }
 
 // New values of the row `cur` (nxt is the row above) and the carry moved up
-// one row.  Cs = psi_const of the row; hn receives h of the new phi.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>
-__device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur,
-                                           const Row2d<R, NP, NM, V, ANISO>& nxt,
+// one row.  Cs = psi_const of the row, tt its T - Te; hn receives h of the
+// new phi.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN = false>
+__device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO, GEN>& cur,
+                                           const Row2d<R, NP, NM, V, ANISO, GEN>& nxt,
                                            Carry2d<R, NP, NM, V, ANISO>& k, const R (&Cs)[NP],
                                            const Coef<R>& c, R (&phin)[NP][V], R (&mun)[NM][V],
-                                           R (&hn)[NP][V]) {
+                                           R (&hn)[NP][V], R tt = R(0), const CoefX<R>* x = nullptr) {
+    constexpr int NMM = mob_n<NM, GEN>();
     R cdy[ANISO ? V : 1][NP];
     if constexpr (ANISO) {
 #pragma unroll
@@ -178,20 +182,19 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur
     // x face to the right of the last cell, with the next lane's first cell
     R Ur[NP], Wr[NP], Jr[NM];
     {
-        R pR[NP], uR[NM], MR[NM], tau[1][NP];
+        R pR[NP], uR[NM], MR[NMM], tau[1][NP];
 #pragma unroll
         for (int a = 0; a < NP; ++a) pR[a] = lane_next(cur.phi[0][a]);
 #pragma unroll
-        for (int kk = 0; kk < NM; ++kk) {
-            uR[kk] = lane_next(cur.mu[0][kk]);
-            MR[kk] = lane_next(cur.Mt[0][kk]);
-        }
+        for (int kk = 0; kk < NM; ++kk) uR[kk] = lane_next(cur.mu[0][kk]);
+#pragma unroll
+        for (int kk = 0; kk < NMM; ++kk) MR[kk] = lane_next(cur.Mt[0][kk]);
         if constexpr (ANISO) {
 #pragma unroll
             for (int a = 0; a < NP; ++a) tau[0][a] = cdy[V - 1][a] + lane_next(cdy[0][a]);
         }
-        face_core<R, NP, NM, ANISO, 1>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR, c,
-                                       Ur, Wr, Jr);
+        face_core<R, NP, NM, ANISO, 1, GEN>(cur.phi[V - 1], pR, tau, cur.Mt[V - 1], MR, cur.mu[V - 1], uR,
+                                            c, Ur, Wr, Jr);
     }
     // the face on the left of the first cell is the previous lane's last face
     R Wxl[NP], Jxl[NM];
@@ -210,8 +213,8 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur
 #pragma unroll
                 for (int a = 0; a < NP; ++a) tau[0][a] = cdy[i][a] + cdy[i + 1][a];
             }
-            face_core<R, NP, NM, ANISO, 1>(cur.phi[i], cur.phi[i + 1], tau, cur.Mt[i], cur.Mt[i + 1],
-                                           cur.mu[i], cur.mu[i + 1], c, Ux, Wx, Jx);
+            face_core<R, NP, NM, ANISO, 1, GEN>(cur.phi[i], cur.phi[i + 1], tau, cur.Mt[i], cur.Mt[i + 1],
+                                                cur.mu[i], cur.mu[i + 1], c, Ux, Wx, Jx);
         } else {
 #pragma unroll
             for (int a = 0; a < NP; ++a) {
@@ -223,7 +226,7 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur
         }
         // y face (m, m+1) above cell i
         R Uy[NP], Wy[NP], Jy[NM];
-        yface<R, NP, NM, ANISO, V>(cur, nxt, i, c, Uy, Wy, Jy);
+        yface<R, NP, NM, ANISO, V, GEN>(cur, nxt, i, c, Uy, Wy, Jy);
         R Gs[NP], Js[NM];
 #pragma unroll
         for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - k.Wlo[i][a]);
@@ -231,7 +234,7 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO>& cur
         for (int kk = 0; kk < NM; ++kk) Js[kk] = (Jx[kk] - Jxl[kk]) + (Jy[kk] - k.Jlo[i][kk]);
         R pn[NP], un[NM], h0[NP], h1[NP];
         interp_h<R, NP>(cur.phi[i], h0);
-        cell_update<R, NP, NM, OBST>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, c, pn, un, h1);
+        cell_update_any<R, NP, NM, OBST, GEN>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, tt, c, x, pn, un, h1);
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
             phin[a][i] = pn[a];
@@ -277,13 +280,13 @@ constexpr unsigned kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt/lgkmcnt unt
 // 1..W, W <= 62), rows [m0, m1).  Called with wave-uniform arguments by the
 // single-grid and the batched kernel.  Requires nx % V == 0.
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int DEPTH = MP_STRIP_DEPTH,
-          int W = W2D_LANES_OUT>
+          int W = W2D_LANES_OUT, bool GEN = false>
 __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                         const Coef<R>& c, double tbase, double tslope, int tx,
-                                        int m0, int m1) {
+                                        int m0, int m1, const CoefX<R>* x = nullptr) {
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
-    typedef Row2d<R, NP, NM, V, ANISO> RowT;
+    typedef Row2d<R, NP, NM, V, ANISO, GEN> RowT;
     const int lane = threadIdx.x & 63;
     const bool perx = g.bcx == MP_BC_PERIODIC;
     const bool pery = g.bcy == MP_BC_PERIODIC;
@@ -310,14 +313,15 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
     };
     auto process = [&](RawT& r, RowT& P) {
         mirror_fix<R, NF, V>(r.v, fixL, fixR);
-        make_row<R, NP, NM, ANISO, V>(r.v, P, c);
+        make_row<R, NP, NM, ANISO, V, false, GEN>(r.v, P, c, nullptr, x);
     };
     Carry2d<R, NP, NM, V, ANISO> k;
     auto row = [&](int m, const RowT& cur, const RowT& nxt) {
         R Cs[NP];
-        psi_const<R, NP>((R)(tbase + tslope * (double)m), c, Cs);
+        const R tt = (R)(tbase + tslope * (double)m);
+        psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(cur, nxt, k, Cs, c, phin, mun, hn);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN>(cur, nxt, k, Cs, c, phin, mun, hn, tt, x);
         if (writes) {
             const int64_t o = (int64_t)m * nx + cs;
 #pragma unroll
@@ -337,7 +341,7 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
         RowT prv;
         process(r0, prv);
         process(r1, cA);
-        carry_init<R, NP, NM, ANISO, V>(prv, cA, k, c);
+        carry_init<R, NP, NM, ANISO, V, GEN>(prv, cA, k, c);
         process(r2, cB);
     }
 
@@ -430,13 +434,14 @@ __device__ __forceinline__ int x2_first_col(int tx, int lane) {
 // XEDGE: the wave holds a mirror ghost column (wave-uniform; only then are
 // the mirror copies of step 1 made).  STORE1: the step-1 rows of the segment
 // are also written, to out1 (the state between the two steps).
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE, bool STORE1 = false>
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE, bool STORE1 = false,
+          bool GEN = false>
 __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
                                            const Geom& g, const Coef<R>& c, double tbase0, double tbase1,
-                                           double tslope, int tx, int m0, int m1) {
+                                           double tslope, int tx, int m0, int m1, const CoefX<R>* x = nullptr) {
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
-    typedef Row2d<R, NP, NM, V, ANISO> RowT;
+    typedef Row2d<R, NP, NM, V, ANISO, GEN> RowT;
     const int lane = threadIdx.x & 63;
     const bool pery = g.bcy == MP_BC_PERIODIC;
     const int nx = g.nx, ny = g.ny;
@@ -457,7 +462,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     };
     auto process = [&](RawT& r, RowT& P) {
         if constexpr (XEDGE) mirror_fix<R, NF, V>(r.v, fixL, fixR);
-        make_row<R, NP, NM, ANISO, V>(r.v, P, c);
+        make_row<R, NP, NM, ANISO, V, false, GEN>(r.v, P, c, nullptr, x);
     };
 
     // step 0 -> 1: rows of the state in c0 (row r) and n0 (row r+1)
@@ -472,7 +477,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         RowT prv;
         process(a, prv);
         process(b, c0);
-        carry_init<R, NP, NM, ANISO, V>(prv, c0, k0, c);
+        carry_init<R, NP, NM, ANISO, V, GEN>(prv, c0, k0, c);
         process(d, n0);
     }
     load(r_first + 2, ld);
@@ -483,9 +488,10 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     // flight stay in the registers they are loaded into.
     auto step1 = [&](int r, RowT& P) {
         R Cs[NP];
-        psi_const<R, NP>((R)(tbase0 + tslope * (double)rowmap(r)), c, Cs);
+        const R tt = (R)(tbase0 + tslope * (double)rowmap(r));
+        psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(c0, n0, k0, Cs, c, phin, mun, hn);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN>(c0, n0, k0, Cs, c, phin, mun, hn, tt, x);
         R v[NF][V];
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -505,9 +511,9 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
                 v[f][V - 1] = fixL ? nextFirst : v[f][V - 1];
                 v[f][0] = fixR ? prevLast : v[f][0];
             }
-            make_row<R, NP, NM, ANISO, V>(v, P, c);
+            make_row<R, NP, NM, ANISO, V, false, GEN>(v, P, c, nullptr, x);
         } else {
-            make_row<R, NP, NM, ANISO, V, true>(v, P, c, hn);
+            make_row<R, NP, NM, ANISO, V, true, GEN>(v, P, c, hn, x);
         }
         if constexpr (STORE1) {
             if (writes && r >= m0 && r < m1) {
@@ -532,13 +538,14 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         } else {
             step1(r_first + 1, c1);
         }
-        carry_init<R, NP, NM, ANISO, V>(lower, c1, k1, c);
+        carry_init<R, NP, NM, ANISO, V, GEN>(lower, c1, k1, c);
     }
     auto step2 = [&](int q) {
         R Cs[NP];
-        psi_const<R, NP>((R)(tbase1 + tslope * (double)q), c, Cs);
+        const R tt = (R)(tbase1 + tslope * (double)q);
+        psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(c1, n1, k1, Cs, c, phin, mun, hn);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN>(c1, n1, k1, Cs, c, phin, mun, hn, tt, x);
         if (writes) {
             const int64_t o = (int64_t)q * nx + cs;
 #pragma unroll
@@ -613,6 +620,78 @@ k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
         strip2d_x2<R, NP, NM, ANISO, OBST, V, false, STORE1>(in, out, out1, g, c, tb0 + tdn * n,
                                                              tb0 + tdn * (n + 1.0), tslope, tx, m0,
                                                              min(m0 + seg, g.ny));
+}
+
+// The general kernels of the extended model (one cell per lane): the same
+// strips with the GEN cell and face arithmetic, and the extended
+// coefficients as a further argument.
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
+k_step2d_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+             const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+             int seg, int ntx, int nseg, CoefX<R> x) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
+    strip2d<R, NP, NM, ANISO, OBST, 1, MP_STRIP_DEPTH, W2D_LANES_OUT, true>(in, out, g, c, tbase, tslope, tx, m0,
+                                                                          min(m0 + seg, g.ny), &x);
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
+k_step2d_x2_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+                const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+                int seg, int ntx, int nseg, CoefX<R> x) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double n = (double)(*stepctr + kstep);
+    bool fixL, fixR;
+    x2_column<1>(g, x2_first_col<1>(tx, threadIdx.x & 63), fixL, fixR);
+    if (__ballot(fixL || fixR) != 0)
+        strip2d_x2<R, NP, NM, ANISO, OBST, 1, true, false, true>(in, out, nullptr, g, c, tb0 + tdn * n,
+                                                                 tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                                 min(m0 + seg, g.ny), &x);
+    else
+        strip2d_x2<R, NP, NM, ANISO, OBST, 1, false, false, true>(in, out, nullptr, g, c, tb0 + tdn * n,
+                                                                  tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                                  min(m0 + seg, g.ny), &x);
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int call_2d_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    const int wout = L.fuse == 2 ? W2X_LANES_OUT : W2D_LANES_OUT;
+    const int ntx = (L.g.nx + wout - 1) / wout;
+    const int nseg = (L.g.ny + L.seg - 1) / L.seg;
+    const int wpb = L.bx / 64;
+    const long long waves = (long long)ntx * nseg;
+    const long long nblocks = (waves + wpb - 1) / wpb;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL || L.out1) return MP_E_PARAM;
+    k.func = L.fuse == 2 ? (const void*)&k_step2d_x2_gen<R, NP, NM, ANISO, OBST>
+                         : (const void*)&k_step2d_gen<R, NP, NM, ANISO, OBST>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(L.bx);
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nseg);
+    k.arg(x);
+    return MP_OK;
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V>

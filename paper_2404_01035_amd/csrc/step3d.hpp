@@ -15,12 +15,14 @@
 
 namespace mp {
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY)
-k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
-         const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
-         int seg, int ntx, int nty) {
+// The step of one block (GEN: the extended model's arithmetic, x its terms).
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY, bool GEN>
+__device__ __forceinline__ void step3d_block(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
+                                             const Coef<R>& c, const int64_t* __restrict__ stepctr, int kstep,
+                                             double tb0, double tdn, double tslope, int seg, int ntx, int nty,
+                                             const CoefX<R>* x) {
     constexpr int NF = NP + NM;
+    constexpr int NMM = mob_n<NM, GEN>();
     constexpr int PW = BX + 2;
     constexpr int PH = BY + 2;
     constexpr int PP = PW * PH;
@@ -28,7 +30,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     constexpr int NPOS = (PP + NT - 1) / NT;
     constexpr int NS = 4;
     __shared__ R sv[NS][NF][PP];
-    __shared__ R sm[NS][NM][PP];
+    __shared__ R sm[NS][NMM][PP];
 
     const int nb = gridDim.x;
     const int q8 = nb / 8;
@@ -80,15 +82,15 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         for (int k = 0; k < NPOS; ++k) {
             const int p = tid + k * NT;
             if (p < PP) {
-                R ph[NP], hh[NP], Mt[NM];
+                R ph[NP], hh[NP], Mt[NMM];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) sv[sl][f][p] = reg[k][f];
 #pragma unroll
                 for (int a = 0; a < NP; ++a) ph[a] = reg[k][a];
                 interp_h<R, NP>(ph, hh);
-                mobility<R, NP, NM>(hh, c, Mt);
+                mobility_any<R, NP, NM, GEN>(hh, c, x, Mt);
 #pragma unroll
-                for (int kk = 0; kk < NM; ++kk) sm[sl][kk][p] = Mt[kk];
+                for (int kk = 0; kk < NMM; ++kk) sm[sl][kk][p] = Mt[kk];
             }
         }
     };
@@ -97,7 +99,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     // steps: dS*[t] is the slot step, dP*[t] the in-plane position step.
     auto face = [&](int sL, int pL, int sR, int pR, const int (&tS)[2], const int (&tP)[2],
                     R (&U)[NP], R (&Wf)[NP], R (&J)[NM]) {
-        R phL[NP], phR[NP], uL[NM], uR[NM], mL[NM], mR[NM];
+        R phL[NP], phR[NP], uL[NM], uR[NM], mL[NMM], mR[NMM];
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
             phL[a] = sv[sL][a][pL];
@@ -107,6 +109,9 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         for (int k = 0; k < NM; ++k) {
             uL[k] = sv[sL][NP + k][pL];
             uR[k] = sv[sR][NP + k][pR];
+        }
+#pragma unroll
+        for (int k = 0; k < NMM; ++k) {
             mL[k] = sm[sL][k][pL];
             mR[k] = sm[sR][k][pR];
         }
@@ -122,7 +127,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
                                 (sv[sRp][a][pR + tP[t]] - sv[sRm][a][pR - tP[t]]);
             }
         }
-        face_core<R, NP, NM, ANISO, 2>(phL, phR, tau, mL, mR, uL, uR, c, U, Wf, J);
+        face_core<R, NP, NM, ANISO, 2, GEN>(phL, phR, tau, mL, mR, uL, uR, c, U, Wf, J);
     };
 
     fetch(m0 - 1);
@@ -139,7 +144,8 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     const bool valid = gx < g.nx && gy < g.ny;
     const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
     R Cs[NP];  // T - Te depends on y only
-    psi_const<R, NP>((R)(tbase + tslope * (double)gy), c, Cs);
+    const R tt = (R)(tbase + tslope * (double)gy);
+    psi_const_any<R, NP, GEN>(tt, c, x, Cs);
 
     // tangential steps: x faces see (y, z), y faces see (x, z), z faces see (x, y)
     const int tSx[2] = {0, 1}, tPx[2] = {PW, 0};
@@ -200,7 +206,7 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         interp_h<R, NP>(phi, h0);
         R phin[NP], mun[NM];
         R h1[NP];
-        cell_update<R, NP, NM, OBST>(phi, mu, h0, Gs, Js, Cs, c, phin, mun, h1);
+        cell_update_any<R, NP, NM, OBST, GEN>(phi, mu, h0, Gs, Js, Cs, tt, c, x, phin, mun, h1);
 
         if (valid) {
             const int64_t o = (int64_t)gx + (int64_t)gy * sy + (int64_t)m * sz;
@@ -213,6 +219,51 @@ k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
         if (m + 2 <= m1) stage(m + 2);
         __syncthreads();
     }
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY>
+__global__ void __launch_bounds__(BX * BY)
+k_step3d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+         const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+         int seg, int ntx, int nty) {
+    step3d_block<R, NP, NM, ANISO, OBST, BX, BY, false>(in, out, g, c, stepctr, kstep, tb0, tdn, tslope, seg,
+                                                        ntx, nty, nullptr);
+}
+
+// The extended model's 3D kernel (64 x 4 tiles).
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+__global__ void __launch_bounds__(256)
+k_step3d_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+             const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+             int seg, int ntx, int nty, CoefX<R> x) {
+    step3d_block<R, NP, NM, ANISO, OBST, 64, 4, true>(in, out, g, c, stepctr, kstep, tb0, tdn, tslope, seg,
+                                                      ntx, nty, &x);
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST>
+int call_3d_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    const int ntx = (L.g.nx + 63) / 64;
+    const int nty = (L.g.ny + 3) / 4;
+    const int nseg = (L.g.nz + L.seg - 1) / L.seg;
+    const long long nblocks = (long long)ntx * nty * nseg;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL) return MP_E_PARAM;
+    k.func = (const void*)&k_step3d_gen<R, NP, NM, ANISO, OBST>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(256);
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nty);
+    k.arg(x);
+    return MP_OK;
 }
 
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int BY>

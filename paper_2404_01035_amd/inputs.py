@@ -402,6 +402,50 @@ def config_c2(precision="f64", n=(4096, 4096, 1), seed=1):
     return p, phi, mu
 
 
+def eutectic_slopes_params(n=(4096, 4096, 1), seed=1, precision="f64", G=1e-3, V=0.01, y0=64.0,
+                           eps=4.0, tau=1.0, dt_frac=0.2) -> Params:
+    """The directional eutectic with temperature-dependent parabolic coefficients.
+
+    Curvatures and equilibrium compositions at Te are those of
+    ``eutectic_params`` (same seed, same draws); the equilibrium compositions
+    move with T along seeded coexistence-line slopes (Sec. 3), |slope| ~ U[2, 6]
+    (dT per unit composition), so B and C depend on T (``parabolic_coefficients_T``)
+    and the mu update carries the dT/dt term of Eq. Mu_explicit_temperature.
+    Solid slopes take random signs; the liquid's are drawn until every solid is
+    the stable phase below Te: at mu = 0 and Te, d(psi^a - psi^l)/dT =
+    (c^a_eq - c^l_eq) . H^l (1 / slope^l), which must be positive.
+    """
+    p = eutectic_params(n=n, seed=seed, precision=precision, G=G, V=V, y0=y0, eps=eps, tau=tau,
+                        dt_frac=dt_frac)
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(0.5, 2.0, size=(3, 2))
+    ceq = rng.uniform(0.1, 0.9, size=(3, 2))
+    rs = np.random.default_rng(seed + 500)
+    slopes = rs.uniform(2.0, 6.0, size=(3, 2)) * rs.choice([-1.0, 1.0], size=(3, 2))
+    H = hessians(A)
+    while True:
+        u = 1.0 / slopes[2]
+        if all((ceq[a] - ceq[2]) @ H[2] @ u > 0.0 for a in range(2)):
+            break
+        slopes[2] = rs.uniform(2.0, 6.0, size=2) * rs.choice([-1.0, 1.0], size=2)
+    B, Bt, C, s, Ct = parabolic_coefficients_T(A, ceq, slopes, liquid=2)
+    p.A[:3, :2], p.B[:3, :2], p.Bt[:3, :2] = A, B, Bt
+    p.C[:3], p.s[:3], p.Ct[:3] = C, s, Ct
+    p.dt = dt_frac * dt_limit(p)
+    return p
+
+
+def config_c2_slopes(precision="f64", n=(4096, 4096, 1), seed=1):
+    """``config_c2`` with temperature-dependent coefficients (``eutectic_slopes_params``)."""
+    scale = n[0] / 4096.0
+    p = eutectic_slopes_params(n=n, seed=seed, precision=precision, y0=max(8.0, 64.0 * scale))
+    slab = int(round(p.y0))
+    wmin = max(4, int(round(16 * scale)))
+    wmax = max(wmin + 2, int(round(48 * scale)))
+    phi, mu = eutectic_initial(p, slab=slab, wmin=wmin, wmax=wmax, seed=seed)
+    return p, phi, mu
+
+
 def dendrite_params(n=(512, 512, 512), precision="f32", gamma0=0.5, delta=0.02,
                     undercooling=0.3, eps=4.0, dt_frac=0.2) -> Params:
     """3D binary dendrite: 2 phases, cubic anisotropy, no-flux on every face."""

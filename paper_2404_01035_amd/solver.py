@@ -62,6 +62,30 @@ class Solver:
     def set_tile(self, bx: int = 0, seg: int = 0, vec: int = 0):
         abi.mp_set_tile(self.st, bx, seg, vec)
 
+    # ---- moving frame (SHIFT) ------------------------------------------------
+    def front_row(self) -> int:
+        """Highest row holding a cell whose liquid fraction is below 1/2 (-1 if none)."""
+        return abi.mp_front_row(self.st, self.stream())
+
+    def shift(self, rows: int, mu_melt) -> int:
+        """Move the frame up by ``rows``: solid rows leave at the bottom, melt at
+        ``mu_melt`` enters at the top.  Returns the total frame offset in rows."""
+        return abi.mp_shift(self.st, rows, mu_melt, self.stream())
+
+    def step_moving_frame(self, nsteps: int, shiftj: int, every: int, mu_melt) -> int:
+        """``nsteps`` steps; every ``every`` steps (and at the end) the front row is
+        found and, when it lies above row ``shiftj``, the frame is shifted by the
+        difference (the SHIFT / Shiftj keys).  Returns the total frame offset."""
+        done, offset = 0, abi.mp_shift(self.st, 0, mu_melt, self.stream())
+        while done < nsteps:
+            n = min(every, nsteps - done)
+            self.step(n)
+            done += n
+            front = self.front_row()
+            if front > shiftj:
+                offset = self.shift(front - shiftj, mu_melt)
+        return offset
+
     def set_graph(self, chunk: int):
         """Replay steps as HIP graphs of ``chunk`` steps (0: launch kernel by kernel)."""
         abi.mp_set_graph(self.st, chunk)

@@ -57,6 +57,48 @@ def test_dt_limit_matches_input_formula():
         assert math.isclose(abi.mp_dt_limit(p), inputs.dt_limit(p), rel_tol=1e-14)
 
 
+def test_dt_limit_matches_input_formula_extended_model():
+    """Per-pair tau and off-diagonal A/D enter the limit the same way on both sides."""
+    rng = np.random.default_rng(4)
+    p = inputs.config_c2(n=(64, 64, 1))[0]
+    for q in range(3):
+        a, b = [(0, 1), (0, 2), (1, 2)][q]
+        p.tau_ab[a, b] = p.tau_ab[b, a] = rng.uniform(0.4, 1.5)
+    assert math.isclose(abi.mp_dt_limit(p), inputs.dt_limit(p), rel_tol=1e-14)
+    p.A01[:3] = rng.uniform(-0.4, 0.4, size=3)
+    p.D[:3, :2] = rng.uniform(0.1, 1.0, size=(3, 2))
+    p.D01[:3] = 0.3 * np.sqrt(p.D[:3, 0] * p.D[:3, 1])
+    assert math.isclose(abi.mp_dt_limit(p), inputs.dt_limit(p), rel_tol=1e-13)
+    p.dt = 0.5 * inputs.dt_limit(p)
+    abi.mp_destroy(abi.mp_create(p))
+
+
+def test_create_rejects_bad_extended_coefficients():
+    p = inputs.config_c2_slopes(n=(32, 32, 1))[0]
+    abi.mp_destroy(abi.mp_create(p))
+    q = p.copy()
+    q.tau_ab[0, 1] = q.tau_ab[1, 0] = 1.0  # one pair only
+    _expect(abi.MP_E_PARAM, q, "every pair")
+    q = p.copy()
+    q.tau_ab[0, 1], q.tau_ab[1, 0] = 1.0, 2.0
+    _expect(abi.MP_E_PARAM, q, "symmetric")
+    q = p.copy()
+    q.A01[1] = 2.0 * np.sqrt(q.A[1, 0] * q.A[1, 1]) + 0.1  # curvature matrix not positive definite
+    _expect(abi.MP_E_PARAM, q, "positive definite")
+    q = p.copy()
+    q.D[2, :2] = (1.0, 1.0)
+    q.D01[2] = 1.5
+    _expect(abi.MP_E_PARAM, q, "semidefinite")
+    q = p.copy()
+    q.Bt[0, 1] = float("inf")
+    _expect(abi.MP_E_PARAM, q, "Bt")
+    import ctypes as C
+    g, c = abi.to_grid(p), abi.to_params(p)
+    c.potential = 3
+    h = C.c_void_p()
+    assert abi.lib().mp_create(C.byref(g), 3, 3, C.byref(c), C.byref(h)) == abi.MP_E_PARAM
+
+
 def _expect(code, p, match=None):
     with pytest.raises(abi.MPError) as ei:
         abi.mp_create(p)

@@ -81,3 +81,9 @@ def test_band_split_oracle_equals_the_full_step():
     f, m = bench.oracle_band_steps(phi, mu, 3, 2, p, workers=3)
     rf, rm = gp.run(phi, mu, 3, 2, p)
     assert np.array_equal(f, rf) and np.array_equal(m, rm)
+
+
+def test_valu_figures_hold_only_for_their_tile_steps_and_sources():
+    for leg, t in bench.VALU.items():
+        assert bench.valu_of(leg, t["tile"], t["fuse"]) == t["insts"], leg
+        assert bench.valu_of(leg, t["tile"], 3 - t["fuse"]) is None
