@@ -188,6 +188,22 @@ int mp_set_step(mp_state* st, int64_t step, int which_buf);
  * MP_E_STATE for a batched state (use mp_diagnostics_batch). */
 int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
 
+/* mp_diagnostics without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  state_buf is a device buffer holding the state at time
+ * level ``step`` in the layout of ``st`` (mp_create or mp_create_batch; st need
+ * not be bound); out receives one mp_diag per instance (host memory).  The
+ * reduction's partial sums and result records live in a static device array
+ * of the library (about 160 KiB: 1024 partial records and one record per
+ * instance, at most 256 instances), which each GPU holds until the process
+ * ends; the call allocates no memory.  Every call on a GPU shares that array:
+ * calls that overlap on one GPU (other streams or host threads) race.  Same
+ * kernels and results as mp_diagnostics / mp_diagnostics_batch.  Synchronises
+ * ``stream``.  Errors: MP_E_NULLPTR, MP_E_PARAM (more than 256 instances,
+ * step < 0), MP_E_NONFINITE (out filled), MP_E_HIP. */
+int mp_diagnostics_static(const mp_state* st, const void* state_buf, int64_t step, mp_diag* out,
+                          void* stream);
+
 /* Tile shape of the step kernel.  2D: bx = threads per block (64, 128 or
  * 256: 1, 2 or 4 independent strip waves), seg = rows per strip segment and
  * vec = the most cells one lane holds (1, 2, or 4 in FP32 only; each lane

@@ -34,7 +34,7 @@ EXPORTS = [
     "mp_last_error", "mp_set_graph", "mp_create_batch", "mp_instance_count", "mp_instance_offset",
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
     "mp_tune_candidates", "mp_tune", "mp_set_fusion", "mp_get_fusion",
-    "mp_set_antitrapping", "mp_get_antitrapping", "mp_front_row", "mp_shift",
+    "mp_set_antitrapping", "mp_get_antitrapping", "mp_diagnostics_static", "mp_front_row", "mp_shift",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -103,6 +103,8 @@ def lib():
         L.mp_set_step.argtypes = [vp, C.c_int64, C.c_int]
         L.mp_diagnostics.restype = C.c_int
         L.mp_diagnostics.argtypes = [vp, C.POINTER(mp_diag), vp]
+        L.mp_diagnostics_static.restype = C.c_int
+        L.mp_diagnostics_static.argtypes = [vp, vp, C.c_int64, C.POINTER(mp_diag), vp]
         L.mp_front_row.restype = C.c_int
         L.mp_front_row.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.mp_shift.restype = C.c_int
@@ -260,6 +262,19 @@ def mp_diagnostics_batch(st, stream: int = 0, allow_nonfinite: bool = False) -> 
     n = mp_instance_count(st)
     arr = (mp_diag * n)()
     rc = lib().mp_diagnostics_batch(st, arr, stream)
+    if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
+        _check(rc)
+    return [_diag_dict(arr[i]) for i in range(n)]
+
+
+def mp_diagnostics_static(st, state_buf: int, step: int, stream: int = 0,
+                          allow_nonfinite: bool = False) -> list:
+    """Diagnostics of the state in device buffer ``state_buf`` at time level
+    ``step``, reduced in the library's static scratch (no workspace); one dict
+    per instance."""
+    n = mp_instance_count(st)
+    arr = (mp_diag * n)()
+    rc = lib().mp_diagnostics_static(st, state_buf, int(step), arr, stream)
     if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
         _check(rc)
     return [_diag_dict(arr[i]) for i in range(n)]

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "adjoint2d.hpp"
+#include "diag_static.hpp"
 #include "mp_internal.hpp"
 
 namespace {
@@ -1129,6 +1130,44 @@ int mp_diagnostics_batch(mp_state* st, mp_diag* out, void* stream) {
     if (!st || !out) return fail(MP_E_NULLPTR, "state or out is NULL");
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_diagnostics_batch before mp_bind");
     return diag_many(st, out, stream);
+}
+
+int mp_diagnostics_static(const mp_state* st, const void* state_buf, int64_t step, mp_diag* out,
+                          void* stream) {
+    if (!st || !state_buf || !out) return fail(MP_E_NULLPTR, "state, state_buf or out is NULL");
+    const int n = (int)st->inst.size();
+    if (n > mp::DIAG_STATIC_INST)
+        return fail(MP_E_PARAM, "mp_diagnostics_static reduces at most %d instances (got %d)",
+                    mp::DIAG_STATIC_INST, n);
+    if (step < 0) return fail(MP_E_PARAM, "step must be >= 0");
+    double* scr = nullptr;
+    int rc = hip_check(mp::diag_static_scratch(&scr), "static diagnostics scratch");
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        if (mp::diag_blocks(ncells_of(st->inst[i].grid)) > mp::DIAG_BLOCKS_MAX)
+            return fail(MP_E_PARAM, "instance %d needs more partial records than the scratch holds", i);
+        rc = diag_instance_at(st, i, state_buf, step, scr, scr + (size_t)(mp::DIAG_BLOCKS_MAX + i) * mp::DIAG_VALS,
+                              s);
+        if (rc) return rc;
+    }
+    // result records into host memory in fixed-size pieces (no allocation)
+    double r[16 * mp::DIAG_VALS];
+    int64_t bad = 0;
+    for (int i0 = 0; i0 < n; i0 += 16) {
+        const int m = std::min(16, n - i0);
+        rc = hip_check(hipMemcpyAsync(r, scr + (size_t)(mp::DIAG_BLOCKS_MAX + i0) * mp::DIAG_VALS,
+                                      sizeof(double) * mp::DIAG_VALS * m, hipMemcpyDeviceToHost, s),
+                       "diagnostics copy");
+        if (rc == MP_OK) rc = hip_check(hipStreamSynchronize(s), "diagnostics sync");
+        if (rc) return rc;
+        for (int j = 0; j < m; ++j) {
+            unpack_diag(st, i0 + j, &r[(size_t)j * mp::DIAG_VALS], step, &out[i0 + j]);
+            bad += out[i0 + j].nonfinite;
+        }
+    }
+    if (bad > 0) return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)bad);
+    return ok();
 }
 
 int mp_set_tile(mp_state* st, int bx, int seg, int vec) {

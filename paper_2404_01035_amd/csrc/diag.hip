@@ -4,9 +4,40 @@
 // count of non-finite cells.  Sums are FP64 with Neumaier compensation; the
 // grid, the per-thread stride and both tree reductions are fixed by the cell
 // count alone, so the result is bitwise reproducible run to run.
+#include <mutex>
+
+#include "diag_static.hpp"
 #include "mp_internal.hpp"
 
 namespace mp {
+
+// The device memory of mp_diagnostics_static: the per-block partial records
+// and one result record per instance, in the library's own storage instead of
+// a caller workspace.  Each GPU the library runs on holds its own copy until
+// the process ends.  Host code must not pass the array's name to a kernel (it
+// is a host-side stand-in there): diag_static_scratch returns its address on
+// the current device.
+static __device__ __align__(256) double scratch[(DIAG_BLOCKS_MAX + DIAG_STATIC_INST) * DIAG_VALS];
+
+hipError_t diag_static_scratch(double** out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex lock;
+    static double* addr[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(lock);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (double*)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 
 namespace {
 
