@@ -192,175 +192,8 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
     }
 }
 
-// 3D: one thread per cell.  The cell's 19-point neighbourhood of phi^n (the
-// 3 x 3 x 3 cube without its corners: every point a face of the cell needs) is
-// read once into registers, then the six faces are evaluated from it.  A face
-// normal to axis a between cells L and R = L + e_a takes, per phase, the normal
-// difference and, along each other axis t, the mean of the two cells' central
-// differences; the components enter |grad phi|^2 and -n_a . n_liq in the order
-// x, y, z.
-template <typename R, int NP>
-struct AtCube {
-    R p[3][3][3][NP];  // [z][y][x], centre at [1][1][1]
-};
-
-template <typename R, int NP>
-__device__ inline R at_cube(const AtCube<R, NP>& C, const int* q, int a) {
-    return C.p[q[2]][q[1]][q[0]][a];
-}
-
-template <typename R, int NP, int NM>
-__device__ inline void at_face_cube(const AtCube<R, NP>& C, int axis, int side, const R* qL, const R* qR,
-                                    const R* uL, const R* uR, const AtCoef<R>& c, R* j) {
-    constexpr int LIQ = NP - 1;
-    int L[3] = {1, 1, 1}, Rr[3] = {1, 1, 1};
-    L[axis] = side;
-    Rr[axis] = side + 1;
-    const R h2 = R(0.5) * c.rdx;
-    R u[3][NP], n2[NP], pL[NP], pR[NP];
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        pL[a] = at_cube(C, L, a);
-        pR[a] = at_cube(C, Rr, a);
-        n2[a] = R(0);
-    }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-#pragma unroll
-        for (int a = 0; a < NP; ++a) {
-            R gc;
-            if (t == axis) {
-                gc = (pR[a] - pL[a]) * c.rdx;
-            } else {
-                int lp[3] = {L[0], L[1], L[2]}, lm[3] = {L[0], L[1], L[2]};
-                int rp[3] = {Rr[0], Rr[1], Rr[2]}, rm[3] = {Rr[0], Rr[1], Rr[2]};
-                lp[t] += 1;
-                lm[t] -= 1;
-                rp[t] += 1;
-                rm[t] -= 1;
-                const R tl = (at_cube(C, lp, a) - at_cube(C, lm, a)) * h2;
-                const R tr = (at_cube(C, rp, a) - at_cube(C, rm, a)) * h2;
-                gc = R(0.5) * (tl + tr);
-            }
-            u[t][a] = gc;
-            n2[a] += gc * gc;
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        const R inv = n2[a] > R(1e-30) ? R(1) / sqrt(n2[a]) : R(0);
-        u[0][a] *= inv;
-        u[1][a] *= inv;
-        u[2][a] *= inv;
-    }
-    R cl_[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k)
-        cl_[k] = R(0.5) * (c.chi[LIQ][k] * (uL[k] - c.B[LIQ][k]) + c.chi[LIQ][k] * (uR[k] - c.B[LIQ][k]));
-#pragma unroll
-    for (int a = 0; a < NP - 1; ++a) {
-        const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
-        const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
-        const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[axis][a] * weight;
-#pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            const R ca = R(0.5) * (c.chi[a][k] * (uL[k] - c.B[a][k]) + c.chi[a][k] * (uR[k] - c.B[a][k]));
-            j[k] += common * (ca - cl_[k]);
-        }
-    }
-}
-
-template <typename R, int NP, int NM>
-__global__ void __launch_bounds__(256) k_antitrap3d(const R* __restrict__ prev, R* __restrict__ next, Geom g,
-                                                     AtCoef<R> c) {
-    const int i = (int)(blockIdx.x * 64 + (threadIdx.x & 63));
-    const int jy = (int)(blockIdx.y * 4 + (threadIdx.x >> 6));
-    const int kz = (int)blockIdx.z;
-    if (i >= g.nx || jy >= g.ny || kz >= g.nz) return;
-    const int64_t fs = g.fstride;
-    const int xs[3] = {at_wrap(i - 1, g.nx, g.bcx), i, at_wrap(i + 1, g.nx, g.bcx)};
-    const int ys[3] = {at_wrap(jy - 1, g.ny, g.bcy), jy, at_wrap(jy + 1, g.ny, g.bcy)};
-    const int zs[3] = {at_wrap(kz - 1, g.nz, g.bcz), kz, at_wrap(kz + 1, g.nz, g.bcz)};
-    AtCube<R, NP> C;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int far = (dz != 1) + (dy != 1) + (dx != 1);
-#pragma unroll
-                for (int a = 0; a < NP; ++a)
-                    C.p[dz][dy][dx][a] =
-                        far == 3 ? R(0) : prev[a * fs + ((int64_t)zs[dz] * g.ny + ys[dy]) * g.nx + xs[dx]];
-            }
-    // phi^{n+1} and mu^n of the cell and its six face neighbours: centre, then (axis, side)
-    R Q[7][NP], U[7][NM];
-#pragma unroll
-    for (int s = 0; s < 7; ++s) {
-        int d[3] = {1, 1, 1};
-        if (s > 0) d[(s - 1) / 2] = ((s - 1) % 2 == 0) ? 0 : 2;
-        const int64_t o = ((int64_t)zs[d[2]] * g.ny + ys[d[1]]) * g.nx + xs[d[0]];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) Q[s][a] = next[a * fs + o];
-#pragma unroll
-        for (int k = 0; k < NM; ++k) U[s][k] = prev[(NP + k) * fs + o];
-    }
-    R div[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k) div[k] = R(0);
-#pragma unroll
-    for (int axis = 0; axis < 3; ++axis) {
-        R jl[NM], jh[NM];
-#pragma unroll
-        for (int k = 0; k < NM; ++k) jl[k] = jh[k] = R(0);
-        const int lo = 1 + 2 * axis, hi = 2 + 2 * axis;
-        at_face_cube<R, NP, NM>(C, axis, 0, Q[lo], Q[0], U[lo], U[0], c, jl);
-        at_face_cube<R, NP, NM>(C, axis, 1, Q[0], Q[hi], U[0], U[hi], c, jh);
-#pragma unroll
-        for (int k = 0; k < NM; ++k) div[k] += (jh[k] - jl[k]) * c.rdx;
-    }
-    const int64_t oc = ((int64_t)kz * g.ny + jy) * g.nx + i;
-    R hb[NP];
-#pragma unroll
-    for (int b = 0; b < NP; ++b) {
-        const R f = Q[0][b];
-        R cross = R(0);
-        if constexpr (NP == 3) cross = Q[0][(b + 1) % 3] * Q[0][(b + 2) % 3];
-        hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
-    }
-#pragma unroll
-    for (int k = 0; k < NM; ++k) {
-        R chik = R(0);
-#pragma unroll
-        for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
-        next[(NP + k) * fs + oc] = next[(NP + k) * fs + oc] - c.dt * div[k] / chik;
-    }
-}
-
 template <typename R>
-int at_launch3d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
-    if (L.g.nx < 1 || L.g.ny < 1 || L.g.nz < 1 || (L.g.ny + 3) / 4 > 65535 || L.g.nz > 65535) return MP_E_PARAM;
-    dim3 block(256);
-    dim3 grid((unsigned)((L.g.nx + 63) / 64), (unsigned)((L.g.ny + 3) / 4), (unsigned)L.g.nz);
-    const R* prev = (const R*)L.prev;
-    R* next = (R*)L.next;
-    if (L.nphases == 2 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap3d<R, 2, 1>), grid, block, 0, s, prev, next, L.g, c);
-    else if (L.nphases == 2 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap3d<R, 2, 2>), grid, block, 0, s, prev, next, L.g, c);
-    else if (L.nphases == 3 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap3d<R, 3, 1>), grid, block, 0, s, prev, next, L.g, c);
-    else if (L.nphases == 3 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap3d<R, 3, 2>), grid, block, 0, s, prev, next, L.g, c);
-    else
-        return MP_E_PARAM;
-    return hipGetLastError() == hipSuccess ? MP_OK : MP_E_HIP;
-}
-
-template <typename R>
-int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
-    if (L.g.nz > 1) return at_launch3d<R>(L, c, s);
+int at_launch2d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
     if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1) return MP_E_PARAM;
     const int nstrips = (L.g.nx + AT_LANES_OUT - 1) / AT_LANES_OUT;
     const int64_t items = (int64_t)nstrips * ((L.g.ny + AT_SEG - 1) / AT_SEG);

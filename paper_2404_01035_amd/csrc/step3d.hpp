@@ -56,12 +56,26 @@ __device__ __forceinline__ void step3d_block(const R* __restrict__ in, R* __rest
     const int lx = tid % BX;
     const int ly = tid / BX;
 
+    // Tile positions as loaded: the first (BY + 2) * BX are the halo rows'
+    // interior columns, one aligned BX-wide row segment per wave; the last
+    // 2 (BY + 2) are the rows' two halo columns.  ppos[k] is the LDS position
+    // (row * PW + column) of this thread's k-th load.
+    constexpr int NCORE = (BY + 2) * BX;
     int64_t poff[NPOS];
+    int ppos[NPOS];
 #pragma unroll
     for (int k = 0; k < NPOS; ++k) {
-        int p = tid + k * NT;
-        if (p >= PP) p = PP - 1;
-        const int ix = p % PW, iy = p / PW;
+        int q = tid + k * NT;
+        if (q >= PP) q = PP - 1;
+        int ix, iy;
+        if (q < NCORE) {
+            iy = q / BX;
+            ix = 1 + q % BX;
+        } else {
+            iy = (q - NCORE) >> 1;
+            ix = ((q - NCORE) & 1) * (PW - 1);
+        }
+        ppos[k] = iy * PW + ix;
         poff[k] = gmap(x0 - 1 + ix, g.nx, perx) + gmap(y0 - 1 + iy, g.ny, pery) * sy;
     }
 
@@ -80,8 +94,8 @@ __device__ __forceinline__ void step3d_block(const R* __restrict__ in, R* __rest
         const int sl = (m + NS) & (NS - 1);
 #pragma unroll
         for (int k = 0; k < NPOS; ++k) {
-            const int p = tid + k * NT;
-            if (p < PP) {
+            const int p = ppos[k];
+            if (tid + k * NT < PP) {
                 R ph[NP], hh[NP], Mt[NMM];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) sv[sl][f][p] = reg[k][f];
