@@ -20,8 +20,10 @@ Further legs, each a block of the same JSON line:
                steps, replayed as HIP graphs, FP32
   adjoint      512^2 three-phase ternary run, FP32: checkpointed forward run
                (every 100 steps) and the adjoint sweep; their cost ratio
-  antitrapping the 4096^2 eutectic and the 512^3 dendrite with the
-               anti-trapping current (step + correction kernel per step)
+  antitrapping the 4096^2 eutectic with the anti-trapping current formed
+               inside the step kernel (and, beside it, the step followed by
+               the separate correction kernel), and the 512^3 dendrite with
+               the 3D correction kernel after each step
   extended     the 4096^2 eutectic with temperature-dependent coefficients
                (the general kernels), FP64 and FP32
 cpu_baseline   the FP64 oracle on the full 4096^2 grid, on the host's cores: two
@@ -57,24 +59,20 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "a9b2f6cb87949665",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "0423d2dfcc88a0c9",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "0ea3e9c72697aab3",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "574e93117ae98038",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4dd4573c704e1d7e",
+                  "bytes": (2.0 * 385370.7 + 658378.8) * 1024},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d",
+                  "bytes": (2.0 * 225018.1 + 331609.6) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "8f12064e5c47603d",
-           "bytes": (2.0 * 1150852.3 + 1572864.0) * 1024},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444",
+           "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
-    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "e225c3bd64067218",
-               "bytes": (2.0 * 867775.7 + 269022.1) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "e225c3bd64067218",
-               "bytes": (2.0 * 459730.5 + 137750.1) * 1024},
-    # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [64, 4, 1], "fuse": 1, "src": "e225c3bd64067218",
-                 "bytes": (2.0 * 2646601.9 + 524288.0) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
 ALL_LEGS = ("c2", "c3", "c4", "c5", "at", "ext")
@@ -115,18 +113,20 @@ def log(msg):
 # The device sources each leg's step kernel is built from.
 _COMMON = ["mp_internal.hpp", "gp_device.hpp"]
 LEG_SOURCES = {
-    "c2_f64": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
-    "c2_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
-    "c2ext_f64": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_gen_f64_2d.hip"],
-    "c2ext_f32": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_gen_f32_2d.hip"],
-    "c3": _COMMON + ["step2d.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
+    "c2_f64": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
+    "c2_f32": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
+    "c2ext_f64": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_gen_f64_2d.hip"],
+    "c2ext_f32": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_gen_f32_2d.hip"],
+    "c3": _COMMON + ["step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
     "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
-    "at_f64": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
-    "at_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
-    "at3d_f32": ["mp_internal.hpp", "antitrap2d.hpp", "antitrap.hip"],
+    "at_f64": _COMMON + ["antitrap2d.hpp", "antitrap.hip"],
+    "at_f32": _COMMON + ["antitrap2d.hpp", "antitrap.hip"],
+    "at3d_f32": _COMMON + ["antitrap2d.hpp", "antitrap3d.hpp", "antitrap.hip"],
+    "atf_f64": _COMMON + ["step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
+    "atf_f32": _COMMON + ["step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
 }
-# The 3D correction kernel's fixed block shape (x cells, y rows, cells per lane).
-AT3D_TILE = [64, 4, 1]
+# The 3D correction kernel's FP32 strip shape (columns written per wave, rows per wave, cells per lane).
+AT3D_TILE = [62, 2, 1]
 # The correction kernel's fixed strip shape (columns written per wave, rows per wave, cells per lane).
 AT_TILE = [62, 12, 1]
 
@@ -209,9 +209,12 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
 VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "a9b2f6cb87949665", "insts": 153857451.0},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "0423d2dfcc88a0c9", "insts": 153857451.0},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "574e93117ae98038", "insts": 138111444.0},
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4dd4573c704e1d7e", "insts": 236893983.0},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d", "insts": 173801142.0},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "8f12064e5c47603d", "insts": 543752776.3},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444", "insts": 545827325.3},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
 }
@@ -430,10 +433,12 @@ def leg_at3d(n, steps, warmup):
 
 
 def leg_at(precision, n, steps, warmup):
-    """The C2 step with the anti-trapping current: one step per launch followed by the
-    correction kernel.  The same run without the current (one step per launch) is
-    timed first; the difference of the two median regions is the correction
-    kernel's time per step."""
+    """The C2 step with the anti-trapping current, one step per launch: the current
+    formed inside the step kernel (the leg's rate), and the step followed by the
+    separate correction kernel.  The same run without the current (one step per
+    launch) is timed first; the difference of the separate path's and the plain
+    step's median regions is the correction kernel's time per step."""
+    from paper_2404_01035_amd import abi
     from paper_2404_01035_amd.solver import Solver
     from paper_2404_01035_amd import inputs
 
@@ -443,27 +448,40 @@ def leg_at(precision, n, steps, warmup):
     del phi, mu
     s.set_fusion(1)
     ms0, _, _ = measure(s.step, steps, warmup)
-    s.set_antitrapping(True)
+    s.set_antitrapping(2)
+    ms2, regions2, _ = measure(s.step, steps, warmup)
+    s.set_antitrapping(1)
     ms1, regions, _ = measure(s.step, steps, warmup)
+    bx, seg, _ = abi.mp_get_tile(s.st)
     d = s.diagnostics()
     s.close()
     elem = 8 if precision == "f64" else 4
     nm = p.ncomp - 1
-    # phi^n, phi^{n+1}, mu^n and mu^{n+1} read, mu^{n+1} written, once per cell
-    bpc = (2 * p.nphases + 3 * nm) * elem
-    ms_plain, ms_at = ms0 / steps, ms1 / steps
-    ms_corr = ms_at - ms_plain
+    # folded: the state read and written once per cell
+    bpc = 2 * (p.nphases + nm) * elem
+    # correction kernel: phi^n, phi^{n+1}, mu^n and mu^{n+1} read, mu^{n+1} written, once per cell
+    bpc_corr = (2 * p.nphases + 3 * nm) * elem
+    ms_plain, ms_at, ms_sep = ms0 / steps, ms1 / steps, ms2 / steps
+    ms_corr = ms_sep - ms_plain
+    tile = [bx, seg, 1]
     return {
         "value": p.ncells * steps / (ms1 * 1e-3),
         "unit": "cell-updates/s",
         "ms_per_step": ms_at,
         "region_ms": [round(x, 4) for x in regions],
+        "bytes_per_cell_update": bpc,
+        "tile": {"bx": bx, "seg": seg, "vec": 1},
+        "roofline": roofline(p.ncells * bpc, ms_at, traffic_of(f"atf_{precision}", tile, 1)),
         "ms_per_step_without_current": ms_plain,
-        "correction_ms_per_step": ms_corr,
-        "correction_bytes_per_cell": bpc,
-        # the correction kernel: time = step with the current - step without
-        "roofline": roofline(p.ncells * bpc, ms_corr, traffic_of(f"at_{precision}", AT_TILE, 1))
-        if ms_corr > 0 else None,
+        "separate_correction": {
+            "ms_per_step": ms_sep,
+            "region_ms": [round(x, 4) for x in regions2],
+            "correction_ms_per_step": ms_corr,
+            "correction_bytes_per_cell": bpc_corr,
+            # the correction kernel: time = step then correction - step without the current
+            "roofline": roofline(p.ncells * bpc_corr, ms_corr, traffic_of(f"at_{precision}", AT_TILE, 1))
+            if ms_corr > 0 else None,
+        },
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
 
@@ -779,7 +797,8 @@ def main():
         at_steps = min(a.steps, 200)
         log(f"anti-trapping current {a.n}x{a.n}, FP64 and FP32, {at_steps} steps")
         out["antitrapping"] = {"workload": f"2D {a.n}x{a.n} directional eutectic with the anti-trapping "
-                                           "current, one step per launch + correction",
+                                           "current, one step per launch (current formed inside the step; "
+                                           "the step + separate correction kernel beside it)",
                                "f64": leg_at("f64", a.n, at_steps, 5),
                                "f32": leg_at("f32", a.n, at_steps, 5),
                                "dendrite_3d_f32": dict(leg_at3d(a.n3d, min(a.steps3d, 50), 3),

@@ -21,6 +21,10 @@
  *   - Device memory is owned by the caller.  The library only borrows the
  *     pointers given to mp_bind and never allocates or frees device memory
  *     itself (mp_destroy frees host-side state only).
+ *   - Environment: MP_LOG (anything but "0") echoes every failure message to
+ *     stderr; MP_TILE="bx,seg,vec" sets the tile shape of every state made by
+ *     mp_create, as mp_set_tile would (an invalid value makes mp_create fail
+ *     with MP_E_PARAM).
  *   - ``stream`` is a hipStream_t passed as void* (NULL = the null stream).
  *     mp_step is asynchronous; faults inside a kernel surface at the next
  *     synchronising call (mp_diagnostics, or the caller's own sync).
@@ -243,7 +247,7 @@ int mp_set_fusion(mp_state* st, int steps);
 int mp_get_fusion(const mp_state* st, int* steps);
 
 /* Anti-trapping current of Eq. jatr (Sec. 2.1) in the mu update of Eq.
- * Mu_explicit_temperature: on = 1 switches it on, 0 off (the default).  With
+ * Mu_explicit_temperature: on = 1 or 2 switches it on, 0 off (the default).  With
  * it, mu^{n+1} = mu^n + (dt div(M grad mu - j_at) - sum_a c^a dh_a) / chi, where
  * j_at = sum over the solid phases a (the liquid is the last phase) of
  * P (c^a - c^liq) dphi_a/dt n_a (-n_a . n_liq), n = grad phi / |grad phi| of
@@ -253,10 +257,13 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * one the mean of their central differences; dphi/dt = (phi^{n+1} - phi^n)/dt,
  * c^a(mu^n) and the prefactor's phi are means of the two cells; a unit normal
  * with |grad phi|^2 <= 1e-30 is zero.  mp_step then runs one step per launch
- * (each step is followed by a correction kernel that reads states n and n+1),
- * ignores mp_set_fusion and mp_set_graph, and mp_adjoint returns MP_E_STATE.
+ * and ignores mp_set_fusion.  On a 2D grid with on = 1 the current is formed
+ * inside the step kernel (the state is read once per step) and mp_set_graph
+ * is honoured; with on = 2, and on a 3D grid, each step is followed by a
+ * correction kernel that reads states n and n+1 and mp_set_graph is ignored.
+ * Both give the same bits.  mp_adjoint returns MP_E_STATE while it is on.
  * 2D and 3D single grids.  Host only.  Errors: MP_E_NULLPTR, MP_E_PARAM (on
- * not 0 or 1), MP_E_STATE (a batched state). */
+ * not 0, 1 or 2), MP_E_STATE (a batched state, the extended model). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 

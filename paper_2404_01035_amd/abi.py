@@ -329,14 +329,15 @@ def mp_get_fusion(st) -> int:
     return v.value
 
 
-def mp_set_antitrapping(st, on: bool):
-    _check(lib().mp_set_antitrapping(st, 1 if on else 0))
+def mp_set_antitrapping(st, on):
+    """on: False/0 off, True/1 on (folded into the 2D step), 2 on with the separate correction kernel."""
+    _check(lib().mp_set_antitrapping(st, int(on)))
 
 
-def mp_get_antitrapping(st) -> bool:
+def mp_get_antitrapping(st) -> int:
     v = C.c_int()
     _check(lib().mp_get_antitrapping(st, C.byref(v)))
-    return bool(v.value)
+    return v.value
 
 
 def mp_set_graph(st, chunk: int):

@@ -19,7 +19,7 @@
 // (plus the halo) and each face is evaluated once.
 #pragma once
 
-#include "mp_internal.hpp"
+#include "gp_device.hpp"
 
 namespace mp {
 
@@ -27,6 +27,16 @@ __device__ inline int at_wrap(int i, int n, int bc) {
     if (i < 0) return bc == MP_BC_PERIODIC ? n - 1 : 0;
     if (i >= n) return bc == MP_BC_PERIODIC ? 0 : n - 1;
     return i;
+}
+
+// 1 / |grad phi| on a face, zero where |grad phi|^2 <= 1e-30 (the unit normal
+// is then zero): the hardware reciprocal square root refined as in the step's
+// anisotropy (the guard keeps its argument normal).
+template <typename R>
+__device__ __forceinline__ R at_inv_norm(R n2) {
+    const bool on = n2 > R(1e-30);
+    const R r = rsqrt_ok(on ? n2 : R(1));
+    return on ? r : R(0);
 }
 
 template <typename R>
@@ -50,7 +60,7 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
         const R gn = (pR[a] - pL[a]) * c.rdx;
         const R gt = R(0.5) * (tL[a] + tR[a]);
         const R n2 = gn * gn + gt * gt;
-        const R inv = n2 > R(1e-30) ? R(1) / sqrt(n2) : R(0);
+        const R inv = at_inv_norm(n2);
         un[a] = gn * inv;
         ut[a] = gt * inv;
     }
@@ -110,7 +120,7 @@ __device__ inline void at_fetch(const R* __restrict__ prev, const R* __restrict_
 template <typename R, int NP, int NM>
 __device__ inline void at_finish(AtRow<R, NP, NM>& r, R h2) {
 #pragma unroll
-    for (int a = 0; a < NP; ++a) r.tx[a] = (__shfl_down(r.p[a], 1) - __shfl_up(r.p[a], 1)) * h2;
+    for (int a = 0; a < NP; ++a) r.tx[a] = (lane_next(r.p[a]) - lane_prev(r.p[a])) * h2;
 }
 
 // A wave owns columns x0 .. x0 + 61 (lanes 1..62; lane 0 and 63 are the x
@@ -153,12 +163,12 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
             ty[a] = (hi.p[a] - lo.p[a]) * h2;
-            tyl[a] = __shfl_up(ty[a], 1);
-            pl[a] = __shfl_up(mid.p[a], 1);
-            ql[a] = __shfl_up(mid.q[a], 1);
+            tyl[a] = lane_prev(ty[a]);
+            pl[a] = lane_prev(mid.p[a]);
+            ql[a] = lane_prev(mid.q[a]);
         }
 #pragma unroll
-        for (int k = 0; k < NM; ++k) ul[k] = __shfl_up(mid.u[k], 1);
+        for (int k = 0; k < NM; ++k) ul[k] = lane_prev(mid.u[k]);
         R jxl[NM] = {};
         at_face<R, NP, NM>(pl, mid.p, tyl, ty, ql, mid.q, ul, mid.u, c, jxl);
         R jyhi[NM] = {};
@@ -175,13 +185,13 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
         const int64_t oc = (int64_t)y * g.nx + col;
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
-            const R jxh = __shfl_down(jxl[k], 1);
+            const R jxh = lane_next(jxl[k]);
             if (own) {
                 R chik = R(0);
 #pragma unroll
                 for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
                 const R div = (jxh - jxl[k]) * c.rdx + (jyhi[k] - jylo[k]) * c.rdx;
-                next[(NP + k) * g.fstride + oc] = mid.m[k] - c.dt * div / chik;
+                next[(NP + k) * g.fstride + oc] = mid.m[k] - (c.dt * div) * fast_rcp(chik);
             }
             jylo[k] = jyhi[k];
         }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void at_face3(const R (&pL)[NP], const R (&pR)[NP], c
         n2 += gx * gx;
         n2 += gy * gy;
         n2 += gz * gz;
-        const R inv = n2 > R(1e-30) ? R(1) / sqrt(n2) : R(0);
+        const R inv = at_inv_norm(n2);
         u[0][a] = gx * inv;
         u[1][a] = gy * inv;
         u[2][a] = gz * inv;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void at3_dx(const R (&p)[NROW][NP], R h2, R (&t)[NROW
 #pragma unroll
     for (int r = 0; r < NROW; ++r)
 #pragma unroll
-        for (int a = 0; a < NP; ++a) t[r][a] = (__shfl_down(p[r][a], 1) - __shfl_up(p[r][a], 1)) * h2;
+        for (int a = 0; a < NP; ++a) t[r][a] = (lane_next(p[r][a]) - lane_prev(p[r][a])) * h2;
 }
 
 template <typename R, int NP, int NM, int BY>
@@ -201,13 +201,13 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
             R pl[NP], ql[NP], ul[NM], tyl[NP], tzl[NP];
 #pragma unroll
             for (int a = 0; a < NP; ++a) {
-                pl[a] = __shfl_up(B.p[r][a], 1);
-                ql[a] = __shfl_up(B.q[r][a], 1);
-                tyl[a] = __shfl_up(tym[a], 1);
-                tzl[a] = __shfl_up(tz[r][a], 1);
+                pl[a] = lane_prev(B.p[r][a]);
+                ql[a] = lane_prev(B.q[r][a]);
+                tyl[a] = lane_prev(tym[a]);
+                tzl[a] = lane_prev(tz[r][a]);
             }
 #pragma unroll
-            for (int k = 0; k < NM; ++k) ul[k] = __shfl_up(B.u[r][k], 1);
+            for (int k = 0; k < NM; ++k) ul[k] = lane_prev(B.u[r][k]);
             R jxl[NM], jzh[NM];
 #pragma unroll
             for (int k = 0; k < NM; ++k) jxl[k] = jzh[k] = R(0);
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
             const int yy = y0 + r - 1;
 #pragma unroll
             for (int k = 0; k < NM; ++k) {
-                const R jxh = __shfl_down(jxl[k], 1);
+                const R jxh = lane_next(jxl[k]);
                 if (ownx && yy < g.ny) {
                     R chik = R(0);
 #pragma unroll
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
                     div += (jxh - jxl[k]) * c.rdx;
                     div += (jy[r][k] - jy[r - 1][k]) * c.rdx;
                     div += (jzh[k] - jzlo[r - 1][k]) * c.rdx;
-                    next[(NP + k) * fs + (zo + yy) * g.nx + col] = mn[r - 1][k] - c.dt * div / chik;
+                    next[(NP + k) * fs + (zo + yy) * g.nx + col] = mn[r - 1][k] - (c.dt * div) * fast_rcp(chik);
                 }
                 jzlo[r - 1][k] = jzh[k];
             }

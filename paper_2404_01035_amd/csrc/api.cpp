@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -20,6 +21,12 @@
 #include "adjoint2d.hpp"
 #include "diag_static.hpp"
 #include "mp_internal.hpp"
+
+namespace mp {
+// step_at.hip: the 2D step with the anti-trapping current folded in
+template <typename R>
+int call_step_at(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k);
+}  // namespace mp
 
 namespace {
 
@@ -51,7 +58,7 @@ struct mp_state {
     int64_t step;
     int bx, seg, vec;  // vec: cap on cells per lane of the 2D strips (-1: none)
     int fuse;  // steps per launch of the step kernel: 1, or 2 (2D single grid)
-    bool antitrap;  // anti-trapping current on (2D and 3D single grids; one step per launch, no graphs)
+    int antitrap;  // anti-trapping current: 0 off, 1 on (folded into the 2D step), 2 on (separate correction)
     int graph_chunk;
     hipGraphExec_t gexec[2];  // by starting buffer
     int gend[2];              // buffer current after a replay, by starting buffer
@@ -70,6 +77,15 @@ namespace {
 
 thread_local std::string g_err;
 
+// MP_LOG set to anything but "0" or "": every failure message also goes to stderr.
+bool log_enabled() {
+    static const bool on = [] {
+        const char* v = std::getenv("MP_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
 int fail(int code, const char* fmt, ...) {
     char msg[512];
     va_list ap;
@@ -77,6 +93,7 @@ int fail(int code, const char* fmt, ...) {
     vsnprintf(msg, sizeof msg, fmt, ap);
     va_end(ap);
     g_err = msg;
+    if (log_enabled()) fprintf(stderr, "[mpstep] error %d: %s\n", code, msg);
     return code;
 }
 
@@ -590,6 +607,13 @@ int sync_batch(mp_state* st) {
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
                      mp::KernelCall& k, int fuse = 1, void* out1 = nullptr);
 
+// The anti-trapping current folded into the step kernel (2D single grids):
+// mp_step then runs the ordinary launch path, one step per launch.
+bool at_folded(const mp_state* st) { return st->antitrap == 1 && !st->batch && st->inst[0].grid.dim == 2; }
+
+// Steps per launch of the ordinary path.
+int launch_fuse(const mp_state* st) { return st->antitrap ? 1 : st->fuse; }
+
 // One launch of `fuse` steps (1 or 2; a batch always 1); kstep is the
 // launch's offset from the device time level.
 int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fuse = 1) {
@@ -634,6 +658,10 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.stepctr = ctr;
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
+    if (at_folded(st) && !out1) {
+        if (st->precision == MP_FP64) return mp::call_step_at<double>(L, make_coef<double>(I), make_at_coef<double>(I), k);
+        return mp::call_step_at<float>(L, make_coef<float>(I), make_at_coef<float>(I), k);
+    }
     if (I.ext) {
         if (st->precision == MP_FP64)
             return I.grid.dim == 3 ? mp::call_step_gen<double, true>(L, make_coef<double>(I), make_coefx<double>(I), k)
@@ -653,7 +681,7 @@ int launch(const mp::KernelCall& k, hipStream_t s) {
 // steps each), then the time-level advance.  Sets gend[from].
 int build_graph(mp_state* st, int from, hipGraphExec_t* out) {
     std::vector<mp::KernelCall>& calls = st->gcalls[from];
-    const int F = st->fuse;
+    const int F = launch_fuse(st);
     const int nl = st->graph_chunk / F;  // graph_chunk is even, F is 1 or 2
     calls.assign((size_t)nl + 1, mp::KernelCall());
     for (int i = 0; i <= nl; ++i) {
@@ -705,7 +733,7 @@ void init_state(mp_state* st) {
     st->step = 0;
     st->graph_chunk = 0;
     st->fuse = 1;
-    st->antitrap = false;
+    st->antitrap = 0;
     st->gexec[0] = st->gexec[1] = nullptr;
     st->gend[0] = 0;
     st->gend[1] = 1;
@@ -979,6 +1007,16 @@ int mp_create(const mp_grid* grid, int nphases, int ncomp, const mp_params* para
     st->batch = false;
     st->inst.push_back(make_inst(grid, nphases, ncomp, params));
     init_state(st);
+    // MP_TILE="bx,seg,vec": the tile shape of new single-grid states, as by mp_set_tile
+    if (const char* t = std::getenv("MP_TILE")) {
+        int bx = 0, seg = 0, vec = 0;
+        if (std::sscanf(t, "%d,%d,%d", &bx, &seg, &vec) != 3 || mp_set_tile(st, bx, seg, vec) != MP_OK) {
+            const std::string why = g_err;
+            delete st;
+            return fail(MP_E_PARAM, "MP_TILE=\"%s\" is not a valid bx,seg,vec for this state%s%s", t,
+                        why.empty() ? "" : ": ", why.c_str());
+        }
+    }
     *out = st;
     return ok();
 }
@@ -1061,7 +1099,7 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
     if (!st->bound) return fail(MP_E_UNBOUND, "mp_step before mp_bind");
     if (nsteps < 0) return fail(MP_E_PARAM, "nsteps must be >= 0");
     hipStream_t s = (hipStream_t)stream;
-    if (st->antitrap) return step_antitrapping(st, nsteps, s);
+    if (st->antitrap && !at_folded(st)) return step_antitrapping(st, nsteps, s);
     int64_t left = nsteps;
     const int C = st->graph_chunk;
     if (C > 0) {
@@ -1079,7 +1117,7 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
     }
     // launches of st->fuse steps, then single steps for the remainder
     for (int64_t i = 0; i < left;) {
-        const int F = left - i >= st->fuse ? st->fuse : 1;
+        const int F = left - i >= launch_fuse(st) ? launch_fuse(st) : 1;
         mp::KernelCall k;
         int rc = make_step_call(st, (int)i, st->cur, k, F);
         if (rc) return fail(rc, "no kernel instance for this configuration");
@@ -1251,7 +1289,7 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
         if (mp_set_fusion(st, c[3]) != MP_OK) continue;
         if (mp_set_tile(st, c[0], c[1], c[2]) != MP_OK) continue;
         mp::KernelCall k;
-        if (make_step_call(st, 0, st->cur, k, st->fuse) != MP_OK) continue;
+        if (make_step_call(st, 0, st->cur, k, launch_fuse(st)) != MP_OK) continue;
         rc = launch(k, s);
         if (rc == MP_OK) rc = hip_check(hipEventRecord(e[0], s), "hipEventRecord");
         for (int r = 0; r < reps && rc == MP_OK; ++r) rc = launch(k, s);
@@ -1260,7 +1298,7 @@ int mp_tune(mp_state* st, const int32_t* cand, int ncand, int reps, double* ms, 
         float t = 0.0f;
         if (rc == MP_OK) rc = hip_check(hipEventElapsedTime(&t, e[0], e[1]), "hipEventElapsedTime");
         if (rc != MP_OK) break;
-        ms[i] = (double)t / reps / st->fuse;
+        ms[i] = (double)t / reps / launch_fuse(st);
         if (bi < 0 || ms[i] < ms[bi]) bi = i;
     }
     for (hipEvent_t x : e)
@@ -1298,18 +1336,18 @@ int mp_get_fusion(const mp_state* st, int* steps) {
 
 int mp_set_antitrapping(mp_state* st, int on) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
-    if (on != 0 && on != 1) return fail(MP_E_PARAM, "on must be 0 or 1 (got %d)", on);
+    if (on < 0 || on > 2) return fail(MP_E_PARAM, "on must be 0, 1 or 2 (got %d)", on);
     if (on && st->batch) return fail(MP_E_STATE, "anti-trapping current: batched states are not supported");
     if (on && st->inst[0].ext)
         return fail(MP_E_STATE, "anti-trapping current: the extended model is not supported");
     drop_graphs(st);
-    st->antitrap = on == 1;
+    st->antitrap = on;
     return ok();
 }
 
 int mp_get_antitrapping(const mp_state* st, int* on) {
     if (!st || !on) return fail(MP_E_NULLPTR, "state or on is NULL");
-    *on = st->antitrap ? 1 : 0;
+    *on = st->antitrap;
     return ok();
 }
 

@@ -94,8 +94,10 @@ class Solver:
         """Steps per kernel launch (1, or 2 for 2D grids: the state crosses HBM once per two steps)."""
         abi.mp_set_fusion(self.st, steps)
 
-    def set_antitrapping(self, on: bool = True):
-        """Anti-trapping current of Eq. jatr in the mu update (2D and 3D; one step per launch, no graphs)."""
+    def set_antitrapping(self, on=True):
+        """Anti-trapping current of Eq. jatr in the mu update (2D and 3D, one step per launch): True/1
+        forms it inside the 2D step kernel, 2 in a separate correction kernel after each step (the
+        only form in 3D); both give the same bits."""
         abi.mp_set_antitrapping(self.st, on)
 
     def autotune(self, reps: int = 10, cache: str | None = None, force: bool = False) -> dict:

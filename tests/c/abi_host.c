@@ -50,11 +50,12 @@ int main(void) {
     if (mp_current(st, &which, &step) != MP_OK || which != 0 || step != 0) return 4;
     /* stepping before mp_bind is refused, with a message */
     if (mp_step(st, 1, NULL) != MP_E_UNBOUND || strlen(mp_last_error()) == 0) return 5;
-    /* the anti-trapping switch: off by default, on and off again, 2 refused */
+    /* the anti-trapping switch: off by default, on (both forms) and off again, 3 refused */
     int on = -1;
     if (mp_get_antitrapping(st, &on) != MP_OK || on != 0) return 9;
+    if (mp_set_antitrapping(st, 2) != MP_OK || mp_get_antitrapping(st, &on) != MP_OK || on != 2) return 10;
     if (mp_set_antitrapping(st, 1) != MP_OK || mp_get_antitrapping(st, &on) != MP_OK || on != 1) return 10;
-    if (mp_set_antitrapping(st, 2) != MP_E_PARAM) return 11;
+    if (mp_set_antitrapping(st, 3) != MP_E_PARAM) return 11;
     if (mp_set_antitrapping(st, 0) != MP_OK || mp_get_antitrapping(st, &on) != MP_OK || on != 0) return 12;
     mp_destroy(st);
 

@@ -335,18 +335,20 @@ def test_antitrapping_switch_validation_without_gpu():
     p, _, _ = inputs.config_c1()
     st = abi.mp_create(p)
     try:
-        assert abi.mp_get_antitrapping(st) is False  # off by default
-        abi.mp_set_antitrapping(st, True)
-        assert abi.mp_get_antitrapping(st) is True
-        for bad in (-1, 2):
+        assert abi.mp_get_antitrapping(st) == 0  # off by default
+        abi.mp_set_antitrapping(st, 2)  # the separate correction kernel
+        assert abi.mp_get_antitrapping(st) == 2
+        abi.mp_set_antitrapping(st, True)  # folded into the step
+        assert abi.mp_get_antitrapping(st) == 1
+        for bad in (-1, 3):
             assert L.mp_set_antitrapping(st, bad) == abi.MP_E_PARAM
-        assert abi.mp_get_antitrapping(st) is True
+        assert abi.mp_get_antitrapping(st) == 1
         # the adjoint refuses it before looking at its buffers
         g = (C.c_double * 10)()
         rc = L.mp_adjoint(st, None, 10, 5, 0, None, None, g, None, None)
         assert rc == abi.MP_E_STATE and "anti-trapping" in abi.mp_last_error()
         abi.mp_set_antitrapping(st, False)
-        assert abi.mp_get_antitrapping(st) is False
+        assert abi.mp_get_antitrapping(st) == 0
     finally:
         abi.mp_destroy(st)
     assert L.mp_set_antitrapping(None, 1) == abi.MP_E_NULLPTR
@@ -354,7 +356,7 @@ def test_antitrapping_switch_validation_without_gpu():
     st = abi.mp_create(inputs.dendrite_params(n=(8, 8, 8)))
     try:
         abi.mp_set_antitrapping(st, True)  # 3D grids take it too
-        assert abi.mp_get_antitrapping(st) is True
+        assert abi.mp_get_antitrapping(st) == 1
     finally:
         abi.mp_destroy(st)
     bst = abi.mp_create_batch([m[0] for m in inputs.config_c4(ninst=2, side=(64, 70))])
@@ -364,3 +366,35 @@ def test_antitrapping_switch_validation_without_gpu():
         assert ei.value.code == abi.MP_E_STATE
     finally:
         abi.mp_destroy(bst)
+
+
+def _in_subprocess(code, env):
+    import subprocess
+    import sys
+
+    e = dict(os.environ)
+    e.update(env)
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=e, cwd=ROOT,
+                          timeout=120)
+
+
+def test_mp_tile_environment_sets_the_tile_of_new_states():
+    code = ("from paper_2404_01035_amd import abi, inputs\n"
+            "p = inputs.config_c2(n=(64, 64, 1))[0]\n"
+            "st = abi.mp_create(p); print(abi.mp_get_tile(st)); abi.mp_destroy(st)\n")
+    r = _in_subprocess(code, {"MP_TILE": "128,16,2"})
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "(128, 16, 2)"
+    bad = _in_subprocess(code, {"MP_TILE": "100,16,1"})
+    assert bad.returncode != 0 and "MP_TILE" in bad.stderr
+
+
+def test_mp_log_echoes_failures_to_stderr():
+    code = ("from paper_2404_01035_amd import abi, inputs\n"
+            "p = inputs.config_c1()[0]\n"
+            "try:\n    abi.mp_create(p.copy(nphases=4))\nexcept abi.MPError:\n    pass\n")
+    r = _in_subprocess(code, {"MP_LOG": "1"})
+    assert r.returncode == 0, r.stderr
+    assert "[mpstep] error -1: nphases must be 2 or 3" in r.stderr
+    quiet = _in_subprocess(code, {"MP_LOG": "0"})
+    assert "[mpstep]" not in quiet.stderr

@@ -1,12 +1,15 @@
 """GPU parity of the step with the anti-trapping current (Eq. jatr) against the
 oracle's ``step_antitrapping``, on the same seeded inputs, through the C ABI.
 
-Sizes span several 62-column x 12-row correction strips with ragged tails, one
-strip exactly, one row and a grid smaller than a strip; the cases mix
-both potentials, N = 2 and 3, K = 2 and 3, periodic and zero-flux axes and a
-temperature gradient.  FP64 is held to 1e-10 (the bar of the plain step),
-FP32 to 1e-4.  The switch's interplay with the launch options (two steps per
-launch, graphs) and the adjoint's refusal are checked too.
+Sizes span several strips of the 2D kernels (60 columns for the step with the
+current folded in, 62 x 12 for the separate correction kernel) with ragged
+tails, one strip exactly, one row and a grid smaller than a strip; the cases
+mix both potentials, N = 2 and 3, K = 2 and 3, periodic and zero-flux axes and
+a temperature gradient.  FP64 is held to 1e-10 (the bar of the plain step),
+FP32 to 1e-4.  In 2D the folded kernel (on = 1) and the step followed by the
+correction kernel (on = 2) give the same bits.  The switch's interplay with the
+launch options (two steps per launch, graphs) and the adjoint's refusal are
+checked too.
 """
 import zlib
 
@@ -57,7 +60,7 @@ CASES = {
     "n3k2_one_strip_periodic": (dict(dim=2, N=3, K=2, n=(62, 33, 1), bc=(0, 0, 0)), 60),
     "n2k2_one_row_63": (dict(dim=2, N=2, K=2, n=(63, 1, 1), bc=(1, 0, 0)), 60),
     "n2k3_tiny_3x2_noflux": (dict(dim=2, N=2, K=3, n=(3, 2, 1), bc=(1, 1, 0)), 60),
-    # 3D (the one-thread-per-cell correction kernel)
+    # 3D (the correction kernel after each step)
     "3d_n2k2_noflux": (dict(dim=3, N=2, K=2, n=(37, 9, 21), bc=(1, 1, 1)), 40),
     "3d_n3k3_mixed_bc_gradient": (dict(dim=3, N=3, K=3, n=(20, 13, 17), bc=(0, 1, 0), G=1e-3), 40),
     "3d_n2k3_periodic_obstacle_aniso": (dict(dim=3, N=2, K=3, n=(17, 11, 9), bc=(0, 0, 0), potential="obstacle",
@@ -83,6 +86,37 @@ def test_fp64_with_antitrapping_matches_oracle(name):
     assert errs(f, of) <= 1e-10
     assert errs(m, om) <= 1e-10
     assert errs(om, pm) > 1e-6  # the case exercises the current
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_folded_current_is_bitwise_the_separate_correction(precision):
+    """Every 2D case: the step with the current formed inside it against the
+    step followed by the correction kernel, and the folded path again with a
+    segment of 5 rows per wave (segment borders inside the grid) and as graphs."""
+    from paper_2404_01035_amd import abi
+    from paper_2404_01035_amd.solver import Solver
+
+    for name in sorted(CASES):
+        if CASES[name][0]["dim"] != 2:
+            continue
+        p, phi, mu, _ = _case(name, precision)
+        steps = 23
+        print(f"case {name} {precision}: folded vs separate, {steps} steps", flush=True)
+        sep = run_gpu_at(p, phi, mu, steps, step0=5, on=2)
+        f, m = run_gpu_at(p, phi, mu, steps, step0=5, on=1)
+        assert np.array_equal(f, sep[0]) and np.array_equal(m, sep[1]), name
+        s = Solver(p)
+        try:
+            s.set_antitrapping(1)
+            bx, _, vec = abi.mp_get_tile(s.st)
+            abi.mp_set_tile(s.st, bx, 5, vec)
+            s.set_graph(6)
+            s.load(phi, mu, 5)
+            s.step(steps)
+            f, m = s.fields()
+        finally:
+            s.close()
+        assert np.array_equal(f, sep[0]) and np.array_equal(m, sep[1]), (name, "seg 5, graphs")
 
 
 def test_c1_fp64_with_antitrapping_500_steps():
@@ -171,6 +205,7 @@ def test_c2_full_grid_sampled_step_with_current(precision, tol):
     # input as loaded, checked window by window against the oracle's windowed step
     # (windows on the correction strips' column and 12-row borders, the grid's
     # edges and across the slab's interface).
+    from paper_2404_01035_amd import abi
     from paper_2404_01035_amd.solver import Solver
     from test_gpu_fullsize import _as_loaded, _slab_windows, _windows_2d
 
@@ -178,6 +213,7 @@ def test_c2_full_grid_sampled_step_with_current(precision, tol):
     s = Solver(p)
     try:
         s.set_antitrapping(True)
+        seg = abi.mp_get_tile(s.st)[1]
         s.load(phi, mu)
         s.step(1)
         gphi, gmu = s.fields()
@@ -185,7 +221,8 @@ def test_c2_full_grid_sampled_step_with_current(precision, tol):
         s.close()
     phi0, mu0 = _as_loaded(phi, mu, precision)
     del phi, mu
-    w = _windows_2d(4096, 4096, np.random.default_rng(11), tile_x=62, seg=12) + _slab_windows(4096)
+    # the folded kernel's strips: 60 columns by the state's segment of rows
+    w = _windows_2d(4096, 4096, np.random.default_rng(11), tile_x=60, seg=seg) + _slab_windows(4096)
     worst = [0.0, 0.0, 0.0]
     for lo, hi in w:
         of, om = gp.step_antitrapping_window(phi0, mu0, 0, p, lo, hi)
