@@ -547,6 +547,10 @@ def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
     b.set_graph(graph_chunk)
     ms, regions, _ = measure(b.step, steps, warmup)
     diags = b.diagnostics()
+    # the same ensemble with the anti-trapping current folded into the batched
+    # step (one step per launch), from the state the run above left
+    b.set_antitrapping(True)
+    ms_at, regions_at, _ = measure(b.step, steps, warmup)
     b.close()
     ms_step = ms / steps
     return {
@@ -566,6 +570,9 @@ def leg_c4(steps, warmup, tile, tune, graph_chunk=50):
         "algorithmic_bytes_per_launch": fuse * bytes_step,
         "tile": {"seg": used[1], "vec": used[2]},
         "nonfinite_instances": sum(1 for d in diags if d["nonfinite"]),
+        "with_current": {"value": cells * steps / (ms_at * 1e-3), "unit": "cell-updates/s",
+                         "ms_per_step": ms_at / steps, "region_ms": [round(x, 4) for x in regions_at],
+                         "steps_per_launch": 1},
     }
 
 

@@ -166,7 +166,7 @@ size_t mp_workspace_bytes(const mp_state* st);
 /* Attach caller-owned device buffers: buf0 and buf1 each mp_state_bytes()
  * long, 256-byte aligned; workspace mp_workspace_bytes() long (reduction
  * partial sums, the device copy of the time level and, for a batch, the
- * instance table).  buf0 is the current buffer afterwards and the time level
+ * instance table, the work list and the anti-trapping coefficients).  buf0 is the current buffer afterwards and the time level
  * is reset to 0 (use mp_set_step to resume).  Needs the GPU: it writes the
  * workspace with a synchronous copy. */
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
@@ -257,13 +257,16 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * one the mean of their central differences; dphi/dt = (phi^{n+1} - phi^n)/dt,
  * c^a(mu^n) and the prefactor's phi are means of the two cells; a unit normal
  * with |grad phi|^2 <= 1e-30 is zero.  mp_step then runs one step per launch
- * and ignores mp_set_fusion.  On a 2D grid with on = 1 the current is formed
- * inside the step kernel (the state is read once per step) and mp_set_graph
- * is honoured; with on = 2, and on a 3D grid, each step is followed by a
- * correction kernel that reads states n and n+1 and mp_set_graph is ignored.
- * Both give the same bits.  mp_adjoint returns MP_E_STATE while it is on.
- * 2D and 3D single grids.  Host only.  Errors: MP_E_NULLPTR, MP_E_PARAM (on
- * not 0, 1 or 2), MP_E_STATE (a batched state, the extended model). */
+ * and ignores mp_set_fusion.  On a 2D grid or a batch with on = 1 the current
+ * is formed inside the step kernel (the state is read once per step) and
+ * mp_set_graph is honoured; with on = 2, and on a 3D grid, each step is
+ * followed by a correction kernel that reads states n and n+1 and
+ * mp_set_graph is ignored.  Both give the same bits, and a batched instance
+ * the bits of the same instance stepped alone.  mp_adjoint returns
+ * MP_E_STATE while it is on.  2D and 3D single grids and batches.  Host only
+ * for a single grid; for a bound batch switching it on or off re-deals the
+ * work list (a synchronous copy).  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0,
+ * 1 or 2), MP_E_STATE (the extended model; on = 2 for a batch). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 

@@ -23,9 +23,11 @@
 #include "mp_internal.hpp"
 
 namespace mp {
-// step_at.hip: the 2D step with the anti-trapping current folded in
+// step_at.hip: the 2D step with the anti-trapping current folded in; batch_at.hip: the same for a batch
 template <typename R>
 int call_step_at(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k);
+template <typename R>
+int call_batch_at(const BatchLaunch& L, const void* atab, KernelCall& k);
 }  // namespace mp
 
 namespace {
@@ -431,6 +433,7 @@ int strips_of(const mp_state* st, const Inst& I) {
 
 // ---- workspace layout -------------------------------------------------------
 // [diag partials + one result record per instance][time level][instance table][work list]
+// [anti-trapping coefficient table]
 size_t ws_diag_bytes(const mp_state* st) {
     return align_up((size_t)(mp::DIAG_BLOCKS_MAX + st->inst.size()) * mp::DIAG_VALS * sizeof(double));
 }
@@ -447,6 +450,12 @@ size_t items_capacity(const mp_state* st) {
     size_t n = 0;  // the work list is longest at seg = 1: one item per strip and row
     for (const Inst& I : st->inst) n += (size_t)strips_of(st, I) * (size_t)I.grid.n[1];
     return n;
+}
+
+size_t ws_attab_off(const mp_state* st) { return ws_items_off(st) + align_up(2 * sizeof(int) * items_capacity(st)); }
+size_t attab_bytes(const mp_state* st) {
+    const size_t one = st->precision == MP_FP64 ? sizeof(mp::AtCoef<double>) : sizeof(mp::AtCoef<float>);
+    return st->batch ? align_up(one * st->inst.size()) : 0;
 }
 
 int64_t* dev_ctr(mp_state* st) { return (int64_t*)((char*)st->ws + ws_ctr_off(st)); }
@@ -552,10 +561,16 @@ int upload_table(mp_state* st) {
         temperature_law(I, d.tb0, d.tdn, d.tslope);
         d.c = make_coef<R>(I);
     }
+    std::vector<mp::AtCoef<R>> atab(st->inst.size());
+    for (size_t i = 0; i < st->inst.size(); ++i) atab[i] = make_at_coef<R>(st->inst[i]);
     char* ws = (char*)st->ws;
     int rc = hip_check(hipMemcpy(ws + ws_table_off(st), tab.data(),
                                  sizeof(mp::InstDesc<R>) * tab.size(), hipMemcpyHostToDevice),
                        "instance table upload");
+    if (rc == MP_OK)
+        rc = hip_check(hipMemcpy(ws + ws_attab_off(st), atab.data(), sizeof(mp::AtCoef<R>) * atab.size(),
+                                 hipMemcpyHostToDevice),
+                       "anti-trapping table upload");
     return rc;
 }
 
@@ -563,6 +578,22 @@ int upload_items(mp_state* st) {
     return hip_check(hipMemcpy((char*)st->ws + ws_items_off(st), st->items.data(), sizeof(int) * st->items.size(),
                                hipMemcpyHostToDevice),
                      "work list upload");
+}
+
+// The anti-trapping current folded into the step kernel (2D single grids and
+// batches): mp_step then runs the ordinary launch path, one step per launch.
+bool at_folded(const mp_state* st) { return st->antitrap == 1 && (st->batch || st->inst[0].grid.dim == 2); }
+
+// Steps per launch of the ordinary path.
+int launch_fuse(const mp_state* st) { return st->antitrap ? 1 : st->fuse; }
+
+// The batched kernel for L: with the current folded in while it is on.
+int batch_call(mp_state* st, const mp::BatchLaunch& L, mp::KernelCall& k) {
+    if (st->antitrap) {
+        const void* atab = (const char*)st->ws + ws_attab_off(st);
+        return st->precision == MP_FP64 ? mp::call_batch_at<double>(L, atab, k) : mp::call_batch_at<float>(L, atab, k);
+    }
+    return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
 }
 
 int choose_batch_blocks(mp_state* st) {
@@ -576,10 +607,10 @@ int choose_batch_blocks(mp_state* st) {
     L.potential = st->potential;
     L.aniso = st->aniso ? 1 : 0;
     L.vmax = vec_cap(st);
-    L.fuse = st->fuse;
+    L.fuse = launch_fuse(st);
     L.nblocks = 8;
     mp::KernelCall k;
-    rc = st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
+    rc = batch_call(st, L, k);
     if (rc) return fail(rc, "no batched kernel instance");
     rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k.func, (int)k.block.x, 0),
                    "occupancy query");
@@ -607,12 +638,6 @@ int sync_batch(mp_state* st) {
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
                      mp::KernelCall& k, int fuse = 1, void* out1 = nullptr);
 
-// The anti-trapping current folded into the step kernel (2D single grids):
-// mp_step then runs the ordinary launch path, one step per launch.
-bool at_folded(const mp_state* st) { return st->antitrap == 1 && !st->batch && st->inst[0].grid.dim == 2; }
-
-// Steps per launch of the ordinary path.
-int launch_fuse(const mp_state* st) { return st->antitrap ? 1 : st->fuse; }
 
 // One launch of `fuse` steps (1 or 2; a batch always 1); kstep is the
 // launch's offset from the device time level.
@@ -631,7 +656,7 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fus
         L.nblocks = st->batch_blocks;
         L.stepctr = dev_ctr(st);
         L.kstep = kstep;
-        return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
+        return batch_call(st, L, k);
     }
     return make_single_call(st, st->buf[from], st->buf[1 - from], dev_ctr(st), kstep, k, fuse);
 }
@@ -1067,7 +1092,7 @@ size_t mp_state_bytes(const mp_state* st) {
 
 size_t mp_workspace_bytes(const mp_state* st) {
     if (!st) return 0;
-    return ws_items_off(st) + align_up(2 * sizeof(int) * items_capacity(st));
+    return ws_attab_off(st) + attab_bytes(st);
 }
 
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace) {
@@ -1337,11 +1362,21 @@ int mp_get_fusion(const mp_state* st, int* steps) {
 int mp_set_antitrapping(mp_state* st, int on) {
     if (!st) return fail(MP_E_NULLPTR, "state is NULL");
     if (on < 0 || on > 2) return fail(MP_E_PARAM, "on must be 0, 1 or 2 (got %d)", on);
-    if (on && st->batch) return fail(MP_E_STATE, "anti-trapping current: batched states are not supported");
+    if (on == 2 && st->batch)
+        return fail(MP_E_STATE, "anti-trapping current: batched states take it folded into the step (on = 1) only");
     if (on && st->inst[0].ext)
         return fail(MP_E_STATE, "anti-trapping current: the extended model is not supported");
     drop_graphs(st);
+    const int was = st->antitrap;
     st->antitrap = on;
+    if (st->batch && st->bound && (was != 0) != (on != 0)) {
+        // the kernel changes, and with it the resident block count and the work list's deal
+        const int rc = choose_batch_blocks(st);
+        if (rc) {
+            st->antitrap = was;
+            return rc;
+        }
+    }
     return ok();
 }
 

@@ -191,6 +191,10 @@ class BatchSolver:
     def set_tile(self, seg: int, vec: int = 0):
         abi.mp_set_tile(self.st, 0, seg, vec)
 
+    def set_antitrapping(self, on=True):
+        """Anti-trapping current of Eq. jatr, formed inside the batched step kernel."""
+        abi.mp_set_antitrapping(self.st, on)
+
     def set_graph(self, chunk: int):
         abi.mp_set_graph(self.st, chunk)
 

@@ -361,9 +361,12 @@ def test_antitrapping_switch_validation_without_gpu():
         abi.mp_destroy(st)
     bst = abi.mp_create_batch([m[0] for m in inputs.config_c4(ninst=2, side=(64, 70))])
     try:
+        # a batch takes the current folded into the step only
         with pytest.raises(abi.MPError) as ei:
-            abi.mp_set_antitrapping(bst, True)
+            abi.mp_set_antitrapping(bst, 2)
         assert ei.value.code == abi.MP_E_STATE
+        abi.mp_set_antitrapping(bst, True)
+        assert abi.mp_get_antitrapping(bst) == 1
     finally:
         abi.mp_destroy(bst)
 

@@ -234,3 +234,62 @@ def test_c2_full_grid_sampled_step_with_current(precision, tol):
     print(f"C2 {precision} with the current, one step: worst window error phi {worst[0]:.2e} mu {worst[1]:.2e}; "
           f"the current moves mu by up to {worst[2]:.2e} there")
     assert worst[2] > 1e-8  # the windows see the current
+
+
+def _batch_at(members, nsteps, step0=0, seg=None, vec=0, graph=0):
+    from paper_2404_01035_amd.solver import BatchSolver
+
+    b = BatchSolver([m[0] for m in members])
+    try:
+        if seg or vec:
+            b.set_tile(seg or 0, vec)
+        if graph:
+            b.set_graph(graph)
+        b.set_antitrapping(True)
+        for i, (_, phi, mu) in enumerate(members):
+            b.load(i, phi, mu)
+        b.start(step0)
+        b.step(nsteps)
+        return [b.fields(i) for i in range(len(members))]
+    finally:
+        b.close()
+
+
+def test_batch_with_current_matches_oracle_fp64():
+    """Four uneven instances (N, K, boundaries and a temperature gradient mixed) in one
+    batched launch per step with the current folded in, against the oracle."""
+    rng = np.random.default_rng(41)
+    members = []
+    for (nx, ny, N, K, bc) in [(70, 50, 2, 2, (1, 1, 0)), (130, 64, 3, 3, (0, 1, 0)), (64, 90, 3, 2, (1, 0, 0)),
+                               (66, 66, 2, 3, (0, 0, 0))]:
+        p, phi, mu = inputs.random_instance(rng, nx, ny, N, K, precision="f64", nuclei=4)
+        p.bc = bc
+        p.G, p.V, p.y0 = 2e-3, 0.05, ny / 3
+        members.append((p, phi, mu))
+    steps = 60
+    print(f"batch of {len(members)} with the current, {steps} steps", flush=True)
+    got = _batch_at(members, steps, step0=5)
+    for i, (p, phi, mu) in enumerate(members):
+        of, om = oracle_run_at(phi, mu, 5, steps, p)
+        _, pm = gp.run(phi, mu, 5, steps, p)
+        print(f"  instance {i}: phi {errs(got[i][0], of):.3e} mu {errs(got[i][1], om):.3e}; "
+              f"the current moves mu by {errs(om, pm):.3e}")
+        assert errs(got[i][0], of) <= 1e-10, i
+        assert errs(got[i][1], om) <= 1e-10, i
+        assert errs(om, pm) > 1e-6, i
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_with_current_is_bitwise_the_single_grid(precision):
+    """Each batched instance against the same instance stepped alone with the current
+    folded in; again with 7-row segments and graphs, and with two cells per lane
+    (each work item then runs as two strips)."""
+    members = inputs.config_c4(ninst=6, seed=23, precision=precision, side=(64, 200))
+    steps = 20
+    refs = [run_gpu_at(p, phi, mu, steps, step0=3) for (p, phi, mu) in members]
+    for seg, vec, graph in [(None, 0, 0), (7, 0, 4), (None, 2, 0)]:
+        print(f"batch {precision}: seg {seg} vec {vec} graph {graph}", flush=True)
+        got = _batch_at(members, steps, step0=3, seg=seg, vec=vec, graph=graph)
+        for i in range(len(members)):
+            assert np.array_equal(got[i][0], refs[i][0]), (seg, vec, graph, i)
+            assert np.array_equal(got[i][1], refs[i][1]), (seg, vec, graph, i)
