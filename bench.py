@@ -70,6 +70,19 @@ TRAFFIC = {
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
+    # profiles/k_step2d_at_eutectic_4096_f64_f32.md
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "4091af1b63140164",
+                "bytes": (2.0 * 416890.2 + 659273.6) * 1024},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "4091af1b63140164",
+                "bytes": (2.0 * 247808.8 + 331443.8) * 1024},
+    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186",
+               "bytes": (2.0 * 870343.7 + 269730.6) * 1024},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186",
+               "bytes": (2.0 * 462493.6 + 140645.4) * 1024},
+    # profiles/k_antitrap3d_dendrite_512_f32.md
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "4f849c078ba4a481",
+                 "bytes": (2.0 * 2760737.2 + 574458.6) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
@@ -215,6 +228,14 @@ VALU = {
     "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d", "insts": 173801142.0},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444", "insts": 545827325.3},
+    # profiles/k_step2d_at_eutectic_4096_f64_f32.md
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "4091af1b63140164", "insts": 206706345.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "4091af1b63140164", "insts": 152623317.0},
+    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186", "insts": 113467320.0},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186", "insts": 85678266.0},
+    # profiles/k_antitrap3d_dendrite_512_f32.md
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "4f849c078ba4a481", "insts": 666687488.0},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
 }
@@ -248,8 +269,14 @@ def bound_record(bytes_per_step, flops_per_step, ms_step, precision, traffic=Non
         rec = roofline(bytes_per_step, ms_step, traffic)
     else:
         rec = alu_roofline(flops_per_step, ms_step, precision, traffic)
-    ms_launch = ms_step * steps_per_launch
     rec["ideal_ms_per_step"] = {"hbm": round(t_hbm, 6), "alu": round(t_alu, 6)}
+    return with_counter_fracs(rec, ms_step * steps_per_launch, precision, traffic, valu_insts)
+
+
+def with_counter_fracs(rec, ms_launch, precision, traffic=None, valu_insts=None):
+    """rec plus ``counter_frac`` (counter traffic per launch / launch time / HBM peak) and
+    ``valu_issue_frac`` (VALU instructions x cycles each / SIMDs / clock / launch time),
+    each null without a counter figure for this exact kernel and tile."""
     rec["counter_frac"] = None if traffic is None else round(traffic / (ms_launch * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
     rec["valu_issue_frac"] = None if valu_insts is None else round(
         valu_insts * VALU_CYCLES[precision] / SIMDS / CLOCK_HZ / (ms_launch * 1e-3), 4)
@@ -426,7 +453,9 @@ def leg_at3d(n, steps, warmup):
         "ms_per_step_without_current": ms_plain,
         "correction_ms_per_step": ms_corr,
         "correction_bytes_per_cell": bpc,
-        "roofline": roofline(p.ncells * bpc, ms_corr, traffic_of("at3d_f32", AT3D_TILE, 1))
+        "roofline": with_counter_fracs(roofline(p.ncells * bpc, ms_corr, traffic_of("at3d_f32", AT3D_TILE, 1)),
+                                       ms_corr, "f32", traffic_of("at3d_f32", AT3D_TILE, 1),
+                                       valu_of("at3d_f32", AT3D_TILE, 1))
         if ms_corr > 0 else None,
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
     }
@@ -471,7 +500,9 @@ def leg_at(precision, n, steps, warmup):
         "region_ms": [round(x, 4) for x in regions],
         "bytes_per_cell_update": bpc,
         "tile": {"bx": bx, "seg": seg, "vec": 1},
-        "roofline": roofline(p.ncells * bpc, ms_at, traffic_of(f"atf_{precision}", tile, 1)),
+        "roofline": with_counter_fracs(roofline(p.ncells * bpc, ms_at, traffic_of(f"atf_{precision}", tile, 1)),
+                                       ms_at, precision, traffic_of(f"atf_{precision}", tile, 1),
+                                       valu_of(f"atf_{precision}", tile, 1)),
         "ms_per_step_without_current": ms_plain,
         "separate_correction": {
             "ms_per_step": ms_sep,
@@ -479,7 +510,9 @@ def leg_at(precision, n, steps, warmup):
             "correction_ms_per_step": ms_corr,
             "correction_bytes_per_cell": bpc_corr,
             # the correction kernel: time = step then correction - step without the current
-            "roofline": roofline(p.ncells * bpc_corr, ms_corr, traffic_of(f"at_{precision}", AT_TILE, 1))
+            "roofline": with_counter_fracs(
+                roofline(p.ncells * bpc_corr, ms_corr, traffic_of(f"at_{precision}", AT_TILE, 1)), ms_corr,
+                precision, traffic_of(f"at_{precision}", AT_TILE, 1), valu_of(f"at_{precision}", AT_TILE, 1))
             if ms_corr > 0 else None,
         },
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},

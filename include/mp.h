@@ -11,9 +11,11 @@
  *        force sum_b psi^b dh_b/dphi_a with h of Eq. hphi, and the Lagrange
  *        multiplier that keeps sum_a phi_a = 1; no elastic term);
  *   mu : Eq. Mu_explicit_temperature with M of Eq. Mass_conservation and the
- *        diagonal parabolic free energies of Eq. free_energy_density; the
- *        anti-trapping current of Eq. jatr is off unless mp_set_antitrapping
- *        switches it on (2D and 3D single grids).
+ *        parabolic free energies of Eq. free_energy_density (diagonal
+ *        curvatures, or for two mu fields the symmetric 2 x 2 with an
+ *        off-diagonal term; B and C optionally functions of T with the dT/dt
+ *        term); the anti-trapping current of Eq. jatr is off unless
+ *        mp_set_antitrapping switches it on (2D and 3D single grids, batches).
  *
  * Conventions for every call:
  *   - Return value: MP_OK (0) or a negative MP_E_* code; mp_last_error()
