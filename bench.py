@@ -81,7 +81,7 @@ TRAFFIC = {
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186",
                "bytes": (2.0 * 462493.6 + 140645.4) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "4f849c078ba4a481",
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "d6eca4e22224d36b",
                  "bytes": (2.0 * 2760737.2 + 574458.6) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
@@ -235,7 +235,7 @@ VALU = {
     "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186", "insts": 113467320.0},
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "b68e1fd8ce620186", "insts": 85678266.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "4f849c078ba4a481", "insts": 666687488.0},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "d6eca4e22224d36b", "insts": 666687488.0},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
 }

@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
     }
 }
 
-// Rows per wave: the planes held in registers grow with it (2 rows: 133 VGPRs
+// Rows per wave: the planes held in registers grow with it (2 rows: 125 VGPRs
 // for the binary FP32 case; FP64 takes 1 row so that its ternary variants do
 // not spill).
 template <typename R>
