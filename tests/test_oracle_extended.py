@@ -383,3 +383,55 @@ def test_shift_equals_the_taller_run(potential):
     ft, mt = gp.run(phi, mu, 0, n1 + n2, tall)
     assert np.array_equal(f, ft[:, s:])
     assert np.array_equal(m, mt[:, s:])
+
+
+# ----------------------------------------------------------------------------
+# The anti-trapping current (Eq. jatr) with the extended model
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0)])
+@pytest.mark.parametrize("offdiag", [False, True])
+def test_antitrapping_conserves_solute_with_the_extended_model(bc, offdiag):
+    """The current enters as a divergence and is divided by the same (matrix)
+    chi(phi^{n+1}) as the rest of the mu update, so the composition of every time
+    level (with its own T under a moving gradient) stays put, while the current
+    moves mu well away from the run without it."""
+    p, _, _ = params(N=3, K1=2, n=(9, 8, 1), bc=bc, slopes=True, offdiag=offdiag, G=0.04, V=0.9, seed=3)
+    phi, mu = simplex_state(p, seed=4)
+    m0 = np.array(gp.diagnostics(phi, mu, p, n=5)["mass"])
+    f, m = phi, mu
+    for i in range(40):
+        f, m = gp.step_antitrapping(f, m, 5 + i, p)
+    m1 = np.array(gp.diagnostics(f, m, p, n=45)["mass"])
+    assert np.all(np.abs(m1 - m0) <= 1e-13 * np.maximum(1.0, np.abs(m0)))
+    _, mp = gp.run(phi, mu, 5, 40, p)
+    assert np.max(np.abs(m - mp)) > 1e-6
+
+
+@pytest.mark.parametrize("offdiag", [False, True])
+def test_antitrapping_ramp_takes_each_rows_composition_at_time_level_n(offdiag):
+    """A two-phase ramp along x under a gradient along y: every x face carries
+    P r (c^s - c^l) with the compositions c^a = chi^a (mu - B^a(T)) of its own row
+    at the temperature of time level n (the unit normals are exact on the ramp
+    and opposite for the two phases); no y face carries anything."""
+    p, _, _ = params(N=2, K1=2, n=(9, 8, 1), bc=(1, 1, 0), slopes=True, offdiag=offdiag, G=0.05, V=0.7, seed=6)
+    x, y = inputs.grid_coords(p)
+    b, r, n = 0.03, 0.21, 7
+    ps = np.broadcast_to(0.5 + b * (x - 4 * p.dx), p.spatial)
+    phi = np.stack([ps, 1.0 - ps])
+    phin = phi + p.dt * r * np.stack([np.ones_like(ps), -np.ones_like(ps)])
+    mu = np.stack([np.full(p.spatial, 0.13), np.full(p.spatial, -0.08)])
+    rows = np.arange(p.n[1])
+    T = p.T0 + p.G * (rows * p.dx - p.y0 - p.V * n * p.dt)  # time level n, one value per row
+    chi = np.linalg.inv(np.stack([[[2 * p.A[a, 0], p.A01[a]], [p.A01[a], 2 * p.A[a, 1]]] for a in range(2)]))
+    pref = p.eps / (2.0 * math.sqrt(2.0))
+    for axis, j in gp.antitrapping_faces(phi, phin, mu, p, n=n):
+        if axis != -1:
+            assert np.all(j == 0.0)
+            continue
+        for row in range(1, p.n[1] - 1):
+            c = [chi[a] @ (np.array([0.13, -0.08]) - (p.B[a, :2] + p.Bt[a, :2] * (T[row] - p.Te))) for a in range(2)]
+            want = pref * r * (c[0] - c[1])
+            # faces between interior columns of this row
+            np.testing.assert_allclose(j[:, row, 1:-1], np.broadcast_to(want[:, None], (2, p.n[0] - 1)),
+                                       rtol=1e-12, atol=1e-15)
