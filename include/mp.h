@@ -267,8 +267,12 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * the bits of the same instance stepped alone.  mp_adjoint returns
  * MP_E_STATE while it is on.  2D and 3D single grids and batches.  Host only
  * for a single grid; for a bound batch switching it on or off re-deals the
- * work list (a synchronous copy).  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0,
- * 1 or 2), MP_E_STATE (the extended model; on = 2 for a batch). */
+ * work list (a synchronous copy).  With the extended model (Bt, Ct, A01, D01,
+ * tau_ab, MP_OBSTACLE_ACTIVE) the compositions of the current are those at each
+ * row's temperature of time level n and the correction solves with the 2 x 2
+ * susceptibility; it takes on = 1 on 2D grids only.  Errors: MP_E_NULLPTR,
+ * MP_E_PARAM (on not 0, 1 or 2), MP_E_STATE (the extended model with on = 2 or
+ * on a 3D grid; on = 2 for a batch). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 

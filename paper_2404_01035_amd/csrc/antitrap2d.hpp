@@ -47,12 +47,34 @@ __device__ inline R at_prefactor(R f, const AtCoef<R>& c) {
     return c.prefo * f * (R(1) - h1) / sqrt(f * (R(1) - f));
 }
 
+// Composition c^a_k(mu, T) = sum_j chi^a_kj (mu_j - B^a_j(T)) of a cell of the
+// extended model (B^a(T) = B^a + Bt^a (T - Te), tt = T - Te of the cell's row;
+// the off-diagonal chi^a_01 for two mu fields).
+template <typename R, int NP, int NM>
+__device__ __forceinline__ void at_comp_gen(const R* u, R tt, const AtCoef<R>& c, const CoefX<R>& x,
+                                            R (&cc)[NP][NM]) {
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        R d[NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) d[k] = u[k] - (c.B[a][k] + x.Bt[a][k] * tt);
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            R v = c.chi[a][k] * d[k];
+            if constexpr (NM == 2) v = v + x.chx[a] * d[1 - k];
+            cc[a][k] = v;
+        }
+    }
+}
+
 // Current on one face.  pL/pR: phi^n of the two cells, tL/tR: their central
 // differences along the tangential axis (already / (2 dx)), qL/qR: phi^{n+1},
-// uL/uR: mu^n.  Adds the face's j_k to j.
-template <typename R, int NP, int NM>
+// uL/uR: mu^n.  Adds the face's j_k to j.  GEN: the extended model's
+// compositions (x its terms, ttL/ttR = T - Te of the two cells' rows).
+template <typename R, int NP, int NM, bool GEN = false>
 __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* tR, const R* qL, const R* qR,
-                               const R* uL, const R* uR, const AtCoef<R>& c, R* j) {
+                               const R* uL, const R* uR, const AtCoef<R>& c, R* j, const CoefX<R>* x = nullptr,
+                               R ttL = R(0), R ttR = R(0)) {
     constexpr int LIQ = NP - 1;
     R un[NP], ut[NP];
 #pragma unroll
@@ -63,6 +85,24 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
         const R inv = at_inv_norm(n2);
         un[a] = gn * inv;
         ut[a] = gt * inv;
+    }
+    if constexpr (GEN) {
+        R cL[NP][NM], cR[NP][NM];
+        at_comp_gen<R, NP, NM>(uL, ttL, c, *x, cL);
+        at_comp_gen<R, NP, NM>(uR, ttR, c, *x, cR);
+#pragma unroll
+        for (int a = 0; a < NP - 1; ++a) {
+            const R weight = -(un[a] * un[LIQ] + ut[a] * ut[LIQ]);
+            const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+            const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * un[a] * weight;
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                const R ca = R(0.5) * (cL[a][k] + cR[a][k]);
+                const R cl = R(0.5) * (cL[LIQ][k] + cR[LIQ][k]);
+                j[k] += common * (ca - cl);
+            }
+        }
+        return;
     }
     R cl[NM];
 #pragma unroll
@@ -78,6 +118,33 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
             const R ca = R(0.5) * (c.chi[a][k] * (uL[k] - c.B[a][k]) + c.chi[a][k] * (uR[k] - c.B[a][k]));
             j[k] += common * (ca - cl[k]);
         }
+    }
+}
+
+// mu^{n+1} - dt chi(phi^{n+1})^-1 div j_at for the extended model: chi = sum_b h_b
+// chi^b with the off-diagonal chi^b_01 for two mu fields (the step's 2 x 2
+// solve), hb = h(phi^{n+1}), dv = div j_at.
+template <typename R, int NP, int NM>
+__device__ __forceinline__ void at_correct_gen(const R (&hb)[NP], const R (&dv)[NM], const AtCoef<R>& c,
+                                               const CoefX<R>& x, R (&mn)[NM]) {
+    R c00 = R(0);
+#pragma unroll
+    for (int b = 0; b < NP; ++b) c00 = c00 + hb[b] * c.chi[b][0];
+    if constexpr (NM == 2) {
+        R c11 = R(0), c01 = R(0);
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+            c11 = c11 + hb[b] * c.chi[b][1];
+            c01 = c01 + hb[b] * x.chx[b];
+        }
+        const R r0 = c.dt * dv[0], r1 = c.dt * dv[1];
+        const R inv = fast_rcp(c00 * c11 - c01 * c01);
+        const R d0 = (c11 * r0 - c01 * r1) * inv;
+        const R d1 = (c00 * r1 - c01 * r0) * inv;
+        mn[0] = mn[0] - d0;
+        mn[1] = mn[1] - d1;
+    } else {
+        mn[0] = mn[0] - (c.dt * dv[0]) * fast_rcp(c00);
     }
 }
 

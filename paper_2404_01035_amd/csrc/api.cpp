@@ -27,6 +27,8 @@ namespace mp {
 template <typename R>
 int call_step_at(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k);
 template <typename R>
+int call_step_at_gen(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>& x, KernelCall& k);
+template <typename R>
 int call_batch_at(const BatchLaunch& L, const void* atab, KernelCall& k);
 }  // namespace mp
 
@@ -381,11 +383,14 @@ mp::AtCoef<R> make_at_coef(const Inst& I) {
     c.rdx = (R)(1.0 / I.grid.dx);
     c.rdt = (R)(1.0 / p.dt);
     c.dt = (R)p.dt;
-    for (int a = 0; a < I.N; ++a)
+    for (int a = 0; a < I.N; ++a) {
+        double chi[2][2];
+        chi_of(p, a, I.K, chi);  // 1 / (2 A) without the off-diagonal curvature
         for (int k = 0; k < I.K - 1; ++k) {
-            c.chi[a][k] = (R)(1.0 / (2.0 * p.A[a][k]));
+            c.chi[a][k] = (R)chi[k][k];
             c.B[a][k] = (R)p.B[a][k];
         }
+    }
     return c;
 }
 
@@ -684,6 +689,13 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.kstep = kstep;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
     if (at_folded(st) && !out1) {
+        if (I.ext) {
+            if (st->precision == MP_FP64)
+                return mp::call_step_at_gen<double>(L, make_coef<double>(I), make_at_coef<double>(I),
+                                                    make_coefx<double>(I), k);
+            return mp::call_step_at_gen<float>(L, make_coef<float>(I), make_at_coef<float>(I), make_coefx<float>(I),
+                                               k);
+        }
         if (st->precision == MP_FP64) return mp::call_step_at<double>(L, make_coef<double>(I), make_at_coef<double>(I), k);
         return mp::call_step_at<float>(L, make_coef<float>(I), make_at_coef<float>(I), k);
     }
@@ -1364,8 +1376,9 @@ int mp_set_antitrapping(mp_state* st, int on) {
     if (on < 0 || on > 2) return fail(MP_E_PARAM, "on must be 0, 1 or 2 (got %d)", on);
     if (on == 2 && st->batch)
         return fail(MP_E_STATE, "anti-trapping current: batched states take it folded into the step (on = 1) only");
-    if (on && st->inst[0].ext)
-        return fail(MP_E_STATE, "anti-trapping current: the extended model is not supported");
+    if (on && st->inst[0].ext && (on == 2 || st->inst[0].grid.dim != 2))
+        return fail(MP_E_STATE, "anti-trapping current with the extended model: 2D grids with the current folded "
+                                "into the step (on = 1) only");
     drop_graphs(st);
     const int was = st->antitrap;
     st->antitrap = on;

@@ -23,15 +23,17 @@ namespace mp {
 // cell it mirrors, so its face carries no current, as in the correction
 // kernel; a periodic ghost row is stepped from its wrapped neighbours.  The
 // arithmetic is that of strip2d followed by k_antitrap2d, operation for
-// operation.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, bool XEDGE>
+// operation.  GEN: the extended model (x its terms): the general step, and
+// compositions at each row's temperature of time level n with the 2 x 2
+// susceptibility in the correction.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool XEDGE, bool GEN = false>
 __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                            const Coef<R>& c, const AtCoef<R>& ac, double tbase, double tslope,
-                                           int tx, int m0, int m1) {
+                                           int tx, int m0, int m1, const CoefX<R>* x = nullptr) {
     constexpr int V = 1;
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
-    typedef Row2d<R, NP, NM, V, ANISO> RowT;
+    typedef Row2d<R, NP, NM, V, ANISO, GEN> RowT;
     const int lane = threadIdx.x & 63;
     const bool pery = g.bcy == MP_BC_PERIODIC;
     const int nx = g.nx, ny = g.ny;
@@ -53,13 +55,14 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
     };
     auto process = [&](RawT& r, RowT& P) {
         if constexpr (XEDGE) mirror_fix<R, NF, V>(r.v, fixL, fixR);
-        make_row<R, NP, NM, ANISO, V>(r.v, P, c);
+        make_row<R, NP, NM, ANISO, V, false, GEN>(r.v, P, c, nullptr, x);
     };
 
     Carry2d<R, NP, NM, V, ANISO> k0;
     RowT c0, n0;
     // rows of phi^n (hp[0] the newest), mu^n, and phi^{n+1}, mu^{n+1} before the correction
     R hp[3][NP], hu[2][NM], nq[2][NP], nm[2][NM];
+    R htt[2] = {R(0), R(0)};  // T - Te of the rows of hu (extended model)
     {
         RawT a, b, d;
         load(r_first - 1, a);
@@ -68,7 +71,7 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
         RowT prv;
         process(a, prv);
         process(b, c0);
-        carry_init<R, NP, NM, ANISO, V>(prv, c0, k0, c);
+        carry_init<R, NP, NM, ANISO, V, GEN>(prv, c0, k0, c);
         process(d, n0);
 #pragma unroll
         for (int q = 0; q < NP; ++q) hp[0][q] = prv.phi[0][q];
@@ -79,9 +82,13 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
     auto step = [&](int r, RawT& raw) {
         R Cs[NP];
         const R tt = (R)(tbase + tslope * (double)rowmap(r));
-        psi_const<R, NP>(tt, c, Cs);
+        psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V>(c0, n0, k0, Cs, c, phin, mun, hn, tt);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN>(c0, n0, k0, Cs, c, phin, mun, hn, tt, x);
+        if constexpr (GEN) {
+            htt[1] = htt[0];
+            htt[0] = tt;
+        }
         R v[NF][V];
 #pragma unroll
         for (int a = 0; a < NP; ++a) v[a][0] = phin[a][0];
@@ -127,6 +134,7 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
             hu[1][kk] = hu[0][kk];
             nm[1][kk] = nm[0][kk];
         }
+        if constexpr (GEN) htt[1] = htt[0];
     };
     // central difference along x (x 1/(2 dx)) of a row of phi^n
     auto ddx = [&](const R (&p)[NP], R (&t)[NP]) {
@@ -152,7 +160,7 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
             ddx(hp[0], tq);
 #pragma unroll
             for (int kk = 0; kk < NM; ++kk) jylo[kk] = R(0);
-            at_face<R, NP, NM>(hp[1], hp[0], ta, tq, nq[1], nq[0], hu[1], hu[0], ac, jylo);
+            at_face<R, NP, NM, GEN>(hp[1], hp[0], ta, tq, nq[1], nq[0], hu[1], hu[0], ac, jylo, x, htt[1], htt[0]);
         }
     };
     // the current around row q (rows q-1, q, q+1 of phi^n are hp[2], hp[1],
@@ -169,10 +177,10 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
 #pragma unroll
         for (int kk = 0; kk < NM; ++kk) ul[kk] = lane_prev(hu[1][kk]);
         R jxl[NM] = {};
-        at_face<R, NP, NM>(pl, hp[1], tyl, ty, ql, nq[1], ul, hu[1], ac, jxl);
+        at_face<R, NP, NM, GEN>(pl, hp[1], tyl, ty, ql, nq[1], ul, hu[1], ac, jxl, x, htt[1], htt[1]);
         ddx(hp[0], txh);
         R jyhi[NM] = {};
-        at_face<R, NP, NM>(hp[1], hp[0], tq, txh, nq[1], nq[0], hu[1], hu[0], ac, jyhi);
+        at_face<R, NP, NM, GEN>(hp[1], hp[0], tq, txh, nq[1], nq[0], hu[1], hu[0], ac, jyhi, x, htt[1], htt[0]);
 #pragma unroll
         for (int a = 0; a < NP; ++a) tq[a] = txh[a];
         R hb[NP];
@@ -187,6 +195,22 @@ __device__ __forceinline__ void strip2d_at(const R* __restrict__ in, R* __restri
         if (writes) {
 #pragma unroll
             for (int a = 0; a < NP; ++a) out[a * fs + o] = nq[1][a];
+        }
+        if constexpr (GEN) {
+            R dv[NM], mn[NM];
+#pragma unroll
+            for (int kk = 0; kk < NM; ++kk) {
+                const R jxh = lane_next(jxl[kk]);
+                dv[kk] = (jxh - jxl[kk]) * ac.rdx + (jyhi[kk] - jylo[kk]) * ac.rdx;
+                mn[kk] = nm[1][kk];
+                jylo[kk] = jyhi[kk];
+            }
+            at_correct_gen<R, NP, NM>(hb, dv, ac, *x, mn);
+            if (writes) {
+#pragma unroll
+                for (int kk = 0; kk < NM; ++kk) out[(NP + kk) * fs + o] = mn[kk];
+            }
+            return;
         }
 #pragma unroll
         for (int kk = 0; kk < NM; ++kk) {
@@ -259,15 +283,43 @@ k_step2d_at(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, At
         strip2d_at<R, NP, NM, ANISO, OBST, false>(in, out, g, c, ac, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
 }
 
+// The extended model's general form: the same strip with the GEN arithmetic
+// and the extended coefficients as a further argument.
 template <typename R, int NP, int NM, bool ANISO, bool OBST>
-int call_2d_at_v(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
+k_step2d_at_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c, AtCoef<R> ac,
+                const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+                int seg, int ntx, int nseg, CoefX<R> x) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
+    bool fixL, fixR;
+    x2_column<1>(g, x2_first_col<1>(tx, threadIdx.x & 63), fixL, fixR);
+    if (__ballot(fixL || fixR) != 0)
+        strip2d_at<R, NP, NM, ANISO, OBST, true, true>(in, out, g, c, ac, tbase, tslope, tx, m0,
+                                                        min(m0 + seg, g.ny), &x);
+    else
+        strip2d_at<R, NP, NM, ANISO, OBST, false, true>(in, out, g, c, ac, tbase, tslope, tx, m0,
+                                                         min(m0 + seg, g.ny), &x);
+}
+
+// GEN: the general kernel with the extended model's terms x (null otherwise).
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool GEN>
+int call_2d_at_v(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>* x, KernelCall& k) {
     const int ntx = (L.g.nx + W2X_LANES_OUT - 1) / W2X_LANES_OUT;
     const int nseg = (L.g.ny + L.seg - 1) / L.seg;
     const int wpb = L.bx / 64;
     const long long waves = (long long)ntx * nseg;
     const long long nblocks = (waves + wpb - 1) / wpb;
     if (nblocks <= 0 || nblocks > 0x7fffffffLL || L.out1 || L.fuse != 1 || L.g.nz != 1) return MP_E_PARAM;
-    k.func = (const void*)&k_step2d_at<R, NP, NM, ANISO, OBST>;
+    if constexpr (GEN)
+        k.func = (const void*)&k_step2d_at_gen<R, NP, NM, ANISO, OBST>;
+    else
+        k.func = (const void*)&k_step2d_at<R, NP, NM, ANISO, OBST>;
     k.grid = dim3((unsigned)nblocks);
     k.block = dim3(L.bx);
     k.arg((const R*)L.in);
@@ -283,26 +335,42 @@ int call_2d_at_v(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, Ker
     k.arg(L.seg);
     k.arg(ntx);
     k.arg(nseg);
+    if constexpr (GEN) k.arg(*x);
     return MP_OK;
 }
 
-template <typename R, int NP, int NM>
-int call_2d_at_flags(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k) {
-    const bool obst = L.potential == MP_OBSTACLE;
+// (both obstacle projections of the general kernel share one instance: the choice is CoefX::proj)
+template <typename R, int NP, int NM, bool GEN>
+int call_2d_at_flags(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>* x, KernelCall& k) {
+    const bool obst = GEN ? L.potential != MP_WELL : L.potential == MP_OBSTACLE;
     if (L.aniso)
-        return obst ? call_2d_at_v<R, NP, NM, true, true>(L, c, ac, k) : call_2d_at_v<R, NP, NM, true, false>(L, c, ac, k);
-    return obst ? call_2d_at_v<R, NP, NM, false, true>(L, c, ac, k) : call_2d_at_v<R, NP, NM, false, false>(L, c, ac, k);
+        return obst ? call_2d_at_v<R, NP, NM, true, true, GEN>(L, c, ac, x, k)
+                    : call_2d_at_v<R, NP, NM, true, false, GEN>(L, c, ac, x, k);
+    return obst ? call_2d_at_v<R, NP, NM, false, true, GEN>(L, c, ac, x, k)
+                : call_2d_at_v<R, NP, NM, false, false, GEN>(L, c, ac, x, k);
+}
+
+template <typename R, bool GEN>
+int call_step_at_any(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>* x, KernelCall& k) {
+    if (L.dim != 2) return MP_E_PARAM;
+    if (L.nphases == 2 && L.nmu == 1) return call_2d_at_flags<R, 2, 1, GEN>(L, c, ac, x, k);
+    if (L.nphases == 2 && L.nmu == 2) return call_2d_at_flags<R, 2, 2, GEN>(L, c, ac, x, k);
+    if (L.nphases == 3 && L.nmu == 1) return call_2d_at_flags<R, 3, 1, GEN>(L, c, ac, x, k);
+    if (L.nphases == 3 && L.nmu == 2) return call_2d_at_flags<R, 3, 2, GEN>(L, c, ac, x, k);
+    return MP_E_PARAM;
 }
 
 // One 2D step with the current: the kernel instance for (N, K-1, anisotropy, potential).
 template <typename R>
 int call_step_at(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k) {
-    if (L.dim != 2) return MP_E_PARAM;
-    if (L.nphases == 2 && L.nmu == 1) return call_2d_at_flags<R, 2, 1>(L, c, ac, k);
-    if (L.nphases == 2 && L.nmu == 2) return call_2d_at_flags<R, 2, 2>(L, c, ac, k);
-    if (L.nphases == 3 && L.nmu == 1) return call_2d_at_flags<R, 3, 1>(L, c, ac, k);
-    if (L.nphases == 3 && L.nmu == 2) return call_2d_at_flags<R, 3, 2>(L, c, ac, k);
-    return MP_E_PARAM;
+    return call_step_at_any<R, false>(L, c, ac, nullptr, k);
+}
+
+// The same for the extended model (the general kernels).
+template <typename R>
+int call_step_at_gen(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>& x,
+                     KernelCall& k) {
+    return call_step_at_any<R, true>(L, c, ac, &x, k);
 }
 
 }  // namespace mp

@@ -4,9 +4,11 @@ coefficients with the dT/dt term (Sec. 3, Eq. Mu_explicit_temperature), the
 obstacle with the multiplier over the active phases and per-pair relaxation
 constants (Eq. Obstacle, the Tau key of Sec. 5), off-diagonal curvatures and
 diffusivities (Eq. free_energy_density, Eq. Mass_conservation), in 2D (one and
-two steps per launch, graphs) and 3D, FP64 to 1e-10 and FP32 to 1e-4; and the
-moving frame (SHIFT): the front row and the shift against the oracle's, and a
-run with shifts against the oracle's run in the shifted frame."""
+two steps per launch, graphs) and 3D, FP64 to 1e-10 and FP32 to 1e-4; the
+anti-trapping current of Eq. jatr with the extended model (2D, folded into the
+step); and the moving frame (SHIFT): the front row and the shift against the
+oracle's, and runs with shifts (with and without the current) against the
+oracle's runs in the shifted frame."""
 import zlib
 
 import numpy as np
@@ -217,8 +219,99 @@ def test_extended_model_refusals():
     assert e.value.code == abi.MP_E_PARAM
     st = abi.mp_create(p)
     try:
+        # the current with the extended model: folded into the 2D step only
+        with pytest.raises(abi.MPError) as e:
+            abi.mp_set_antitrapping(st, 2)
+        assert e.value.code == abi.MP_E_STATE
+        abi.mp_set_antitrapping(st, True)
+        assert abi.mp_get_antitrapping(st) == 1
+    finally:
+        abi.mp_destroy(st)
+    st = abi.mp_create(extended(dim=3, N=3, K=3, n=(20, 13, 17), bc=(0, 1, 0)))
+    try:
         with pytest.raises(abi.MPError) as e:
             abi.mp_set_antitrapping(st, True)
         assert e.value.code == abi.MP_E_STATE
     finally:
         abi.mp_destroy(st)
+
+
+def run_gpu_at(p, phi, mu, nsteps, step0=0, graph=0):
+    from paper_2404_01035_amd.solver import Solver
+
+    s = Solver(p)
+    try:
+        if graph:
+            s.set_graph(graph)
+        s.set_antitrapping(True)
+        s.load(phi, mu, step0)
+        s.step(nsteps)
+        return s.fields()
+    finally:
+        s.close()
+
+
+def oracle_run_at(phi, mu, n0, nsteps, p, y_origin=0):
+    for i in range(nsteps):
+        phi, mu = gp.step_antitrapping(phi, mu, n0 + i, p, y_origin)
+    return phi, mu
+
+
+AT_CASES = [name for name in sorted(CASES) if name.startswith("2d")]
+
+
+@pytest.mark.parametrize("name", AT_CASES)
+def test_fp64_extended_with_antitrapping_matches_oracle(name):
+    """The anti-trapping current folded into the general 2D step: compositions at
+    each row's temperature, the 2 x 2 susceptibility in the correction."""
+    kw, steps = CASES[name]
+    steps = min(steps, 120)
+    p = extended(seed=zlib.crc32(name.encode()) % 1000, **kw)
+    phi, mu = nuclei(p, seed=9)
+    print(f"{name} with the current: {steps} steps", flush=True)
+    f, m = run_gpu_at(p, phi, mu, steps, step0=7)
+    of, om = oracle_run_at(phi, mu, 7, steps, p)
+    _, pm = gp.run(phi, mu, 7, steps, p)
+    print(f"  phi {errs(f, of):.3e} mu {errs(m, om):.3e}; the current moves mu by {errs(om, pm):.3e}", flush=True)
+    assert errs(f, of) <= 1e-10
+    assert errs(m, om) <= 1e-10
+    assert errs(om, pm) > 1e-6
+
+
+def test_fp32_extended_with_antitrapping_and_graphs():
+    kw, steps = CASES["2d_n3k3_all_noflux_y"]
+    p = extended(seed=11, precision="f32", **kw)
+    phi, mu = nuclei(p, seed=9)
+    f, m = run_gpu_at(p, phi, mu, 100, step0=7)
+    of, om = oracle_run_at(phi, mu, 7, 100, p)
+    print(f"FP32 with the current: phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
+    assert errs(f, of) <= 1e-4 and errs(m, om) <= 1e-4
+    g = run_gpu_at(p, phi, mu, 100, step0=7, graph=10)
+    assert np.array_equal(g[0], f) and np.array_equal(g[1], m)
+
+
+def test_moving_frame_with_antitrapping_matches_oracle():
+    """Shifts of the frame with the current on: the compositions follow the frame's temperature."""
+    from paper_2404_01035_amd.solver import Solver
+
+    p, phi, mu = inputs.config_c2_slopes(precision="f64", n=(64, 48, 1))
+    p.V = 2.0
+    p.dt = 0.2 * inputs.dt_limit(p)
+    melt = np.array([0.0, 0.0])
+    shiftj, every, nsteps = 5, 20, 80
+    s = Solver(p)
+    s.set_antitrapping(True)
+    s.load(phi, mu)
+    off = s.step_moving_frame(nsteps, shiftj, every, melt)
+    f, m = s.fields()
+    s.close()
+    of, om, ooff = phi, mu, 0
+    for i in range(0, nsteps, every):
+        of, om = oracle_run_at(of, om, i, every, p, y_origin=ooff)
+        front = gp.front_row(of)
+        if front > shiftj:
+            of, om = gp.shift(of, om, front - shiftj, melt)
+            ooff += front - shiftj
+    print(f"moving frame with the current: offset {off}, phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
+    assert off == ooff and off > 0
+    assert errs(f, of) <= 1e-10 and errs(m, om) <= 1e-10
