@@ -70,14 +70,6 @@ TRAFFIC = {
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
-    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "d3fc3a371b72452d",
-               "bytes": (2.0 * 870343.7 + 269730.6) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "d3fc3a371b72452d",
-               "bytes": (2.0 * 462493.6 + 140645.4) * 1024},
-    # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "b2c566947925f4e7",
-                 "bytes": (2.0 * 2760737.2 + 574458.6) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
@@ -223,11 +215,6 @@ VALU = {
     "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d", "insts": 173801142.0},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444", "insts": 545827325.3},
-    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "d3fc3a371b72452d", "insts": 113467320.0},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "d3fc3a371b72452d", "insts": 85678266.0},
-    # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "b2c566947925f4e7", "insts": 666687488.0},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
 }

@@ -270,9 +270,8 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * work list (a synchronous copy).  With the extended model (Bt, Ct, A01, D01,
  * tau_ab, MP_OBSTACLE_ACTIVE) the compositions of the current are those at each
  * row's temperature of time level n and the correction solves with the 2 x 2
- * susceptibility; it takes on = 1 on 2D grids only.  Errors: MP_E_NULLPTR,
- * MP_E_PARAM (on not 0, 1 or 2), MP_E_STATE (the extended model with on = 2 or
- * on a 3D grid; on = 2 for a batch). */
+ * susceptibility.  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0, 1 or 2),
+ * MP_E_STATE (on = 2 for a batch). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 

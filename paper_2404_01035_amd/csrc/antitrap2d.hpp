@@ -197,9 +197,13 @@ __device__ inline void at_finish(AtRow<R, NP, NM>& r, R h2) {
 // its right neighbour's; the y face below a row is the one above the row
 // before it.  Each face is evaluated once, with the operands and operations
 // of the per-face definition, whichever cell it serves.
-template <typename R, int NP, int NM>
-__global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restrict__ prev, R* __restrict__ next,
-                                                              Geom g, AtCoef<R> c, int nstrips, int nitems) {
+// GEN: the extended model (x its terms): the compositions at each row's
+// temperature of time level n, T - Te = tbase + tslope * row, and the 2 x 2
+// susceptibility in the correction.
+template <typename R, int NP, int NM, bool GEN>
+__device__ __forceinline__ void antitrap2d_strip(const R* __restrict__ prev, R* __restrict__ next, const Geom& g,
+                                                 const AtCoef<R>& c, int nstrips, int nitems, const CoefX<R>* x,
+                                                 double tbase, double tslope) {
     const int item = (int)blockIdx.x * AT_WAVES + (int)(threadIdx.x >> 6);
     if (item >= nitems) return;  // whole waves only
     const int lane = (int)(threadIdx.x & 63);
@@ -210,21 +214,26 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
     const bool own = lane >= 1 && lane <= AT_LANES_OUT && craw < g.nx;
     const int col = at_wrap(craw < g.nx ? craw : g.nx, g.nx, g.bcx);  // lanes past the right ghost repeat it
     const R h2 = R(0.5) * c.rdx;
+    // T - Te of a row (the extended model)
+    auto rowtt = [&](int row) { return GEN ? (R)(tbase + tslope * (double)row) : R(0); };
     AtRow<R, NP, NM> lo, mid, hi, ahead;
-    at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(y0 - 1, g.ny, g.bcy), lo);
+    const int ylo = at_wrap(y0 - 1, g.ny, g.bcy), yhi = at_wrap(y0 + 1, g.ny, g.bcy);
+    at_fetch<R, NP, NM>(prev, next, g, col, ylo, lo);
     at_fetch<R, NP, NM>(prev, next, g, col, y0, mid);
-    at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(y0 + 1, g.ny, g.bcy), hi);
+    at_fetch<R, NP, NM>(prev, next, g, col, yhi, hi);
+    R tlo = rowtt(ylo), tmid = rowtt(y0), thi = rowtt(yhi), tah = R(0);
     at_finish<R, NP, NM>(lo, h2);
     at_finish<R, NP, NM>(mid, h2);
     at_finish<R, NP, NM>(hi, h2);
     // y face between rows y0 - 1 and y0
     R jylo[NM] = {};
-    at_face<R, NP, NM>(lo.p, mid.p, lo.tx, mid.tx, lo.q, mid.q, lo.u, mid.u, c, jylo);
+    at_face<R, NP, NM, GEN>(lo.p, mid.p, lo.tx, mid.tx, lo.q, mid.q, lo.u, mid.u, c, jylo, x, tlo, tmid);
     for (int y = y0; y < y1; ++y) {
         // row y + 2, needed by the next pass (past the grid's ghost row it is
         // a clamped or wrapped row that goes unused)
-        const int ya = y + 2 < g.ny + 1 ? y + 2 : g.ny;
-        at_fetch<R, NP, NM>(prev, next, g, col, at_wrap(ya, g.ny, g.bcy), ahead);
+        const int ya = at_wrap(y + 2 < g.ny + 1 ? y + 2 : g.ny, g.ny, g.bcy);
+        at_fetch<R, NP, NM>(prev, next, g, col, ya, ahead);
+        if constexpr (GEN) tah = rowtt(ya);
         // x face between this lane's cell and the left neighbour, on row y
         R ty[NP], tyl[NP], pl[NP], ql[NP], ul[NM];
 #pragma unroll
@@ -237,9 +246,9 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
 #pragma unroll
         for (int k = 0; k < NM; ++k) ul[k] = lane_prev(mid.u[k]);
         R jxl[NM] = {};
-        at_face<R, NP, NM>(pl, mid.p, tyl, ty, ql, mid.q, ul, mid.u, c, jxl);
+        at_face<R, NP, NM, GEN>(pl, mid.p, tyl, ty, ql, mid.q, ul, mid.u, c, jxl, x, tmid, tmid);
         R jyhi[NM] = {};
-        at_face<R, NP, NM>(mid.p, hi.p, mid.tx, hi.tx, mid.q, hi.q, mid.u, hi.u, c, jyhi);
+        at_face<R, NP, NM, GEN>(mid.p, hi.p, mid.tx, hi.tx, mid.q, hi.q, mid.u, hi.u, c, jyhi, x, tmid, thi);
         // chi_k(phi^{n+1}) = sum_b h_b chi^b_k, h of Eq. hphi
         R hb[NP];
 #pragma unroll
@@ -250,44 +259,99 @@ __global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restric
             hb[b] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
         }
         const int64_t oc = (int64_t)y * g.nx + col;
+        if constexpr (GEN) {
+            R dv[NM], mn[NM];
 #pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            const R jxh = lane_next(jxl[k]);
-            if (own) {
-                R chik = R(0);
-#pragma unroll
-                for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
-                const R div = (jxh - jxl[k]) * c.rdx + (jyhi[k] - jylo[k]) * c.rdx;
-                next[(NP + k) * g.fstride + oc] = mid.m[k] - (c.dt * div) * fast_rcp(chik);
+            for (int k = 0; k < NM; ++k) {
+                const R jxh = lane_next(jxl[k]);
+                dv[k] = (jxh - jxl[k]) * c.rdx + (jyhi[k] - jylo[k]) * c.rdx;
+                mn[k] = mid.m[k];
+                jylo[k] = jyhi[k];
             }
-            jylo[k] = jyhi[k];
+            at_correct_gen<R, NP, NM>(hb, dv, c, *x, mn);
+            if (own) {
+#pragma unroll
+                for (int k = 0; k < NM; ++k) next[(NP + k) * g.fstride + oc] = mn[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NM; ++k) {
+                const R jxh = lane_next(jxl[k]);
+                if (own) {
+                    R chik = R(0);
+#pragma unroll
+                    for (int b = 0; b < NP; ++b) chik += hb[b] * c.chi[b][k];
+                    const R div = (jxh - jxl[k]) * c.rdx + (jyhi[k] - jylo[k]) * c.rdx;
+                    next[(NP + k) * g.fstride + oc] = mid.m[k] - (c.dt * div) * fast_rcp(chik);
+                }
+                jylo[k] = jyhi[k];
+            }
         }
         at_finish<R, NP, NM>(ahead, h2);
         lo = mid;
         mid = hi;
         hi = ahead;
+        if constexpr (GEN) {
+            tlo = tmid;
+            tmid = thi;
+            thi = tah;
+        }
     }
 }
 
-template <typename R>
-int at_launch2d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
-    if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1) return MP_E_PARAM;
+template <typename R, int NP, int NM>
+__global__ void __launch_bounds__(64 * AT_WAVES) k_antitrap2d(const R* __restrict__ prev, R* __restrict__ next,
+                                                              Geom g, AtCoef<R> c, int nstrips, int nitems) {
+    antitrap2d_strip<R, NP, NM, false>(prev, next, g, c, nstrips, nitems, nullptr, 0.0, 0.0);
+}
+
+// The extended model: the time level and temperature law as the step kernels take them.
+template <typename R, int NP, int NM>
+__global__ void __launch_bounds__(64 * AT_WAVES)
+k_antitrap2d_gen(const R* __restrict__ prev, R* __restrict__ next, Geom g, AtCoef<R> c, int nstrips, int nitems,
+                 CoefX<R> x, const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope) {
+    antitrap2d_strip<R, NP, NM, true>(prev, next, g, c, nstrips, nitems, &x, tb0 + tdn * (double)(*stepctr + kstep),
+                                      tslope);
+}
+
+// The time level and temperature law of the extended model's correction.
+struct AtTime {
+    const int64_t* stepctr;
+    int kstep;
+    double tb0, tdn, tslope;
+};
+
+template <typename R, int NP, int NM, bool GEN>
+void at_launch2d_kernel(const AtLaunch& L, const AtCoef<R>& c, const CoefX<R>* x, const AtTime* t, dim3 grid,
+                        dim3 block, int nstrips, int nitems, hipStream_t s) {
+    const R* prev = (const R*)L.prev;
+    R* next = (R*)L.next;
+    if constexpr (GEN)
+        hipLaunchKernelGGL((k_antitrap2d_gen<R, NP, NM>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems, *x,
+                           t->stepctr, t->kstep, t->tb0, t->tdn, t->tslope);
+    else
+        hipLaunchKernelGGL((k_antitrap2d<R, NP, NM>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
+}
+
+// GEN: the extended model, x and t its terms and time (unused otherwise).
+template <typename R, bool GEN = false>
+int at_launch2d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s, const CoefX<R>* x = nullptr,
+                const AtTime* t = nullptr) {
+    if (L.g.nz != 1 || L.g.nx < 1 || L.g.ny < 1 || (GEN && (!x || !t))) return MP_E_PARAM;
     const int nstrips = (L.g.nx + AT_LANES_OUT - 1) / AT_LANES_OUT;
     const int64_t items = (int64_t)nstrips * ((L.g.ny + AT_SEG - 1) / AT_SEG);
     if (items > INT32_MAX - AT_WAVES) return MP_E_PARAM;
     const int nitems = (int)items;
     dim3 block(64 * AT_WAVES);
     dim3 grid((unsigned)((nitems + AT_WAVES - 1) / AT_WAVES));
-    const R* prev = (const R*)L.prev;
-    R* next = (R*)L.next;
     if (L.nphases == 2 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap2d<R, 2, 1>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
+        at_launch2d_kernel<R, 2, 1, GEN>(L, c, x, t, grid, block, nstrips, nitems, s);
     else if (L.nphases == 2 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap2d<R, 2, 2>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
+        at_launch2d_kernel<R, 2, 2, GEN>(L, c, x, t, grid, block, nstrips, nitems, s);
     else if (L.nphases == 3 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap2d<R, 3, 1>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
+        at_launch2d_kernel<R, 3, 1, GEN>(L, c, x, t, grid, block, nstrips, nitems, s);
     else if (L.nphases == 3 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap2d<R, 3, 2>), grid, block, 0, s, prev, next, L.g, c, nstrips, nitems);
+        at_launch2d_kernel<R, 3, 2, GEN>(L, c, x, t, grid, block, nstrips, nitems, s);
     else
         return MP_E_PARAM;
     return hipGetLastError() == hipSuccess ? MP_OK : MP_E_HIP;

@@ -26,12 +26,14 @@ namespace mp {
 
 // Current of one face normal to axis AX between cells L and R: s and t are the
 // two cells' central differences (already x 1/(2 dx)) along the tangential axes
-// in increasing axis order.  Adds the face's j_k to j.
-template <typename R, int NP, int NM, int AX>
+// in increasing axis order.  Adds the face's j_k to j.  GEN: the extended
+// model's compositions (x its terms, ttL/ttR = T - Te of the two cells' rows).
+template <typename R, int NP, int NM, int AX, bool GEN = false>
 __device__ __forceinline__ void at_face3(const R (&pL)[NP], const R (&pR)[NP], const R (&sL)[NP], const R (&sR)[NP],
                                          const R (&tL)[NP], const R (&tR)[NP], const R (&qL)[NP],
                                          const R (&qR)[NP], const R (&uL)[NM], const R (&uR)[NM],
-                                         const AtCoef<R>& c, R (&j)[NM]) {
+                                         const AtCoef<R>& c, R (&j)[NM], const CoefX<R>* x = nullptr,
+                                         R ttL = R(0), R ttR = R(0)) {
     constexpr int LIQ = NP - 1;
     R u[3][NP];
 #pragma unroll
@@ -50,6 +52,21 @@ __device__ __forceinline__ void at_face3(const R (&pL)[NP], const R (&pR)[NP], c
         u[0][a] = gx * inv;
         u[1][a] = gy * inv;
         u[2][a] = gz * inv;
+    }
+    if constexpr (GEN) {
+        R cL[NP][NM], cR[NP][NM];
+        at_comp_gen<R, NP, NM>(uL, ttL, c, *x, cL);
+        at_comp_gen<R, NP, NM>(uR, ttR, c, *x, cR);
+#pragma unroll
+        for (int a = 0; a < NP - 1; ++a) {
+            const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
+            const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+            const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[AX][a] * weight;
+#pragma unroll
+            for (int k = 0; k < NM; ++k)
+                j[k] += common * (R(0.5) * (cL[a][k] + cR[a][k]) - R(0.5) * (cL[LIQ][k] + cR[LIQ][k]));
+        }
+        return;
     }
     R cl[NM];
 #pragma unroll
@@ -110,10 +127,11 @@ __device__ __forceinline__ void at3_dx(const R (&p)[NROW][NP], R h2, R (&t)[NROW
         for (int a = 0; a < NP; ++a) t[r][a] = (lane_next(p[r][a]) - lane_prev(p[r][a])) * h2;
 }
 
-template <typename R, int NP, int NM, int BY>
-__global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restrict__ prev, R* __restrict__ next,
-                                                               Geom g, AtCoef<R> c, int nstrips, int nygroups,
-                                                               int nitems) {
+// GEN: the extended model (x its terms, T - Te = tbase + tslope * row).
+template <typename R, int NP, int NM, int BY, bool GEN>
+__device__ __forceinline__ void antitrap3d_wave(const R* __restrict__ prev, R* __restrict__ next, const Geom& g,
+                                                const AtCoef<R>& c, int nstrips, int nygroups, int nitems,
+                                                const CoefX<R>* x, double tbase, double tslope) {
     const int nb = gridDim.x;
     const int q8 = nb / 8;
     const int b = blockIdx.x;
@@ -132,6 +150,11 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
     const int col = at_wrap(craw < g.nx ? craw : g.nx, g.nx, g.bcx);  // lanes past the right ghost repeat it
     const R h2 = R(0.5) * c.rdx;
     const int64_t fs = g.fstride;
+    // T - Te of the wave's rows y0-1 .. y0+BY (the extended model; T depends on y only)
+    R ttr[BY + 2];
+#pragma unroll
+    for (int r = 0; r < BY + 2; ++r)
+        ttr[r] = GEN ? (R)(tbase + tslope * (double)at_wrap(y0 - 1 + r, g.ny, g.bcy)) : R(0);
 
     At3Plane<R, NP, NM, BY> A, B, C, D;
     at3_fetch<R, NP, NM, BY>(prev, next, g, col, y0, z0 - 1, A);
@@ -154,8 +177,8 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
             }
 #pragma unroll
             for (int k = 0; k < NM; ++k) jzlo[r - 1][k] = R(0);
-            at_face3<R, NP, NM, 2>(A.p[r], B.p[r], txa[r], txb[r], tya, tyb, A.q[r], B.q[r], A.u[r], B.u[r], c,
-                                   jzlo[r - 1]);
+            at_face3<R, NP, NM, 2, GEN>(A.p[r], B.p[r], txa[r], txb[r], tya, tyb, A.q[r], B.q[r], A.u[r], B.u[r], c,
+                                        jzlo[r - 1], x, ttr[r], ttr[r]);
         }
     }
 
@@ -186,8 +209,8 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
         for (int r = 0; r <= BY; ++r) {
 #pragma unroll
             for (int k = 0; k < NM; ++k) jy[r][k] = R(0);
-            at_face3<R, NP, NM, 1>(B.p[r], B.p[r + 1], txm[r], txm[r + 1], tz[r], tz[r + 1], B.q[r], B.q[r + 1],
-                                   B.u[r], B.u[r + 1], c, jy[r]);
+            at_face3<R, NP, NM, 1, GEN>(B.p[r], B.p[r + 1], txm[r], txm[r + 1], tz[r], tz[r + 1], B.q[r],
+                                        B.q[r + 1], B.u[r], B.u[r + 1], c, jy[r], x, ttr[r], ttr[r + 1]);
         }
 #pragma unroll
         for (int r = 1; r <= BY; ++r) {
@@ -211,10 +234,11 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
             R jxl[NM], jzh[NM];
 #pragma unroll
             for (int k = 0; k < NM; ++k) jxl[k] = jzh[k] = R(0);
-            at_face3<R, NP, NM, 0>(pl, B.p[r], tyl, tym, tzl, tz[r], ql, B.q[r], ul, B.u[r], c, jxl);
+            at_face3<R, NP, NM, 0, GEN>(pl, B.p[r], tyl, tym, tzl, tz[r], ql, B.q[r], ul, B.u[r], c, jxl, x, ttr[r],
+                                        ttr[r]);
             // z face to plane m + 1
-            at_face3<R, NP, NM, 2>(B.p[r], C.p[r], txm[r], txc[r], tym, tyc, B.q[r], C.q[r], B.u[r], C.u[r], c,
-                                   jzh);
+            at_face3<R, NP, NM, 2, GEN>(B.p[r], C.p[r], txm[r], txc[r], tym, tyc, B.q[r], C.q[r], B.u[r], C.u[r], c,
+                                        jzh, x, ttr[r], ttr[r]);
             // chi_k(phi^{n+1}) = sum_b h_b chi^b_k, h of Eq. hphi
             R hb[NP];
 #pragma unroll
@@ -225,26 +249,63 @@ __global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restri
                 hb[a] = R(3) * f * f - R(2) * f * f * f + R(2) * f * cross;
             }
             const int yy = y0 + r - 1;
+            if constexpr (GEN) {
+                R dv[NM], mc[NM];
 #pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                const R jxh = lane_next(jxl[k]);
-                if (ownx && yy < g.ny) {
-                    R chik = R(0);
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) chik += hb[a] * c.chi[a][k];
+                for (int k = 0; k < NM; ++k) {
+                    const R jxh = lane_next(jxl[k]);
                     R div = R(0);
                     div += (jxh - jxl[k]) * c.rdx;
                     div += (jy[r][k] - jy[r - 1][k]) * c.rdx;
                     div += (jzh[k] - jzlo[r - 1][k]) * c.rdx;
-                    next[(NP + k) * fs + (zo + yy) * g.nx + col] = mn[r - 1][k] - (c.dt * div) * fast_rcp(chik);
+                    dv[k] = div;
+                    mc[k] = mn[r - 1][k];
+                    jzlo[r - 1][k] = jzh[k];
                 }
-                jzlo[r - 1][k] = jzh[k];
+                at_correct_gen<R, NP, NM>(hb, dv, c, *x, mc);
+                if (ownx && yy < g.ny) {
+#pragma unroll
+                    for (int k = 0; k < NM; ++k) next[(NP + k) * fs + (zo + yy) * g.nx + col] = mc[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NM; ++k) {
+                    const R jxh = lane_next(jxl[k]);
+                    if (ownx && yy < g.ny) {
+                        R chik = R(0);
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) chik += hb[a] * c.chi[a][k];
+                        R div = R(0);
+                        div += (jxh - jxl[k]) * c.rdx;
+                        div += (jy[r][k] - jy[r - 1][k]) * c.rdx;
+                        div += (jzh[k] - jzlo[r - 1][k]) * c.rdx;
+                        next[(NP + k) * fs + (zo + yy) * g.nx + col] = mn[r - 1][k] - (c.dt * div) * fast_rcp(chik);
+                    }
+                    jzlo[r - 1][k] = jzh[k];
+                }
             }
         }
         A = B;
         B = C;
         C = D;
     }
+}
+
+template <typename R, int NP, int NM, int BY>
+__global__ void __launch_bounds__(64 * AT3_WAVES) k_antitrap3d(const R* __restrict__ prev, R* __restrict__ next,
+                                                               Geom g, AtCoef<R> c, int nstrips, int nygroups,
+                                                               int nitems) {
+    antitrap3d_wave<R, NP, NM, BY, false>(prev, next, g, c, nstrips, nygroups, nitems, nullptr, 0.0, 0.0);
+}
+
+// The extended model: the time level and temperature law as the step kernels take them.
+template <typename R, int NP, int NM, int BY>
+__global__ void __launch_bounds__(64 * AT3_WAVES)
+k_antitrap3d_gen(const R* __restrict__ prev, R* __restrict__ next, Geom g, AtCoef<R> c, int nstrips, int nygroups,
+                 int nitems, CoefX<R> x, const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn,
+                 double tslope) {
+    antitrap3d_wave<R, NP, NM, BY, true>(prev, next, g, c, nstrips, nygroups, nitems, &x,
+                                         tb0 + tdn * (double)(*stepctr + kstep), tslope);
 }
 
 // Rows per wave: the planes held in registers grow with it (2 rows: 125 VGPRs
@@ -255,10 +316,24 @@ constexpr int at3_rows() {
     return sizeof(R) == 4 ? 2 : 1;
 }
 
-template <typename R>
-int at_launch3d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
+template <typename R, int NP, int NM, int BY, bool GEN>
+void at_launch3d_kernel(const AtLaunch& L, const AtCoef<R>& c, const CoefX<R>* x, const AtTime* t, dim3 grid,
+                        dim3 block, int nstrips, int nyg, int nitems, hipStream_t s) {
+    const R* prev = (const R*)L.prev;
+    R* next = (R*)L.next;
+    if constexpr (GEN)
+        hipLaunchKernelGGL((k_antitrap3d_gen<R, NP, NM, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg,
+                           nitems, *x, t->stepctr, t->kstep, t->tb0, t->tdn, t->tslope);
+    else
+        hipLaunchKernelGGL((k_antitrap3d<R, NP, NM, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg, nitems);
+}
+
+// GEN: the extended model, x and t its terms and time (unused otherwise).
+template <typename R, bool GEN = false>
+int at_launch3d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s, const CoefX<R>* x = nullptr,
+                const AtTime* t = nullptr) {
     constexpr int BY = at3_rows<R>();
-    if (L.g.nx < 1 || L.g.ny < 1 || L.g.nz < 1) return MP_E_PARAM;
+    if (L.g.nx < 1 || L.g.ny < 1 || L.g.nz < 1 || (GEN && (!x || !t))) return MP_E_PARAM;
     const int nstrips = (L.g.nx + AT3_LANES_OUT - 1) / AT3_LANES_OUT;
     const int nyg = (L.g.ny + BY - 1) / BY;
     const int64_t items = (int64_t)nstrips * nyg * ((L.g.nz + AT3_SEG - 1) / AT3_SEG);
@@ -266,16 +341,14 @@ int at_launch3d(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s) {
     const int nitems = (int)items;
     dim3 block(64 * AT3_WAVES);
     dim3 grid((unsigned)((nitems + AT3_WAVES - 1) / AT3_WAVES));
-    const R* prev = (const R*)L.prev;
-    R* next = (R*)L.next;
     if (L.nphases == 2 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap3d<R, 2, 1, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg, nitems);
+        at_launch3d_kernel<R, 2, 1, BY, GEN>(L, c, x, t, grid, block, nstrips, nyg, nitems, s);
     else if (L.nphases == 2 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap3d<R, 2, 2, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg, nitems);
+        at_launch3d_kernel<R, 2, 2, BY, GEN>(L, c, x, t, grid, block, nstrips, nyg, nitems, s);
     else if (L.nphases == 3 && L.nmu == 1)
-        hipLaunchKernelGGL((k_antitrap3d<R, 3, 1, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg, nitems);
+        at_launch3d_kernel<R, 3, 1, BY, GEN>(L, c, x, t, grid, block, nstrips, nyg, nitems, s);
     else if (L.nphases == 3 && L.nmu == 2)
-        hipLaunchKernelGGL((k_antitrap3d<R, 3, 2, BY>), grid, block, 0, s, prev, next, L.g, c, nstrips, nyg, nitems);
+        at_launch3d_kernel<R, 3, 2, BY, GEN>(L, c, x, t, grid, block, nstrips, nyg, nitems, s);
     else
         return MP_E_PARAM;
     return hipGetLastError() == hipSuccess ? MP_OK : MP_E_HIP;

@@ -28,6 +28,10 @@ template <typename R>
 int call_step_at(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, KernelCall& k);
 template <typename R>
 int call_step_at_gen(const StepLaunch& L, const Coef<R>& c, const AtCoef<R>& ac, const CoefX<R>& x, KernelCall& k);
+// antitrap_gen.hip: the correction kernels for the extended model
+template <typename R>
+int at_launch_gen(const AtLaunch& L, const AtCoef<R>& c, const CoefX<R>& x, const int64_t* stepctr, int kstep,
+                  double tb0, double tdn, double tslope, hipStream_t s);
 template <typename R>
 int call_batch_at(const BatchLaunch& L, const void* atab, KernelCall& k);
 }  // namespace mp
@@ -1008,8 +1012,18 @@ int step_antitrapping(mp_state* st, int64_t nsteps, hipStream_t s) {
         if (rc) return rc;
         A.prev = st->buf[st->cur];
         A.next = st->buf[1 - st->cur];
-        rc = st->precision == MP_FP64 ? mp::at_launch<double>(A, make_at_coef<double>(I), s)
-                                      : mp::at_launch<float>(A, make_at_coef<float>(I), s);
+        if (I.ext) {
+            double tb0, tdn, tslope;
+            temperature_law(I, tb0, tdn, tslope);
+            rc = st->precision == MP_FP64
+                     ? mp::at_launch_gen<double>(A, make_at_coef<double>(I), make_coefx<double>(I), dev_ctr(st), (int)i,
+                                                 tb0, tdn, tslope, s)
+                     : mp::at_launch_gen<float>(A, make_at_coef<float>(I), make_coefx<float>(I), dev_ctr(st), (int)i,
+                                                tb0, tdn, tslope, s);
+        } else {
+            rc = st->precision == MP_FP64 ? mp::at_launch<double>(A, make_at_coef<double>(I), s)
+                                          : mp::at_launch<float>(A, make_at_coef<float>(I), s);
+        }
         if (rc) return fail(rc, "anti-trapping kernel launch failed");
         st->cur = 1 - st->cur;
     }
@@ -1376,9 +1390,6 @@ int mp_set_antitrapping(mp_state* st, int on) {
     if (on < 0 || on > 2) return fail(MP_E_PARAM, "on must be 0, 1 or 2 (got %d)", on);
     if (on == 2 && st->batch)
         return fail(MP_E_STATE, "anti-trapping current: batched states take it folded into the step (on = 1) only");
-    if (on && st->inst[0].ext && (on == 2 || st->inst[0].grid.dim != 2))
-        return fail(MP_E_STATE, "anti-trapping current with the extended model: 2D grids with the current folded "
-                                "into the step (on = 1) only");
     drop_graphs(st);
     const int was = st->antitrap;
     st->antitrap = on;

@@ -5,8 +5,8 @@ obstacle with the multiplier over the active phases and per-pair relaxation
 constants (Eq. Obstacle, the Tau key of Sec. 5), off-diagonal curvatures and
 diffusivities (Eq. free_energy_density, Eq. Mass_conservation), in 2D (one and
 two steps per launch, graphs) and 3D, FP64 to 1e-10 and FP32 to 1e-4; the
-anti-trapping current of Eq. jatr with the extended model (2D, folded into the
-step); and the moving frame (SHIFT): the front row and the shift against the
+anti-trapping current of Eq. jatr with the extended model (2D folded into the
+step and as a correction kernel, bitwise equal; 3D); and the moving frame (SHIFT): the front row and the shift against the
 oracle's, and runs with shifts (with and without the current) against the
 oracle's runs in the shifted frame."""
 import zlib
@@ -212,38 +212,29 @@ def test_moving_frame_run_matches_oracle(fuse):
     assert errs(f, of) <= 1e-10 and errs(m, om) <= 1e-10
 
 
-def test_extended_model_refusals():
+def test_extended_model_switches():
     p = extended(dim=2, N=3, K=3, n=(32, 24, 1), bc=(0, 0, 0))
     with pytest.raises(abi.MPError) as e:
         abi.mp_create_batch([p, p])
     assert e.value.code == abi.MP_E_PARAM
     st = abi.mp_create(p)
     try:
-        # the current with the extended model: folded into the 2D step only
-        with pytest.raises(abi.MPError) as e:
-            abi.mp_set_antitrapping(st, 2)
-        assert e.value.code == abi.MP_E_STATE
-        abi.mp_set_antitrapping(st, True)
-        assert abi.mp_get_antitrapping(st) == 1
-    finally:
-        abi.mp_destroy(st)
-    st = abi.mp_create(extended(dim=3, N=3, K=3, n=(20, 13, 17), bc=(0, 1, 0)))
-    try:
-        with pytest.raises(abi.MPError) as e:
-            abi.mp_set_antitrapping(st, True)
-        assert e.value.code == abi.MP_E_STATE
+        # the anti-trapping current takes the extended model in both of its forms
+        for on in (2, 1, 0):
+            abi.mp_set_antitrapping(st, on)
+            assert abi.mp_get_antitrapping(st) == on
     finally:
         abi.mp_destroy(st)
 
 
-def run_gpu_at(p, phi, mu, nsteps, step0=0, graph=0):
+def run_gpu_at(p, phi, mu, nsteps, step0=0, graph=0, on=1):
     from paper_2404_01035_amd.solver import Solver
 
     s = Solver(p)
     try:
         if graph:
             s.set_graph(graph)
-        s.set_antitrapping(True)
+        s.set_antitrapping(on)
         s.load(phi, mu, step0)
         s.step(nsteps)
         return s.fields()
@@ -257,13 +248,12 @@ def oracle_run_at(phi, mu, n0, nsteps, p, y_origin=0):
     return phi, mu
 
 
-AT_CASES = [name for name in sorted(CASES) if name.startswith("2d")]
-
-
-@pytest.mark.parametrize("name", AT_CASES)
+@pytest.mark.parametrize("name", sorted(CASES))
 def test_fp64_extended_with_antitrapping_matches_oracle(name):
-    """The anti-trapping current folded into the general 2D step: compositions at
-    each row's temperature, the 2 x 2 susceptibility in the correction."""
+    """The anti-trapping current with the general kernels: compositions at each
+    row's temperature of time level n, the 2 x 2 susceptibility in the correction;
+    in 2D folded into the step and, bit for bit the same, by the step followed by
+    the correction kernel; in 3D by the correction kernel."""
     kw, steps = CASES[name]
     steps = min(steps, 120)
     p = extended(seed=zlib.crc32(name.encode()) % 1000, **kw)
@@ -276,6 +266,9 @@ def test_fp64_extended_with_antitrapping_matches_oracle(name):
     assert errs(f, of) <= 1e-10
     assert errs(m, om) <= 1e-10
     assert errs(om, pm) > 1e-6
+    if p.dim == 2:
+        f2, m2 = run_gpu_at(p, phi, mu, steps, step0=7, on=2)
+        assert np.array_equal(f2, f) and np.array_equal(m2, m)
 
 
 def test_fp32_extended_with_antitrapping_and_graphs():
