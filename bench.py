@@ -70,6 +70,19 @@ TRAFFIC = {
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
+    # profiles/k_step2d_at_eutectic_4096_f64_f32.md
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "ced584c5b48970ff",
+                "bytes": (2.0 * 416826.7 + 659186.5) * 1024},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "ced584c5b48970ff",
+                "bytes": (2.0 * 247552.7 + 331791.2) * 1024},
+    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899",
+               "bytes": (2.0 * 870583.4 + 270298.6) * 1024},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899",
+               "bytes": (2.0 * 462431.8 + 140617.0) * 1024},
+    # profiles/k_antitrap3d_dendrite_512_f32.md
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "30588acb0539565b",
+                 "bytes": (2.0 * 2724874.4 + 574835.7) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
@@ -215,6 +228,14 @@ VALU = {
     "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d", "insts": 173801142.0},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444", "insts": 545827325.3},
+    # profiles/k_step2d_at_eutectic_4096_f64_f32.md
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "ced584c5b48970ff", "insts": 203122347.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "ced584c5b48970ff", "insts": 145416750.0},
+    # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899", "insts": 106811674.0},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899", "insts": 78199324.0},
+    # profiles/k_antitrap3d_dendrite_512_f32.md
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "30588acb0539565b", "insts": 654651392.0},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
 }

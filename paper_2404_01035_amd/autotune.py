@@ -4,7 +4,8 @@ The library times each candidate -- tile (bx, seg, vec) and steps per launch --
 on the bound state itself (``mp_tune``: launches from the current buffer into
 the other, repeated, with events on the stream) and keeps the fastest per step.  The choice is cached per
 workload signature -- grid, phases, components, precision, potential,
-anisotropy, batch composition and device name -- in a JSON file, so later runs
+anisotropy, the extended model, the anti-trapping current's form, batch
+composition and device name -- in a JSON file, so later runs
 of the same workload set the tile without timing.  Results never depend on the
 tile (bitwise), only speed does.
 """
@@ -14,6 +15,8 @@ import hashlib
 import json
 import os
 import tempfile
+
+import numpy as np
 
 from . import abi
 
@@ -27,18 +30,26 @@ def default_cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2404_01035_amd", "tiles.json")
 
 
+def _extended(p) -> bool:
+    """Whether p uses the extended model (the general kernels)."""
+    return bool(p.potential == "obstacle_active" or any(
+        np.any(np.asarray(v) != 0) for v in (p.Bt, p.Ct, p.A01, p.D01, p.tau_ab)))
+
+
 def _one(p) -> list:
-    return [p.dim, list(p.n), p.nphases, p.ncomp, bool(abs(p.delta).max() > 0)]
+    return [p.dim, list(p.n), p.nphases, p.ncomp, bool(abs(p.delta).max() > 0), _extended(p)]
 
 
-def signature(plist, device: str) -> str:
-    """Cache key of a single (len 1) or batched workload on ``device``."""
+def signature(plist, device: str, antitrapping: int = 0) -> str:
+    """Cache key of a single (len 1) or batched workload on ``device``
+    (``antitrapping``: the state's mp_get_antitrapping value; it selects other kernels)."""
     p0 = plist[0]
     body = {
         "kind": "batch" if len(plist) > 1 else "single",
         "precision": p0.precision,
         "potential": p0.potential,
         "device": device,
+        "antitrapping": int(antitrapping),
     }
     if len(plist) == 1:
         body["grid"] = _one(p0)
@@ -74,7 +85,7 @@ def tune(st, plist, stream: int, device: str, reps: int = 10, cache: str | None 
     "ms": {"bx,seg,vec,fuse": ms per step}}.
     """
     path = cache or default_cache_path()
-    key = signature(plist, device)
+    key = signature(plist, device, abi.mp_get_antitrapping(st))
     data = _load(path)
     hit = data.get(key)
     if hit and not force:

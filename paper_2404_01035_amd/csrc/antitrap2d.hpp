@@ -86,38 +86,29 @@ __device__ inline void at_face(const R* pL, const R* pR, const R* tL, const R* t
         un[a] = gn * inv;
         ut[a] = gt * inv;
     }
+    // The compositions are affine in mu (and B^a(T) in T), so the mean of the
+    // two cells' compositions is the composition at the mean mu (and T).
+    R ub[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) ub[k] = R(0.5) * (uL[k] + uR[k]);
+    R cb[NP][NM];
     if constexpr (GEN) {
-        R cL[NP][NM], cR[NP][NM];
-        at_comp_gen<R, NP, NM>(uL, ttL, c, *x, cL);
-        at_comp_gen<R, NP, NM>(uR, ttR, c, *x, cR);
+        at_comp_gen<R, NP, NM>(ub, R(0.5) * (ttL + ttR), c, *x, cb);
+    } else {
 #pragma unroll
-        for (int a = 0; a < NP - 1; ++a) {
-            const R weight = -(un[a] * un[LIQ] + ut[a] * ut[LIQ]);
-            const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
-            const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * un[a] * weight;
+        for (int a = 0; a < NP; ++a)
 #pragma unroll
-            for (int k = 0; k < NM; ++k) {
-                const R ca = R(0.5) * (cL[a][k] + cR[a][k]);
-                const R cl = R(0.5) * (cL[LIQ][k] + cR[LIQ][k]);
-                j[k] += common * (ca - cl);
-            }
-        }
-        return;
+            for (int k = 0; k < NM; ++k) cb[a][k] = c.chi[a][k] * (ub[k] - c.B[a][k]);
     }
-    R cl[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k)
-        cl[k] = R(0.5) * (c.chi[LIQ][k] * (uL[k] - c.B[LIQ][k]) + c.chi[LIQ][k] * (uR[k] - c.B[LIQ][k]));
+    // dphi/dt of the face: (mean phi^{n+1} - mean phi^n) / dt
+    const R hrdt = R(0.5) * c.rdt;
 #pragma unroll
     for (int a = 0; a < NP - 1; ++a) {
         const R weight = -(un[a] * un[LIQ] + ut[a] * ut[LIQ]);
-        const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+        const R rate = ((qL[a] + qR[a]) - (pL[a] + pR[a])) * hrdt;
         const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * un[a] * weight;
 #pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            const R ca = R(0.5) * (c.chi[a][k] * (uL[k] - c.B[a][k]) + c.chi[a][k] * (uR[k] - c.B[a][k]));
-            j[k] += common * (ca - cl[k]);
-        }
+        for (int k = 0; k < NM; ++k) j[k] += common * (cb[a][k] - cb[LIQ][k]);
     }
 }
 

@@ -53,35 +53,27 @@ __device__ __forceinline__ void at_face3(const R (&pL)[NP], const R (&pR)[NP], c
         u[1][a] = gy * inv;
         u[2][a] = gz * inv;
     }
+    // the composition at the mean mu (and T) is the mean composition (at_face)
+    R ub[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) ub[k] = R(0.5) * (uL[k] + uR[k]);
+    R cb[NP][NM];
     if constexpr (GEN) {
-        R cL[NP][NM], cR[NP][NM];
-        at_comp_gen<R, NP, NM>(uL, ttL, c, *x, cL);
-        at_comp_gen<R, NP, NM>(uR, ttR, c, *x, cR);
+        at_comp_gen<R, NP, NM>(ub, R(0.5) * (ttL + ttR), c, *x, cb);
+    } else {
 #pragma unroll
-        for (int a = 0; a < NP - 1; ++a) {
-            const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
-            const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
-            const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[AX][a] * weight;
+        for (int a = 0; a < NP; ++a)
 #pragma unroll
-            for (int k = 0; k < NM; ++k)
-                j[k] += common * (R(0.5) * (cL[a][k] + cR[a][k]) - R(0.5) * (cL[LIQ][k] + cR[LIQ][k]));
-        }
-        return;
+            for (int k = 0; k < NM; ++k) cb[a][k] = c.chi[a][k] * (ub[k] - c.B[a][k]);
     }
-    R cl[NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k)
-        cl[k] = R(0.5) * (c.chi[LIQ][k] * (uL[k] - c.B[LIQ][k]) + c.chi[LIQ][k] * (uR[k] - c.B[LIQ][k]));
+    const R hrdt = R(0.5) * c.rdt;
 #pragma unroll
     for (int a = 0; a < NP - 1; ++a) {
         const R weight = -((u[0][a] * u[0][LIQ] + u[1][a] * u[1][LIQ]) + u[2][a] * u[2][LIQ]);
-        const R rate = (R(0.5) * (qL[a] + qR[a]) - R(0.5) * (pL[a] + pR[a])) * c.rdt;
+        const R rate = ((qL[a] + qR[a]) - (pL[a] + pR[a])) * hrdt;
         const R common = at_prefactor(R(0.5) * (pL[a] + pR[a]), c) * rate * u[AX][a] * weight;
 #pragma unroll
-        for (int k = 0; k < NM; ++k) {
-            const R ca = R(0.5) * (c.chi[a][k] * (uL[k] - c.B[a][k]) + c.chi[a][k] * (uR[k] - c.B[a][k]));
-            j[k] += common * (ca - cl[k]);
-        }
+        for (int k = 0; k < NM; ++k) j[k] += common * (cb[a][k] - cb[LIQ][k]);
     }
 }
 

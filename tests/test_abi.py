@@ -301,6 +301,14 @@ def test_autotune_signature_distinguishes_workloads():
     assert a != autotune.signature([q], "dev") and a != autotune.signature([p], "other")
     members = [m[0] for m in inputs.config_c4(ninst=3, side=(64, 80))]
     assert autotune.signature(members, "dev") != autotune.signature(members[:2], "dev")
+    # the anti-trapping current's form and the extended model select other kernels
+    assert a != autotune.signature([p], "dev", antitrapping=1)
+    assert autotune.signature([p], "dev", 1) != autotune.signature([p], "dev", 2)
+    e = p.copy()
+    e.Bt[0, 0] = 0.1
+    assert a != autotune.signature([e], "dev")
+    e = p.copy(potential="obstacle_active")
+    assert autotune.signature([e], "dev") != autotune.signature([p.copy(potential="obstacle")], "dev")
 
 
 def test_fusion_setting_validation_without_gpu():
