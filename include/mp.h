@@ -291,8 +291,11 @@ int mp_set_graph(mp_state* st, int chunk);
  * potential.  One state buffer holds every instance's state, each at a
  * 256-byte aligned offset (mp_instance_offset) in the single-state layout.
  * mp_step advances every instance by the same number of steps, each with its
- * own dt; mp_diagnostics_batch reduces each instance.  Errors: as mp_create,
- * plus MP_E_PARAM for ninst < 1, a 3D grid, or mixed precision/potential. */
+ * own dt; mp_diagnostics_batch reduces each instance.  When one instance uses
+ * the extended model (Bt, Ct, A01, D01, tau_ab, MP_OBSTACLE_ACTIVE) every
+ * instance is stepped with the general kernels (bitwise as a single grid of
+ * the extended model would be).  Errors: as mp_create, plus MP_E_PARAM for
+ * ninst < 1, a 3D grid, or mixed precision/potential. */
 int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const int* ncomp,
                     const mp_params* params, mp_state** out);
 

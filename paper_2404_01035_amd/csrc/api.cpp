@@ -34,6 +34,11 @@ int at_launch_gen(const AtLaunch& L, const AtCoef<R>& c, const CoefX<R>& x, cons
                   double tb0, double tdn, double tslope, hipStream_t s);
 template <typename R>
 int call_batch_at(const BatchLaunch& L, const void* atab, KernelCall& k);
+// batch_gen.hip: the batch of the extended model, plain and with the current
+template <typename R>
+int call_batch_gen(const BatchLaunch& L, const void* xtab, KernelCall& k);
+template <typename R>
+int call_batch_at_gen(const BatchLaunch& L, const void* atab, const void* xtab, KernelCall& k);
 }  // namespace mp
 
 namespace {
@@ -442,7 +447,7 @@ int strips_of(const mp_state* st, const Inst& I) {
 
 // ---- workspace layout -------------------------------------------------------
 // [diag partials + one result record per instance][time level][instance table][work list]
-// [anti-trapping coefficient table]
+// [anti-trapping coefficient table][extended-model coefficient table]
 size_t ws_diag_bytes(const mp_state* st) {
     return align_up((size_t)(mp::DIAG_BLOCKS_MAX + st->inst.size()) * mp::DIAG_VALS * sizeof(double));
 }
@@ -465,6 +470,17 @@ size_t ws_attab_off(const mp_state* st) { return ws_items_off(st) + align_up(2 *
 size_t attab_bytes(const mp_state* st) {
     const size_t one = st->precision == MP_FP64 ? sizeof(mp::AtCoef<double>) : sizeof(mp::AtCoef<float>);
     return st->batch ? align_up(one * st->inst.size()) : 0;
+}
+size_t ws_xtab_off(const mp_state* st) { return ws_attab_off(st) + attab_bytes(st); }
+size_t xtab_bytes(const mp_state* st) {
+    const size_t one = st->precision == MP_FP64 ? sizeof(mp::CoefX<double>) : sizeof(mp::CoefX<float>);
+    return st->batch ? align_up(one * st->inst.size()) : 0;
+}
+// A batch with an instance of the extended model steps every instance with the general kernels.
+bool batch_gen(const mp_state* st) {
+    for (const Inst& I : st->inst)
+        if (I.ext) return true;
+    return false;
 }
 
 int64_t* dev_ctr(mp_state* st) { return (int64_t*)((char*)st->ws + ws_ctr_off(st)); }
@@ -572,6 +588,8 @@ int upload_table(mp_state* st) {
     }
     std::vector<mp::AtCoef<R>> atab(st->inst.size());
     for (size_t i = 0; i < st->inst.size(); ++i) atab[i] = make_at_coef<R>(st->inst[i]);
+    std::vector<mp::CoefX<R>> xtab(st->inst.size());
+    for (size_t i = 0; i < st->inst.size(); ++i) xtab[i] = make_coefx<R>(st->inst[i]);
     char* ws = (char*)st->ws;
     int rc = hip_check(hipMemcpy(ws + ws_table_off(st), tab.data(),
                                  sizeof(mp::InstDesc<R>) * tab.size(), hipMemcpyHostToDevice),
@@ -580,6 +598,10 @@ int upload_table(mp_state* st) {
         rc = hip_check(hipMemcpy(ws + ws_attab_off(st), atab.data(), sizeof(mp::AtCoef<R>) * atab.size(),
                                  hipMemcpyHostToDevice),
                        "anti-trapping table upload");
+    if (rc == MP_OK)
+        rc = hip_check(hipMemcpy(ws + ws_xtab_off(st), xtab.data(), sizeof(mp::CoefX<R>) * xtab.size(),
+                                 hipMemcpyHostToDevice),
+                       "extended-model table upload");
     return rc;
 }
 
@@ -598,11 +620,16 @@ int launch_fuse(const mp_state* st) { return st->antitrap ? 1 : st->fuse; }
 
 // The batched kernel for L: with the current folded in while it is on.
 int batch_call(mp_state* st, const mp::BatchLaunch& L, mp::KernelCall& k) {
-    if (st->antitrap) {
-        const void* atab = (const char*)st->ws + ws_attab_off(st);
-        return st->precision == MP_FP64 ? mp::call_batch_at<double>(L, atab, k) : mp::call_batch_at<float>(L, atab, k);
+    const void* atab = (const char*)st->ws + ws_attab_off(st);
+    const void* xtab = (const char*)st->ws + ws_xtab_off(st);
+    const bool f64 = st->precision == MP_FP64;
+    if (batch_gen(st)) {
+        if (st->antitrap)
+            return f64 ? mp::call_batch_at_gen<double>(L, atab, xtab, k) : mp::call_batch_at_gen<float>(L, atab, xtab, k);
+        return f64 ? mp::call_batch_gen<double>(L, xtab, k) : mp::call_batch_gen<float>(L, xtab, k);
     }
-    return st->precision == MP_FP64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
+    if (st->antitrap) return f64 ? mp::call_batch_at<double>(L, atab, k) : mp::call_batch_at<float>(L, atab, k);
+    return f64 ? mp::call_batch<double>(L, k) : mp::call_batch<float>(L, k);
 }
 
 int choose_batch_blocks(mp_state* st) {
@@ -1091,9 +1118,6 @@ int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const i
             rc = fail(MP_E_PARAM, "%sall instances must share one precision", who);
         if (rc == MP_OK && i > 0 && params[i].potential != params[0].potential)
             rc = fail(MP_E_PARAM, "%sall instances must share one potential", who);
-        if (rc == MP_OK && uses_extended(nphases[i], ncomp[i], params[i]))
-            rc = fail(MP_E_PARAM, "%sbatched states take the base model only (no Bt, Ct, A01, D01, tau_ab, "
-                      "MP_OBSTACLE_ACTIVE)", who);
         if (rc) {
             delete st;
             return rc;
@@ -1118,7 +1142,7 @@ size_t mp_state_bytes(const mp_state* st) {
 
 size_t mp_workspace_bytes(const mp_state* st) {
     if (!st) return 0;
-    return ws_attab_off(st) + attab_bytes(st);
+    return ws_xtab_off(st) + xtab_bytes(st);
 }
 
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace) {

@@ -214,9 +214,6 @@ def test_moving_frame_run_matches_oracle(fuse):
 
 def test_extended_model_switches():
     p = extended(dim=2, N=3, K=3, n=(32, 24, 1), bc=(0, 0, 0))
-    with pytest.raises(abi.MPError) as e:
-        abi.mp_create_batch([p, p])
-    assert e.value.code == abi.MP_E_PARAM
     st = abi.mp_create(p)
     try:
         # the anti-trapping current takes the extended model in both of its forms
@@ -308,3 +305,77 @@ def test_moving_frame_with_antitrapping_matches_oracle():
     print(f"moving frame with the current: offset {off}, phi {errs(f, of):.3e} mu {errs(m, om):.3e}")
     assert off == ooff and off > 0
     assert errs(f, of) <= 1e-10 and errs(m, om) <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Batches of the extended model
+# ----------------------------------------------------------------------------
+
+def _ext_members(precision="f64"):
+    """Uneven 2D instances of the extended model sharing one potential (multi-well)."""
+    out = []
+    specs = [dict(N=3, K=3, n=(130, 70, 1), bc=(0, 1, 0)),
+             dict(N=3, K=3, n=(90, 64, 1), bc=(0, 1, 0), offdiag=False, tau_pairs=False),
+             dict(N=3, K=3, n=(77, 50, 1), bc=(0, 0, 0), slopes=False, tau_pairs=False),
+             dict(N=3, K=2, n=(70, 45, 1), bc=(1, 1, 0), tau_pairs=False),
+             dict(N=2, K=3, n=(66, 61, 1), bc=(1, 0, 0))]
+    for i, kw in enumerate(specs):
+        p = extended(dim=2, seed=40 + i, precision=precision, **kw)
+        phi, mu = nuclei(p, seed=50 + i)
+        out.append((p, phi, mu))
+    return out
+
+
+def _batch_ext(members, nsteps, step0=0, on=0, fuse=None, vec=0):
+    from paper_2404_01035_amd.solver import BatchSolver
+
+    b = BatchSolver([m[0] for m in members])
+    try:
+        if fuse:
+            abi.mp_set_fusion(b.st, fuse)
+        if vec:
+            b.set_tile(0, vec)
+        if on:
+            b.set_antitrapping(on)
+        for i, (_, phi, mu) in enumerate(members):
+            b.load(i, phi, mu)
+        b.start(step0)
+        b.step(nsteps)
+        return [b.fields(i) for i in range(len(members))]
+    finally:
+        b.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_of_the_extended_model_is_bitwise_the_single_grid(precision):
+    """Each instance of an extended-model batch against the same instance stepped
+    alone: two steps per launch, one, two cells per lane (two strips per item),
+    and with the anti-trapping current."""
+    members = _ext_members(precision)
+    steps = 24
+    refs = [run_gpu(p, phi, mu, steps, step0=5, fuse=2) for (p, phi, mu) in members]
+    for fuse, vec in [(2, 0), (1, 0), (2, 2)]:
+        print(f"extended batch {precision}: fuse {fuse} vec {vec}", flush=True)
+        got = _batch_ext(members, steps, step0=5, fuse=fuse, vec=vec)
+        for i in range(len(members)):
+            assert np.array_equal(got[i][0], refs[i][0]), (fuse, vec, i)
+            assert np.array_equal(got[i][1], refs[i][1]), (fuse, vec, i)
+    refs = [run_gpu_at(p, phi, mu, steps, step0=5) for (p, phi, mu) in members]
+    got = _batch_ext(members, steps, step0=5, on=1)
+    for i in range(len(members)):
+        assert np.array_equal(got[i][0], refs[i][0]), ("current", i)
+        assert np.array_equal(got[i][1], refs[i][1]), ("current", i)
+
+
+def test_batch_of_the_extended_model_matches_oracle_fp64():
+    members = _ext_members("f64")
+    steps = 60
+    got = _batch_ext(members, steps, step0=5)
+    got_at = _batch_ext(members, steps, step0=5, on=1)
+    for i, (p, phi, mu) in enumerate(members):
+        of, om = gp.run(phi, mu, 5, steps, p)
+        af, am = oracle_run_at(phi, mu, 5, steps, p)
+        print(f"instance {i}: phi {errs(got[i][0], of):.3e} mu {errs(got[i][1], om):.3e}; with the current "
+              f"phi {errs(got_at[i][0], af):.3e} mu {errs(got_at[i][1], am):.3e}", flush=True)
+        assert errs(got[i][0], of) <= 1e-10 and errs(got[i][1], om) <= 1e-10, i
+        assert errs(got_at[i][0], af) <= 1e-10 and errs(got_at[i][1], am) <= 1e-10, i
