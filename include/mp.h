@@ -153,8 +153,8 @@ double mp_dt_limit(const mp_grid* grid, int nphases, int ncomp, const mp_params*
  * nphases N in {2, 3}; ncomp K in {2, 3} (K - 1 diffusion potentials).  A
  * problem that uses the extended model (non-zero Bt, Ct, A01, D01 or tau_ab, or
  * MP_OBSTACLE_ACTIVE) runs the general kernels: one cell per lane in 2D and
- * 64 x 4 tiles in 3D whatever mp_set_tile says; batched states, the adjoint
- * and the anti-trapping current do not take it.
+ * 64 x 4 tiles in 3D whatever mp_set_tile says (batched instances too, and
+ * with the anti-trapping current); the adjoint does not take it.
  * Errors: MP_E_NULLPTR, MP_E_PARAM (dim, n, bc, dx, N, K, precision,
  * potential, eps, tau, A, D, gamma, delta or an extended coefficient out of
  * range), MP_E_UNSTABLE. */
