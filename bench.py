@@ -59,32 +59,32 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "0423d2dfcc88a0c9",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "f86898c84c213454",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "574e93117ae98038",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5fb89be603452a04",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4dd4573c704e1d7e",
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "61097bfcf3b534b5",
                   "bytes": (2.0 * 385370.7 + 658378.8) * 1024},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d",
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "142350a8e9137e5d",
                   "bytes": (2.0 * 225018.1 + 331609.6) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "85ca83f1ab392ead",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "ced584c5b48970ff",
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "833c3e0a6559514a",
                 "bytes": (2.0 * 416826.7 + 659186.5) * 1024},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "ced584c5b48970ff",
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "833c3e0a6559514a",
                 "bytes": (2.0 * 247552.7 + 331791.2) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899",
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2",
                "bytes": (2.0 * 870583.4 + 270298.6) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899",
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2",
                "bytes": (2.0 * 462431.8 + 140617.0) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "30588acb0539565b",
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "f27333f9b37b87ce",
                  "bytes": (2.0 * 2724874.4 + 574835.7) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "ba50631a53c3ae66",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
@@ -126,17 +126,17 @@ def log(msg):
 # The device sources each leg's step kernel is built from.
 _COMMON = ["mp_internal.hpp", "gp_device.hpp"]
 LEG_SOURCES = {
-    "c2_f64": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
-    "c2_f32": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
-    "c2ext_f64": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_gen_f64_2d.hip"],
-    "c2ext_f32": _COMMON + ["step2d.hpp", "step_dispatch.hpp", "step_gen_f32_2d.hip"],
-    "c3": _COMMON + ["step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
-    "c4": _COMMON + ["step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
+    "c2_f64": _COMMON + ["diag_cell.hpp", "step2d.hpp", "step_dispatch.hpp", "step_f64_2d.hip"],
+    "c2_f32": _COMMON + ["diag_cell.hpp", "step2d.hpp", "step_dispatch.hpp", "step_f32_2d.hip"],
+    "c2ext_f64": _COMMON + ["diag_cell.hpp", "step2d.hpp", "step_dispatch.hpp", "step_gen_f64_2d.hip"],
+    "c2ext_f32": _COMMON + ["diag_cell.hpp", "step2d.hpp", "step_dispatch.hpp", "step_gen_f32_2d.hip"],
+    "c3": _COMMON + ["diag_cell.hpp", "step3d.hpp", "step_dispatch.hpp", "step_f32_3d.hip"],
+    "c4": _COMMON + ["diag_cell.hpp", "step2d.hpp", "batch2d.hpp", "batch_f32.hip"],
     "at_f64": _COMMON + ["antitrap2d.hpp", "antitrap.hip"],
     "at_f32": _COMMON + ["antitrap2d.hpp", "antitrap.hip"],
     "at3d_f32": _COMMON + ["antitrap2d.hpp", "antitrap3d.hpp", "antitrap.hip"],
-    "atf_f64": _COMMON + ["step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
-    "atf_f32": _COMMON + ["step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
+    "atf_f64": _COMMON + ["diag_cell.hpp", "step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
+    "atf_f32": _COMMON + ["diag_cell.hpp", "step2d.hpp", "antitrap2d.hpp", "step2d_at.hpp", "step_at.hip"],
 }
 # The 3D correction kernel's FP32 strip shape (columns written per wave, rows per wave, cells per lane).
 AT3D_TILE = [62, 2, 1]
@@ -222,22 +222,22 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
 VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "0423d2dfcc88a0c9", "insts": 153857451.0},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "574e93117ae98038", "insts": 138111444.0},
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4dd4573c704e1d7e", "insts": 236893983.0},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "a47157be335cd55d", "insts": 173801142.0},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "f86898c84c213454", "insts": 153857451.0},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5fb89be603452a04", "insts": 138111444.0},
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "61097bfcf3b534b5", "insts": 236893983.0},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "142350a8e9137e5d", "insts": 173801142.0},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "2d98a31657953444", "insts": 545827325.3},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "85ca83f1ab392ead", "insts": 545827325.3},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "ced584c5b48970ff", "insts": 203122347.0},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "ced584c5b48970ff", "insts": 145416750.0},
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "833c3e0a6559514a", "insts": 203122347.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "833c3e0a6559514a", "insts": 145416750.0},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899", "insts": 106811674.0},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "6a2311bc8c60f899", "insts": 78199324.0},
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2", "insts": 106811674.0},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2", "insts": 78199324.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "30588acb0539565b", "insts": 654651392.0},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "f27333f9b37b87ce", "insts": 654651392.0},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "f873b245f65a4d68", "insts": 468028690.0},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "ba50631a53c3ae66", "insts": 468028690.0},
 }
 VALU_CYCLES = {"f64": 4, "f32": 2}
 SIMDS = 1024         # 256 CUs x 4 SIMDs
@@ -379,6 +379,30 @@ def copy_calibration(n, steps):
                       "frac_of_8TBs": gbs / HBM_PEAK_GBS}), flush=True)
 
 
+def diag_timing(s, fuse, reps=REGIONS):
+    """One launch of ``fuse`` steps followed by the diagnostics of the state
+    reached: the separate reduction pass (mp_step + mp_diagnostics) against the
+    partial sums formed inside the step launch (mp_step_diag).  Both end in the
+    same host synchronisation and copy; median of ``reps`` event-timed calls."""
+    def separate():
+        s.step(fuse)
+        s.diagnostics()
+
+    def fused():
+        s.step_diag(fuse)
+
+    out = {"steps": fuse}
+    for name, fn in (("separate_ms", separate), ("fused_ms", fused)):
+        fn()
+        ms = []
+        for _ in range(reps):
+            with Timer() as t:
+                fn()
+            ms.append(t.ms)
+        out[name] = round(sorted(ms)[reps // 2], 4)
+    return out
+
+
 def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
     """The 4096^2 eutectic; slopes: with temperature-dependent coefficients
     (the general kernels of the extended model)."""
@@ -402,6 +426,7 @@ def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
     fuse = abi.mp_get_fusion(s.st)
     ms, regions, settle = measure(s.step, steps, warmup)
     d = s.diagnostics()
+    dt = None if slopes else diag_timing(s, fuse)
     s.close()
     elem = 8 if precision == "f64" else 4
     bpc = p.nfields * 2 * elem  # read + write of every field once
@@ -423,6 +448,7 @@ def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
         "algorithmic_bytes_per_launch": fuse * p.ncells * bpc,
         "tile": {"bx": used[0], "seg": used[1], "vec": used[2], "source": source},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
+        **({"diag_timing": dt} if dt else {}),
     }
 
 
@@ -534,6 +560,7 @@ def leg_c3(n, steps, warmup, tile, tune):
     used = list(abi.mp_get_tile(s.st))
     ms, regions, settle = measure(s.step, steps, warmup)
     d = s.diagnostics()
+    dt = diag_timing(s, 1)
     s.close()
     bpc = p.nfields * 2 * 4
     fpc = flops_per_cell_update(p.nphases, p.ncomp, dim=3, aniso=True)
@@ -555,6 +582,7 @@ def leg_c3(n, steps, warmup, tile, tune):
         "algorithmic_bytes_per_launch": p.ncells * bpc,
         "tile": {"bx": used[0], "seg": used[1], "vec": used[2]},
         "diag": {"max_sum_dev": d["max_sum_dev"], "nonfinite": d["nonfinite"]},
+        "diag_timing": dt,
     }
 
 
@@ -817,6 +845,7 @@ def main():
         "algorithmic_bytes_per_launch": r64["algorithmic_bytes_per_launch"],
         "tile": r64["tile"],
         "diag": r64["diag"],
+        "diag_timing": r64.get("diag_timing"),
         "cpu_baseline": None,
     }
     if "c2" in legs:

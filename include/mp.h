@@ -167,8 +167,10 @@ size_t mp_workspace_bytes(const mp_state* st);
 
 /* Attach caller-owned device buffers: buf0 and buf1 each mp_state_bytes()
  * long, 256-byte aligned; workspace mp_workspace_bytes() long (reduction
- * partial sums, the device copy of the time level and, for a batch, the
- * instance table, the work list and the anti-trapping coefficients).  buf0 is the current buffer afterwards and the time level
+ * partial sums, the device copy of the time level, for a single grid the
+ * partial records of mp_step_diag (at most 8 MiB) and, for a batch, the
+ * instance table, the work list and the anti-trapping and extended-model
+ * coefficients).  buf0 is the current buffer afterwards and the time level
  * is reset to 0 (use mp_set_step to resume).  Needs the GPU: it writes the
  * workspace with a synchronous copy. */
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace);
@@ -193,6 +195,25 @@ int mp_set_step(mp_state* st, int64_t step, int which_buf);
  * Returns MP_E_NONFINITE (with *out filled) when a NaN/Inf is present, and
  * MP_E_STATE for a batched state (use mp_diagnostics_batch). */
 int mp_diagnostics(mp_state* st, mp_diag* out, void* stream);
+
+/* Advance nsteps >= 1 steps as mp_step does, then reduce the state reached
+ * into *out with the diagnostics' partial sums formed inside the last step
+ * launch from the values it stores, so the state is not read again (the
+ * global checks of Sec. 2.1: the constraint sum_a phi_a = 1, the solute of the
+ * composition constraint, phase volumes, the susceptibility).  The fields are
+ * those of mp_diagnostics: max_sum_dev, min_chi and nonfinite equal its values
+ * bit for bit; mass and volume agree with them to rounding (FP64 Neumaier
+ * partial sums grouped by the step kernel's strips or tiles, reproducible run
+ * to run for one tile shape).  The state after the call is bitwise that of
+ * mp_step.  Formed in the step launch for single grids in FP64 2D and in 3D;
+ * a batched state (out then takes one record per instance), the anti-trapping
+ * current, an FP32 2D grid (there the separate pass is faster) or a tile
+ * whose last launch would write more than 65536 partial records (2D: one per
+ * strip wave, 3D: one per tile) takes mp_step followed by the separate
+ * reduction.  Partial records live in the
+ * workspace.  Synchronises ``stream``.  Errors: MP_E_NULLPTR, MP_E_UNBOUND,
+ * MP_E_PARAM (nsteps < 1), MP_E_NONFINITE (*out filled), MP_E_HIP. */
+int mp_step_diag(mp_state* st, int64_t nsteps, mp_diag* out, void* stream);
 
 /* mp_diagnostics without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

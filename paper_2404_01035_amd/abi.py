@@ -35,6 +35,7 @@ EXPORTS = [
     "mp_diagnostics_batch", "mp_step_ckpt", "mp_adjoint_work_bytes", "mp_adjoint",
     "mp_tune_candidates", "mp_tune", "mp_set_fusion", "mp_get_fusion",
     "mp_set_antitrapping", "mp_get_antitrapping", "mp_diagnostics_static", "mp_front_row", "mp_shift",
+    "mp_step_diag",
 ]
 
 # Layout of the parameter gradient filled by mp_adjoint.
@@ -103,6 +104,8 @@ def lib():
         L.mp_set_step.argtypes = [vp, C.c_int64, C.c_int]
         L.mp_diagnostics.restype = C.c_int
         L.mp_diagnostics.argtypes = [vp, C.POINTER(mp_diag), vp]
+        L.mp_step_diag.restype = C.c_int
+        L.mp_step_diag.argtypes = [vp, C.c_int64, C.POINTER(mp_diag), vp]
         L.mp_diagnostics_static.restype = C.c_int
         L.mp_diagnostics_static.argtypes = [vp, vp, C.c_int64, C.POINTER(mp_diag), vp]
         L.mp_front_row.restype = C.c_int
@@ -256,6 +259,17 @@ def mp_diagnostics(st, stream: int = 0, allow_nonfinite: bool = False) -> dict:
     if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
         _check(rc)
     return _diag_dict(d)
+
+
+def mp_step_diag(st, nsteps: int, stream: int = 0, allow_nonfinite: bool = False) -> list:
+    """nsteps steps, then the diagnostics of the state reached, their partial
+    sums formed by the last step launch; one dict per instance."""
+    n = mp_instance_count(st)
+    arr = (mp_diag * n)()
+    rc = lib().mp_step_diag(st, int(nsteps), arr, stream)
+    if rc != MP_OK and not (allow_nonfinite and rc == MP_E_NONFINITE):
+        _check(rc)
+    return [_diag_dict(arr[i]) for i in range(n)]
 
 
 def mp_diagnostics_batch(st, stream: int = 0, allow_nonfinite: bool = False) -> list:

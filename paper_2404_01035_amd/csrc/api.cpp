@@ -448,6 +448,7 @@ int strips_of(const mp_state* st, const Inst& I) {
 // ---- workspace layout -------------------------------------------------------
 // [diag partials + one result record per instance][time level][instance table][work list]
 // [anti-trapping coefficient table][extended-model coefficient table]
+// [partial diagnostics records of a fused step launch (single grids)]
 size_t ws_diag_bytes(const mp_state* st) {
     return align_up((size_t)(mp::DIAG_BLOCKS_MAX + st->inst.size()) * mp::DIAG_VALS * sizeof(double));
 }
@@ -476,6 +477,23 @@ size_t xtab_bytes(const mp_state* st) {
     const size_t one = st->precision == MP_FP64 ? sizeof(mp::CoefX<double>) : sizeof(mp::CoefX<float>);
     return st->batch ? align_up(one * st->inst.size()) : 0;
 }
+size_t ws_frec_off(const mp_state* st) { return ws_xtab_off(st) + xtab_bytes(st); }
+// Records a fused step launch writes: one per 2D strip wave or 3D tile, most
+// at seg = 1; capped at FUSED_REC_MAX (a launch over the cap reduces in a
+// separate pass instead).
+int64_t frec_cap(const mp_state* st) {
+    if (st->batch) return 0;
+    const mp_grid& g = st->inst[0].grid;
+    int64_t n;
+    if (g.dim == 3)
+        n = ((g.n[0] + 63) / 64) * ((g.n[1] + 3) / 4) * g.n[2];
+    else
+        n = ((g.n[0] + mp::W2X_LANES_OUT_HOST - 1) / mp::W2X_LANES_OUT_HOST) * g.n[1];
+    return n < mp::FUSED_REC_MAX ? n : mp::FUSED_REC_MAX;
+}
+size_t frec_bytes(const mp_state* st) { return align_up((size_t)frec_cap(st) * mp::DIAG_VALS * sizeof(double)); }
+double* dev_frec(mp_state* st) { return (double*)((char*)st->ws + ws_frec_off(st)); }
+
 // A batch with an instance of the extended model steps every instance with the general kernels.
 bool batch_gen(const mp_state* st) {
     for (const Inst& I : st->inst)
@@ -618,6 +636,15 @@ bool at_folded(const mp_state* st) { return st->antitrap == 1 && (st->batch || s
 // Steps per launch of the ordinary path.
 int launch_fuse(const mp_state* st) { return st->antitrap ? 1 : st->fuse; }
 
+// mp_step_diag forms the diagnostics inside the last step launch for single
+// grids without the anti-trapping current, in FP64 2D and in 3D.  The FP32 2D
+// strips take the separate pass: their lane shuffles go through the LDS
+// pipe, where the accumulators' atomics delay them, and the fused launch
+// measured slower than the step plus the separate pass.
+bool fused_diag(const mp_state* st) {
+    return !st->batch && !st->antitrap && (st->inst[0].grid.dim == 3 || st->precision == MP_FP64);
+}
+
 // The batched kernel for L: with the current folded in while it is on.
 int batch_call(mp_state* st, const mp::BatchLaunch& L, mp::KernelCall& k) {
     const void* atab = (const char*)st->ws + ws_attab_off(st);
@@ -672,7 +699,7 @@ int sync_batch(mp_state* st) {
 }
 
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k, int fuse = 1, void* out1 = nullptr);
+                     mp::KernelCall& k, int fuse = 1, void* out1 = nullptr, const mp::DiagOut* diag = nullptr);
 
 
 // One launch of `fuse` steps (1 or 2; a batch always 1); kstep is the
@@ -700,7 +727,7 @@ int make_step_call(mp_state* st, int kstep, int from, mp::KernelCall& k, int fus
 // Single-grid launch of `fuse` steps from ``in`` to ``out`` at time level
 // *ctr + kstep.
 int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr, int kstep,
-                     mp::KernelCall& k, int fuse, void* out1) {
+                     mp::KernelCall& k, int fuse, void* out1, const mp::DiagOut* diag) {
     const Inst& I = st->inst[0];
     mp::StepLaunch L;
     L.in = in;
@@ -718,7 +745,23 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.out1 = out1;
     L.stepctr = ctr;
     L.kstep = kstep;
+    L.diag = diag;
     temperature_law(I, L.tb0, L.tdn, L.tslope);
+    if (diag) {
+        // the instances that also write the diagnostics' partial records
+        // (fused_diag: FP64 2D strips and 3D tiles)
+        if (at_folded(st) || out1 || !fused_diag(st)) return MP_E_PARAM;
+        const bool d3 = I.grid.dim == 3;
+        if (st->precision == MP_FP64) {
+            if (I.ext)
+                return d3 ? mp::call_step_gen<double, true, true>(L, make_coef<double>(I), make_coefx<double>(I), k)
+                          : mp::call_step_gen<double, false, true>(L, make_coef<double>(I), make_coefx<double>(I), k);
+            return d3 ? mp::call_step_dim<double, true, true>(L, make_coef<double>(I), k)
+                      : mp::call_step_dim<double, false, true>(L, make_coef<double>(I), k);
+        }
+        if (I.ext) return mp::call_step_gen<float, true, true>(L, make_coef<float>(I), make_coefx<float>(I), k);
+        return mp::call_step_dim<float, true, true>(L, make_coef<float>(I), k);
+    }
     if (at_folded(st) && !out1) {
         if (I.ext) {
             if (st->precision == MP_FP64)
@@ -742,6 +785,7 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
 }
 
 int launch(const mp::KernelCall& k, hipStream_t s) {
+    if (k.bad) return fail(MP_E_PARAM, "kernel arguments exceed the launch record");
     return hip_check(hipLaunchKernel(k.func, k.grid, k.block, (void**)k.args, 0, s), "kernel launch");
 }
 
@@ -840,28 +884,38 @@ void init_state(mp_state* st) {
 
 // Diagnostics of instance i of the state held in ``base`` (one state buffer),
 // with per-block partials in ``partials`` and the result record in ``result``.
-int diag_instance_at(const mp_state* st, int i, const void* base, int64_t step, double* partials, double* result,
-                     hipStream_t s) {
+mp::DiagCoef make_diag_coef(const mp_state* st, int i, int64_t step) {
     const Inst& I = st->inst[i];
     mp::DiagCoef dc;
     std::memset(&dc, 0, sizeof dc);
+    const int K1 = I.K - 1;
     for (int a = 0; a < I.N; ++a) {
         double chi[2][2];
         chi_of(I.prm, a, I.K, chi);
-        dc.chx[a] = I.K == 3 ? chi[0][1] : 0.0;
-        for (int k = 0; k < I.K - 1; ++k) {
+        dc.chx[a] = K1 == 2 ? chi[0][1] : 0.0;
+        for (int k = 0; k < K1; ++k) {
             dc.chi[a][k] = chi[k][k];
-            dc.B[a][k] = I.prm.B[a][k];
-            dc.Bt[a][k] = I.prm.Bt[a][k];
+            dc.cb[a][k] = chi[k][k] * I.prm.B[a][k];
+            dc.cbt[a][k] = chi[k][k] * I.prm.Bt[a][k];
+            if (K1 == 2) {
+                dc.cb[a][k] += chi[k][1 - k] * I.prm.B[a][1 - k];
+                dc.cbt[a][k] += chi[k][1 - k] * I.prm.Bt[a][1 - k];
+            }
         }
     }
-    dc.vol = std::pow(I.grid.dx, I.grid.dim);
     double tb0, tdn, tslope;
     temperature_law(I, tb0, tdn, tslope);
     dc.tt0 = tb0 + tdn * (double)step;
     dc.tslope = tslope;
     dc.nx = (int32_t)I.grid.n[0];
     dc.ny = (int32_t)I.grid.n[1];
+    return dc;
+}
+
+int diag_instance_at(const mp_state* st, int i, const void* base, int64_t step, double* partials, double* result,
+                     hipStream_t s) {
+    const Inst& I = st->inst[i];
+    const mp::DiagCoef dc = make_diag_coef(st, i, step);
     const void* state = (const char*)base + I.off_bytes;
     int rc = mp::launch_diag(state, st->precision, make_geom(I.grid), I.N, I.K - 1, dc, partials, result, s);
     if (rc) return fail(rc, "no diagnostics instance");
@@ -878,22 +932,20 @@ void unpack_diag(const mp_state* st, int i, const double* r, int64_t step, mp_di
     const Inst& I = st->inst[i];
     std::memset(out, 0, sizeof *out);
     out->step = step;
+    // the records hold sums of c_k and phi_a over cells; dx^d once here
+    const double vol = std::pow(I.grid.dx, I.grid.dim);
     for (int k = 0; k < I.K - 1; ++k) {
-        out->mass[k] = r[mp::DV_MASS + 2 * k] + r[mp::DV_MASS + 2 * k + 1];
+        out->mass[k] = (r[mp::DV_MASS + 2 * k] + r[mp::DV_MASS + 2 * k + 1]) * vol;
         out->min_chi[k] = r[mp::DV_MINCHI + k];
     }
-    for (int a = 0; a < I.N; ++a) out->volume[a] = r[mp::DV_VOL + 2 * a] + r[mp::DV_VOL + 2 * a + 1];
+    for (int a = 0; a < I.N; ++a) out->volume[a] = (r[mp::DV_VOL + 2 * a] + r[mp::DV_VOL + 2 * a + 1]) * vol;
     out->max_sum_dev = r[mp::DV_MAXDEV];
     out->nonfinite = (int64_t)r[mp::DV_NONFIN];
 }
 
-int diag_many(mp_state* st, mp_diag* out, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
+// Copy the instances' result records to the host and unpack them.
+int diag_collect(mp_state* st, mp_diag* out, hipStream_t s) {
     const int n = (int)st->inst.size();
-    for (int i = 0; i < n; ++i) {
-        const int rc = diag_instance(st, i, s);
-        if (rc) return rc;
-    }
     std::vector<double> r((size_t)n * mp::DIAG_VALS);
     int rc = hip_check(hipMemcpyAsync(r.data(),
                                       (double*)st->ws + (size_t)mp::DIAG_BLOCKS_MAX * mp::DIAG_VALS,
@@ -909,6 +961,16 @@ int diag_many(mp_state* st, mp_diag* out, void* stream) {
     }
     if (bad > 0) return fail(MP_E_NONFINITE, "%lld cells hold NaN or Inf", (long long)bad);
     return ok();
+}
+
+int diag_many(mp_state* st, mp_diag* out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)st->inst.size();
+    for (int i = 0; i < n; ++i) {
+        const int rc = diag_instance(st, i, s);
+        if (rc) return rc;
+    }
+    return diag_collect(st, out, s);
 }
 
 // ---- adjoint driver -----------------------------------------------------------
@@ -1142,7 +1204,7 @@ size_t mp_state_bytes(const mp_state* st) {
 
 size_t mp_workspace_bytes(const mp_state* st) {
     if (!st) return 0;
-    return ws_xtab_off(st) + xtab_bytes(st);
+    return ws_frec_off(st) + frec_bytes(st);
 }
 
 int mp_bind(mp_state* st, void* buf0, void* buf1, void* workspace) {
@@ -1209,6 +1271,49 @@ int mp_step(mp_state* st, int64_t nsteps, void* stream) {
         st->step += left;
     }
     return ok();
+}
+
+int mp_step_diag(mp_state* st, int64_t nsteps, mp_diag* out, void* stream) {
+    if (!st || !out) return fail(MP_E_NULLPTR, "state or out is NULL");
+    if (!st->bound) return fail(MP_E_UNBOUND, "mp_step_diag before mp_bind");
+    if (nsteps < 1) return fail(MP_E_PARAM, "nsteps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    // the other paths: the steps, then the separate pass
+    if (!fused_diag(st)) {
+        const int rc = mp_step(st, nsteps, stream);
+        if (rc) return rc;
+        return diag_many(st, out, stream);
+    }
+    const int F = launch_fuse(st) == 2 && nsteps >= 2 ? 2 : 1;
+    int rc = mp_step(st, nsteps - F, stream);
+    if (rc) return rc;
+    // the last launch also writes the partial records of the state it stores
+    mp::DiagOut d;
+    d.part = dev_frec(st);
+    d.dc = make_diag_coef(st, 0, st->step + F);
+    mp::KernelCall k;
+    rc = make_single_call(st, st->buf[st->cur], st->buf[1 - st->cur], dev_ctr(st), 0, k, F, nullptr, &d);
+    if (rc) return fail(rc, "no kernel instance for this configuration");
+    if (k.nrec < 1 || k.nrec > frec_cap(st)) {
+        // more records than the workspace holds (very short segments)
+        rc = mp_step(st, F, stream);
+        if (rc) return rc;
+        return diag_many(st, out, stream);
+    }
+    rc = launch(k, s);
+    if (rc) return rc;
+    st->cur = 1 - st->cur;
+    mp::KernelCall adv;
+    mp::call_advance(dev_ctr(st), F, adv);
+    rc = launch(adv, s);
+    if (rc) return rc;
+    st->step += F;
+    rc = mp::launch_diag_final(dev_frec(st), k.nrec, (double*)st->ws + (size_t)mp::DIAG_BLOCKS_MAX * mp::DIAG_VALS,
+                               s);
+    if (rc) return fail(rc, "diagnostics reduction");
+    rc = hip_check(hipGetLastError(), "diagnostics launch");
+    if (rc) return rc;
+    return diag_collect(st, out, s);
 }
 
 int mp_current(const mp_state* st, int* which_buf, int64_t* step) {

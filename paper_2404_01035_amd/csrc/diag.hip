@@ -6,6 +6,7 @@
 // count alone, so the result is bitwise reproducible run to run.
 #include <mutex>
 
+#include "diag_cell.hpp"
 #include "diag_static.hpp"
 #include "mp_internal.hpp"
 
@@ -43,160 +44,57 @@ namespace {
 
 constexpr int DT = 256;  // threads per diagnostics block
 
-struct Neu {
-    double s, c;
-};
-
-__device__ __forceinline__ void neu_add(Neu& a, double x) {
-    double t = a.s + x;
-    if (fabs(a.s) >= fabs(x))
-        a.c += (a.s - t) + x;
-    else
-        a.c += (x - t) + a.s;
-    a.s = t;
-}
-
-__device__ __forceinline__ void neu_merge(Neu& a, const Neu& b) {
-    neu_add(a, b.s);
-    a.c += b.c;
-}
-
-template <int NP>
-__device__ __forceinline__ void h_fp64(const double (&p)[NP], double (&h)[NP]) {
-    for (int a = 0; a < NP; ++a) {
-        double o = 0.0;
-        if (NP == 3) {
-            int b = (a + 1) % 3, g = (a + 2) % 3;
-            o = p[b] * p[g];
-        }
-        h[a] = 3.0 * p[a] * p[a] - 2.0 * p[a] * p[a] * p[a] + 2.0 * p[a] * o;
-    }
-}
-
-struct Acc {
-    Neu mass[2];
-    Neu vol[3];
-    double maxdev;
-    double minchi[2];
-    double nonfin;
-};
-
-__device__ __forceinline__ void acc_init(Acc& A) {
-    for (int k = 0; k < 2; ++k) A.mass[k] = {0.0, 0.0};
-    for (int a = 0; a < 3; ++a) A.vol[a] = {0.0, 0.0};
-    A.maxdev = 0.0;
-    A.minchi[0] = A.minchi[1] = INFINITY;
-    A.nonfin = 0.0;
-}
-
-__device__ __forceinline__ void acc_merge(Acc& A, const Acc& B) {
-    for (int k = 0; k < 2; ++k) neu_merge(A.mass[k], B.mass[k]);
-    for (int a = 0; a < 3; ++a) neu_merge(A.vol[a], B.vol[a]);
-    A.maxdev = fmax(A.maxdev, B.maxdev);
-    A.minchi[0] = fmin(A.minchi[0], B.minchi[0]);
-    A.minchi[1] = fmin(A.minchi[1], B.minchi[1]);
-    A.nonfin += B.nonfin;
-}
-
-__device__ __forceinline__ void acc_store(double* r, const Acc& A) {
-    for (int k = 0; k < 2; ++k) {
-        r[DV_MASS + 2 * k] = A.mass[k].s;
-        r[DV_MASS + 2 * k + 1] = A.mass[k].c;
-    }
-    for (int a = 0; a < 3; ++a) {
-        r[DV_VOL + 2 * a] = A.vol[a].s;
-        r[DV_VOL + 2 * a + 1] = A.vol[a].c;
-    }
-    r[DV_MAXDEV] = A.maxdev;
-    r[DV_MINCHI] = A.minchi[0];
-    r[DV_MINCHI + 1] = A.minchi[1];
-    r[DV_NONFIN] = A.nonfin;
-}
-
-__device__ __forceinline__ void acc_load(Acc& A, const double* r) {
-    for (int k = 0; k < 2; ++k) A.mass[k] = {r[DV_MASS + 2 * k], r[DV_MASS + 2 * k + 1]};
-    for (int a = 0; a < 3; ++a) A.vol[a] = {r[DV_VOL + 2 * a], r[DV_VOL + 2 * a + 1]};
-    A.maxdev = r[DV_MAXDEV];
-    A.minchi[0] = r[DV_MINCHI];
-    A.minchi[1] = r[DV_MINCHI + 1];
-    A.nonfin = r[DV_NONFIN];
-}
-
 // Fixed-shape tree over the block's records in LDS.
-__device__ void block_tree(Acc& A, double (*rec)[DIAG_VALS]) {
+__device__ void block_tree(DiagRec& A, double (*rec)[DIAG_VALS]) {
     const int t = threadIdx.x;
-    acc_store(rec[t], A);
+    rec_store(rec[t], A);
     __syncthreads();
     for (int w = DT / 2; w > 0; w >>= 1) {
         if (t < w) {
-            Acc a, b;
-            acc_load(a, rec[t]);
-            acc_load(b, rec[t + w]);
-            acc_merge(a, b);
-            acc_store(rec[t], a);
+            DiagRec a, b;
+            rec_load(a, rec[t]);
+            rec_load(b, rec[t + w]);
+            rec_merge(a, b);
+            rec_store(rec[t], a);
         }
         __syncthreads();
     }
-    acc_load(A, rec[0]);
+    rec_load(A, rec[0]);
 }
 
 template <typename R, int NP, int NM>
 __global__ void __launch_bounds__(DT) k_diag(const R* __restrict__ st, int64_t ncells, DiagCoef dc,
                                              double* __restrict__ partial) {
     __shared__ double rec[DT][DIAG_VALS];
-    Acc A;
+    DiagAcc A;
     acc_init(A);
     const int64_t stride = (int64_t)gridDim.x * DT;
     for (int64_t i = (int64_t)blockIdx.x * DT + threadIdx.x; i < ncells; i += stride) {
-        double p[NP], mu[NM], h[NP];
-        bool fin = true;
-        double sum = 0.0;
-        for (int a = 0; a < NP; ++a) {
-            p[a] = (double)st[a * ncells + i];
-            fin = fin && isfinite(p[a]);
-            sum += p[a];
-        }
-        for (int k = 0; k < NM; ++k) {
-            mu[k] = (double)st[(NP + k) * ncells + i];
-            fin = fin && isfinite(mu[k]);
-        }
-        if (!fin) A.nonfin += 1.0;
-        h_fp64<NP>(p, h);
-        A.maxdev = fmax(A.maxdev, fabs(sum - 1.0));
-        for (int a = 0; a < NP; ++a) neu_add(A.vol[a], p[a] * dc.vol);
+        double p[NP], mu[NM];
+        for (int a = 0; a < NP; ++a) p[a] = (double)st[a * ncells + i];
+        for (int k = 0; k < NM; ++k) mu[k] = (double)st[(NP + k) * ncells + i];
         // T - Te of the cell's row (the composition depends on T through B(T))
         const double tt = dc.tt0 + dc.tslope * (double)((i / dc.nx) % dc.ny);
-        double dm[NP][NM];
-        for (int a = 0; a < NP; ++a)
-            for (int k = 0; k < NM; ++k) dm[a][k] = mu[k] - dc.B[a][k] - dc.Bt[a][k] * tt;
-        for (int k = 0; k < NM; ++k) {
-            double cc = 0.0, chi = 0.0;
-            for (int a = 0; a < NP; ++a) {
-                double ca = dm[a][k] * dc.chi[a][k];
-                if (NM == 2) ca += dm[a][1 - k] * dc.chx[a];  // c^a = chi^a (mu - B^a(T))
-                cc += h[a] * ca;
-                chi += h[a] * dc.chi[a][k];
-            }
-            neu_add(A.mass[k], cc * dc.vol);
-            A.minchi[k] = fmin(A.minchi[k], chi);
-        }
+        diag_cell<NP, NM, true>(p, mu, tt, dc, A);
     }
-    block_tree(A, rec);
-    if (threadIdx.x == 0) acc_store(partial + (int64_t)blockIdx.x * DIAG_VALS, A);
+    DiagRec B;
+    rec_from(B, A);
+    block_tree(B, rec);
+    if (threadIdx.x == 0) rec_store(partial + (int64_t)blockIdx.x * DIAG_VALS, B);
 }
 
 __global__ void __launch_bounds__(DT) k_diag_final(const double* __restrict__ partial, int nblocks,
                                                    double* __restrict__ result) {
     __shared__ double rec[DT][DIAG_VALS];
-    Acc A;
-    acc_init(A);
+    DiagRec A;
+    rec_init(A);
     for (int i = threadIdx.x; i < nblocks; i += DT) {
-        Acc b;
-        acc_load(b, partial + (int64_t)i * DIAG_VALS);
-        acc_merge(A, b);
+        DiagRec b;
+        rec_load(b, partial + (int64_t)i * DIAG_VALS);
+        rec_merge(A, b);
     }
     block_tree(A, rec);
-    if (threadIdx.x == 0) acc_store(result, A);
+    if (threadIdx.x == 0) rec_store(result, A);
 }
 
 template <typename R, int NP, int NM>
@@ -226,6 +124,12 @@ int diag_blocks(int64_t ncells) {
     if (nb > DIAG_BLOCKS_MAX) nb = DIAG_BLOCKS_MAX;
     if (nb < 1) nb = 1;
     return (int)nb;
+}
+
+int launch_diag_final(const double* partials, int64_t nrec, double* result, hipStream_t s) {
+    if (nrec < 1 || nrec > 0x7fffffffLL) return MP_E_PARAM;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DT), 0, s, partials, (int)nrec, result);
+    return MP_OK;
 }
 
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,

@@ -56,15 +56,24 @@ struct CoefX {
 };
 
 // Coefficients the FP64 diagnostics reduction needs.
+// c^a(mu) = chi^a (mu - B^a - Bt^a (T - Te)), so
+// c^a_k = chi_kk mu_k + chi_01 mu_{1-k} - cb_k - cbt_k (T - Te).
 struct DiagCoef {
-    double chi[3][2];
-    double B[3][2];
-    double vol;      // dx^d
-    double Bt[3][2]; // B^a_k(T) = B + Bt (T - Te)
-    double chx[3];   // off-diagonal susceptibility (K = 3)
-    double tt0;      // T - Te at row 0 of the reduced state's time level
+    double chi[3][2];  // chi^a_kk
+    double chx[3];     // chi^a_01 (K = 3)
+    double cb[3][2];   // (chi^a B^a)_k
+    double cbt[3][2];  // (chi^a Bt^a)_k (the extended model's B^a(T))
+    double tt0;        // T - Te at row 0 of the reduced state's time level
     double tslope;   // T - Te per row
     int32_t nx, ny;  // rows: cell i lies in row (i / nx) mod ny
+};
+
+// Where a step kernel leaves the diagnostics of the state it stores: one
+// partial record of DIAG_VALS doubles per wave (2D strips) or per block (3D
+// tiles), reduced afterwards by the diagnostics' final kernel.
+struct DiagOut {
+    double* part;
+    DiagCoef dc;
 };
 
 // One launch of the fused step kernel.  The time level of the launch is
@@ -82,6 +91,7 @@ struct StepLaunch {
     const int64_t* stepctr;
     int kstep;
     double tb0, tdn, tslope;
+    const DiagOut* diag = nullptr;  // the diagnostics kernels: partial records of the stored state
 };
 
 // A kernel launch described as data: launched directly or added to a graph.
@@ -92,12 +102,18 @@ struct KernelCall {
     size_t used = 0;
     void* args[16];
     int nargs = 0;
+    bool bad = false;      // an argument did not fit: the call must not be launched
+    long long nrec = 0;    // partial diagnostics records the launch writes
     template <typename T>
     void arg(const T& v) {
-        used = (used + alignof(T) - 1) / alignof(T) * alignof(T);
-        __builtin_memcpy(store + used, &v, sizeof(T));
-        args[nargs++] = store + used;
-        used += sizeof(T);
+        const size_t at = (used + alignof(T) - 1) / alignof(T) * alignof(T);
+        if (bad || nargs >= 16 || at + sizeof(T) > sizeof store) {
+            bad = true;
+            return;
+        }
+        __builtin_memcpy(store + at, &v, sizeof(T));
+        args[nargs++] = store + at;
+        used = at + sizeof(T);
     }
 };
 
@@ -140,11 +156,13 @@ constexpr int DV_MASS = 0, DV_VOL = 4, DV_MAXDEV = 10, DV_MINCHI = 11, DV_NONFIN
 
 int call_step_f64(const StepLaunch& L, const Coef<double>& c, KernelCall& k);
 int call_step_f32(const StepLaunch& L, const Coef<float>& c, KernelCall& k);
-template <typename R, bool D3>
+// DIAG: the instances that also write the partial diagnostics records of the
+// state they store (StepLaunch::diag), one per 2D strip wave or 3D tile.
+template <typename R, bool D3, bool DIAG = false>
 int call_step_dim(const StepLaunch& L, const Coef<R>& c, KernelCall& k);
 // The general kernels of the extended model (one cell per lane in 2D, 64 x 4
 // tiles in 3D).
-template <typename R, bool D3>
+template <typename R, bool D3, bool DIAG = false>
 int call_step_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k);
 template <typename R>
 int call_batch(const BatchLaunch& L, KernelCall& k);
@@ -203,6 +221,10 @@ int at_launch(const AtLaunch& L, const AtCoef<R>& c, hipStream_t s);
 int launch_diag(const void* state, int precision, const Geom& g, int nphases, int nmu,
                 const DiagCoef& dc, double* partials, double* result, hipStream_t s);
 int diag_blocks(int64_t ncells);
+// The final reduction alone, over nrec partial records (fixed order).
+int launch_diag_final(const double* partials, int64_t nrec, double* result, hipStream_t s);
+// Most partial records one fused step launch may write (8 MiB of records).
+constexpr int64_t FUSED_REC_MAX = 65536;
 
 // Moving frame (frame.hip): the front row (partials: front_blocks ints) and
 // the shift of a state by whole rows along y with melt appended.

@@ -19,6 +19,7 @@
 // XCD's L2.
 #pragma once
 
+#include "diag_cell.hpp"
 #include "gp_device.hpp"
 
 namespace mp {
@@ -274,16 +275,33 @@ __device__ __forceinline__ void mirror_fix(R (&v)[NF][V], bool fixL, bool fixR) 
 #define MP_STRIP_DEPTH 2
 #endif
 
+// Diagnostics of one stored row record (V cells of a lane), in FP64; TDEP:
+// B^a depends on T (the extended model).
+template <typename R, int NP, int NM, int V, bool TDEP>
+__device__ __forceinline__ void diag_row(const R (&phin)[NP][V], const R (&mun)[NM][V], double tt,
+                                         const DiagCoef& dc, DiagStrip<NP, NM, TDEP>& A) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        double p[NP], u[NM];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) p[a] = (double)phin[a][v];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) u[k] = (double)mun[k][v];
+        A.cell(p, u, tt, dc);
+    }
+}
+
 constexpr unsigned kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt/lgkmcnt untouched
 
 // One wave's strip of one step: columns tx*W*V .. (tx+1)*W*V - 1 (lanes
 // 1..W, W <= 62), rows [m0, m1).  Called with wave-uniform arguments by the
 // single-grid and the batched kernel.  Requires nx % V == 0.
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, int DEPTH = MP_STRIP_DEPTH,
-          int W = W2D_LANES_OUT, bool GEN = false>
+          int W = W2D_LANES_OUT, bool GEN = false, bool DIAG = false>
 __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                         const Coef<R>& c, double tbase, double tslope, int tx,
-                                        int m0, int m1, const CoefX<R>* x = nullptr) {
+                                        int m0, int m1, const CoefX<R>* x = nullptr,
+                                        DiagStrip<NP, NM, GEN>* da = nullptr, const DiagCoef* dc = nullptr) {
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
     typedef Row2d<R, NP, NM, V, ANISO, GEN> RowT;
@@ -328,6 +346,7 @@ __device__ __forceinline__ void strip2d(const R* __restrict__ in, R* __restrict_
             for (int a = 0; a < NP; ++a) vstore<R, V>(out + a * fs + o, phin[a]);
 #pragma unroll
             for (int kk = 0; kk < NM; ++kk) vstore<R, V>(out + (NP + kk) * fs + o, mun[kk]);
+            if constexpr (DIAG) diag_row<R, NP, NM, V, GEN>(phin, mun, dc->tt0 + dc->tslope * (double)m, *dc, *da);
         }
     };
 
@@ -435,10 +454,11 @@ __device__ __forceinline__ int x2_first_col(int tx, int lane) {
 // the mirror copies of step 1 made).  STORE1: the step-1 rows of the segment
 // are also written, to out1 (the state between the two steps).
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE, bool STORE1 = false,
-          bool GEN = false>
+          bool GEN = false, bool DIAG = false>
 __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
                                            const Geom& g, const Coef<R>& c, double tbase0, double tbase1,
-                                           double tslope, int tx, int m0, int m1, const CoefX<R>* x = nullptr) {
+                                           double tslope, int tx, int m0, int m1, const CoefX<R>* x = nullptr,
+                                           DiagStrip<NP, NM, GEN>* da = nullptr, const DiagCoef* dc = nullptr) {
     constexpr int NF = NP + NM;
     typedef Raw2d<R, NF, V> RawT;
     typedef Row2d<R, NP, NM, V, ANISO, GEN> RowT;
@@ -552,6 +572,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
             for (int a = 0; a < NP; ++a) vstore<R, V>(out + a * fs + o, phin[a]);
 #pragma unroll
             for (int kk = 0; kk < NM; ++kk) vstore<R, V>(out + (NP + kk) * fs + o, mun[kk]);
+            if constexpr (DIAG) diag_row<R, NP, NM, V, GEN>(phin, mun, dc->tt0 + dc->tslope * (double)q, *dc, *da);
         }
         c1 = n1;
     };
@@ -665,8 +686,110 @@ k_step2d_x2_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c
                                                                   min(m0 + seg, g.ny), &x);
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+// The same launches writing, beside the state, one partial diagnostics record
+// per strip wave: the diagnostics of the state they store, so that it need
+// not be read again (the record of wave w at d.part + w * DIAG_VALS).  The
+// lanes' accumulators live in LDS (DiagStrip), 256 slots per sum.
+template <int NP, int NM, bool TDEP>
+__device__ __forceinline__ void diag_finish(const DiagStrip<NP, NM, TDEP>& A, const DiagOut& d, int wid) {
+    DiagRec R;
+    A.record(d.dc, R);
+    rec_wave_reduce(R);
+    if ((threadIdx.x & 63) == 0) rec_store(d.part + (int64_t)wid * DIAG_VALS, R);
+}
+
+// One cell per lane: at least the occupancy of the plain kernels with the most
+// fields (FP64 3 waves per SIMD, FP32 5); the LDS accumulators take no VGPRs.
+#define MP_DIAG_WAVES(R, V) ((V) == 1 ? (sizeof(R) == 8 ? 3 : 5) : MP_WAVES_PER_EU)
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_DIAG_WAVES(R, V))))
+k_step2d_diag(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+              const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+              int seg, int ntx, int nseg, CoefX<R> x, DiagOut d) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double tbase = tb0 + tdn * (double)(*stepctr + kstep);
+    typedef DiagStrip<NP, NM, GEN> DS;
+    __shared__ double dls[DS::WORDS];
+    DS A;
+    A.init(dls, threadIdx.x);
+    strip2d<R, NP, NM, ANISO, OBST, V, MP_STRIP_DEPTH, W2D_LANES_OUT, GEN, true>(
+        in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny), GEN ? &x : nullptr, &A, &d.dc);
+    diag_finish(A, d, wid);
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_DIAG_WAVES(R, V))))
+k_step2d_x2_diag(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+                 const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+                 int seg, int ntx, int nseg, CoefX<R> x, DiagOut d) {
+    const int wpb = blockDim.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (threadIdx.x >> 6));
+    if (wid >= ntx * nseg) return;
+    const int tx = wid % ntx;
+    const int sg = wid / ntx;
+    const int m0 = sg * seg;
+    const double n = (double)(*stepctr + kstep);
+    const CoefX<R>* xp = GEN ? &x : nullptr;
+    typedef DiagStrip<NP, NM, GEN> DS;
+    __shared__ double dls[DS::WORDS];
+    DS A;
+    A.init(dls, threadIdx.x);
+    bool fixL, fixR;
+    x2_column<V>(g, x2_first_col<V>(tx, threadIdx.x & 63), fixL, fixR);
+    if (__ballot(fixL || fixR) != 0)
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, true, false, GEN, true>(in, out, nullptr, g, c, tb0 + tdn * n,
+                                                                      tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                                      min(m0 + seg, g.ny), xp, &A, &d.dc);
+    else
+        strip2d_x2<R, NP, NM, ANISO, OBST, V, false, false, GEN, true>(in, out, nullptr, g, c, tb0 + tdn * n,
+                                                                       tb0 + tdn * (n + 1.0), tslope, tx, m0,
+                                                                       min(m0 + seg, g.ny), xp, &A, &d.dc);
+    diag_finish(A, d, wid);
+}
+
+// Launch of a diagnostics instance: the plain or general strips, one or two
+// steps, V cells per lane.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN>
+int call_2d_diag(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    const int wout = L.fuse == 2 ? W2X_LANES_OUT : W2D_LANES_OUT;
+    const int ntx = (L.g.nx + wout * V - 1) / (wout * V);
+    const int nseg = (L.g.ny + L.seg - 1) / L.seg;
+    const int wpb = L.bx / 64;
+    const long long waves = (long long)ntx * nseg;
+    const long long nblocks = (waves + wpb - 1) / wpb;
+    // the lanes' LDS accumulators hold 256 slots per sum
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL || L.out1 || !L.diag || L.bx > 256) return MP_E_PARAM;
+    k.func = L.fuse == 2 ? (const void*)&k_step2d_x2_diag<R, NP, NM, ANISO, OBST, V, GEN>
+                         : (const void*)&k_step2d_diag<R, NP, NM, ANISO, OBST, V, GEN>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(L.bx);
+    k.nrec = waves;
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nseg);
+    k.arg(x);
+    k.arg(*L.diag);
+    return MP_OK;
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool DIAG = false>
 int call_2d_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    if constexpr (DIAG) return call_2d_diag<R, NP, NM, ANISO, OBST, 1, true>(L, c, x, k);
     const int wout = L.fuse == 2 ? W2X_LANES_OUT : W2D_LANES_OUT;
     const int ntx = (L.g.nx + wout - 1) / wout;
     const int nseg = (L.g.ny + L.seg - 1) / L.seg;
@@ -734,15 +857,25 @@ int call_2d_v(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     return MP_OK;
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool DIAG = false>
 int call_2d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
     const int v = vec2d_width(L.g.nx, (int)sizeof(R), L.vec);
-    if (v == 1) return call_2d_v<R, NP, NM, ANISO, OBST, 1>(L, c, k);
-    if (v == 2) return call_2d_v<R, NP, NM, ANISO, OBST, 2>(L, c, k);
-    if constexpr (sizeof(R) == 4) {
-        if (v == 4) return call_2d_v<R, NP, NM, ANISO, OBST, 4>(L, c, k);
+    if constexpr (DIAG) {
+        const CoefX<R> none{};
+        if (v == 1) return call_2d_diag<R, NP, NM, ANISO, OBST, 1, false>(L, c, none, k);
+        if (v == 2) return call_2d_diag<R, NP, NM, ANISO, OBST, 2, false>(L, c, none, k);
+        if constexpr (sizeof(R) == 4) {
+            if (v == 4) return call_2d_diag<R, NP, NM, ANISO, OBST, 4, false>(L, c, none, k);
+        }
+        return MP_E_PARAM;
+    } else {
+        if (v == 1) return call_2d_v<R, NP, NM, ANISO, OBST, 1>(L, c, k);
+        if (v == 2) return call_2d_v<R, NP, NM, ANISO, OBST, 2>(L, c, k);
+        if constexpr (sizeof(R) == 4) {
+            if (v == 4) return call_2d_v<R, NP, NM, ANISO, OBST, 4>(L, c, k);
+        }
+        return MP_E_PARAM;
     }
-    return MP_E_PARAM;
 }
 
 }  // namespace mp

@@ -11,16 +11,18 @@
 // dealt XCD-aware so that a band of tiles shares one XCD's L2.
 #pragma once
 
+#include "diag_cell.hpp"
 #include "gp_device.hpp"
 
 namespace mp {
 
 // The step of one block (GEN: the extended model's arithmetic, x its terms).
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY, bool GEN>
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY, bool GEN, bool DIAG = false>
 __device__ __forceinline__ void step3d_block(const R* __restrict__ in, R* __restrict__ out, const Geom& g,
                                              const Coef<R>& c, const int64_t* __restrict__ stepctr, int kstep,
                                              double tb0, double tdn, double tslope, int seg, int ntx, int nty,
-                                             const CoefX<R>* x) {
+                                             const CoefX<R>* x, DiagAcc* da = nullptr,
+                                             const DiagCoef* dc = nullptr) {
     constexpr int NF = NP + NM;
     constexpr int NMM = mob_n<NM, GEN>();
     constexpr int PW = BX + 2;
@@ -228,6 +230,14 @@ __device__ __forceinline__ void step3d_block(const R* __restrict__ in, R* __rest
             for (int a = 0; a < NP; ++a) out[a * fs + o] = phin[a];
 #pragma unroll
             for (int k = 0; k < NM; ++k) out[(NP + k) * fs + o] = mun[k];
+            if constexpr (DIAG) {
+                double p[NP], u[NM];
+#pragma unroll
+                for (int a = 0; a < NP; ++a) p[a] = (double)phin[a];
+#pragma unroll
+                for (int k = 0; k < NM; ++k) u[k] = (double)mun[k];
+                diag_cell<NP, NM, GEN>(p, u, dc->tt0 + dc->tslope * (double)gy, *dc, *da);
+            }
         }
 
         if (m + 2 <= m1) stage(m + 2);
@@ -254,8 +264,66 @@ k_step3d_gen(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
                                                       ntx, nty, &x);
 }
 
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+// The same tiles writing, beside the state, one partial diagnostics record
+// per block (block b's at d.part + b * DIAG_VALS): the diagnostics of the
+// state they store.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BX, int BY, bool GEN>
+__global__ void __launch_bounds__(BX * BY)
+k_step3d_diag(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
+              const int64_t* __restrict__ stepctr, int kstep, double tb0, double tdn, double tslope,
+              int seg, int ntx, int nty, CoefX<R> x, DiagOut d) {
+    constexpr int NW = BX * BY / 64;
+    __shared__ double drec[NW][DIAG_VALS];
+    DiagAcc A;
+    acc_init(A);
+    step3d_block<R, NP, NM, ANISO, OBST, BX, BY, GEN, true>(in, out, g, c, stepctr, kstep, tb0, tdn, tslope, seg,
+                                                            ntx, nty, GEN ? &x : nullptr, &A, &d.dc);
+    diag_wave_store(A, drec[threadIdx.x >> 6]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DiagRec T;
+        rec_load(T, drec[0]);
+        for (int w = 1; w < NW; ++w) {
+            DiagRec B;
+            rec_load(B, drec[w]);
+            rec_merge(T, B);
+        }
+        rec_store(d.part + (int64_t)blockIdx.x * DIAG_VALS, T);
+    }
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int BY, bool GEN>
+int call_3d_diag(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    constexpr int BX = 64;
+    const int ntx = (L.g.nx + BX - 1) / BX;
+    const int nty = (L.g.ny + BY - 1) / BY;
+    const int nseg = (L.g.nz + L.seg - 1) / L.seg;
+    const long long nblocks = (long long)ntx * nty * nseg;
+    if (nblocks <= 0 || nblocks > 0x7fffffffLL || !L.diag) return MP_E_PARAM;
+    k.func = (const void*)&k_step3d_diag<R, NP, NM, ANISO, OBST, BX, BY, GEN>;
+    k.grid = dim3((unsigned)nblocks);
+    k.block = dim3(BX * BY);
+    k.nrec = nblocks;
+    k.arg((const R*)L.in);
+    k.arg((R*)L.out);
+    k.arg(L.g);
+    k.arg(c);
+    k.arg(L.stepctr);
+    k.arg(L.kstep);
+    k.arg(L.tb0);
+    k.arg(L.tdn);
+    k.arg(L.tslope);
+    k.arg(L.seg);
+    k.arg(ntx);
+    k.arg(nty);
+    k.arg(x);
+    k.arg(*L.diag);
+    return MP_OK;
+}
+
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool DIAG = false>
 int call_3d_gen(const StepLaunch& L, const Coef<R>& c, const CoefX<R>& x, KernelCall& k) {
+    if constexpr (DIAG) return call_3d_diag<R, NP, NM, ANISO, OBST, 4, true>(L, c, x, k);
     const int ntx = (L.g.nx + 63) / 64;
     const int nty = (L.g.ny + 3) / 4;
     const int nseg = (L.g.nz + L.seg - 1) / L.seg;
@@ -314,14 +382,24 @@ constexpr int lds3d_bytes() {
 
 // bx = threads per block: 256 (64 x 4 tiles) or 512 (64 x 8 tiles, taller, so
 // fewer y-halo rows are loaded per cell; only where the LDS ring stays small).
-template <typename R, int NP, int NM, bool ANISO, bool OBST>
+template <typename R, int NP, int NM, bool ANISO, bool OBST, bool DIAG = false>
 int call_3d(const StepLaunch& L, const Coef<R>& c, KernelCall& k) {
-    if (L.bx == 512) {
-        if constexpr (lds3d_bytes<R, NP, NM, 8>() <= 64 * 1024)
-            return call_3d_by<R, NP, NM, ANISO, OBST, 8>(L, c, k);
-        return MP_E_PARAM;
+    if constexpr (DIAG) {
+        const CoefX<R> none{};
+        if (L.bx == 512) {
+            if constexpr (lds3d_bytes<R, NP, NM, 8>() <= 64 * 1024)
+                return call_3d_diag<R, NP, NM, ANISO, OBST, 8, false>(L, c, none, k);
+            return MP_E_PARAM;
+        }
+        return call_3d_diag<R, NP, NM, ANISO, OBST, 4, false>(L, c, none, k);
+    } else {
+        if (L.bx == 512) {
+            if constexpr (lds3d_bytes<R, NP, NM, 8>() <= 64 * 1024)
+                return call_3d_by<R, NP, NM, ANISO, OBST, 8>(L, c, k);
+            return MP_E_PARAM;
+        }
+        return call_3d_by<R, NP, NM, ANISO, OBST, 4>(L, c, k);
     }
-    return call_3d_by<R, NP, NM, ANISO, OBST, 4>(L, c, k);
 }
 
 }  // namespace mp

@@ -1,0 +1,7 @@
+// Kernel instances of the fused step that also writes the partial
+// diagnostics records of the stored state: precision double, 3d.
+#include "step_dispatch.hpp"
+
+namespace mp {
+template int call_step_dim<double, true, true>(const StepLaunch&, const Coef<double>&, KernelCall&);
+}  // namespace mp

@@ -59,6 +59,11 @@ class Solver:
     def diagnostics(self, allow_nonfinite: bool = False) -> dict:
         return abi.mp_diagnostics(self.st, self.stream(), allow_nonfinite)
 
+    def step_diag(self, nsteps: int, allow_nonfinite: bool = False) -> dict:
+        """nsteps steps and the diagnostics of the state reached, reduced from
+        partial sums the last step launch forms as it stores the state."""
+        return abi.mp_step_diag(self.st, nsteps, self.stream(), allow_nonfinite)[0]
+
     def set_tile(self, bx: int = 0, seg: int = 0, vec: int = 0):
         abi.mp_set_tile(self.st, bx, seg, vec)
 
@@ -187,6 +192,10 @@ class BatchSolver:
 
     def diagnostics(self, allow_nonfinite: bool = False):
         return abi.mp_diagnostics_batch(self.st, Solver.stream(), allow_nonfinite)
+
+    def step_diag(self, nsteps: int, allow_nonfinite: bool = False):
+        """nsteps steps, then the diagnostics of every instance (one dict each)."""
+        return abi.mp_step_diag(self.st, nsteps, Solver.stream(), allow_nonfinite)
 
     def set_tile(self, seg: int, vec: int = 0):
         abi.mp_set_tile(self.st, 0, seg, vec)

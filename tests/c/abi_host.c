@@ -50,6 +50,10 @@ int main(void) {
     if (mp_current(st, &which, &step) != MP_OK || which != 0 || step != 0) return 4;
     /* stepping before mp_bind is refused, with a message */
     if (mp_step(st, 1, NULL) != MP_E_UNBOUND || strlen(mp_last_error()) == 0) return 5;
+    /* so is stepping with the diagnostics; a NULL output is refused first */
+    mp_diag d;
+    if (mp_step_diag(st, 1, &d, NULL) != MP_E_UNBOUND) return 13;
+    if (mp_step_diag(st, 1, NULL, NULL) != MP_E_NULLPTR) return 14;
     /* the anti-trapping switch: off by default, on (both forms) and off again, 3 refused */
     int on = -1;
     if (mp_get_antitrapping(st, &on) != MP_OK || on != 0) return 9;
