@@ -30,6 +30,17 @@ Diffusion potentials, Eq. Mu_explicit_temperature with j_at = 0:
     value the mean of the two cells; chi_k = sum_a h_a(phi^{n+1}) chi^a_k.
   * B^a is temperature independent, so the dT/dt term vanishes.
 
+KKS variant (Sec. 2.2, ``p.model == "kks"``): the phase fields follow Eq. aceq,
+    (1/M_phi) dphi_a/dt = (eps^2/2)(div da/dgrad(phi_a) - da/dphi_a) - g_{,a} - d/dphi_a[f - c.mu] - lambda
+  with eps the gradient-energy coefficient of Eq. fe, the same a and face
+  discretisation as above, g either of the form of Eq. Well (no 1/eps) or the
+  sextic Eq. Well1 (``potential == "theta"``), and the driving force
+  d/dphi_a[f - c.mu] = sum_b psi^b dh_b/dphi_a: with the equal-potential
+  condition (Eq. eqmu) and the composition constraint (Eq. cint), f^b(c^b) -
+  mu.c^b is the grand potential psi^b(mu) of the phase.  The diffusion
+  potentials follow the linearised composition equation, which the paper states
+  is Eq. Mu_explicit_temperature (the same update as above).
+
 With the anti-trapping current of Eq. jatr (``step_antitrapping``, kept apart
 from ``step``), the mu update divides dt div(M grad mu - j_at) - sum_a c^a dh_a
 instead; ``antitrapping_faces`` states how the current is placed on faces.
@@ -166,6 +177,45 @@ def dw(phi, p):
                 if b != a:
                     prod = prod * phi[b]
             acc = acc + p.gamma3 * prod
+        out.append(acc)
+    return np.stack(out)
+
+
+def kks(p):
+    """The KKS variant of Sec. 2.2 (Eq. aceq for the phase fields)."""
+    return getattr(p, "model", "gp") == "kks"
+
+
+def g_theta(phi, p):
+    """Sextic multi-well potential of Eq. Well1:
+    sum_a Theta_a phi_a^2 (1 - phi_a)^2 + sum_{a<b} Theta_ab phi_a^2 phi_b^2
+    + sum_{a<b<d} Theta_abd phi_a^2 phi_b^2 phi_d^2 (one triple for N = 3)."""
+    N = phi.shape[0]
+    out = 0.0
+    for a in range(N):
+        out = out + p.theta[a] * phi[a] ** 2 * (1.0 - phi[a]) ** 2
+        for b in range(a + 1, N):
+            out = out + p.theta_ab[a][b] * phi[a] ** 2 * phi[b] ** 2
+    if N == 3:
+        out = out + p.theta3 * phi[0] ** 2 * phi[1] ** 2 * phi[2] ** 2
+    return out
+
+
+def dg_theta(phi, p):
+    """dg/dphi_a of Eq. Well1, differentiated by hand term by term."""
+    N = phi.shape[0]
+    out = []
+    for a in range(N):
+        acc = 2.0 * p.theta[a] * phi[a] * (1.0 - phi[a]) * (1.0 - 2.0 * phi[a])
+        for b in range(N):
+            if b != a:
+                acc = acc + 2.0 * p.theta_ab[min(a, b)][max(a, b)] * phi[a] * phi[b] ** 2
+        if N == 3:
+            rest = 1.0
+            for b in range(N):
+                if b != a:
+                    rest = rest * phi[b] ** 2
+            acc = acc + 2.0 * p.theta3 * phi[a] * rest
         out.append(acc)
     return np.stack(out)
 
@@ -439,6 +489,10 @@ def _rhs_padded(Pphi, Pmu, n, p, y_origin=0):
     psi = psi_phase(mu, T, p)
     dhm = dh(phi)
     dpsi = [sum(psi[b] * dhm[b][a] for b in range(p.nphases)) for a in range(p.nphases)]
+    if kks(p):
+        # Eq. aceq: gradient energy eps^2/2 a, potential g without a 1/eps
+        dg = dg_theta(phi, p) if p.potential == "theta" else dw(phi, p)
+        return 0.5 * p.eps ** 2 * grad - dg - np.stack(dpsi)
     return p.eps * grad - dw(phi, p) / p.eps - np.stack(dpsi)
 
 
@@ -451,7 +505,10 @@ def _step_padded(Pphi, Pmu, n, p, y_origin=0):
     # phase fields
     R = _rhs_padded(Pphi, Pmu, n, p, y_origin)
     lam = sum(R[a] for a in range(N)) / N
-    phin = phi + p.dt * (R - lam) / (relaxation(phi, p) * p.eps)
+    if kks(p):
+        phin = phi + p.dt * p.Mphi * (R - lam)
+    else:
+        phin = phi + p.dt * (R - lam) / (relaxation(phi, p) * p.eps)
     if p.potential == "obstacle":
         phin = obstacle_clip(phin)
     elif p.potential == "obstacle_active":
@@ -643,8 +700,8 @@ def adjoint_step(phi, mu, n, p, lphi1, lmu1):
     and 'tau'.  Written by hand, term by term, from the forward scheme of
     ``step``; only the isotropic multi-well variant is differentiable here.
     """
-    if p.potential != "well":
-        raise ValueError("adjoint: the obstacle projection is not differentiable")
+    if p.potential != "well" or kks(p):
+        raise ValueError("adjoint: the obstacle projection and the KKS variant are not supported")
     if extended(p):
         raise ValueError("adjoint: temperature-dependent B/C, off-diagonal A/D and per-pair tau "
                          "are not supported")
@@ -933,6 +990,8 @@ def step_antitrapping(phi, mu, n, p, y_origin=0):
         mu^{n+1} = mu^n + chi^-1 (dt div(M grad mu - j_at) - sum_a c^a(mu^n) [h_a(phi^{n+1}) - h_a(phi^n)] - Theta).
     phi^{n+1} and the rest of mu^{n+1} are those of ``step``; j_at is
     ``antitrapping_faces`` of (phi^n, phi^{n+1}, mu^n)."""
+    if kks(p):
+        raise ValueError("anti-trapping current: defined here for the grand-potential model only")
     phin, mun = step(phi, mu, n, p, y_origin)
     div = [0.0 * mu[k] for k in range(p.nmu)]
     for a, j in antitrapping_faces(phi, phin, mu, p, n, y_origin):
@@ -964,6 +1023,8 @@ def step_antitrapping_window(phi, mu, n, p, lo, hi, y_origin=0):
     """
     import itertools
 
+    if kks(p):
+        raise ValueError("anti-trapping current: defined here for the grand-potential model only")
     nd = p.dim
     bcs = [bc for _, bc in spatial_axes(p)][::-1]  # array order
     shape = phi.shape[1:]

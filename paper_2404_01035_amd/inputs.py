@@ -27,6 +27,14 @@ Parameter meaning follows the grand-potential model of MICROSIM
 * ``potential``    "well" (Eq. Well), "obstacle" (Eq. Obstacle; clip-and-renormalise
                    projection) or "obstacle_active" (Eq. Obstacle with the Lagrange
                    multiplier over the active phases: projection onto the simplex)
+* ``model``        "gp" (Sec. 2.1) or "kks": the KKS variant of Sec. 2.2, whose phase
+                   fields follow Eq. aceq: ``eps`` is then the gradient-energy coefficient
+                   of Eq. fe (the gradient term carries eps^2/2), ``Mphi`` the phase-field
+                   mobility M_phi (``tau`` and ``tau_ab`` unused), and the potential g is
+                   "well" (the form of Eq. Well without the 1/eps) or "theta" (Eq. Well1
+                   with ``theta[a]`` = Theta_a, ``theta_ab[a][b]`` = Theta_ab and
+                   ``theta3`` = Theta_abd); the diffusion potentials follow the same
+                   linearised update as the grand-potential model
 * ``Te``           temperature at which C^a is given (Equilibrium_temperature, Sec. 5)
 * ``T0, G, V, y0`` frozen, translating temperature field
                    T(y, t) = T0 + G (y - y0 - V t) (the Tempgrady input of Sec. 5:
@@ -65,7 +73,7 @@ class Params:
     nphases: int = 2                # N, the liquid is the last phase
     ncomp: int = 2                  # K, components; K - 1 independent mu fields
     precision: str = "f64"          # "f64" | "f32"
-    potential: str = "well"         # "well" | "obstacle" | "obstacle_active"
+    potential: str = "well"         # "well" | "obstacle" | "obstacle_active" | "theta" (KKS)
     eps: float = 4.0
     tau: float = 1.0
     dt: float = 0.05
@@ -82,6 +90,11 @@ class Params:
     A01: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
     D01: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
     tau_ab: np.ndarray = field(default_factory=_z33)
+    model: str = "gp"               # "gp" | "kks"
+    Mphi: float = 1.0               # KKS phase-field mobility
+    theta: np.ndarray = field(default_factory=lambda: np.zeros(MAX_PHASES))
+    theta_ab: np.ndarray = field(default_factory=_z33)
+    theta3: float = 0.0
     Te: float = 1.0
     T0: float = 1.0
     G: float = 0.0
@@ -107,7 +120,8 @@ class Params:
 
     def copy(self, **kw) -> "Params":
         p = replace(self, **kw)
-        for name in ("gamma", "delta", "A", "B", "C", "s", "D", "Bt", "Ct", "A01", "D01", "tau_ab"):
+        for name in ("gamma", "delta", "A", "B", "C", "s", "D", "Bt", "Ct", "A01", "D01", "tau_ab", "theta",
+                     "theta_ab"):
             if name not in kw:
                 setattr(p, name, np.array(getattr(self, name), dtype=np.float64))
         return p
@@ -233,8 +247,21 @@ def dt_limit(p: Params) -> float:
     tab = np.asarray(p.tau_ab)[:N, :N][np.triu_indices(N, 1)]
     if np.any(tab != 0.0):
         tau = min(tau, float(np.min(tab)))
+    if p.model == "kks":
+        # Eq. aceq: the gradient term's coefficient is M_phi eps^2/2 where the
+        # grand-potential model has 1/tau; the potential's stiffness
+        # max_a d^2 g/dphi_a^2 <= S bounds dt M_phi S <= 1 as well
+        tau = 2.0 / (p.Mphi * p.eps ** 2)
+        th = np.asarray(p.theta_ab)[:N, :N]
+        if p.potential == "theta":
+            S = max(2.0 * p.theta[a] + sum(2.0 * th[min(a, b), max(a, b)] for b in range(N) if b != a)
+                    for a in range(N))
+        else:
+            S = max(sum(18.0 * g[min(a, b), max(a, b)] for b in range(N) if b != a) for a in range(N))
+        if S > 0:
+            lim = 1.0 / (p.Mphi * S)
     if gmax > 0:
-        lim = base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax))
+        lim = min(lim, base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax)))
     Dm = np.asarray(p.D)[:N, :K1]
     if K1 == 2 and (np.any(np.asarray(p.A01)[:N] != 0.0) or np.any(np.asarray(p.D01)[:N] != 0.0)):
         chi = np.linalg.inv(hessians(np.asarray(p.A)[:N, :K1], np.asarray(p.A01)[:N]))
@@ -318,6 +345,29 @@ def binary_two_phase(dim=2, n=(64, 64, 1), bc=(0, 0, 0), precision="f64",
     p.G, p.V, p.y0 = 0.0, 0.0, 0.0
     p.dt = dt_frac * dt_limit(p)
     return p
+
+
+def kks_from(p: Params, eps_k=None, Mphi=None, potential="well", theta=None, theta_ab=None, theta3=0.0,
+             dt_frac=0.2) -> Params:
+    """The KKS variant (Sec. 2.2) of a parameter set: the same phases, free
+    energies, diffusivities, boundaries and temperature law; gradient-energy
+    coefficient eps_k (default 1.5 eps), mobility Mphi (default 2 / (tau eps_k^2),
+    the grand-potential set's relaxation of the gradient term), potential
+    "well" (Eq. Well's form with the same gamma) or "theta" (Eq. Well1; Theta_ab
+    defaults to 9 gamma_ab), dt a fraction of the explicit limit."""
+    eps_k = 1.5 * p.eps if eps_k is None else eps_k
+    q = p.copy(model="kks", eps=float(eps_k), potential=potential, tau_ab=_z33())
+    q.Mphi = 2.0 / (p.tau * eps_k ** 2) if Mphi is None else float(Mphi)
+    N = p.nphases
+    if theta is not None:
+        q.theta[:N] = theta
+    q.theta_ab[:] = 0.0
+    for a in range(N):
+        for b in range(a + 1, N):
+            q.theta_ab[a, b] = q.theta_ab[b, a] = 9.0 * p.gamma[a][b] if theta_ab is None else theta_ab[a][b]
+    q.theta3 = float(theta3)
+    q.dt = dt_frac * dt_limit(q)
+    return q
 
 
 def config_c1(seed: int = 0):
