@@ -59,32 +59,28 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "f86898c84c213454",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "42074847e62c031c",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5fb89be603452a04",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "de8ae63f6a4eb49b",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "61097bfcf3b534b5",
-                  "bytes": (2.0 * 385370.7 + 658378.8) * 1024},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "142350a8e9137e5d",
-                  "bytes": (2.0 * 225018.1 + 331609.6) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "85ca83f1ab392ead",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "1ef33a5a755a5a06",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "833c3e0a6559514a",
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "77be379c915cd8fa",
                 "bytes": (2.0 * 416826.7 + 659186.5) * 1024},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "833c3e0a6559514a",
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "77be379c915cd8fa",
                 "bytes": (2.0 * 247552.7 + 331791.2) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2",
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a",
                "bytes": (2.0 * 870583.4 + 270298.6) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2",
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a",
                "bytes": (2.0 * 462431.8 + 140617.0) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "f27333f9b37b87ce",
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "495ba759b06a6325",
                  "bytes": (2.0 * 2724874.4 + 574835.7) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "ba50631a53c3ae66",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "0abacedc1980a089",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
@@ -222,22 +218,20 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
 VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "f86898c84c213454", "insts": 153857451.0},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5fb89be603452a04", "insts": 138111444.0},
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "61097bfcf3b534b5", "insts": 236893983.0},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "142350a8e9137e5d", "insts": 173801142.0},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "42074847e62c031c", "insts": 153857451.0},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "de8ae63f6a4eb49b", "insts": 138111444.0},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "85ca83f1ab392ead", "insts": 545827325.3},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "1ef33a5a755a5a06", "insts": 545827325.3},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "833c3e0a6559514a", "insts": 203122347.0},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "833c3e0a6559514a", "insts": 145416750.0},
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "77be379c915cd8fa", "insts": 203122347.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "77be379c915cd8fa", "insts": 145416750.0},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2", "insts": 106811674.0},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "de435e535823d1b2", "insts": 78199324.0},
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a", "insts": 106811674.0},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a", "insts": 78199324.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "f27333f9b37b87ce", "insts": 654651392.0},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "495ba759b06a6325", "insts": 654651392.0},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "ba50631a53c3ae66", "insts": 468028690.0},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "0abacedc1980a089", "insts": 468028690.0},
 }
 VALU_CYCLES = {"f64": 4, "f32": 2}
 SIMDS = 1024         # 256 CUs x 4 SIMDs

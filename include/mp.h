@@ -69,7 +69,11 @@ enum { MP_FP64 = 0, MP_FP32 = 1 };
  * renormalising (MP_OBSTACLE) or with the Lagrange multiplier over the active
  * phases, i.e. the update's nearest point of the simplex {phi >= 0, sum phi = 1}
  * (MP_OBSTACLE_ACTIVE). */
-enum { MP_WELL = 0, MP_OBSTACLE = 1, MP_OBSTACLE_ACTIVE = 2 };
+enum { MP_WELL = 0, MP_OBSTACLE = 1, MP_OBSTACLE_ACTIVE = 2, MP_THETA = 3 };
+/* The model (Sec. 2): grand potential (Sec. 2.1), or the KKS variant (Sec.
+ * 2.2) whose phase fields follow Eq. aceq; MP_THETA, the sextic potential of
+ * Eq. Well1, is a KKS potential. */
+enum { MP_GP = 0, MP_KKS = 1 };
 
 typedef struct mp_state mp_state; /* opaque */
 
@@ -110,10 +114,23 @@ typedef struct {
  *   tau_ab       relaxation constant per phase pair (the Tau key of Sec. 5;
  *                symmetric, all > 0 or all 0): tau of Eq. phi_eqn becomes
  *                sum_{a<b} tau_ab phi_a phi_b / sum_{a<b} phi_a phi_b, and tau
- *                where that pair sum is <= 1e-30 */
+ *                where that pair sum is <= 1e-30
+ * KKS variant (model = MP_KKS; Sec. 2.2): the phase fields follow Eq. aceq,
+ *   (1/Mphi) dphi_a/dt = (eps^2/2)(div da/dgrad phi_a - da/dphi_a) - dg/dphi_a
+ *                        - sum_b psi^b dh_b/dphi_a - lambda,
+ *   with eps the gradient-energy coefficient of Eq. fe, the same a, faces and
+ *   driving force as above, and g of the form of Eq. Well (potential MP_WELL,
+ *   with gamma and gamma3, no 1/eps) or Eq. Well1 (MP_THETA):
+ *   sum_a theta[a] phi_a^2 (1-phi_a)^2 + sum_{a<b} theta_ab[a][b] phi_a^2 phi_b^2
+ *   + theta3 phi_0^2 phi_1^2 phi_2^2 (N = 3).  The diffusion potentials take
+ *   the same update (the linearised composition equation of Eq. cheq is Eq.
+ *   Mu_explicit_temperature).  tau and tau_ab are not read (tau_ab must be 0).
+ *   Mphi         phase-field mobility M_phi of Eq. aceq (> 0)
+ *   theta, theta_ab, theta3  the Theta coefficients of Eq. Well1 (>= 0;
+ *                theta_ab symmetric) */
 typedef struct {
     int32_t precision; /* MP_FP64 | MP_FP32 */
-    int32_t potential; /* MP_WELL | MP_OBSTACLE | MP_OBSTACLE_ACTIVE */
+    int32_t potential; /* MP_WELL | MP_OBSTACLE | MP_OBSTACLE_ACTIVE | MP_THETA (KKS) */
     double eps, tau, dt;
     double gamma[3][3];
     double gamma3;
@@ -125,6 +142,12 @@ typedef struct {
     double Bt[3][2], Ct[3];
     double A01[3], D01[3];
     double tau_ab[3][3];
+    int32_t model;     /* MP_GP | MP_KKS */
+    int32_t reserved;  /* 0 */
+    double Mphi;
+    double theta[3];
+    double theta_ab[3][3];
+    double theta3;
 } mp_params;
 
 /* Global diagnostics of the current state, reduced in FP64 with Neumaier
@@ -143,21 +166,27 @@ typedef struct {
  *                  min_k min_a chi^a_k / max_a (D^a_k chi^a_k) ), chi = 1/(2A);
  * with per-pair tau_ab the smallest of them and tau counts, and with A01 or D01
  * the mu part is min_a lambda_min(chi^a) / max_a |D^a chi^a|_2 (chi^a the
- * inverse curvature matrix), a bound on the eigenvalues of chi^-1 M.
+ * inverse curvature matrix), a bound on the eigenvalues of chi^-1 M.  KKS:
+ * tau is replaced by 2 / (Mphi eps^2) (the gradient term of Eq. aceq) and the
+ * potential's stiffness adds dt <= 1 / (Mphi S), S = max_a of
+ * 2 theta[a] + sum_b 2 theta_ab[a][b] (MP_THETA) or sum_b 18 gamma[a][b] (MP_WELL).
  * Returns a negative value for invalid input. */
 double mp_dt_limit(const mp_grid* grid, int nphases, int ncomp, const mp_params* params);
 
 /* Validate the problem and build a solver state (host only, no GPU needed):
  * the grand-potential step of Sec. 2.1 (Eq. phi_eqn for the phase fields, Eq.
- * Mu_explicit_temperature for the diffusion potentials) on this grid.
+ * Mu_explicit_temperature for the diffusion potentials) on this grid, or with
+ * model = MP_KKS the KKS variant of Sec. 2.2 (Eq. aceq for the phase fields).
  * nphases N in {2, 3}; ncomp K in {2, 3} (K - 1 diffusion potentials).  A
- * problem that uses the extended model (non-zero Bt, Ct, A01, D01 or tau_ab, or
- * MP_OBSTACLE_ACTIVE) runs the general kernels: one cell per lane in 2D and
- * 64 x 4 tiles in 3D whatever mp_set_tile says (batched instances too, and
- * with the anti-trapping current); the adjoint does not take it.
- * Errors: MP_E_NULLPTR, MP_E_PARAM (dim, n, bc, dx, N, K, precision,
- * potential, eps, tau, A, D, gamma, delta or an extended coefficient out of
- * range), MP_E_UNSTABLE. */
+ * problem that uses the extended model (non-zero Bt, Ct, A01, D01 or tau_ab,
+ * MP_OBSTACLE_ACTIVE, or the KKS potential MP_THETA) runs the general
+ * kernels: one cell per lane in 2D and 64 x 4 tiles in 3D whatever
+ * mp_set_tile says (batched instances too, and with the anti-trapping
+ * current); the adjoint does not take it.  The KKS variant with MP_WELL runs
+ * the plain kernels with its own folded coefficients.
+ * Errors: MP_E_NULLPTR, MP_E_PARAM (dim, n, bc, dx, N, K, precision, model,
+ * potential, eps, tau, Mphi, A, D, gamma, delta, theta or an extended
+ * coefficient out of range), MP_E_UNSTABLE. */
 int mp_create(const mp_grid* grid, int nphases, int ncomp, const mp_params* params,
               mp_state** out);
 
@@ -292,7 +321,7 @@ int mp_get_fusion(const mp_state* st, int* steps);
  * tau_ab, MP_OBSTACLE_ACTIVE) the compositions of the current are those at each
  * row's temperature of time level n and the correction solves with the 2 x 2
  * susceptibility.  Errors: MP_E_NULLPTR, MP_E_PARAM (on not 0, 1 or 2),
- * MP_E_STATE (on = 2 for a batch). */
+ * MP_E_STATE (on = 2 for a batch; on != 0 for a state with a KKS instance). */
 int mp_set_antitrapping(mp_state* st, int on);
 int mp_get_antitrapping(const mp_state* st, int* on);
 
@@ -356,7 +385,8 @@ size_t mp_adjoint_work_bytes(const mp_state* st, int64_t every);
  * segment runs on a second stream (created on first use, kept until
  * mp_destroy) while the current one is swept.  Results do not depend on
  * ``every`` (bitwise).  Synchronises ``stream``.  Errors: MP_E_STATE (batched
- * state), MP_E_PARAM (3D, obstacle, anisotropy, bad sizes or alignment). */
+ * state), MP_E_PARAM (3D, obstacle, anisotropy, the KKS variant, bad sizes or
+ * alignment). */
 int mp_adjoint(mp_state* st, const void* ckpt_buf, int64_t nsteps, int64_t every, int64_t n0,
                const void* lam_final, void* lam_initial, double* grad_theta, void* work,
                void* stream);

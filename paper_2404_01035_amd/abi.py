@@ -18,8 +18,10 @@ MP_E_PARAM, MP_E_UNSTABLE, MP_E_NULLPTR, MP_E_UNBOUND, MP_E_HIP, MP_E_NONFINITE,
     -1, -2, -3, -4, -5, -6, -7)
 MP_BC_PERIODIC, MP_BC_NOFLUX = 0, 1
 MP_FP64, MP_FP32 = 0, 1
-MP_WELL, MP_OBSTACLE, MP_OBSTACLE_ACTIVE = 0, 1, 2
-POTENTIALS = {"well": MP_WELL, "obstacle": MP_OBSTACLE, "obstacle_active": MP_OBSTACLE_ACTIVE}
+MP_WELL, MP_OBSTACLE, MP_OBSTACLE_ACTIVE, MP_THETA = 0, 1, 2, 3
+POTENTIALS = {"well": MP_WELL, "obstacle": MP_OBSTACLE, "obstacle_active": MP_OBSTACLE_ACTIVE, "theta": MP_THETA}
+MP_GP, MP_KKS = 0, 1
+MODELS = {"gp": MP_GP, "kks": MP_KKS}
 
 ERROR_NAMES = {
     MP_E_PARAM: "MP_E_PARAM", MP_E_UNSTABLE: "MP_E_UNSTABLE", MP_E_NULLPTR: "MP_E_NULLPTR",
@@ -57,6 +59,8 @@ class mp_params(C.Structure):
         ("y0", C.c_double),
         ("Bt", (C.c_double * 2) * 3), ("Ct", C.c_double * 3), ("A01", C.c_double * 3), ("D01", C.c_double * 3),
         ("tau_ab", (C.c_double * 3) * 3),
+        ("model", C.c_int32), ("reserved", C.c_int32), ("Mphi", C.c_double),
+        ("theta", C.c_double * 3), ("theta_ab", (C.c_double * 3) * 3), ("theta3", C.c_double),
     ]
 
 
@@ -204,6 +208,15 @@ def to_params(p) -> mp_params:
             c.Bt[a][k] = float(Bt[a, k])
         for b in range(3):
             c.tau_ab[a][b] = float(tab[a, b])
+    c.model = MODELS[getattr(p, "model", "gp")]
+    c.Mphi = float(getattr(p, "Mphi", 1.0))
+    th = np.asarray(getattr(p, "theta", np.zeros(3)), dtype=np.float64)
+    thab = np.asarray(getattr(p, "theta_ab", np.zeros((3, 3))), dtype=np.float64)
+    for a in range(3):
+        c.theta[a] = float(th[a])
+        for b in range(3):
+            c.theta_ab[a][b] = float(thab[a, b])
+    c.theta3 = float(getattr(p, "theta3", 0.0))
     return c
 
 

@@ -141,10 +141,31 @@ int check_params(int N, int K, const mp_params* p) {
     if (K != 2 && K != 3) return fail(MP_E_PARAM, "ncomp must be 2 or 3 (got %d)", K);
     if (p->precision != MP_FP64 && p->precision != MP_FP32)
         return fail(MP_E_PARAM, "precision must be MP_FP64 or MP_FP32");
-    if (p->potential != MP_WELL && p->potential != MP_OBSTACLE && p->potential != MP_OBSTACLE_ACTIVE)
+    if (p->model != MP_GP && p->model != MP_KKS) return fail(MP_E_PARAM, "model must be MP_GP or MP_KKS");
+    if (p->model == MP_GP && p->potential != MP_WELL && p->potential != MP_OBSTACLE &&
+        p->potential != MP_OBSTACLE_ACTIVE)
         return fail(MP_E_PARAM, "potential must be MP_WELL, MP_OBSTACLE or MP_OBSTACLE_ACTIVE");
+    if (p->model == MP_KKS && p->potential != MP_WELL && p->potential != MP_THETA)
+        return fail(MP_E_PARAM, "the KKS variant takes MP_WELL (Eq. Well) or MP_THETA (Eq. Well1)");
     if (!(p->eps > 0) || !finite(p->eps)) return fail(MP_E_PARAM, "eps must be positive and finite");
-    if (!(p->tau > 0)) return fail(MP_E_PARAM, "tau must be positive");
+    if (p->model == MP_GP && !(p->tau > 0)) return fail(MP_E_PARAM, "tau must be positive");
+    if (p->model == MP_KKS) {
+        if (!(p->Mphi > 0) || !finite(p->Mphi)) return fail(MP_E_PARAM, "Mphi must be positive and finite");
+        if (!(p->theta3 >= 0) || !finite(p->theta3)) return fail(MP_E_PARAM, "theta3 must be >= 0 and finite");
+        for (int a = 0; a < N; ++a) {
+            if (!(p->theta[a] >= 0) || !finite(p->theta[a]))
+                return fail(MP_E_PARAM, "theta[%d] must be >= 0 and finite", a);
+            for (int b = 0; b < N; ++b) {
+                if (a == b) continue;
+                if (!(p->theta_ab[a][b] >= 0) || !finite(p->theta_ab[a][b]))
+                    return fail(MP_E_PARAM, "theta_ab[%d][%d] must be >= 0 and finite", a, b);
+                if (p->theta_ab[a][b] != p->theta_ab[b][a])
+                    return fail(MP_E_PARAM, "theta_ab must be symmetric (theta_ab[%d][%d])", a, b);
+                if (p->tau_ab[a][b] != 0.0)
+                    return fail(MP_E_PARAM, "the KKS variant relaxes with Mphi: tau_ab must be 0");
+            }
+        }
+    }
     if (!(p->dt > 0) || !finite(p->dt)) return fail(MP_E_PARAM, "dt must be positive and finite");
     for (int a = 0; a < N; ++a)
         for (int b = 0; b < N; ++b) {
@@ -218,8 +239,12 @@ void diff_of(const mp_params& p, int a, int K, double D[2][2]) {
     D[0][1] = D[1][0] = K == 3 ? p.D01[a] : 0.0;
 }
 
+// The kernels' potential switch: Eq. Well1 runs in the multi-well kernels
+// (general instances, CoefX::well1).
+int kernel_potential(int potential) { return potential == MP_THETA ? MP_WELL : potential; }
+
 bool uses_extended(int N, int K, const mp_params& p) {
-    if (p.potential == MP_OBSTACLE_ACTIVE) return true;
+    if (p.potential == MP_OBSTACLE_ACTIVE || p.potential == MP_THETA) return true;
     for (int a = 0; a < N; ++a) {
         if (p.Ct[a] != 0.0) return true;
         for (int k = 0; k < K - 1; ++k)
@@ -241,7 +266,21 @@ double dt_limit_of(const mp_grid* g, int N, int K, const mp_params* p) {
         }
     const double base = g->dx * g->dx / (2.0 * g->dim);
     double lim = INFINITY;
-    if (gmax > 0) lim = base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax));
+    if (p->model == MP_KKS) {
+        // Eq. aceq: the gradient term's coefficient is Mphi eps^2/2 where the
+        // grand-potential model has 1/tau; the potential's stiffness
+        // max_a d^2 g/dphi_a^2 <= S bounds dt Mphi S <= 1 as well
+        tau = 2.0 / (p->Mphi * p->eps * p->eps);
+        double S = 0.0;
+        for (int a = 0; a < N; ++a) {
+            double sa = p->potential == MP_THETA ? 2.0 * p->theta[a] : 0.0;
+            for (int b = 0; b < N; ++b)
+                if (b != a) sa += p->potential == MP_THETA ? 2.0 * p->theta_ab[a][b] : 18.0 * p->gamma[a][b];
+            S = std::fmax(S, sa);
+        }
+        if (S > 0) lim = 1.0 / (p->Mphi * S);
+    }
+    if (gmax > 0) lim = std::fmin(lim, base * tau / (2.0 * gmax * (N - 1) / N * (1.0 + 20.0 * dmax)));
     bool cross = false;
     for (int a = 0; a < N && K == 3; ++a) cross = cross || p->A01[a] != 0.0 || p->D01[a] != 0.0;
     if (cross) {
@@ -313,19 +352,26 @@ mp::Coef<R> make_coef(const Inst& I) {
     const double dx = I.grid.dx;
     mp::Coef<R> c;
     std::memset(&c, 0, sizeof c);
-    c.cE = (R)(p.eps / (2.0 * dx));
-    c.kphi = (R)(p.dt / (p.tau * p.eps));
+    const bool kks = p.model == MP_KKS;
+    // the bracket of Eq. phi_eqn is eps G - w_{,a}/eps - psi_{,a} - lambda with
+    // the rate 1/(tau eps); that of Eq. aceq (KKS) is eps^2/2 G - g_{,a} -
+    // psi_{,a} - lambda with the rate Mphi
+    c.cE = (R)((kks ? 0.5 * p.eps * p.eps : p.eps) / (2.0 * dx));
+    c.kphi = (R)(kks ? p.dt * p.Mphi : p.dt / (p.tau * p.eps));
     c.qguard = (R)(4.0 * dx * dx * 1e-30);
-    const double wfac = p.potential != MP_WELL ? 16.0 / (M_PI * M_PI) : 18.0;  // both obstacle projections
+    const double wfac = p.potential == MP_OBSTACLE || p.potential == MP_OBSTACLE_ACTIVE ? 16.0 / (M_PI * M_PI)
+                                                                                        : 18.0;
+    const double weps = kks ? 1.0 : p.eps;
     const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
     for (int q = 0; q < 3; ++q) {
         const double g = p.gamma[pa[q]][pb[q]];
         c.g4d[q] = (R)(4.0 * g / dx);
         c.gd[q] = (R)(g / dx);
         c.del[q] = (R)p.delta[pa[q]][pb[q]];
-        c.wce[q] = (R)(wfac * g / p.eps);
+        // Eq. Well1's pair term Theta_ab phi_a^2 phi_b^2 has the form of Eq. Well's 9 gamma_ab
+        c.wce[q] = (R)(p.potential == MP_THETA ? 2.0 * p.theta_ab[pa[q]][pb[q]] : wfac * g / weps);
     }
-    c.g3e = (R)(p.gamma3 / p.eps);
+    c.g3e = (R)(p.potential == MP_THETA ? 0.0 : p.gamma3 / weps);
     const double dtf = p.dt / (2.0 * dx * dx);
     for (int a = 0; a < I.N; ++a) {
         c.C[a] = (R)p.C[a];
@@ -378,6 +424,11 @@ mp::CoefX<R> make_coefx(const Inst& I) {
     }
     x.ktau = (R)(p.dt / p.eps);
     x.proj = p.potential == MP_OBSTACLE_ACTIVE ? 1 : 0;
+    // Eq. Well1 beyond its pair terms: 2 Theta_a phi_a (1 - phi_a)(1 - 2 phi_a) and
+    // 2 Theta_abd phi_a phi_b^2 phi_d^2 in dg/dphi_a
+    x.well1 = p.potential == MP_THETA ? 1 : 0;
+    for (int a = 0; a < I.N; ++a) x.th1[a] = (R)(p.potential == MP_THETA ? 2.0 * p.theta[a] : 0.0);
+    x.th3 = (R)(p.potential == MP_THETA ? 2.0 * p.theta3 : 0.0);
     return x;
 }
 
@@ -736,7 +787,7 @@ int make_single_call(mp_state* st, const void* in, void* out, const int64_t* ctr
     L.nphases = I.N;
     L.nmu = I.K - 1;
     L.dim = I.grid.dim;
-    L.potential = I.prm.potential;
+    L.potential = kernel_potential(I.prm.potential);
     L.aniso = I.aniso ? 1 : 0;
     L.bx = st->bx;
     L.seg = st->seg;
@@ -857,7 +908,7 @@ void init_state(mp_state* st) {
     for (const Inst& I : st->inst) st->aniso = st->aniso || I.aniso;
     st->precision = st->inst[0].prm.precision;
     st->vec = -1;
-    st->potential = st->inst[0].prm.potential;
+    st->potential = kernel_potential(st->inst[0].prm.potential);
     if (st->inst[0].grid.dim == 3) {
         // measured best on 512^3 FP32: tall tiles, long z segments
         st->bx = d3_tall_ok(st) ? 512 : 256;
@@ -1067,6 +1118,7 @@ int adj_supported(const mp_state* st) {
     if (I.ext)
         return fail(MP_E_PARAM, "adjoint: the extended model (Bt, Ct, A01, D01, tau_ab, MP_OBSTACLE_ACTIVE) is not supported");
     if (I.grid.dim != 2) return fail(MP_E_PARAM, "adjoint: 2D grids only");
+    if (I.prm.model != MP_GP) return fail(MP_E_PARAM, "adjoint: the KKS variant is not supported");
     if (I.prm.potential != MP_WELL) return fail(MP_E_PARAM, "adjoint: the obstacle projection is not differentiable");
     if (I.aniso) return fail(MP_E_PARAM, "adjoint: anisotropic gradient energy not supported");
     return MP_OK;
@@ -1178,7 +1230,7 @@ int mp_create_batch(int ninst, const mp_grid* grids, const int* nphases, const i
         if (rc == MP_OK && grids[i].dim != 2) rc = fail(MP_E_PARAM, "%sbatched grids must be 2D", who);
         if (rc == MP_OK && i > 0 && params[i].precision != params[0].precision)
             rc = fail(MP_E_PARAM, "%sall instances must share one precision", who);
-        if (rc == MP_OK && i > 0 && params[i].potential != params[0].potential)
+        if (rc == MP_OK && i > 0 && kernel_potential(params[i].potential) != kernel_potential(params[0].potential))
             rc = fail(MP_E_PARAM, "%sall instances must share one potential", who);
         if (rc) {
             delete st;
@@ -1519,6 +1571,10 @@ int mp_set_antitrapping(mp_state* st, int on) {
     if (on < 0 || on > 2) return fail(MP_E_PARAM, "on must be 0, 1 or 2 (got %d)", on);
     if (on == 2 && st->batch)
         return fail(MP_E_STATE, "anti-trapping current: batched states take it folded into the step (on = 1) only");
+    if (on != 0)
+        for (const Inst& I : st->inst)
+            if (I.prm.model == MP_KKS)
+                return fail(MP_E_STATE, "anti-trapping current: built for the grand-potential model only");
     drop_graphs(st);
     const int was = st->antitrap;
     st->antitrap = on;

@@ -53,6 +53,9 @@ struct CoefX {
     R ktau;         // dt / eps
     int32_t tpair;  // 1: tau(phi) from tab; 0: the single tau (Coef::kphi)
     int32_t proj;   // obstacle projection: 0 clip and renormalise, 1 onto the simplex (active set)
+    int32_t well1;  // 1: the KKS potential of Eq. Well1 (its pair terms sit in Coef::wce)
+    R th1[3];       // 2 Theta_a
+    R th3;          // 2 Theta_abd
 };
 
 // Coefficients the FP64 diagnostics reduction needs.

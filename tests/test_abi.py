@@ -239,6 +239,7 @@ def test_adjoint_rejects_unsupported_variants_without_gpu():
     q.dt = 0.2 * inputs.dt_limit(q)
     cases.append((q, abi.MP_E_PARAM, "anisotropic"))
     cases.append((inputs.dendrite_params(n=(8, 8, 8), delta=0.0), abi.MP_E_PARAM, "2D"))
+    cases.append((inputs.kks_from(p), abi.MP_E_PARAM, "KKS"))
     buf = C.c_void_p(256)
     g = (C.c_double * 10)()
     for prm, code, word in cases:
@@ -409,3 +410,59 @@ def test_mp_log_echoes_failures_to_stderr():
     assert "[mpstep] error -1: nphases must be 2 or 3" in r.stderr
     quiet = _in_subprocess(code, {"MP_LOG": "0"})
     assert "[mpstep]" not in quiet.stderr
+
+
+def _kks_base(potential="well"):
+    p, _, _ = inputs.config_c2(n=(64, 48, 1))
+    return inputs.kks_from(p, potential=potential, theta=[0.2, 0.3, 0.1], theta3=0.5)
+
+
+@pytest.mark.parametrize("potential", ["well", "theta"])
+def test_kks_dt_limit_matches_input_formula(potential):
+    p = _kks_base(potential)
+    assert math.isclose(abi.mp_dt_limit(p), inputs.dt_limit(p), rel_tol=1e-14)
+    if potential == "theta":
+        # a stiff potential takes over from the gradient term
+        q = p.copy()
+        q.theta[0] = 400.0
+        assert inputs.dt_limit(q) < inputs.dt_limit(p)
+        assert math.isclose(abi.mp_dt_limit(q), inputs.dt_limit(q), rel_tol=1e-14)
+    st = abi.mp_create(p)
+    abi.mp_destroy(st)
+
+
+def test_kks_validation_without_gpu():
+    p = _kks_base("theta")
+    _expect(abi.MP_E_PARAM, p.copy(Mphi=0.0), "Mphi")
+    _expect(abi.MP_E_PARAM, p.copy(potential="obstacle"), "KKS")
+    q = p.copy()
+    q.theta[1] = -1.0
+    _expect(abi.MP_E_PARAM, q, "theta\\[1\\]")
+    q = p.copy()
+    q.theta_ab[0, 1] = 2.0  # asymmetric
+    _expect(abi.MP_E_PARAM, q, "theta_ab")
+    q = p.copy()
+    q.tau_ab[0, 1] = q.tau_ab[1, 0] = 1.0
+    _expect(abi.MP_E_PARAM, q, "tau_ab")
+    # Eq. Well1 is a KKS potential
+    g, _, _ = inputs.config_c2(n=(64, 48, 1))
+    _expect(abi.MP_E_PARAM, g.copy(potential="theta"), "potential")
+    import ctypes as C
+    c = abi.to_params(p)
+    c.model = 5
+    h = C.c_void_p()
+    assert abi.lib().mp_create(C.byref(abi.to_grid(p)), 3, 3, C.byref(c), C.byref(h)) == abi.MP_E_PARAM
+    assert "model" in abi.mp_last_error()
+    # KKS does not read tau
+    st = abi.mp_create(p.copy(tau=-1.0))
+    abi.mp_destroy(st)
+
+
+def test_kks_refuses_the_current_without_gpu():
+    st = abi.mp_create(_kks_base("well"))
+    try:
+        assert abi.lib().mp_set_antitrapping(st, 1) == abi.MP_E_STATE
+        assert "grand-potential" in abi.mp_last_error()
+        assert abi.lib().mp_set_antitrapping(st, 0) == abi.MP_OK
+    finally:
+        abi.mp_destroy(st)
