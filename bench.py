@@ -59,32 +59,32 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "42074847e62c031c",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "8c827609c4fc2113",
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "de8ae63f6a4eb49b",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "22fef4302647ba4c",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "1ef33a5a755a5a06",
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "77be379c915cd8fa",
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "0e5cdd010387cb4d",
                 "bytes": (2.0 * 416826.7 + 659186.5) * 1024},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "77be379c915cd8fa",
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "0e5cdd010387cb4d",
                 "bytes": (2.0 * 247552.7 + 331791.2) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a",
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc",
                "bytes": (2.0 * 870583.4 + 270298.6) * 1024},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a",
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc",
                "bytes": (2.0 * 462431.8 + 140617.0) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "495ba759b06a6325",
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "7f9e2fd3fc58094e",
                  "bytes": (2.0 * 2724874.4 + 574835.7) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "0abacedc1980a089",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "43d11e31e1a8fcb8",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
-ALL_LEGS = ("c2", "c3", "c4", "c5", "at", "ext")
+ALL_LEGS = ("c2", "c3", "c4", "c5", "at", "ext", "kks")
 
 
 def parse():
@@ -165,7 +165,7 @@ def roofline(bytes_per_step, ms_step, traffic=None):
             "traffic": None if traffic is None else round(traffic)}
 
 
-def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False, ext=False):
+def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False, ext=False, well1=False):
     """Floating-point operations (an FMA counts 2) of one cell update of the
     multi-well step as the kernels evaluate it, each face once: the cell
     record (h, mobility), one face per axis, the face sums, h of the old phi,
@@ -175,7 +175,9 @@ def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False, ext=False):
     normal component of d(a_c^2 |q|^2)/dq (one reciprocal square root).  The
     extended model's general cell (ext) adds B(T) and the quadratic C(T), the
     dT/dt term, for two mu fields the off-diagonal susceptibility terms, the
-    mobility matrix with its face products and the 2 x 2 solve, and tau(phi)."""
+    mobility matrix with its face products and the 2 x 2 solve, and tau(phi).
+    The KKS potential of Eq. Well1 (well1, general cell) adds per phase
+    2 Theta_a (1 - phi_a)(1 - 2 phi_a) (6) and, for N = 3, 2 Theta_abd phi_b^2 phi_d^2 (3)."""
     n, m, d = nphases, ncomp - 1, dim
     pairs = n * (n - 1) // 2
     h = 5 * n + 3 if n == 3 else 4 * n
@@ -200,6 +202,8 @@ def flops_per_cell_update(nphases, ncomp, dim=2, aniso=False, ext=False):
         extra = 3 * n * m + 2 * n + 2 * n * m + 14  # B(T), C(T)^2 term, Theta, tau(phi)
         if m == 2:
             extra += 4 * n + 6 * d + 2 * (2 * n - 1) + 4  # cross chi, face J products, M matrix, solve
+    if well1:
+        extra += n * (6 + (3 if n == 3 else 0))
     return record + faces + sums + h + cell + extra
 
 
@@ -218,20 +222,20 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
 VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "42074847e62c031c", "insts": 153857451.0},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "de8ae63f6a4eb49b", "insts": 138111444.0},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "8c827609c4fc2113", "insts": 153857451.0},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "22fef4302647ba4c", "insts": 138111444.0},
     # profiles/k_step3d_dendrite_512_f32.md
-    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "1ef33a5a755a5a06", "insts": 545827325.3},
+    "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136", "insts": 545827325.3},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "77be379c915cd8fa", "insts": 203122347.0},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "77be379c915cd8fa", "insts": 145416750.0},
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "0e5cdd010387cb4d", "insts": 203122347.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "0e5cdd010387cb4d", "insts": 145416750.0},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
-    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a", "insts": 106811674.0},
-    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "69e84ebb0b684a7a", "insts": 78199324.0},
+    "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 106811674.0},
+    "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 78199324.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "495ba759b06a6325", "insts": 654651392.0},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "7f9e2fd3fc58094e", "insts": 654651392.0},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "0abacedc1980a089", "insts": 468028690.0},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "43d11e31e1a8fcb8", "insts": 468028690.0},
 }
 VALU_CYCLES = {"f64": 4, "f32": 2}
 SIMDS = 1024         # 256 CUs x 4 SIMDs
@@ -397,14 +401,19 @@ def diag_timing(s, fuse, reps=REGIONS):
     return out
 
 
-def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
+def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False, kks=None):
     """The 4096^2 eutectic; slopes: with temperature-dependent coefficients
-    (the general kernels of the extended model)."""
+    (the general kernels of the extended model); kks: the KKS variant with the
+    potential of Eq. Well's form ("well", the plain kernels) or Eq. Well1
+    ("theta", the general kernels)."""
     from paper_2404_01035_amd import abi, inputs
     from paper_2404_01035_amd.solver import Solver
 
     cfg = inputs.config_c2_slopes if slopes else inputs.config_c2
     p, phi, mu = cfg(precision=precision, n=(n, n, 1))
+    if kks:
+        p = inputs.kks_from(p, potential=kks, theta=[0.3, 0.2, 0.4] if kks == "theta" else None,
+                            theta3=0.6 if kks == "theta" else 0.0)
     s = Solver(p)
     s.load(phi, mu)
     del phi, mu
@@ -420,13 +429,13 @@ def leg_c2(precision, n, steps, warmup, tile, tune, slopes=False):
     fuse = abi.mp_get_fusion(s.st)
     ms, regions, settle = measure(s.step, steps, warmup)
     d = s.diagnostics()
-    dt = None if slopes else diag_timing(s, fuse)
+    dt = None if (slopes or kks) else diag_timing(s, fuse)
     s.close()
     elem = 8 if precision == "f64" else 4
     bpc = p.nfields * 2 * elem  # read + write of every field once
-    fpc = flops_per_cell_update(p.nphases, p.ncomp, ext=slopes)
+    fpc = flops_per_cell_update(p.nphases, p.ncomp, ext=slopes or kks == "theta", well1=kks == "theta")
     ms_step = ms / steps
-    leg = f"c2{'ext' if slopes else ''}_{precision}"
+    leg = f"c2{'ext' if slopes else ''}{'kks' + kks if kks else ''}_{precision}"
     traffic = traffic_of(leg, used, fuse)
     return {
         "value": p.ncells * steps / (ms * 1e-3),
@@ -874,6 +883,14 @@ def main():
             "f64": leg_c2("f64", a.n, a.steps, a.warmup, None, False, slopes=True),
             "f32": dict(leg_c2("f32", a.n, a.steps, a.warmup, None, False, slopes=True),
                         dtype="f32 (FP64 Lagrange multiplier and reductions)"),
+        }
+    if "kks" in legs:
+        log(f"KKS variant: {a.n}x{a.n} eutectic, Eq. Well's form and Eq. Well1")
+        out["kks"] = {
+            "workload": f"2D {a.n}x{a.n} directional eutectic, KKS variant (Eq. aceq), FP64, two steps per "
+                        "launch: the potential of Eq. Well's form (plain kernels) and Eq. Well1 (general kernels)",
+            "well_f64": leg_c2("f64", a.n, a.steps, a.warmup, None, False, kks="well"),
+            "theta_f64": leg_c2("f64", a.n, a.steps, a.warmup, None, False, kks="theta"),
         }
     out["copy_bandwidth"] = copy_bandwidth(a.n)
     if not a.no_cpu:

@@ -411,15 +411,6 @@ __device__ __forceinline__ void cell_update_gen(const R (&phi)[NP], const R (&mu
             else
                 dw = dw + wc * sq[b];
         }
-        if constexpr (!OBST) {
-            // Eq. Well1 (KKS): dg/dphi_a = phi_a [sum_b 2 Theta_ab phi_b^2 (in wce)
-            // + 2 Theta_a (1 - phi_a)(1 - 2 phi_a) + 2 Theta_abd phi_b^2 phi_d^2]
-            if (x.well1) {
-                R e = x.th1[a] * ((R(1) - phi[a]) * (R(1) - R(2) * phi[a]));
-                if constexpr (NP == 3) e = e + x.th3 * (sq[(a + 1) % 3] * sq[(a + 2) % 3]);
-                dw = dw + e;
-            }
-        }
         const R t3 = R(3) - R(3) * phi[a];
         R Y;
         if constexpr (OBST)
@@ -428,6 +419,19 @@ __device__ __forceinline__ void cell_update_gen(const R (&phi)[NP], const R (&mu
             Y = phi[a] * (dw + psi2[a] * t3);
         if constexpr (NP == 3) Y = Y + P[a] * Z;
         Rr[a] = c.cE * Gs[a] - Y;
+    }
+    if constexpr (!OBST) {
+        // Eq. Well1 (KKS): dg/dphi_a = phi_a [sum_b 2 Theta_ab phi_b^2 (in wce)
+        // + 2 Theta_a (1 - phi_a)(1 - 2 phi_a) + 2 Theta_abd phi_b^2 phi_d^2]; one
+        // uniform branch around all phases, so that the other states skip it
+        if (x.well1) {
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                R e = x.th1[a] * ((R(1) - phi[a]) * (R(1) - R(2) * phi[a]));
+                if constexpr (NP == 3) e = e + x.th3 * (sq[(a + 1) % 3] * sq[(a + 2) % 3]);
+                Rr[a] = Rr[a] - phi[a] * e;
+            }
+        }
     }
     double lam = 0.0;
 #pragma unroll
