@@ -63,6 +63,11 @@ TRAFFIC = {
                "bytes": (2.0 * 388809.3 + 665712.5) * 1024},
     "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "22fef4302647ba4c",
                "bytes": (2.0 * 224223.4 + 333893.5) * 1024},
+    # profiles/k_step2d_x2_gen_eutectic_4096_f64_f32.md
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "41cef1c31fdd73bc",
+                  "bytes": (2.0 * 384876.0 + 656564.4) * 1024},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "7ac86cba69b90d38",
+                  "bytes": (2.0 * 224329.2 + 329085.2) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
@@ -224,6 +229,9 @@ VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
     "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "8c827609c4fc2113", "insts": 153857451.0},
     "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "22fef4302647ba4c", "insts": 138111444.0},
+    # profiles/k_step2d_x2_gen_eutectic_4096_f64_f32.md
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "41cef1c31fdd73bc", "insts": 229763385.0},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "7ac86cba69b90d38", "insts": 176406168.0},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136", "insts": 545827325.3},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
