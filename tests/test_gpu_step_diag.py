@@ -189,3 +189,15 @@ def test_matches_oracle_diagnostics():
     for a in range(3):
         assert abs(d["volume"][a] - o["volume"][a]) <= 1e-10 * abs(o["volume"][a])
     assert abs(d["max_sum_dev"] - o["max_sum_dev"]) <= 1e-12
+
+
+def test_more_records_than_the_workspace_holds_takes_the_separate_pass():
+    # one-row segments on a 1200 x 4000 grid: 20 strips x 4000 segments = 80,000 wave records,
+    # beyond the 65,536 the workspace holds, so the last launch runs plainly and the separate
+    # pass reduces: the same numbers as mp_step + mp_diagnostics, sums included
+    p, phi, mu = inputs.config_c2(n=(1200, 4000, 1))
+
+    def setup(s):
+        s.set_tile(256, 1, 1)
+
+    _check(p, phi, mu, 2, setup, rel=0.0)
