@@ -82,8 +82,8 @@ TRAFFIC = {
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc",
                "bytes": (2.0 * 462431.8 + 140617.0) * 1024},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "7f9e2fd3fc58094e",
-                 "bytes": (2.0 * 2724874.4 + 574835.7) * 1024},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "827edfbe96172ad2",
+                 "bytes": (2.0 * 2125895.1 + 581596.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "43d11e31e1a8fcb8",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
@@ -241,7 +241,7 @@ VALU = {
     "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 106811674.0},
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 78199324.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
-    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "7f9e2fd3fc58094e", "insts": 654651392.0},
+    "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "827edfbe96172ad2", "insts": 654686208.0},
     # profiles/k_batch2d_ensemble_256_f32.md
     "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "43d11e31e1a8fcb8", "insts": 468028690.0},
 }

@@ -15,9 +15,12 @@
 //     above and below);
 //   z faces: the face to plane m+1 is evaluated once and carried as the lower
 //     face of the next plane.
-// The four waves of a block take consecutive row groups of one strip, and
-// blocks are dealt XCD-aware, so the halo rows the groups share are found in
-// one XCD's L2.
+// Work items run strip-fastest (strip, then row group, then z segment) and
+// blocks are dealt XCD-aware, so the strips of one row group run together on
+// one XCD: the 128-byte lines where two strips' 64-column rows overlap (a
+// strip's rows start one column before its first column) are fetched once
+// into that XCD's L2, and the row groups above and below, a few blocks away,
+// share their halo rows there too.
 #pragma once
 
 #include "antitrap2d.hpp"
@@ -131,10 +134,10 @@ __device__ __forceinline__ void antitrap3d_wave(const R* __restrict__ prev, R* _
     const int item = __builtin_amdgcn_readfirstlane(blk * AT3_WAVES + (int)(threadIdx.x >> 6));
     if (item >= nitems) return;  // whole waves only; nothing below synchronises
     const int lane = (int)(threadIdx.x & 63);
-    const int yg = item % nygroups;
-    const int rest = item / nygroups;
-    const int strip = rest % nstrips;
-    const int z0 = (rest / nstrips) * AT3_SEG;
+    const int strip = item % nstrips;
+    const int rest = item / nstrips;
+    const int yg = rest % nygroups;
+    const int z0 = (rest / nygroups) * AT3_SEG;
     const int z1 = z0 + AT3_SEG < g.nz ? z0 + AT3_SEG : g.nz;
     const int y0 = yg * BY;
     const int craw = strip * AT3_LANES_OUT - 1 + lane;  // -1 .. nx + 62
