@@ -90,7 +90,9 @@ struct Row2d {
 };
 
 // What one pass over the rows carries from a row to the next: the W, J of the
-// y faces below the current row's cells and (anisotropy) phi of the row below.
+// y faces below the current row's cells and (anisotropy) phi of the row below;
+// in a pass from the top down, the U, J of the faces above and phi of the row
+// above.
 template <typename R, int NP, int NM, int V, bool ANISO>
 struct Carry2d {
     R Wlo[V][NP];
@@ -145,15 +147,19 @@ __device__ __forceinline__ void yface(const Row2d<R, NP, NM, V, ANISO, GEN>& A,
                                         J);
 }
 
-// Carry of the first row of a pass, from the row below it.
-template <typename R, int NP, int NM, bool ANISO, int V, bool GEN = false>
+// Carry of the first row of a pass, from the row before it in the pass (below
+// it, or above it when DOWN).
+template <typename R, int NP, int NM, bool ANISO, int V, bool GEN = false, bool DOWN = false>
 __device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO, GEN>& prv,
                                            const Row2d<R, NP, NM, V, ANISO, GEN>& cur,
                                            Carry2d<R, NP, NM, V, ANISO>& k, const Coef<R>& c) {
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         R Ud[NP];
-        yface<R, NP, NM, ANISO, V, GEN>(prv, cur, i, c, Ud, k.Wlo[i], k.Jlo[i]);
+        if constexpr (DOWN)
+            yface<R, NP, NM, ANISO, V, GEN>(cur, prv, i, c, k.Wlo[i], Ud, k.Jlo[i]);
+        else
+            yface<R, NP, NM, ANISO, V, GEN>(prv, cur, i, c, Ud, k.Wlo[i], k.Jlo[i]);
     }
     if constexpr (ANISO) {
 #pragma unroll
@@ -163,10 +169,10 @@ __device__ __forceinline__ void carry_init(const Row2d<R, NP, NM, V, ANISO, GEN>
     }
 }
 
-// New values of the row `cur` (nxt is the row above) and the carry moved up
-// one row.  Cs = psi_const of the row, tt its T - Te; hn receives h of the
-// new phi.
-template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN = false>
+// New values of the row `cur` (nxt is the next row of the pass: the row above,
+// or the row below when DOWN) and the carry moved on one row.  Cs = psi_const
+// of the row, tt its T - Te; hn receives h of the new phi.
+template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool GEN = false, bool DOWN = false>
 __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO, GEN>& cur,
                                            const Row2d<R, NP, NM, V, ANISO, GEN>& nxt,
                                            Carry2d<R, NP, NM, V, ANISO>& k, const R (&Cs)[NP],
@@ -178,7 +184,8 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO, GEN>
 #pragma unroll
         for (int i = 0; i < V; ++i)
 #pragma unroll
-            for (int a = 0; a < NP; ++a) cdy[i][a] = nxt.phi[i][a] - k.prvphi[i][a];
+            for (int a = 0; a < NP; ++a)
+                cdy[i][a] = DOWN ? k.prvphi[i][a] - nxt.phi[i][a] : nxt.phi[i][a] - k.prvphi[i][a];
     }
     // x face to the right of the last cell, with the next lane's first cell
     R Ur[NP], Wr[NP], Jr[NM];
@@ -227,12 +234,17 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO, GEN>
         }
         // y face (m, m+1) above cell i
         R Uy[NP], Wy[NP], Jy[NM];
-        yface<R, NP, NM, ANISO, V, GEN>(cur, nxt, i, c, Uy, Wy, Jy);
+        if constexpr (DOWN)
+            yface<R, NP, NM, ANISO, V, GEN>(nxt, cur, i, c, Uy, Wy, Jy);
+        else
+            yface<R, NP, NM, ANISO, V, GEN>(cur, nxt, i, c, Uy, Wy, Jy);
         R Gs[NP], Js[NM];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) Gs[a] = (Ux[a] - Wxl[a]) + (Uy[a] - k.Wlo[i][a]);
+        for (int a = 0; a < NP; ++a)
+            Gs[a] = (Ux[a] - Wxl[a]) + (DOWN ? k.Wlo[i][a] - Wy[a] : Uy[a] - k.Wlo[i][a]);
 #pragma unroll
-        for (int kk = 0; kk < NM; ++kk) Js[kk] = (Jx[kk] - Jxl[kk]) + (Jy[kk] - k.Jlo[i][kk]);
+        for (int kk = 0; kk < NM; ++kk)
+            Js[kk] = (Jx[kk] - Jxl[kk]) + (DOWN ? k.Jlo[i][kk] - Jy[kk] : Jy[kk] - k.Jlo[i][kk]);
         R pn[NP], un[NM], h0[NP], h1[NP];
         interp_h<R, NP>(cur.phi[i], h0);
         cell_update_any<R, NP, NM, OBST, GEN>(cur.phi[i], cur.mu[i], h0, Gs, Js, Cs, tt, c, x, pn, un, h1);
@@ -240,7 +252,7 @@ __device__ __forceinline__ void row_update(const Row2d<R, NP, NM, V, ANISO, GEN>
         for (int a = 0; a < NP; ++a) {
             phin[a][i] = pn[a];
             hn[a][i] = h1[a];
-            k.Wlo[i][a] = Wy[a];
+            k.Wlo[i][a] = DOWN ? Uy[a] : Wy[a];
             Wxl[a] = Wx[a];
         }
 #pragma unroll
@@ -452,9 +464,11 @@ __device__ __forceinline__ int x2_first_col(int tx, int lane) {
 
 // XEDGE: the wave holds a mirror ghost column (wave-uniform; only then are
 // the mirror copies of step 1 made).  STORE1: the step-1 rows of the segment
-// are also written, to out1 (the state between the two steps).
+// are also written, to out1 (the state between the two steps).  DOWN: the
+// rows are visited from the top of the segment down (the y face below a row
+// is formed there and its lower-cell part carried to the next row).
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool XEDGE, bool STORE1 = false,
-          bool GEN = false, bool DIAG = false>
+          bool GEN = false, bool DIAG = false, bool DOWN = false>
 __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
                                            const Geom& g, const Coef<R>& c, double tbase0, double tbase1,
                                            double tslope, int tx, int m0, int m1, const CoefX<R>* x = nullptr,
@@ -472,7 +486,11 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     const bool writes = lane >= 2 && lane <= W2X_LANES_OUT + 1 && cs < nx;
     const bool top = !pery && m0 == 0;   // step-1 row -1 is a copy of row 0
     const bool bot = !pery && m1 == ny;  // step-1 row ny is a copy of row ny-1
-    const int r_first = top ? 0 : m0 - 1;  // step-1 rows computed: r_first .. (bot ? ny - 1 : m1)
+    // step-1 rows computed: (top ? 0 : m0 - 1) .. (bot ? ny - 1 : m1), from the
+    // bottom up, or from the top down (DOWN)
+    constexpr int dir = DOWN ? -1 : 1;
+    const bool first_edge = DOWN ? bot : top;  // the start row's outer neighbour is the row itself
+    const int r_first = DOWN ? (bot ? ny - 1 : m1) : (top ? 0 : m0 - 1);
 
     auto rowmap = [&](int s) { return pery ? wrap(s, ny) : gmap(s, ny, false); };
     auto load = [&](int s, RawT& r) {
@@ -491,16 +509,16 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     RawT ld;
     {
         RawT a, b, d;
-        load(r_first - 1, a);
+        load(r_first - dir, a);
         load(r_first, b);
-        load(r_first + 1, d);
+        load(r_first + dir, d);
         RowT prv;
         process(a, prv);
         process(b, c0);
-        carry_init<R, NP, NM, ANISO, V, GEN>(prv, c0, k0, c);
+        carry_init<R, NP, NM, ANISO, V, GEN, DOWN>(prv, c0, k0, c);
         process(d, n0);
     }
-    load(r_first + 2, ld);
+    load(r_first + 2 * dir, ld);
 
     // Step-1 row r into P, then the state window moves up one row.  The
     // window always moves (past the last row needed it reads clamped rows that
@@ -511,7 +529,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         const R tt = (R)(tbase0 + tslope * (double)rowmap(r));
         psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V, GEN>(c0, n0, k0, Cs, c, phin, mun, hn, tt, x);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN, DOWN>(c0, n0, k0, Cs, c, phin, mun, hn, tt, x);
         R v[NF][V];
 #pragma unroll
         for (int i = 0; i < V; ++i) {
@@ -545,27 +563,27 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         c0 = n0;
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         process(ld, n0);
-        load(r + 3, ld);
+        load(r + 3 * dir, ld);
     };
 
     // step 1 -> 2: step-1 rows in c1 (row q) and n1 (row q+1)
     RowT c1, n1;
     {
-        RowT lower;
-        step1(r_first, lower);
-        if (top) {
-            c1 = lower;
+        RowT outer;
+        step1(r_first, outer);
+        if (first_edge) {
+            c1 = outer;
         } else {
-            step1(r_first + 1, c1);
+            step1(r_first + dir, c1);
         }
-        carry_init<R, NP, NM, ANISO, V, GEN>(lower, c1, k1, c);
+        carry_init<R, NP, NM, ANISO, V, GEN, DOWN>(outer, c1, k1, c);
     }
     auto step2 = [&](int q) {
         R Cs[NP];
         const R tt = (R)(tbase1 + tslope * (double)q);
         psi_const_any<R, NP, GEN>(tt, c, x, Cs);
         R phin[NP][V], mun[NM][V], hn[NP][V];
-        row_update<R, NP, NM, ANISO, OBST, V, GEN>(c1, n1, k1, Cs, c, phin, mun, hn, tt, x);
+        row_update<R, NP, NM, ANISO, OBST, V, GEN, DOWN>(c1, n1, k1, Cs, c, phin, mun, hn, tt, x);
         if (writes) {
             const int64_t o = (int64_t)q * nx + cs;
 #pragma unroll
@@ -576,16 +594,29 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
         }
         c1 = n1;
     };
-    for (int q = m0; q < m1 - 1; ++q) {
-        step1(q + 1, n1);
-        step2(q);
+    if constexpr (DOWN) {
+        for (int q = m1 - 1; q > m0; --q) {
+            step1(q - 1, n1);
+            step2(q);
+        }
+        // last row: above a no-flux bottom edge step-1 row -1 is a copy of row 0
+        if (top)
+            n1 = c1;
+        else
+            step1(m0 - 1, n1);
+        step2(m0);
+    } else {
+        for (int q = m0; q < m1 - 1; ++q) {
+            step1(q + 1, n1);
+            step2(q);
+        }
+        // last row: below a no-flux top edge step-1 row ny is a copy of row ny-1
+        if (bot)
+            n1 = c1;
+        else
+            step1(m1, n1);
+        step2(m1 - 1);
     }
-    // last row: below a no-flux top edge step-1 row ny is a copy of row ny-1
-    if (bot)
-        n1 = c1;
-    else
-        step1(m1, n1);
-    step2(m1 - 1);
 }
 
 #ifndef MP_WAVES_PER_EU
@@ -619,6 +650,10 @@ k_step2d(const R* __restrict__ in, R* __restrict__ out, Geom g, Coef<R> c,
     strip2d<R, NP, NM, ANISO, OBST, V>(in, out, g, c, tbase, tslope, tx, m0, min(m0 + seg, g.ny));
 }
 
+// Odd row segments march from the top down, so that the two segments on either
+// side of a segment border reach the rows around it at about the same time and
+// the second reads them from L2 (the results do not depend on the direction:
+// every face takes the same operands in the same order).
 template <typename R, int NP, int NM, bool ANISO, bool OBST, int V, bool STORE1 = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP_WAVES_PER_EU)))
 k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1, Geom g, Coef<R> c,
@@ -633,14 +668,22 @@ k_step2d_x2(const R* __restrict__ in, R* __restrict__ out, R* __restrict__ out1,
     const double n = (double)(*stepctr + kstep);
     bool fixL, fixR;
     x2_column<V>(g, x2_first_col<V>(tx, threadIdx.x & 63), fixL, fixR);
-    if (__ballot(fixL || fixR) != 0)
-        strip2d_x2<R, NP, NM, ANISO, OBST, V, true, STORE1>(in, out, out1, g, c, tb0 + tdn * n,
-                                                            tb0 + tdn * (n + 1.0), tslope, tx, m0,
-                                                            min(m0 + seg, g.ny));
-    else
-        strip2d_x2<R, NP, NM, ANISO, OBST, V, false, STORE1>(in, out, out1, g, c, tb0 + tdn * n,
-                                                             tb0 + tdn * (n + 1.0), tslope, tx, m0,
-                                                             min(m0 + seg, g.ny));
+    const bool xe = __ballot(fixL || fixR) != 0;
+    const double t0 = tb0 + tdn * n, t1 = tb0 + tdn * (n + 1.0);
+    const int m1 = min(m0 + seg, g.ny);
+    if (sg & 1) {
+        if (xe)
+            strip2d_x2<R, NP, NM, ANISO, OBST, V, true, STORE1, false, false, true>(in, out, out1, g, c, t0, t1,
+                                                                                   tslope, tx, m0, m1);
+        else
+            strip2d_x2<R, NP, NM, ANISO, OBST, V, false, STORE1, false, false, true>(in, out, out1, g, c, t0, t1,
+                                                                                    tslope, tx, m0, m1);
+    } else {
+        if (xe)
+            strip2d_x2<R, NP, NM, ANISO, OBST, V, true, STORE1>(in, out, out1, g, c, t0, t1, tslope, tx, m0, m1);
+        else
+            strip2d_x2<R, NP, NM, ANISO, OBST, V, false, STORE1>(in, out, out1, g, c, t0, t1, tslope, tx, m0, m1);
+    }
 }
 
 // The general kernels of the extended model (one cell per lane): the same
