@@ -59,22 +59,22 @@ CSRC = os.path.join(ROOT, "paper_2404_01035_amd", "csrc")
 # it was taken on (LEG_SOURCES); otherwise the leg reports traffic null.
 TRAFFIC = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "e6cf09bd40a6b43b",
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4a474857c5ff4d5f",
                "bytes": (2.0 * 369660.8 + 667176.8) * 1024},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "61f395319885c485",
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5d7d2c7608a102ff",
                "bytes": (2.0 * 190450.6 + 337887.8) * 1024},
     # profiles/k_step2d_x2_gen_eutectic_4096_f64_f32.md
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "ec5a6dc66a9a7422",
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "74a41cb44a9264f6",
                   "bytes": (2.0 * 384876.0 + 656564.4) * 1024},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "e73fdc2cf5e827f0",
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "dedc49bcd4c6aefc",
                   "bytes": (2.0 * 224329.2 + 329085.2) * 1024},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136",
            "bytes": (2.0 * 1151502.1 + 1572864.0) * 1024},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "1e1c14ee6bb36107",
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "a1969566f127ef6b",
                 "bytes": (2.0 * 416826.7 + 659186.5) * 1024},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "1e1c14ee6bb36107",
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "a1969566f127ef6b",
                 "bytes": (2.0 * 247552.7 + 331791.2) * 1024},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
     "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc",
@@ -85,7 +85,7 @@ TRAFFIC = {
     "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "827edfbe96172ad2",
                  "bytes": (2.0 * 2125895.1 + 581596.0) * 1024},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "737301a364704c4a",
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "4a2ddb4fb8f20f42",
            "bytes": (2.0 * 706252.1 + 1235989.5) * 1024},
 }
 METRIC = "cell-updates/s of fused phi+mu step (FP64 vs FP32), % HBM peak, adjoint/fwd cost"
@@ -227,23 +227,23 @@ def alu_roofline(flops_per_step, ms_step, precision, traffic=None):
 # peaks above: 16 FP64 or 32 FP32 lanes per SIMD per cycle).
 VALU = {
     # profiles/k_step2d_eutectic_4096_f64_f32.md
-    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "e6cf09bd40a6b43b", "insts": 153843513.0},
-    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "61f395319885c485", "insts": 138091296.0},
+    "c2_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "4a474857c5ff4d5f", "insts": 153843513.0},
+    "c2_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "5d7d2c7608a102ff", "insts": 138091296.0},
     # profiles/k_step2d_x2_gen_eutectic_4096_f64_f32.md
-    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "ec5a6dc66a9a7422", "insts": 229763385.0},
-    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "e73fdc2cf5e827f0", "insts": 176406168.0},
+    "c2ext_f64": {"tile": [256, 31, 1], "fuse": 2, "src": "74a41cb44a9264f6", "insts": 229763385.0},
+    "c2ext_f32": {"tile": [256, 14, 1], "fuse": 2, "src": "dedc49bcd4c6aefc", "insts": 176406168.0},
     # profiles/k_step3d_dendrite_512_f32.md
     "c3": {"tile": [512, 64, -1], "fuse": 1, "src": "cd5215f0b01a0136", "insts": 545827325.3},
     # profiles/k_step2d_at_eutectic_4096_f64_f32.md
-    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "1e1c14ee6bb36107", "insts": 203122347.0},
-    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "1e1c14ee6bb36107", "insts": 145416750.0},
+    "atf_f64": {"tile": [256, 31, 1], "fuse": 1, "src": "a1969566f127ef6b", "insts": 203122347.0},
+    "atf_f32": {"tile": [256, 14, 1], "fuse": 1, "src": "a1969566f127ef6b", "insts": 145416750.0},
     # profiles/k_antitrap2d_eutectic_4096_f64_f32.md
     "at_f64": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 106811674.0},
     "at_f32": {"tile": [62, 12, 1], "fuse": 1, "src": "2bbd3f220a9e5ebc", "insts": 78199324.0},
     # profiles/k_antitrap3d_dendrite_512_f32.md
     "at3d_f32": {"tile": [62, 2, 1], "fuse": 1, "src": "827edfbe96172ad2", "insts": 654686208.0},
     # profiles/k_batch2d_ensemble_256_f32.md
-    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "737301a364704c4a", "insts": 468028690.0},
+    "c4": {"tile": [256, 32, 1], "fuse": 2, "src": "4a2ddb4fb8f20f42", "insts": 468028690.0},
 }
 VALU_CYCLES = {"f64": 4, "f32": 2}
 SIMDS = 1024         # 256 CUs x 4 SIMDs

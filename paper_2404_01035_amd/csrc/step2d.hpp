@@ -520,7 +520,7 @@ __device__ __forceinline__ void strip2d_x2(const R* __restrict__ in, R* __restri
     }
     load(r_first + 2 * dir, ld);
 
-    // Step-1 row r into P, then the state window moves up one row.  The
+    // Step-1 row r into P, then the state window moves on one row.  The
     // window always moves (past the last row needed it reads clamped rows that
     // go unused), so that the row loop below has a single path and the rows in
     // flight stay in the registers they are loaded into.
