@@ -6,6 +6,8 @@ that every cell is written by exactly one lane, and that every written cell's
 stencil operands are the right columns: its x neighbours in the one-step
 strip, and in the two-step strip the step-1 values (column labels) of the
 cell and its neighbours -- including the mirror copies made at no-flux edges.
+Also the two-step strip's row schedule, upward and (odd segments) downward:
+each row update sees the rows it needs, and every row is written once.
 """
 import pytest
 
@@ -126,3 +128,65 @@ def test_strip_lane_mapping(elem, cap, periodic):
         V = vec_width(nx, elem, cap)
         one_step(nx, V, periodic)
         two_steps(nx, V, periodic)
+
+
+def two_step_rows(ny, m0, m1, per, down):
+    """Row schedule of the two-step strip (strip2d_x2) over rows m0..m1-1, marching up or, for
+    odd segments, down: checks that every step-1 row update sees the state rows it needs in its
+    window (the row itself, the next row of the march, and the row before it for the carried
+    face), every step-2 update the step-1 rows it needs, and returns the rows written."""
+    d = -1 if down else 1
+    top = not per and m0 == 0
+    bot = not per and m1 == ny
+    first_edge = bot if down else top
+
+    def rowmap(s):
+        return s % ny if per else min(max(s, 0), ny - 1)
+
+    r_first = (ny - 1 if bot else m1) if down else (0 if top else m0 - 1)
+    win = {"prev": rowmap(r_first - d), "cur": rowmap(r_first), "next": rowmap(r_first + d),
+           "ahead": rowmap(r_first + 2 * d)}
+
+    def step1(r):
+        assert per or 0 <= r < ny, ("step-1 row outside the grid", r)
+        assert win["cur"] == rowmap(r) and win["next"] == rowmap(r + d) and win["prev"] == rowmap(r - d), r
+        win["prev"], win["cur"], win["next"] = win["cur"], win["next"], win["ahead"]
+        win["ahead"] = rowmap(r + 3 * d)
+        return ("s1", rowmap(r))  # step-1 value of that row (a mirror ghost is the same record)
+
+    written = []
+    outer = step1(r_first)
+    c1 = outer if first_edge else step1(r_first + d)
+    k1 = outer
+
+    def step2(q):
+        nonlocal c1, k1
+        assert c1 == ("s1", rowmap(q)) and n1[0] == ("s1", rowmap(q + d)) and k1 == ("s1", rowmap(q - d)), q
+        written.append(q)
+        k1, c1 = c1, n1[0]
+
+    n1 = [None]
+    q0, qlast = (m1 - 1, m0) if down else (m0, m1 - 1)
+    q = q0
+    while q != qlast:
+        n1[0] = step1(q + d)
+        step2(q)
+        q += d
+    last_edge = top if down else bot
+    n1[0] = c1 if last_edge else step1(qlast + d)
+    step2(qlast)
+    return written
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_two_step_row_schedule_both_directions(periodic):
+    for ny in range(1, 14):
+        for seg in range(1, 6):
+            written = []
+            for sg, m0 in enumerate(range(0, ny, seg)):
+                m1 = min(m0 + seg, ny)
+                rows = two_step_rows(ny, m0, m1, periodic, down=bool(sg & 1))
+                assert sorted(rows) == list(range(m0, m1))
+                assert rows == (list(range(m1 - 1, m0 - 1, -1)) if sg & 1 else list(range(m0, m1)))
+                written += rows
+            assert sorted(written) == list(range(ny)), (ny, seg)
